@@ -1,0 +1,24 @@
+"""FP64 CPU oracle for the probabilistic local-divergence path.
+
+TEST INFRASTRUCTURE ONLY.  Nothing in the product path may import or call this
+package: only the test suite, the smoke check and the benchmark's CPU-baseline
+leg use it.  It shares no code with the HIP library (no kernels, headers,
+helpers, tables or constants) and never imports it.
+
+The oracle is written from the paper (Ouermi et al., "Efficient Probabilistic
+Visualization of Local Divergence of 2D Vector Fields with Independent Gaussian
+Uncertainty"): plain, slow, obviously correct numpy in float64.
+"""
+
+from .pdiv_oracle import (  # noqa: F401
+    moments,
+    fd_divergence,
+    divergence_gaussian,
+    vertex_probs,
+    lcp,
+    philox4x32_10,
+    box_muller,
+    mc_sample_field,
+    mc_lcp,
+    mc_lcp_vertex,
+)

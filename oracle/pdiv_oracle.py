@@ -1,0 +1,305 @@
+"""Plain FP64 oracle of the probabilistic local-divergence path.
+
+TEST INFRASTRUCTURE ONLY (see the package docstring): the product path never
+imports this module.
+
+Grid convention (the reading of Section 3.1 used throughout): i is the x index
+(0 <= i < nx), j the y index (0 <= j < ny); arrays are row-major [ny][nx] with
+x fastest.  U is the x component and V the y component of the uncertain vector
+field F = (U, V); U_{i+-1} means U at (i+-1, j) and V_{j+-1} means V at
+(i, j+-1).  Cell (i, j) has corners (i,j), (i+1,j), (i,j+1), (i+1,j+1).
+
+Parity status per function:
+  moments            pinned (numpy mean/var, closed forms, invariants)
+  fd_divergence      pinned (numpy.gradient, linear fields)
+  divergence_gaussian pinned (Fig. 2 worked example, numpy.gradient, closed forms,
+                      brute-force sampling)
+  lcp                pinned (marching-squares limit, i.i.d. closed form, symmetry,
+                      brute-force sampling, mpmath tails)
+  philox4x32_10      pinned (published known-answer vectors, rocRAND routine)
+  box_muller         pinned (closed form at chosen inputs, normality tests)
+  mc_lcp             pinned statistically against lcp on interior cells; a single
+                     MC draw has no closed form to pin to.
+"""
+
+from __future__ import annotations
+
+import numpy as np
+from scipy.special import erfc
+
+# ---------------------------------------------------------------------------
+# (a) Gaussian fit per point (Section 3: each component independently
+#     N(mu, sigma^2); Section 4 fits it over 15 or 20 ensemble members).
+#     The paper does not name the estimator; the reading is the sample mean
+#     and the sample variance with ddof in {0, 1} (default 1, unbiased).
+# ---------------------------------------------------------------------------
+
+def moments(u_members, v_members, ddof: int = 1):
+    """Two-pass FP64 mean and variance over the member axis (axis 0).
+
+    mu = (1/M) sum_m x_m;  sigma^2 = sum_m (x_m - mu)^2 / (M - ddof).
+    Returns (mean_u, var_u, mean_v, var_v), each [ny][nx] float64."""
+    out = []
+    for x in (u_members, v_members):
+        x = np.asarray(x, dtype=np.float64)
+        m = x.shape[0]
+        if m <= ddof:
+            raise ValueError("need more members than ddof")
+        mu = x.sum(axis=0) / m
+        var = ((x - mu[None]) ** 2).sum(axis=0) / (m - ddof)
+        out += [mu, var]
+    return tuple(out)
+
+
+# ---------------------------------------------------------------------------
+# (b) Finite-difference divergence, Eq. 1: central differences inside,
+#     forward / backward differences at the boundary (Section 3.1).
+#     The order of the one-sided differences is not stated; the reading is
+#     first order: (f_1 - f_0)/h at the low edge, (f_{n-1} - f_{n-2})/h at the
+#     high edge.
+# ---------------------------------------------------------------------------
+
+def _ddx(f, h):
+    """Derivative along x (axis 1) by Eq. 1's differences, float64."""
+    f = np.asarray(f, np.float64)
+    nx = f.shape[1]
+    d = np.empty_like(f)
+    d[:, 1:nx - 1] = (f[:, 2:] - f[:, :nx - 2]) / (2.0 * h)
+    d[:, 0] = (f[:, 1] - f[:, 0]) / h
+    d[:, nx - 1] = (f[:, nx - 1] - f[:, nx - 2]) / h
+    return d
+
+
+def fd_divergence(u, v, dx: float, dy: float):
+    """Eq. 1 applied to one deterministic field (u, v): du/dx + dv/dy."""
+    return _ddx(u, dx) + _ddx(np.asarray(v, np.float64).T, dy).T
+
+
+def divergence_gaussian(mean_u, var_u, mean_v, var_v, dx: float, dy: float):
+    """Eq. 2 (mean) and Eq. 3 (variance) of the divergence at every vertex.
+
+    Inside, Eq. 2 and Eq. 3 as printed:
+      mu  = mu^U_{i+1}/(2dx) - mu^U_{i-1}/(2dx) + mu^V_{j+1}/(2dy) - mu^V_{j-1}/(2dy)
+      var = (s^U_{i+1}/(2dx))^2 + (s^U_{i-1}/(2dx))^2 + (s^V_{j+1}/(2dy))^2 + (s^V_{j-1}/(2dy))^2
+    At a boundary the difference of Eq. 1 is one-sided with step h instead of
+    2h; the same independence argument then gives, e.g. at i = 0,
+      mu_x = (mu^U_1 - mu^U_0)/dx,  var_x = (s^U_1)^2/dx^2 + (s^U_0)^2/dx^2.
+    Returns (div_mean, div_var), each [ny][nx] float64."""
+    mu_u = np.asarray(mean_u, np.float64)
+    mu_v = np.asarray(mean_v, np.float64)
+    s_u = np.sqrt(np.asarray(var_u, np.float64))
+    s_v = np.sqrt(np.asarray(var_v, np.float64))
+    ny, nx = mu_u.shape
+
+    mean = np.zeros((ny, nx), np.float64)
+    var = np.zeros((ny, nx), np.float64)
+    # x part, column by column over i
+    for i in range(nx):
+        if 0 < i < nx - 1:
+            lo, hi, h = i - 1, i + 1, 2.0 * dx
+        elif i == 0:
+            lo, hi, h = 0, 1, dx
+        else:
+            lo, hi, h = nx - 2, nx - 1, dx
+        mean[:, i] += mu_u[:, hi] / h - mu_u[:, lo] / h
+        var[:, i] += (s_u[:, hi] / h) ** 2 + (s_u[:, lo] / h) ** 2
+    # y part, row by row over j
+    for j in range(ny):
+        if 0 < j < ny - 1:
+            lo, hi, h = j - 1, j + 1, 2.0 * dy
+        elif j == 0:
+            lo, hi, h = 0, 1, dy
+        else:
+            lo, hi, h = ny - 2, ny - 1, dy
+        mean[j, :] += mu_v[hi, :] / h - mu_v[lo, :] / h
+        var[j, :] += (s_v[hi, :] / h) ** 2 + (s_v[lo, :] / h) ** 2
+    return mean, var
+
+
+# ---------------------------------------------------------------------------
+# (c) Level-crossing probability (Section 3.1, after Poethkow et al.): the
+#     probability that the c-isocontour crosses a cell whose four corners hold
+#     independent Gaussians N(mu_k, sigma_k^2).  The contour crosses unless all
+#     four corners lie on the same side of c, so
+#         LCP = 1 - prod_k P(X_k >= c) - prod_k P(X_k < c).
+#     Ties follow the marching-squares convention: a corner is "above" iff its
+#     value >= c.  With sigma_k = 0 the corner is deterministic.
+# ---------------------------------------------------------------------------
+
+def vertex_probs(mu, var, c: float):
+    """(a, b) = (P(X >= c), P(X < c)) for X ~ N(mu, var), elementwise float64."""
+    mu = np.asarray(mu, np.float64)
+    var = np.asarray(var, np.float64)
+    sd = np.sqrt(var)
+    with np.errstate(divide="ignore", invalid="ignore"):
+        a = 0.5 * erfc((c - mu) / (sd * np.sqrt(2.0)))
+        b = 0.5 * erfc((mu - c) / (sd * np.sqrt(2.0)))
+    det = sd == 0.0
+    a = np.where(det, np.where(mu >= c, 1.0, 0.0), a)
+    b = np.where(det, np.where(mu >= c, 0.0, 1.0), b)
+    bad = np.isnan(mu) | np.isnan(var)
+    a = np.where(bad, np.nan, a)
+    b = np.where(bad, np.nan, b)
+    return a, b
+
+
+def lcp(div_mean, div_var, isovalues):
+    """Closed-form LCP maps [K][ny-1][nx-1] float64 from the vertex Gaussians."""
+    mu = np.asarray(div_mean, np.float64)
+    var = np.asarray(div_var, np.float64)
+    ny, nx = mu.shape
+    iso = np.atleast_1d(np.asarray(isovalues, np.float64))
+    out = np.empty((iso.size, ny - 1, nx - 1), np.float64)
+    for k, c in enumerate(iso):
+        a, b = vertex_probs(mu, var, c)
+        corners_a = (a[:-1, :-1], a[:-1, 1:], a[1:, :-1], a[1:, 1:])
+        corners_b = (b[:-1, :-1], b[:-1, 1:], b[1:, :-1], b[1:, 1:])
+        all_above = corners_a[0] * corners_a[1] * corners_a[2] * corners_a[3]
+        all_below = corners_b[0] * corners_b[1] * corners_b[2] * corners_b[3]
+        out[k] = 1.0 - all_above - all_below
+    return out
+
+
+# ---------------------------------------------------------------------------
+# (d) Monte Carlo LCP, the paper's comparison (Section 3.2 and Section 4):
+#     draw samples of the uncertain vectors at every grid point, form the
+#     divergence of each sample by Eq. 1, count per cell how often the
+#     c-isocontour crosses it, divide by the sample count.
+#
+#     The paper names no random number generator.  Reading: Philox4x32-10
+#     (Salmon, Moraes, Dror, Shaw, "Parallel random numbers: as easy as 1, 2,
+#     3", SC 2011) keyed by the 64-bit seed, with counter
+#     (point index p = j*nx + i, sample pair q = s // 2, 0, 0); its four output
+#     words feed two Box-Muller transforms (Box & Muller 1958): words (w0, w1)
+#     give (U, V) standard normals of sample 2q, words (w2, w3) of sample 2q+1.
+# ---------------------------------------------------------------------------
+
+_PHILOX_M0 = np.uint64(0xD2511F53)
+_PHILOX_M1 = np.uint64(0xCD9E8D57)
+_PHILOX_W0 = 0x9E3779B9
+_PHILOX_W1 = 0xBB67AE85
+_MASK32 = np.uint64(0xFFFFFFFF)
+
+
+def philox4x32_10(c0, c1, c2, c3, k0: int, k1: int):
+    """Philox4x32 with 10 rounds on uint32 arrays (c0..c3) and a 2-word key.
+
+    One round: (hi0, lo0) = M0 * x0 and (hi1, lo1) = M1 * x2 as 64-bit products;
+    new state = (hi1 ^ x1 ^ k0, lo1, hi0 ^ x3 ^ k1, lo0).  Between rounds the key
+    advances by the Weyl constants (W0, W1) modulo 2^32."""
+    x0 = np.asarray(c0, np.uint32).astype(np.uint64)
+    x1 = np.asarray(c1, np.uint32).astype(np.uint64)
+    x2 = np.asarray(c2, np.uint32).astype(np.uint64)
+    x3 = np.asarray(c3, np.uint32).astype(np.uint64)
+    ka, kb = int(k0) & 0xFFFFFFFF, int(k1) & 0xFFFFFFFF
+    for r in range(10):
+        if r > 0:
+            ka = (ka + _PHILOX_W0) & 0xFFFFFFFF
+            kb = (kb + _PHILOX_W1) & 0xFFFFFFFF
+        p0 = _PHILOX_M0 * x0
+        p1 = _PHILOX_M1 * x2
+        hi0, lo0 = p0 >> np.uint64(32), p0 & _MASK32
+        hi1, lo1 = p1 >> np.uint64(32), p1 & _MASK32
+        x0, x1, x2, x3 = (hi1 ^ x1 ^ np.uint64(ka), lo1, hi0 ^ x3 ^ np.uint64(kb), lo0)
+    return tuple(w.astype(np.uint32) for w in (x0, x1, x2, x3))
+
+
+def box_muller(wa, wb):
+    """Two standard normals from two uint32 words, float64.
+
+    u1 = (wa + 1) / 2^32 in (0, 1], u2 = wb / 2^32 in [0, 1);
+    r = sqrt(-2 ln u1), z0 = r cos(2 pi u2), z1 = r sin(2 pi u2)."""
+    u1 = (np.asarray(wa, np.float64) + 1.0) / 4294967296.0
+    u2 = np.asarray(wb, np.float64) / 4294967296.0
+    r = np.sqrt(-2.0 * np.log(u1))
+    return r * np.cos(2.0 * np.pi * u2), r * np.sin(2.0 * np.pi * u2)
+
+
+def _normals(n_points: int, s: int, seed: int):
+    """Standard normals (zu, zv) of sample s at points 0..n_points-1."""
+    p = np.arange(n_points, dtype=np.uint64).astype(np.uint32)
+    q = np.full(n_points, s // 2, np.uint32)
+    zero = np.zeros(n_points, np.uint32)
+    w0, w1, w2, w3 = philox4x32_10(p, q, zero, zero, seed & 0xFFFFFFFF, (seed >> 32) & 0xFFFFFFFF)
+    return box_muller(w0, w1) if s % 2 == 0 else box_muller(w2, w3)
+
+
+def mc_sample_field(mean_u, var_u, mean_v, var_v, s: int, seed: int):
+    """Sample s of the uncertain field: U = mu_u + sigma_u zu, V = mu_v + sigma_v zv (float64)."""
+    mu_u = np.asarray(mean_u, np.float64)
+    ny, nx = mu_u.shape
+    zu, zv = _normals(ny * nx, s, seed)
+    u = mu_u + np.sqrt(np.asarray(var_u, np.float64)) * zu.reshape(ny, nx)
+    v = np.asarray(mean_v, np.float64) + np.sqrt(np.asarray(var_v, np.float64)) * zv.reshape(ny, nx)
+    return u, v
+
+
+def _crossed(d, c):
+    """Cells whose four corners are not all on one side of c (>= is above)."""
+    up = d >= c
+    a = up[:-1, :-1].astype(np.int8) + up[:-1, 1:] + up[1:, :-1] + up[1:, 1:]
+    return (a != 0) & (a != 4)
+
+
+def mc_lcp(mean_u, var_u, mean_v, var_v, dx: float, dy: float, isovalues,
+           n_samples: int, seed: int, precision: str = "f64"):
+    """Vector-level MC LCP maps [K][ny-1][nx-1] (crossing counts / n_samples).
+
+    precision="f64": every step in float64 (the definition).
+    precision="f32": the same steps with the sample field, the divergence and
+    the crossing test rounded to float32 -- the precision in which a float32
+    implementation takes the crossing decision.  The normals themselves are
+    computed in float64 and rounded once."""
+    iso = np.atleast_1d(np.asarray(isovalues, np.float64))
+    mu_u = np.asarray(mean_u, np.float64)
+    ny, nx = mu_u.shape
+    counts = np.zeros((iso.size, ny - 1, nx - 1), np.int64)
+    if precision == "f64":
+        for s in range(n_samples):
+            u, v = mc_sample_field(mean_u, var_u, mean_v, var_v, s, seed)
+            d = fd_divergence(u, v, dx, dy)
+            for k, c in enumerate(iso):
+                counts[k] += _crossed(d, c)
+    elif precision == "f32":
+        f = np.float32
+        mu_u32 = np.asarray(mean_u, f)
+        mu_v32 = np.asarray(mean_v, f)
+        sd_u32 = np.sqrt(np.asarray(var_u, f))
+        sd_v32 = np.sqrt(np.asarray(var_v, f))
+        iso32 = iso.astype(f)
+        cx_in, cx_bd = f(1.0 / (2.0 * dx)), f(1.0 / dx)
+        cy_in, cy_bd = f(1.0 / (2.0 * dy)), f(1.0 / dy)
+        for s in range(n_samples):
+            zu, zv = _normals(ny * nx, s, seed)
+            u = mu_u32 + sd_u32 * zu.reshape(ny, nx).astype(f)
+            v = mu_v32 + sd_v32 * zv.reshape(ny, nx).astype(f)
+            ddx = np.empty((ny, nx), f)
+            ddx[:, 1:nx - 1] = (u[:, 2:] - u[:, :nx - 2]) * cx_in
+            ddx[:, 0] = (u[:, 1] - u[:, 0]) * cx_bd
+            ddx[:, nx - 1] = (u[:, nx - 1] - u[:, nx - 2]) * cx_bd
+            ddy = np.empty((ny, nx), f)
+            ddy[1:ny - 1, :] = (v[2:, :] - v[:ny - 2, :]) * cy_in
+            ddy[0, :] = (v[1, :] - v[0, :]) * cy_bd
+            ddy[ny - 1, :] = (v[ny - 1, :] - v[ny - 2, :]) * cy_bd
+            d = ddx + ddy
+            for k, c in enumerate(iso32):
+                counts[k] += _crossed(d, c)
+    else:
+        raise ValueError(precision)
+    return counts / float(n_samples)
+
+
+def mc_lcp_vertex(div_mean, div_var, isovalues, n_samples: int, seed: int):
+    """Vertex-level brute force: draw each vertex divergence independently from
+    N(mu, var) with numpy's PCG64 and count crossings.  Converges to lcp() on
+    every cell (the closed form's own model), unlike the vector-level MC."""
+    rng = np.random.default_rng(seed)
+    mu = np.asarray(div_mean, np.float64)
+    sd = np.sqrt(np.asarray(div_var, np.float64))
+    iso = np.atleast_1d(np.asarray(isovalues, np.float64))
+    counts = np.zeros((iso.size,) + (mu.shape[0] - 1, mu.shape[1] - 1), np.int64)
+    for _ in range(n_samples):
+        d = mu + sd * rng.standard_normal(mu.shape)
+        for k, c in enumerate(iso):
+            counts[k] += _crossed(d, c)
+    return counts / float(n_samples)

@@ -1,0 +1,155 @@
+"""Pins for the oracle's Monte Carlo LCP (Sections 3.2 and 4) and its random numbers."""
+
+import os
+import shutil
+import subprocess
+
+import numpy as np
+import pytest
+from scipy import stats
+
+import oracle as O
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+
+# Published known-answer vectors of Philox4x32-10 (Random123 distribution,
+# Salmon et al., SC 2011): counter words, key words, output words.
+KAT = [
+    ((0, 0, 0, 0), (0, 0), (0x6627E8D5, 0xE169C58D, 0xBC57AC4C, 0x9B00DBD8)),
+    ((0xFFFFFFFF,) * 4, (0xFFFFFFFF, 0xFFFFFFFF), (0x408F276D, 0x41C83B0E, 0xA20BC7C6, 0x6D5451FD)),
+    ((0x243F6A88, 0x85A308D3, 0x13198A2E, 0x03707344), (0xA4093822, 0x299F31D0),
+     (0xD16CFE09, 0x94FDCCEB, 0x5001E420, 0x24126EA1)),
+]
+
+
+@pytest.mark.parametrize("ctr,key,want", KAT)
+def test_philox_known_answers(ctr, key, want):
+    got = O.philox4x32_10(*[np.array([c], np.uint32) for c in ctr], *key)
+    assert tuple(int(g[0]) for g in got) == want
+
+
+def test_philox_matches_rocrand_routine(tmp_path):
+    hipcc = shutil.which("hipcc")
+    if hipcc is None:
+        pytest.skip("hipcc not available")
+    exe = str(tmp_path / "philox_check")
+    subprocess.run([hipcc, "-x", "hip", "--offload-arch=gfx950", "-O1",
+                    os.path.join(HERE, "philox_rocrand_check.cpp"), "-o", exe],
+                   check=True, capture_output=True)
+    rng = np.random.default_rng(9)
+    tup = rng.integers(0, 2 ** 32, (64, 6), dtype=np.uint64).astype(np.uint32)
+    inp = "\n".join(" ".join(f"{int(x):x}" for x in row) for row in tup) + "\n"
+    out = subprocess.run([exe], input=inp, capture_output=True, text=True, check=True).stdout
+    lib = np.array([[int(w, 16) for w in line.split()] for line in out.strip().splitlines()])
+    for r in range(64):
+        got = O.philox4x32_10(*[tup[r:r + 1, c] for c in range(4)], int(tup[r, 4]), int(tup[r, 5]))
+        assert [int(g[0]) for g in got] == list(lib[r])
+
+
+def test_box_muller_closed_forms():
+    full = np.uint32(0xFFFFFFFF)
+    z0, z1 = O.box_muller(np.array([full]), np.array([12345], np.uint32))
+    assert z0[0] == 0.0 and z1[0] == 0.0  # u1 = 1: radius 0
+    wa = np.array([int(round(np.exp(-0.5) * 2 ** 32)) - 1], np.uint32)  # u1 ~ e^-1/2: radius 1
+    r = np.sqrt(-2.0 * np.log((float(wa[0]) + 1.0) / 2 ** 32))
+    assert abs(r - 1.0) < 1e-9
+    for wb, (c, s) in [(0, (1.0, 0.0)), (2 ** 30, (0.0, 1.0)), (2 ** 31, (-1.0, 0.0)), (3 * 2 ** 30, (0.0, -1.0))]:
+        z0, z1 = O.box_muller(wa, np.array([wb], np.uint32))
+        assert z0[0] == pytest.approx(r * c, abs=1e-15) and z1[0] == pytest.approx(r * s, abs=1e-15)
+
+
+def test_normals_are_standard_and_independent():
+    n = 200000
+    p = np.arange(n, dtype=np.uint32)
+    zero = np.zeros(n, np.uint32)
+    w = O.philox4x32_10(p, zero + 3, zero, zero, 0x1234, 0x5678)
+    a0, a1 = O.box_muller(w[0], w[1])
+    b0, b1 = O.box_muller(w[2], w[3])
+    for z in (a0, a1, b0, b1):
+        assert stats.kstest(z, "norm").pvalue > 1e-4
+        assert abs(z.mean()) < 5 / np.sqrt(n) and abs(z.var() - 1) < 5 * np.sqrt(2 / n)
+    for x, y in ((a0, a1), (a0, b0), (a1, b1), (a0, b1)):
+        assert abs(np.corrcoef(x, y)[0, 1]) < 5 / np.sqrt(n)
+
+
+def test_sample_field_moments():
+    rng = np.random.default_rng(2)
+    ny, nx = 3, 4
+    mu_u, mu_v = rng.normal(0, 1, (ny, nx)), rng.normal(0, 1, (ny, nx))
+    var_u, var_v = rng.uniform(0.1, 2, (ny, nx)), rng.uniform(0.1, 2, (ny, nx))
+    S = 20000
+    us = np.empty((S, ny, nx)); vs = np.empty((S, ny, nx))
+    for s in range(S):
+        us[s], vs[s] = O.mc_sample_field(mu_u, var_u, mu_v, var_v, s, seed=77)
+    assert np.all(np.abs(us.mean(0) - mu_u) < 4.5 * np.sqrt(var_u / S))
+    assert np.all(np.abs(vs.mean(0) - mu_v) < 4.5 * np.sqrt(var_v / S))
+    assert np.all(np.abs(us.var(0) / var_u - 1) < 4.5 * np.sqrt(2 / S))
+    assert np.all(np.abs(vs.var(0) / var_v - 1) < 4.5 * np.sqrt(2 / S))
+
+
+def _interior(ny, nx):
+    m = np.zeros((ny - 1, nx - 1), bool)
+    m[1:ny - 2, 1:nx - 2] = True  # 1 <= i <= nx-3, 1 <= j <= ny-3
+    return m
+
+
+def test_mc_matches_closed_form_on_interior_cells():
+    """Interior cells use disjoint U and V samples at their four corners, so the
+    vector-level MC estimates exactly the independent-corner LCP there."""
+    rng = np.random.default_rng(3)
+    ny, nx = 12, 14
+    mu_u, mu_v = rng.normal(0, 0.5, (ny, nx)), rng.normal(0, 0.5, (ny, nx))
+    var_u, var_v = rng.uniform(0.05, 0.5, (ny, nx)) ** 2, rng.uniform(0.05, 0.5, (ny, nx)) ** 2
+    iso = [-0.1, 0.2]
+    S = 4000
+    m, v = O.divergence_gaussian(mu_u, var_u, mu_v, var_v, 1.0, 1.0)
+    L = O.lcp(m, v, iso)
+    E = O.mc_lcp(mu_u, var_u, mu_v, var_v, 1.0, 1.0, iso, S, seed=42)
+    inner = np.broadcast_to(_interior(ny, nx), L.shape)
+    se = np.sqrt(np.maximum(L * (1 - L), 1.0 / S) / S)
+    z = (np.abs(E - L) / se)[inner]
+    assert np.sum(z > 3.0 + 1.0 / (S * se[inner])) <= max(1, int(0.01 * z.size))
+    assert np.mean(z ** 2) < 1.5
+
+
+def test_mc_boundary_cells_are_correlated():
+    """At the boundary the one-sided differences share samples, so the MC and
+    the independent-corner closed form differ there (the paper's model ignores
+    that correlation).  A field dominated by U at column 0 makes it stark."""
+    ny, nx = 6, 6
+    mu = np.zeros((ny, nx))
+    var_u = np.full((ny, nx), 1e-4); var_u[:, 0] = 100.0
+    var_v = np.full((ny, nx), 1e-4)
+    S = 4000
+    m, v = O.divergence_gaussian(mu, var_u, mu, var_v, 1.0, 1.0)
+    L = O.lcp(m, v, [0.0])[0]
+    E = O.mc_lcp(mu, var_u, mu, var_v, 1.0, 1.0, [0.0], S, seed=5)[0]
+    se = np.sqrt(L * (1 - L) / S)
+    assert np.all(np.abs(E[:, 0] - L[:, 0]) > 10 * se[:, 0])  # column-0 cells: ~0.5 vs 0.875
+    inner = _interior(ny, nx)
+    assert np.all(np.abs(E - L)[inner] < 4.5 * se[inner])
+
+
+def test_mc_zero_variance_is_deterministic_crossing():
+    rng = np.random.default_rng(6)
+    mu_u, mu_v = rng.normal(0, 1, (7, 9)), rng.normal(0, 1, (7, 9))
+    z = np.zeros_like(mu_u)
+    iso = [-0.5, 0.0, 0.3]
+    d = O.fd_divergence(mu_u, mu_v, 1.0, 1.0)
+    for prec in ("f64", "f32"):
+        E = O.mc_lcp(mu_u, z, mu_v, z, 1.0, 1.0, iso, 10, seed=1, precision=prec)
+        for k, c in enumerate(iso):
+            up = d >= c
+            n_up = up[:-1, :-1].astype(int) + up[:-1, 1:] + up[1:, :-1] + up[1:, 1:]
+            np.testing.assert_array_equal(E[k], ((n_up % 4) != 0).astype(float))
+
+
+def test_mc_f32_and_f64_agree_up_to_rare_flips():
+    rng = np.random.default_rng(8)
+    ny, nx = 10, 11
+    mu_u, mu_v = rng.normal(0, 0.5, (ny, nx)), rng.normal(0, 0.5, (ny, nx))
+    var_u, var_v = rng.uniform(0.05, 0.5, (ny, nx)) ** 2, rng.uniform(0.05, 0.5, (ny, nx)) ** 2
+    S = 1000
+    a = O.mc_lcp(mu_u, var_u, mu_v, var_v, 1.0, 1.0, [0.0, 0.3], S, seed=3, precision="f64")
+    b = O.mc_lcp(mu_u, var_u, mu_v, var_v, 1.0, 1.0, [0.0, 0.3], S, seed=3, precision="f32")
+    assert np.sum(np.abs(a - b) * S) <= 5
