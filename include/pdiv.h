@@ -1,0 +1,245 @@
+/*
+ * pdiv.h -- C ABI of libpdiv, the gfx950 (MI355X) implementation of the
+ * probabilistic local-divergence path of Ouermi et al., "Efficient
+ * Probabilistic Visualization of Local Divergence of 2D Vector Fields with
+ * Independent Gaussian Uncertainty".
+ *
+ * Conventions shared by every call
+ * --------------------------------
+ *  - Grids are uniform with spacing dx, dy (Section 3).  A field is stored as
+ *    row-major [ny][nx] planes with x (index i) fastest; U is the x component
+ *    and V the y component of the vector field.  Cell (i, j), 0 <= i < nx-1,
+ *    0 <= j < ny-1, has corners (i,j), (i+1,j), (i,j+1), (i+1,j+1).
+ *  - LCP outputs are float32 planes [n_iso][ny-1][nx-1], one per isovalue,
+ *    densely packed.
+ *  - Pointers without a _host suffix are DEVICE pointers (hipMalloc'd or
+ *    torch CUDA tensors) owned by the caller.  The core calls allocate
+ *    nothing and keep no state between calls.
+ *  - `stream` is a hipStream_t (NULL = the null stream).  Every call is
+ *    asynchronous on that stream: it validates its arguments, enqueues
+ *    kernels and returns.  Host arrays (isovalues_host) are copied into
+ *    kernel arguments before the call returns and may be reused at once.
+ *  - Errors: every size and pointer argument is checked synchronously before
+ *    anything is enqueued; a bad argument returns PDIV_ERR_INVALID and leaves
+ *    the outputs untouched, with a message in pdiv_last_error().  A failed
+ *    launch returns PDIV_ERR_DEVICE.  Faults inside kernels surface at the
+ *    caller's next synchronisation, as with any HIP kernel.  Value
+ *    preconditions (variances >= 0 and finite) are the caller's: NaN inputs
+ *    give NaN outputs.  No C++ exception crosses this ABI.
+ *  - The core calls are thread-safe.
+ */
+#ifndef PDIV_H_
+#define PDIV_H_
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum pdiv_status {
+  PDIV_OK = 0,
+  PDIV_ERR_INVALID = 1,     /* bad argument; nothing was enqueued            */
+  PDIV_ERR_UNSUPPORTED = 2, /* valid request this build cannot serve         */
+  PDIV_ERR_NOMEM = 3,       /* an owned allocation (batch, server) failed    */
+  PDIV_ERR_DEVICE = 4,      /* HIP runtime or launch error                   */
+  PDIV_ERR_BUSY = 5,        /* server: admission refused (budget or queue)   */
+  PDIV_ERR_TIMEOUT = 6      /* server: wait timed out                        */
+} pdiv_status;
+
+/* Storage type of the moment planes (mean and variance of U and V).  All
+ * arithmetic is float32 whatever the storage type. */
+typedef enum pdiv_dtype { PDIV_F32 = 0, PDIV_F16 = 1, PDIV_BF16 = 2 } pdiv_dtype;
+
+/* Largest isovalue count one call accepts. */
+#define PDIV_MAX_ISO 256
+
+/* A hipStream_t, kept opaque so this header needs no HIP headers. */
+typedef void* pdiv_stream;
+
+/* ------------------------------------------------------------------------
+ * Core calls
+ * ------------------------------------------------------------------------ */
+
+/* (a) Per-point Gaussian fit over ensemble members.
+ *
+ * Section 3 models each vector component at each grid point as an independent
+ * Gaussian N(mu, sigma^2); Section 4 fits it over 15 (wind) and 20 (Red Sea)
+ * ensemble members.  For every point p and component x in {U, V}:
+ *     mean = (1/M) sum_m x_m(p),   var = sum_m (x_m(p) - mean)^2 / (M - ddof).
+ * u_members, v_members: [n_members] planes of ny*nx values of in_dtype, plane
+ *   m starting at element m*member_stride (member_stride = 0 means ny*nx;
+ *   otherwise member_stride >= ny*nx).
+ * ddof: 0 or 1 (1 = unbiased sample variance); n_members > ddof.
+ * mean_u, var_u, mean_v, var_v: outputs, ny*nx values of out_dtype each.
+ * Accumulation is float32 (streaming Welford); out_dtype rounds once at the
+ * store (round to nearest even). */
+pdiv_status pdiv_moments(const void* u_members, const void* v_members, pdiv_dtype in_dtype,
+                         int64_t n_members, int64_t ny, int64_t nx, int64_t member_stride,
+                         int32_t ddof, void* mean_u, void* var_u, void* mean_v, void* var_v,
+                         pdiv_dtype out_dtype, pdiv_stream stream);
+
+/* (b) Divergence Gaussian at every vertex: Eq. 2 (mean) and Eq. 3 (variance)
+ * of Section 3.1, from the finite-difference divergence of Eq. 1.  Interior
+ * vertices use the central difference; at i = 0, i = nx-1, j = 0, j = ny-1 the
+ * difference along that axis is the first-order forward/backward one,
+ * e.g. mean_x = (mu^U(1,j) - mu^U(0,j))/dx, var_x = (var^U(1,j) + var^U(0,j))/dx^2.
+ * Inputs: four [ny][nx] planes of in_dtype; dx, dy finite and > 0.
+ * Outputs: div_mean, div_var, [ny][nx] float32. */
+pdiv_status pdiv_divergence_gaussian(const void* mean_u, const void* var_u, const void* mean_v,
+                                     const void* var_v, pdiv_dtype in_dtype, int64_t ny,
+                                     int64_t nx, double dx, double dy, float* div_mean,
+                                     float* div_var, pdiv_stream stream);
+
+/* (c) Closed-form level-crossing probability (Section 3.1, the
+ * independent-Gaussian LCP of Poethkow et al.): for every cell and isovalue c,
+ *     LCP = 1 - prod_k P(X_k >= c) - prod_k P(X_k < c)
+ * over the cell's four corners X_k ~ N(div_mean, div_var).  A corner with
+ * variance 0 is deterministic and counts as above iff its mean >= c, so zero
+ * variance gives the marching-squares crossing indicator.  Evaluated in
+ * float32 with one Gaussian tail per corner and isovalue and a cancellation-
+ * free combination, so cells near 0 and near 1 keep their relative accuracy.
+ * div_mean, div_var: [ny][nx] float32; isovalues_host: n_iso floats in host
+ * memory, 1 <= n_iso <= PDIV_MAX_ISO; lcp: [n_iso][ny-1][nx-1] float32. */
+pdiv_status pdiv_lcp(const float* div_mean, const float* div_var, int64_t ny, int64_t nx,
+                     const float* isovalues_host, int32_t n_iso, float* lcp,
+                     pdiv_stream stream);
+
+/* (d) Monte Carlo LCP, the paper's comparison (Sections 3.2 and 4): draw
+ * n_samples samples of the uncertain vectors at every grid point, take the
+ * divergence of each sample by Eq. 1 (one-sided at the boundary), and count
+ * per cell and isovalue the samples whose four corner divergences are not all
+ * on one side of c (>= counts as above); lcp = count / n_samples.
+ * Sample s at point p = j*nx + i uses Philox4x32-10 keyed by seed (low word,
+ * high word) at counter (p, s/2, 0, 0); output words (w0, w1) feed a
+ * Box-Muller pair giving the U and V normals of even s, (w2, w3) those of odd
+ * s.  U = mean_u + sqrt(var_u) * z, likewise V.
+ * Requires ny*nx < 2^32 and 1 <= n_samples < 2^31.  Other arguments as in
+ * pdiv_divergence_gaussian and pdiv_lcp. */
+pdiv_status pdiv_mc_lcp(const void* mean_u, const void* var_u, const void* mean_v,
+                        const void* var_v, pdiv_dtype in_dtype, int64_t ny, int64_t nx,
+                        double dx, double dy, const float* isovalues_host, int32_t n_iso,
+                        int64_t n_samples, uint64_t seed, float* lcp, pdiv_stream stream);
+
+/* (b)+(c) fused: Eq. 2-3 and the closed-form LCP in one pass over the moment
+ * planes; the divergence Gaussians never leave the chip.  Gives bitwise the
+ * same LCP as pdiv_divergence_gaussian followed by pdiv_lcp. */
+pdiv_status pdiv_lcp_from_moments(const void* mean_u, const void* var_u, const void* mean_v,
+                                  const void* var_v, pdiv_dtype in_dtype, int64_t ny,
+                                  int64_t nx, double dx, double dy,
+                                  const float* isovalues_host, int32_t n_iso, float* lcp,
+                                  pdiv_stream stream);
+
+/* Diagnostic: sample s of the uncertain field exactly as pdiv_mc_lcp draws it
+ * (same generator, counters and transform): u_s, v_s are [ny][nx] float32. */
+pdiv_status pdiv_mc_sample_field(const void* mean_u, const void* var_u, const void* mean_v,
+                                 const void* var_v, pdiv_dtype in_dtype, int64_t ny, int64_t nx,
+                                 int64_t sample, uint64_t seed, float* u_s, float* v_s,
+                                 pdiv_stream stream);
+
+/* ------------------------------------------------------------------------
+ * Batched launch: many independent fields of uneven size, each with its own
+ * isovalues, in ONE persistent kernel (fused Eq. 2-3 + closed-form LCP).
+ * The paper's GPU run is dominated by launch overhead on a small field
+ * (Section 4, Red Sea); a batch amortises one launch over all fields.
+ * ------------------------------------------------------------------------ */
+
+typedef struct pdiv_field {
+  const void* mean_u;      /* [ny][nx] planes of the batch's dtype (device)       */
+  const void* var_u;
+  const void* mean_v;
+  const void* var_v;
+  int64_t ny, nx;          /* >= 2 each                                           */
+  double dx, dy;           /* finite, > 0                                         */
+  const float* isovalues;  /* n_iso float32 isovalues, DEVICE memory, read at each
+                              launch (update them between launches to move a slider) */
+  int32_t n_iso;           /* 1 .. 16                                             */
+  float* lcp;              /* [n_iso][ny-1][nx-1] float32 output (device)         */
+} pdiv_field;
+
+typedef struct pdiv_batch_s* pdiv_batch;
+
+/* Flags for pdiv_batch_create. */
+#define PDIV_BATCH_GRAPH 1u    /* capture the launch in a hipGraph, replay it     */
+#define PDIV_BATCH_AUTOTUNE 2u /* time the candidate tile shapes on this batch and
+                                  keep the fastest (cached per shape class)       */
+
+/* Builds the tile table for fields_host[0..n) (host array, copied), uploads it,
+ * and with PDIV_BATCH_GRAPH captures the launch on `stream`.  The batch owns
+ * its device tables and graph; the fields' buffers stay the caller's and must
+ * outlive the batch.  Returns PDIV_ERR_INVALID on a bad field, PDIV_ERR_NOMEM
+ * if a table allocation fails. */
+pdiv_status pdiv_batch_create(const pdiv_field* fields_host, int32_t n_fields, pdiv_dtype dtype,
+                              uint32_t flags, pdiv_stream stream, pdiv_batch* out);
+/* Enqueues one pass over every field of the batch on `stream`. */
+pdiv_status pdiv_batch_launch(pdiv_batch batch, pdiv_stream stream);
+/* Tile shape chosen for the batch: rows per band and columns per lane. */
+pdiv_status pdiv_batch_info(pdiv_batch batch, int32_t* band_rows, int32_t* lane_cols,
+                            int64_t* n_tiles);
+/* Releases the batch (synchronises its stream first). */
+pdiv_status pdiv_batch_destroy(pdiv_batch batch);
+
+/* ------------------------------------------------------------------------
+ * Server: continuous batching of LCP requests over fields kept resident on
+ * the device.  A worker thread admits requests as HBM budget and stream slots
+ * free up, merges the isovalue-slider requests that are waiting into batched
+ * launches, overlaps them on n_streams streams, and completes tickets from
+ * device events.
+ * ------------------------------------------------------------------------ */
+
+typedef struct pdiv_server_s* pdiv_server;
+
+typedef struct pdiv_server_stats_t {
+  uint64_t done;            /* completed requests                                */
+  uint64_t failed;          /* requests that ended with an error                 */
+  uint64_t launches;        /* kernel launches issued for LCP requests           */
+  double p50_us, p99_us;    /* latency, submission -> result on device           */
+  double p50_new_us, p99_new_us;       /* ... for new-field requests             */
+  double p50_slider_us, p99_slider_us; /* ... for slider requests                */
+  double lcp_cells;         /* LCP values produced                               */
+  size_t resident_bytes;    /* device bytes held now (fields + in-flight scratch) */
+  size_t peak_bytes;        /* high-water mark of resident_bytes                 */
+} pdiv_server_stats_t;
+
+/* hbm_budget: bytes the server may hold on the device (resident divergence
+ * Gaussians, 8 B per point, plus staging of fields being uploaded).
+ * n_streams: 1..8 compute streams. */
+pdiv_status pdiv_server_create(size_t hbm_budget, int32_t n_streams, pdiv_server* out);
+/* New field from host moment planes (pageable or pinned host memory, dtype as
+ * given, [ny][nx] each): uploaded, reduced to its divergence Gaussians
+ * (Eq. 2-3) and kept resident under id.  The host planes are copied before the
+ * call returns.  Returns PDIV_ERR_BUSY if the field can never fit the budget;
+ * otherwise the request waits for room (evicting least recently used fields
+ * that no pending request names). */
+pdiv_status pdiv_server_put_field(pdiv_server srv, uint64_t id, const void* mean_u_host,
+                                  const void* var_u_host, const void* mean_v_host,
+                                  const void* var_v_host, pdiv_dtype dtype, int64_t ny,
+                                  int64_t nx, double dx, double dy, uint64_t* ticket);
+/* Slider request: LCP maps of resident field id at n_iso (1..16) isovalues
+ * (host array, copied) into out, a device buffer of n_iso*(ny-1)*(nx-1) floats
+ * that must stay valid until the ticket completes. */
+pdiv_status pdiv_server_submit_lcp(pdiv_server srv, uint64_t id, const float* isovalues_host,
+                                   int32_t n_iso, float* out, uint64_t* ticket);
+/* Waits up to timeout_us (< 0: forever) for a ticket; *result receives the
+ * request's own status.  Returns PDIV_ERR_TIMEOUT if it is still running. */
+pdiv_status pdiv_server_wait(pdiv_server srv, uint64_t ticket, int64_t timeout_us,
+                             pdiv_status* result);
+pdiv_status pdiv_server_stats(pdiv_server srv, pdiv_server_stats_t* out);
+/* Drains every pending request, then frees all device memory of the server. */
+pdiv_status pdiv_server_destroy(pdiv_server srv);
+
+/* ------------------------------------------------------------------------
+ * Status
+ * ------------------------------------------------------------------------ */
+const char* pdiv_status_string(pdiv_status s);
+/* Message of the last failing call on this thread ("" if none). */
+const char* pdiv_last_error(void);
+/* Library version, e.g. "0.1.0". */
+const char* pdiv_version(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* PDIV_H_ */

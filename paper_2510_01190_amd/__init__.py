@@ -1,0 +1,336 @@
+"""Python binding of libpdiv, the gfx950 probabilistic local-divergence library.
+
+Thin ctypes layer over the C ABI declared in include/pdiv.h: it checks tensor
+shapes, passes device pointers and the current HIP stream, and raises
+PdivError on a non-OK status.  All computation happens in the library's HIP
+kernels; there is no fallback of any kind.  If libpdiv.so has not been built
+(python -m paper_2510_01190_amd.build_lib), every call raises.
+
+Tensors are torch CUDA tensors (ROCm): torch provides device memory and
+streams only.  Planes are row-major [ny][nx] with x fastest; LCP outputs are
+[n_iso][ny-1][nx-1] float32.
+"""
+
+from __future__ import annotations
+
+import ctypes
+import os
+from typing import Sequence
+
+import numpy as np
+
+__all__ = [
+    "PdivError", "lib", "moments", "divergence_gaussian", "lcp", "lcp_from_moments",
+    "mc_lcp", "mc_sample_field", "Batch", "Server", "STATUS", "MAX_ISO",
+]
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libpdiv.so")
+MAX_ISO = 256
+
+STATUS = {0: "PDIV_OK", 1: "PDIV_ERR_INVALID", 2: "PDIV_ERR_UNSUPPORTED", 3: "PDIV_ERR_NOMEM",
+          4: "PDIV_ERR_DEVICE", 5: "PDIV_ERR_BUSY", 6: "PDIV_ERR_TIMEOUT"}
+_DT = {"float32": 0, "float16": 1, "bfloat16": 2}
+
+_c = ctypes
+_p = _c.c_void_p
+_i64 = _c.c_int64
+_i32 = _c.c_int32
+_f64 = _c.c_double
+_u64 = _c.c_uint64
+_fp = _c.POINTER(_c.c_float)
+
+
+class PdivError(RuntimeError):
+    def __init__(self, status: int, message: str):
+        super().__init__(f"{STATUS.get(status, status)}: {message}")
+        self.status = status
+
+
+class _Field(_c.Structure):
+    _fields_ = [("mean_u", _p), ("var_u", _p), ("mean_v", _p), ("var_v", _p),
+                ("ny", _i64), ("nx", _i64), ("dx", _f64), ("dy", _f64),
+                ("isovalues", _p), ("n_iso", _i32), ("lcp", _p)]
+
+
+class ServerStats(_c.Structure):
+    _fields_ = [("done", _u64), ("failed", _u64), ("launches", _u64),
+                ("p50_us", _f64), ("p99_us", _f64), ("p50_new_us", _f64), ("p99_new_us", _f64),
+                ("p50_slider_us", _f64), ("p99_slider_us", _f64), ("lcp_cells", _f64),
+                ("resident_bytes", _c.c_size_t), ("peak_bytes", _c.c_size_t)]
+
+    def as_dict(self):
+        return {k: getattr(self, k) for k, _ in self._fields_}
+
+
+_SIGS = {
+    "pdiv_moments": [_p, _p, _c.c_int, _i64, _i64, _i64, _i64, _i32, _p, _p, _p, _p, _c.c_int, _p],
+    "pdiv_divergence_gaussian": [_p, _p, _p, _p, _c.c_int, _i64, _i64, _f64, _f64, _p, _p, _p],
+    "pdiv_lcp": [_p, _p, _i64, _i64, _fp, _i32, _p, _p],
+    "pdiv_mc_lcp": [_p, _p, _p, _p, _c.c_int, _i64, _i64, _f64, _f64, _fp, _i32, _i64, _u64, _p, _p],
+    "pdiv_lcp_from_moments": [_p, _p, _p, _p, _c.c_int, _i64, _i64, _f64, _f64, _fp, _i32, _p, _p],
+    "pdiv_mc_sample_field": [_p, _p, _p, _p, _c.c_int, _i64, _i64, _i64, _u64, _p, _p, _p],
+    "pdiv_batch_create": [_c.POINTER(_Field), _i32, _c.c_int, _c.c_uint32, _p, _c.POINTER(_p)],
+    "pdiv_batch_launch": [_p, _p],
+    "pdiv_batch_info": [_p, _c.POINTER(_i32), _c.POINTER(_i32), _c.POINTER(_i64)],
+    "pdiv_batch_destroy": [_p],
+    "pdiv_server_create": [_c.c_size_t, _i32, _c.POINTER(_p)],
+    "pdiv_server_put_field": [_p, _u64, _p, _p, _p, _p, _c.c_int, _i64, _i64, _f64, _f64,
+                              _c.POINTER(_u64)],
+    "pdiv_server_submit_lcp": [_p, _u64, _fp, _i32, _p, _c.POINTER(_u64)],
+    "pdiv_server_wait": [_p, _u64, _i64, _c.POINTER(_c.c_int)],
+    "pdiv_server_stats": [_p, _c.POINTER(ServerStats)],
+    "pdiv_server_destroy": [_p],
+}
+EXPORTS = list(_SIGS) + ["pdiv_status_string", "pdiv_last_error", "pdiv_version"]
+
+_lib = None
+
+
+def lib() -> ctypes.CDLL:
+    """The loaded libpdiv.so; raises if it has not been built."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise RuntimeError(
+                f"libpdiv.so not found at {LIB_PATH}; build it with "
+                "`python -m paper_2510_01190_amd.build_lib` (there is no fallback)")
+        L = ctypes.CDLL(LIB_PATH)
+        for name, args in _SIGS.items():
+            f = getattr(L, name)
+            f.argtypes = args
+            f.restype = _c.c_int
+        for name in ("pdiv_status_string",):
+            getattr(L, name).argtypes = [_c.c_int]
+            getattr(L, name).restype = _c.c_char_p
+        for name in ("pdiv_last_error", "pdiv_version"):
+            getattr(L, name).argtypes = []
+            getattr(L, name).restype = _c.c_char_p
+        _lib = L
+    return _lib
+
+
+def _check(status: int):
+    if status != 0:
+        raise PdivError(status, lib().pdiv_last_error().decode())
+
+
+def _torch():
+    import torch
+    return torch
+
+
+def _stream():
+    return _p(_torch().cuda.current_stream().cuda_stream)
+
+
+def _dtype_code(t) -> int:
+    name = str(t.dtype).replace("torch.", "")
+    if name not in _DT:
+        raise TypeError(f"unsupported dtype {t.dtype}; use float32, float16 or bfloat16")
+    return _DT[name]
+
+
+def _dev(t, name, shape=None, dtype=None):
+    if not t.is_cuda:
+        raise ValueError(f"{name} must be a device tensor")
+    if not t.is_contiguous():
+        raise ValueError(f"{name} must be contiguous")
+    if shape is not None and tuple(t.shape) != tuple(shape):
+        raise ValueError(f"{name} has shape {tuple(t.shape)}, expected {tuple(shape)}")
+    if dtype is not None and t.dtype != dtype:
+        raise ValueError(f"{name} has dtype {t.dtype}, expected {dtype}")
+    return _p(t.data_ptr())
+
+
+def _iso_arr(isovalues):
+    iso = np.ascontiguousarray(np.atleast_1d(np.asarray(isovalues, np.float32)))
+    return iso, iso.ctypes.data_as(_fp)
+
+
+def _moment_ptrs(mean_u, var_u, mean_v, var_v):
+    ny, nx = mean_u.shape
+    dt = mean_u.dtype
+    ptrs = [_dev(t, n, (ny, nx), dt) for t, n in
+            ((mean_u, "mean_u"), (var_u, "var_u"), (mean_v, "mean_v"), (var_v, "var_v"))]
+    return ptrs, ny, nx, _dtype_code(mean_u)
+
+
+def moments(u_members, v_members, ddof: int = 1, out_dtype=None):
+    """Per-point mean and variance over members: inputs [M][ny][nx] -> 4 planes [ny][nx]."""
+    torch = _torch()
+    m, ny, nx = u_members.shape
+    od = out_dtype or torch.float32
+    outs = [torch.empty((ny, nx), dtype=od, device=u_members.device) for _ in range(4)]
+    pu = _dev(u_members, "u_members", (m, ny, nx))
+    pv = _dev(v_members, "v_members", (m, ny, nx), u_members.dtype)
+    _check(lib().pdiv_moments(pu, pv, _dtype_code(u_members), m, ny, nx, 0, ddof,
+                              *[_p(o.data_ptr()) for o in outs], _dtype_code(outs[0]), _stream()))
+    return tuple(outs)
+
+
+def divergence_gaussian(mean_u, var_u, mean_v, var_v, dx: float = 1.0, dy: float = 1.0):
+    """Eq. 2-3: (div_mean, div_var) float32 planes."""
+    torch = _torch()
+    ptrs, ny, nx, dt = _moment_ptrs(mean_u, var_u, mean_v, var_v)
+    dm = torch.empty((ny, nx), dtype=torch.float32, device=mean_u.device)
+    dv = torch.empty_like(dm)
+    _check(lib().pdiv_divergence_gaussian(*ptrs, dt, ny, nx, dx, dy, _p(dm.data_ptr()),
+                                          _p(dv.data_ptr()), _stream()))
+    return dm, dv
+
+
+def lcp(div_mean, div_var, isovalues, out=None):
+    """Closed-form LCP [K][ny-1][nx-1] from divergence Gaussians."""
+    torch = _torch()
+    ny, nx = div_mean.shape
+    pm = _dev(div_mean, "div_mean", (ny, nx), torch.float32)
+    pv = _dev(div_var, "div_var", (ny, nx), torch.float32)
+    iso, ip = _iso_arr(isovalues)
+    if out is None:
+        out = torch.empty((iso.size, ny - 1, nx - 1), dtype=torch.float32, device=div_mean.device)
+    po = _dev(out, "out", (iso.size, ny - 1, nx - 1), torch.float32)
+    _check(lib().pdiv_lcp(pm, pv, ny, nx, ip, iso.size, po, _stream()))
+    return out
+
+
+def lcp_from_moments(mean_u, var_u, mean_v, var_v, isovalues, dx: float = 1.0,
+                     dy: float = 1.0, out=None):
+    """Fused Eq. 2-3 + closed-form LCP [K][ny-1][nx-1]."""
+    torch = _torch()
+    ptrs, ny, nx, dt = _moment_ptrs(mean_u, var_u, mean_v, var_v)
+    iso, ip = _iso_arr(isovalues)
+    if out is None:
+        out = torch.empty((iso.size, ny - 1, nx - 1), dtype=torch.float32, device=mean_u.device)
+    po = _dev(out, "out", (iso.size, ny - 1, nx - 1), torch.float32)
+    _check(lib().pdiv_lcp_from_moments(*ptrs, dt, ny, nx, dx, dy, ip, iso.size, po, _stream()))
+    return out
+
+
+def mc_lcp(mean_u, var_u, mean_v, var_v, isovalues, n_samples: int, seed: int,
+           dx: float = 1.0, dy: float = 1.0, out=None):
+    """Vector-level Monte Carlo LCP [K][ny-1][nx-1]."""
+    torch = _torch()
+    ptrs, ny, nx, dt = _moment_ptrs(mean_u, var_u, mean_v, var_v)
+    iso, ip = _iso_arr(isovalues)
+    if out is None:
+        out = torch.empty((iso.size, ny - 1, nx - 1), dtype=torch.float32, device=mean_u.device)
+    po = _dev(out, "out", (iso.size, ny - 1, nx - 1), torch.float32)
+    _check(lib().pdiv_mc_lcp(*ptrs, dt, ny, nx, dx, dy, ip, iso.size, n_samples,
+                             seed & 0xFFFFFFFFFFFFFFFF, po, _stream()))
+    return out
+
+
+def mc_sample_field(mean_u, var_u, mean_v, var_v, sample: int, seed: int):
+    """Sample `sample` of the uncertain field as the MC draws it: (U, V) float32."""
+    torch = _torch()
+    ptrs, ny, nx, dt = _moment_ptrs(mean_u, var_u, mean_v, var_v)
+    us = torch.empty((ny, nx), dtype=torch.float32, device=mean_u.device)
+    vs = torch.empty_like(us)
+    _check(lib().pdiv_mc_sample_field(*ptrs, dt, ny, nx, sample, seed & 0xFFFFFFFFFFFFFFFF,
+                                      _p(us.data_ptr()), _p(vs.data_ptr()), _stream()))
+    return us, vs
+
+
+class Batch:
+    """Many fields of uneven size in one persistent launch (optionally graph-replayed).
+
+    fields: sequence of dicts with mean_u, var_u, mean_v, var_v (device planes of one
+    dtype), isovalues (device float32 tensor, 1..16 values), dx, dy, and optionally
+    lcp (device output [K][ny-1][nx-1]; allocated if absent)."""
+
+    GRAPH = 1
+    AUTOTUNE = 2
+
+    def __init__(self, fields: Sequence[dict], graph: bool = True, autotune: bool = False):
+        torch = _torch()
+        arr = (_Field * len(fields))()
+        self.fields = []
+        dt = None
+        for k, f in enumerate(fields):
+            ptrs, ny, nx, d = _moment_ptrs(f["mean_u"], f["var_u"], f["mean_v"], f["var_v"])
+            dt = d if dt is None else dt
+            if d != dt:
+                raise ValueError("all fields of a batch share one dtype")
+            iso = f["isovalues"]
+            _dev(iso, "isovalues", None, torch.float32)
+            out = f.get("lcp")
+            if out is None:
+                out = torch.empty((iso.numel(), ny - 1, nx - 1), dtype=torch.float32,
+                                  device=f["mean_u"].device)
+            _dev(out, "lcp", (iso.numel(), ny - 1, nx - 1), torch.float32)
+            arr[k] = _Field(ptrs[0], ptrs[1], ptrs[2], ptrs[3], ny, nx,
+                            float(f.get("dx", 1.0)), float(f.get("dy", 1.0)),
+                            _p(iso.data_ptr()), iso.numel(), _p(out.data_ptr()))
+            self.fields.append(dict(f, lcp=out))
+        flags = (self.GRAPH if graph else 0) | (self.AUTOTUNE if autotune else 0)
+        h = _p()
+        _check(lib().pdiv_batch_create(arr, len(fields), dt or 0, flags, _stream(), _c.byref(h)))
+        self._h = h
+
+    def launch(self):
+        _check(lib().pdiv_batch_launch(self._h, _stream()))
+
+    def info(self):
+        a, b, c = _i32(), _i32(), _i64()
+        _check(lib().pdiv_batch_info(self._h, _c.byref(a), _c.byref(b), _c.byref(c)))
+        return dict(band_rows=a.value, lane_cols=b.value, n_tiles=c.value)
+
+    def close(self):
+        if getattr(self, "_h", None):
+            _check(lib().pdiv_batch_destroy(self._h))
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+class Server:
+    """Continuous-batching LCP server over device-resident fields."""
+
+    def __init__(self, hbm_budget: int, n_streams: int = 2):
+        h = _p()
+        _check(lib().pdiv_server_create(hbm_budget, n_streams, _c.byref(h)))
+        self._h = h
+
+    def put_field(self, fid: int, mean_u, var_u, mean_v, var_v, dx=1.0, dy=1.0) -> int:
+        """Host numpy planes (float32/float16) -> ticket."""
+        arrs = [np.ascontiguousarray(a) for a in (mean_u, var_u, mean_v, var_v)]
+        code = {np.dtype(np.float32): 0, np.dtype(np.float16): 1}[arrs[0].dtype]
+        ny, nx = arrs[0].shape
+        t = _u64()
+        _check(lib().pdiv_server_put_field(self._h, fid, *[_p(a.ctypes.data) for a in arrs],
+                                           code, ny, nx, dx, dy, _c.byref(t)))
+        return t.value
+
+    def submit_lcp(self, fid: int, isovalues, out) -> int:
+        iso, ip = _iso_arr(isovalues)
+        t = _u64()
+        _check(lib().pdiv_server_submit_lcp(self._h, fid, ip, iso.size, _p(out.data_ptr()),
+                                            _c.byref(t)))
+        return t.value
+
+    def wait(self, ticket: int, timeout_us: int = -1) -> int:
+        r = _c.c_int()
+        st = lib().pdiv_server_wait(self._h, ticket, timeout_us, _c.byref(r))
+        _check(st)
+        return r.value
+
+    def stats(self) -> dict:
+        s = ServerStats()
+        _check(lib().pdiv_server_stats(self._h, _c.byref(s)))
+        return s.as_dict()
+
+    def close(self):
+        if getattr(self, "_h", None):
+            _check(lib().pdiv_server_destroy(self._h))
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass

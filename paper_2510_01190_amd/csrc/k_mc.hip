@@ -1,0 +1,279 @@
+// Monte Carlo level-crossing probability, the paper's comparison method
+// (Sections 3.2 and 4): sample the uncertain vectors at every grid point,
+// take each sample's divergence by Eq. 1, count per cell how often the
+// isocontour crosses it.
+//
+// A workgroup owns a 32x32 tile of cells.  Per pair of samples it draws U and
+// V at every grid point of the tile and its one-point halo (one Philox4x32-10
+// call per point gives both samples of the pair), writes them to LDS, forms
+// the divergence of both samples at the tile's 33x33 vertices, and tests the
+// 32x32 cells against every isovalue, accumulating integer counts in
+// registers.  Samples are regenerated from their counters, never stored, so
+// neighbouring tiles see identical values at shared points.  This path is
+// bound by integer multiplies and transcendentals, not by memory.
+#include "pdiv_device.hpp"
+#include "pdiv_internal.hpp"
+
+namespace pdiv {
+namespace {
+
+constexpr int TX = 32, TY = 32;            // cells per tile
+constexpr int VX = TX + 1, VY = TY + 1;    // vertices per tile
+constexpr int PX = TX + 3, PY = TY + 3;    // grid points (vertices + halo)
+constexpr int NP = PX * PY;
+constexpr int NV = VX * VY;
+constexpr int kBlock = 256;
+constexpr int PPT = (NP + kBlock - 1) / kBlock;  // points per thread
+constexpr int VPT = (NV + kBlock - 1) / kBlock;  // vertices per thread
+constexpr int CPT = (TX * TY) / kBlock;          // cells per thread
+
+// One sample value U = mu + sigma z, rounded twice (no contraction), as the
+// float32 definition of the draw.
+__device__ __forceinline__ float draw(float mu, float sd, float z) {
+#pragma clang fp contract(off)
+  return mu + sd * z;
+}
+
+// Eq. 1 for one sample from the U neighbours along x and V neighbours along y.
+__device__ __forceinline__ float fd_div(float ul, float ur, float vl, float vr, float cxm,
+                                        float cym) {
+#pragma clang fp contract(off)
+  return (ur - ul) * cxm + (vr - vl) * cym;
+}
+
+template <int KC, typename T>
+__global__ __launch_bounds__(kBlock) void mc_kernel(const T* __restrict__ mu,
+                                                    const T* __restrict__ vu,
+                                                    const T* __restrict__ mv,
+                                                    const T* __restrict__ vv, int ny, int nx,
+                                                    StencilCoef k, IsoChunk iso, int n_store,
+                                                    int n_samples, uint32_t key0, uint32_t key1,
+                                                    float* __restrict__ out, int64_t plane) {
+  __shared__ float sU[2][NP];
+  __shared__ float sV[2][NP];
+  __shared__ float sD[2][NV];
+
+  const int tid = threadIdx.x;
+  const int x0 = blockIdx.x * TX;
+  const int y0 = blockIdx.y * TY;
+
+  float pmu[PPT], psu[PPT], pmv[PPT], psv[PPT];
+  uint32_t pid[PPT];
+  bool pin[PPT];
+#pragma unroll
+  for (int m = 0; m < PPT; ++m) {
+    const int p = tid + m * kBlock;
+    const int gx = x0 - 1 + p % PX;
+    const int gy = y0 - 1 + p / PX;
+    pin[m] = (p < NP) & (gx >= 0) & (gx < nx) & (gy >= 0) & (gy < ny);
+    pmu[m] = psu[m] = pmv[m] = psv[m] = 0.0f;
+    pid[m] = 0;
+    if (pin[m]) {
+      const int64_t o = static_cast<int64_t>(gy) * nx + gx;
+      pid[m] = static_cast<uint32_t>(o);
+      pmu[m] = ld(mu, o);
+      psu[m] = __fsqrt_rn(ld(vu, o));
+      pmv[m] = ld(mv, o);
+      psv[m] = __fsqrt_rn(ld(vv, o));
+    }
+  }
+
+  uint32_t cnt[CPT][KC];
+#pragma unroll
+  for (int m = 0; m < CPT; ++m)
+#pragma unroll
+    for (int q = 0; q < KC; ++q) cnt[m][q] = 0;
+
+  const int n_pairs = (n_samples + 1) >> 1;
+  for (int pr = 0; pr < n_pairs; ++pr) {
+    // 1. draw both samples of the pair at every point of tile + halo
+#pragma unroll
+    for (int m = 0; m < PPT; ++m) {
+      if (pin[m]) {
+        const int p = tid + m * kBlock;
+        U4 c;
+        c.x = pid[m];
+        c.y = static_cast<uint32_t>(pr);
+        c.z = 0u;
+        c.w = 0u;
+        const U4 w = philox4x32_10(c, key0, key1);
+        const F2 z0 = box_muller(w.x, w.y);
+        const F2 z1 = box_muller(w.z, w.w);
+        sU[0][p] = draw(pmu[m], psu[m], z0.x);
+        sV[0][p] = draw(pmv[m], psv[m], z0.y);
+        sU[1][p] = draw(pmu[m], psu[m], z1.x);
+        sV[1][p] = draw(pmv[m], psv[m], z1.y);
+      }
+    }
+    __syncthreads();
+    // 2. divergence of both samples at the tile's vertices (one-sided on the
+    //    grid boundary, exactly as Eq. 1 is read for the closed form)
+#pragma unroll
+    for (int m = 0; m < VPT; ++m) {
+      const int v = tid + m * kBlock;
+      if (v < NV) {
+        const int gx = x0 + v % VX;
+        const int gy = y0 + v / VX;
+        if (gx < nx && gy < ny) {
+          const int xl = gx > 0 ? gx - 1 : 0;
+          const int xr = gx < nx - 1 ? gx + 1 : nx - 1;
+          const int yl = gy > 0 ? gy - 1 : 0;
+          const int yr = gy < ny - 1 ? gy + 1 : ny - 1;
+          const bool bx = (gx == 0) | (gx == nx - 1);
+          const bool by = (gy == 0) | (gy == ny - 1);
+          const float cxm = bx ? k.cxm_bd : k.cxm_in;
+          const float cym = by ? k.cym_bd : k.cym_in;
+          const int py = gy - (y0 - 1), px = gx - (x0 - 1);
+          const int il = py * PX + (xl - (x0 - 1));
+          const int ir = py * PX + (xr - (x0 - 1));
+          const int jl = (yl - (y0 - 1)) * PX + px;
+          const int jr = (yr - (y0 - 1)) * PX + px;
+#pragma unroll
+          for (int s = 0; s < 2; ++s)
+            sD[s][v] = fd_div(sU[s][il], sU[s][ir], sV[s][jl], sV[s][jr], cxm, cym);
+        }
+      }
+    }
+    __syncthreads();
+    // 3. crossing test per cell: not all four corners on one side (>= is above)
+#pragma unroll
+    for (int m = 0; m < CPT; ++m) {
+      const int cidx = tid + m * kBlock;
+      const int cx = cidx % TX, cy = cidx / TX;
+      if (x0 + cx < nx - 1 && y0 + cy < ny - 1) {
+        const int v00 = cy * VX + cx;
+#pragma unroll
+        for (int s = 0; s < 2; ++s) {
+          if (2 * pr + s < n_samples) {
+            const float d0 = sD[s][v00], d1 = sD[s][v00 + 1];
+            const float d2 = sD[s][v00 + VX], d3 = sD[s][v00 + VX + 1];
+            const float lo = fminf(fminf(d0, d1), fminf(d2, d3));
+            const float hi = fmaxf(fmaxf(d0, d1), fmaxf(d2, d3));
+#pragma unroll
+            for (int q = 0; q < KC; ++q)
+              cnt[m][q] += static_cast<uint32_t>((lo < iso.c[q]) & (hi >= iso.c[q]));
+          }
+        }
+      }
+    }
+    __syncthreads();
+  }
+
+  const float fs = static_cast<float>(n_samples);
+#pragma unroll
+  for (int m = 0; m < CPT; ++m) {
+    const int cidx = tid + m * kBlock;
+    const int gx = x0 + cidx % TX, gy = y0 + cidx / TX;
+    if (gx < nx - 1 && gy < ny - 1) {
+      float* o = out + static_cast<int64_t>(gy) * (nx - 1) + gx;
+#pragma unroll
+      for (int q = 0; q < KC; ++q)
+        if (q < n_store) o[q * plane] = static_cast<float>(cnt[m][q]) / fs;
+    }
+  }
+}
+
+template <typename T>
+__global__ __launch_bounds__(kBlock) void mc_sample_kernel(const T* __restrict__ mu,
+                                                           const T* __restrict__ vu,
+                                                           const T* __restrict__ mv,
+                                                           const T* __restrict__ vv,
+                                                           int64_t n, uint32_t pair, int odd,
+                                                           uint32_t key0, uint32_t key1,
+                                                           float* __restrict__ us,
+                                                           float* __restrict__ vs) {
+  const int64_t p = static_cast<int64_t>(blockIdx.x) * kBlock + threadIdx.x;
+  if (p >= n) return;
+  U4 c;
+  c.x = static_cast<uint32_t>(p);
+  c.y = pair;
+  c.z = 0u;
+  c.w = 0u;
+  const U4 w = philox4x32_10(c, key0, key1);
+  const F2 z = odd ? box_muller(w.z, w.w) : box_muller(w.x, w.y);
+  us[p] = draw(ld(mu, p), __fsqrt_rn(ld(vu, p)), z.x);
+  vs[p] = draw(ld(mv, p), __fsqrt_rn(ld(vv, p)), z.y);
+}
+
+template <int KC, typename T>
+hipError_t launch_kc(const void* mu, const void* vu, const void* mv, const void* vv, int ny,
+                     int nx, const StencilCoef& k, const IsoChunk& iso, int kc, int n_samples,
+                     uint64_t seed, float* out, hipStream_t s) {
+  dim3 grid(static_cast<unsigned>((nx - 1 + TX - 1) / TX),
+            static_cast<unsigned>((ny - 1 + TY - 1) / TY));
+  const int64_t plane = static_cast<int64_t>(ny - 1) * (nx - 1);
+  hipLaunchKernelGGL((mc_kernel<KC, T>), grid, dim3(kBlock), 0, s,
+                     static_cast<const T*>(mu), static_cast<const T*>(vu),
+                     static_cast<const T*>(mv), static_cast<const T*>(vv), ny, nx, k, iso, kc,
+                     n_samples, static_cast<uint32_t>(seed), static_cast<uint32_t>(seed >> 32),
+                     out, plane);
+  return hipGetLastError();
+}
+
+template <typename T>
+hipError_t launch_typed(const void* mu, const void* vu, const void* mv, const void* vv, int ny,
+                        int nx, const StencilCoef& k, const IsoChunk& iso, int kc,
+                        int n_samples, uint64_t seed, float* out, hipStream_t s) {
+  // isovalue counts are bucketed to 1, 2, 4, 8, 16; the caller pads the
+  // unused isovalue slots and only the first kc planes are stored
+  const int kb = kc <= 1 ? 1 : kc <= 2 ? 2 : kc <= 4 ? 4 : kc <= 8 ? 8 : 16;
+  switch (kb) {
+    case 1: return launch_kc<1, T>(mu, vu, mv, vv, ny, nx, k, iso, kc, n_samples, seed, out, s);
+    case 2: return launch_kc<2, T>(mu, vu, mv, vv, ny, nx, k, iso, kc, n_samples, seed, out, s);
+    case 4: return launch_kc<4, T>(mu, vu, mv, vv, ny, nx, k, iso, kc, n_samples, seed, out, s);
+    case 8: return launch_kc<8, T>(mu, vu, mv, vv, ny, nx, k, iso, kc, n_samples, seed, out, s);
+    case 16: return launch_kc<16, T>(mu, vu, mv, vv, ny, nx, k, iso, kc, n_samples, seed, out, s);
+  }
+  return hipErrorInvalidValue;
+}
+
+}  // namespace
+
+hipError_t launch_mc(const void* mu, const void* vu, const void* mv, const void* vv,
+                     pdiv_dtype dt, int64_t ny, int64_t nx, const StencilCoef& k,
+                     const IsoChunk& iso, int kc, int64_t n_samples, uint64_t seed,
+                     float* lcp_k0, hipStream_t s) {
+  const int iny = static_cast<int>(ny), inx = static_cast<int>(nx);
+  const int ns = static_cast<int>(n_samples);
+  switch (dt) {
+    case PDIV_F32: return launch_typed<float>(mu, vu, mv, vv, iny, inx, k, iso, kc, ns, seed, lcp_k0, s);
+    case PDIV_F16: return launch_typed<__half>(mu, vu, mv, vv, iny, inx, k, iso, kc, ns, seed, lcp_k0, s);
+    case PDIV_BF16: return launch_typed<bf16_t>(mu, vu, mv, vv, iny, inx, k, iso, kc, ns, seed, lcp_k0, s);
+  }
+  return hipErrorInvalidValue;
+}
+
+hipError_t launch_mc_sample(const void* mu, const void* vu, const void* mv, const void* vv,
+                            pdiv_dtype dt, int64_t ny, int64_t nx, int64_t sample,
+                            uint64_t seed, float* us, float* vs, hipStream_t s) {
+  const int64_t n = ny * nx;
+  dim3 grid(static_cast<unsigned>((n + kBlock - 1) / kBlock));
+  const uint32_t pair = static_cast<uint32_t>(sample >> 1);
+  const int odd = static_cast<int>(sample & 1);
+  const uint32_t k0 = static_cast<uint32_t>(seed), k1 = static_cast<uint32_t>(seed >> 32);
+  switch (dt) {
+    case PDIV_F32:
+      hipLaunchKernelGGL(mc_sample_kernel<float>, grid, dim3(kBlock), 0, s,
+                         static_cast<const float*>(mu), static_cast<const float*>(vu),
+                         static_cast<const float*>(mv), static_cast<const float*>(vv), n, pair,
+                         odd, k0, k1, us, vs);
+      break;
+    case PDIV_F16:
+      hipLaunchKernelGGL(mc_sample_kernel<__half>, grid, dim3(kBlock), 0, s,
+                         static_cast<const __half*>(mu), static_cast<const __half*>(vu),
+                         static_cast<const __half*>(mv), static_cast<const __half*>(vv), n,
+                         pair, odd, k0, k1, us, vs);
+      break;
+    case PDIV_BF16:
+      hipLaunchKernelGGL(mc_sample_kernel<bf16_t>, grid, dim3(kBlock), 0, s,
+                         static_cast<const bf16_t*>(mu), static_cast<const bf16_t*>(vu),
+                         static_cast<const bf16_t*>(mv), static_cast<const bf16_t*>(vv), n,
+                         pair, odd, k0, k1, us, vs);
+      break;
+    default:
+      return hipErrorInvalidValue;
+  }
+  return hipGetLastError();
+}
+
+}  // namespace pdiv

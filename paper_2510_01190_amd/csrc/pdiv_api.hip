@@ -1,0 +1,256 @@
+// C ABI of libpdiv: argument validation, dtype dispatch and launch of the
+// core calls.  Every check runs before any HIP call, so a rejected call
+// touches neither the device nor the outputs.
+#include <cmath>
+#include <cstdarg>
+#include <cstdio>
+#include <cstring>
+#include <string>
+
+#include "pdiv_internal.hpp"
+
+namespace pdiv {
+
+thread_local std::string g_last_error;
+
+void set_error(const char* fmt, ...) {
+  char buf[512];
+  va_list ap;
+  va_start(ap, fmt);
+  std::vsnprintf(buf, sizeof buf, fmt, ap);
+  va_end(ap);
+  g_last_error = buf;
+}
+
+pdiv_status invalid(const char* fmt, ...) {
+  char buf[512];
+  va_list ap;
+  va_start(ap, fmt);
+  std::vsnprintf(buf, sizeof buf, fmt, ap);
+  va_end(ap);
+  g_last_error = buf;
+  return PDIV_ERR_INVALID;
+}
+
+pdiv_status device_status(hipError_t e, const char* what) {
+  if (e == hipSuccess) return PDIV_OK;
+  set_error("%s: %s", what, hipGetErrorString(e));
+  return PDIV_ERR_DEVICE;
+}
+
+// Grid limits of the kernels' launch geometry: nx <= 2^30, ny <= 2^21.
+constexpr int64_t kMaxNx = int64_t(1) << 30;
+constexpr int64_t kMaxNy = int64_t(1) << 21;
+
+pdiv_status check_grid(int64_t ny, int64_t nx) {
+  if (ny < 2 || nx < 2) return invalid("grid must be at least 2x2 (got ny=%lld nx=%lld)",
+                                       (long long)ny, (long long)nx);
+  if (nx > kMaxNx || ny > kMaxNy)
+    return invalid("grid too large (ny=%lld > 2^21 or nx=%lld > 2^30)", (long long)ny,
+                   (long long)nx);
+  return PDIV_OK;
+}
+
+pdiv_status check_spacing(double dx, double dy) {
+  if (!(std::isfinite(dx) && dx > 0.0) || !(std::isfinite(dy) && dy > 0.0))
+    return invalid("dx and dy must be finite and > 0 (got %g, %g)", dx, dy);
+  return PDIV_OK;
+}
+
+pdiv_status check_dtype(pdiv_dtype d, const char* name) {
+  if (d != PDIV_F32 && d != PDIV_F16 && d != PDIV_BF16)
+    return invalid("%s: unknown dtype %d", name, (int)d);
+  return PDIV_OK;
+}
+
+pdiv_status check_iso(const float* iso, int32_t n) {
+  if (iso == nullptr) return invalid("isovalues_host is NULL");
+  if (n < 1 || n > PDIV_MAX_ISO) return invalid("n_iso must be in [1, %d] (got %d)", PDIV_MAX_ISO, n);
+  return PDIV_OK;
+}
+
+#define PDIV_TRY(expr)                \
+  do {                                \
+    pdiv_status st_ = (expr);         \
+    if (st_ != PDIV_OK) return st_;   \
+  } while (0)
+
+#define PDIV_NONNULL(p) \
+  do {                  \
+    if ((p) == nullptr) return invalid("%s is NULL", #p); \
+  } while (0)
+
+pdiv_status lcp_chunks(bool fused, const void* p0, const void* p1, const void* p2,
+                       const void* p3, pdiv_dtype dt, int64_t ny, int64_t nx, double dx,
+                       double dy, const float* iso_host, int32_t n_iso, float* lcp,
+                       hipStream_t s) {
+  const StencilCoef k = make_coef(dx, dy);
+  const int64_t plane = (ny - 1) * (nx - 1);
+  const LcpShape shape = default_lcp_shape(ny, nx, n_iso);
+  for (int32_t k0 = 0; k0 < n_iso; k0 += kIsoChunk) {
+    const int kc = (n_iso - k0) < kIsoChunk ? (n_iso - k0) : kIsoChunk;
+    IsoChunk c;
+    for (int q = 0; q < kIsoChunk; ++q) c.c[q] = iso_host[k0 + (q < kc ? q : kc - 1)];
+    hipError_t e = launch_lcp(fused, p0, p1, p2, p3, dt, ny, nx, k, c, kc, lcp + k0 * plane,
+                              shape, s);
+    if (e != hipSuccess) return device_status(e, "LCP launch");
+  }
+  return PDIV_OK;
+}
+
+}  // namespace pdiv
+
+using namespace pdiv;
+
+extern "C" {
+
+const char* pdiv_version(void) { return "0.1.0"; }
+
+const char* pdiv_last_error(void) { return g_last_error.c_str(); }
+
+const char* pdiv_status_string(pdiv_status s) {
+  switch (s) {
+    case PDIV_OK: return "ok";
+    case PDIV_ERR_INVALID: return "invalid argument";
+    case PDIV_ERR_UNSUPPORTED: return "unsupported";
+    case PDIV_ERR_NOMEM: return "out of memory";
+    case PDIV_ERR_DEVICE: return "device error";
+    case PDIV_ERR_BUSY: return "busy";
+    case PDIV_ERR_TIMEOUT: return "timeout";
+  }
+  return "unknown status";
+}
+
+pdiv_status pdiv_moments(const void* u_members, const void* v_members, pdiv_dtype in_dtype,
+                         int64_t n_members, int64_t ny, int64_t nx, int64_t member_stride,
+                         int32_t ddof, void* mean_u, void* var_u, void* mean_v, void* var_v,
+                         pdiv_dtype out_dtype, pdiv_stream stream) {
+  g_last_error.clear();
+  PDIV_NONNULL(u_members);
+  PDIV_NONNULL(v_members);
+  PDIV_NONNULL(mean_u);
+  PDIV_NONNULL(var_u);
+  PDIV_NONNULL(mean_v);
+  PDIV_NONNULL(var_v);
+  PDIV_TRY(check_dtype(in_dtype, "in_dtype"));
+  PDIV_TRY(check_dtype(out_dtype, "out_dtype"));
+  if (ny < 1 || nx < 1 || ny > kMaxNy || nx > kMaxNx)
+    return invalid("bad grid ny=%lld nx=%lld", (long long)ny, (long long)nx);
+  if (ddof != 0 && ddof != 1) return invalid("ddof must be 0 or 1 (got %d)", ddof);
+  if (n_members <= ddof || n_members > (int64_t(1) << 30))
+    return invalid("n_members must be in (ddof, 2^30] (got %lld)", (long long)n_members);
+  const int64_t n = ny * nx;
+  if (member_stride == 0) member_stride = n;
+  if (member_stride < n)
+    return invalid("member_stride %lld < ny*nx %lld", (long long)member_stride, (long long)n);
+  return device_status(launch_moments(u_members, v_members, in_dtype, n_members, n,
+                                      member_stride, ddof, mean_u, var_u, mean_v, var_v,
+                                      out_dtype, static_cast<hipStream_t>(stream)),
+                       "moments launch");
+}
+
+pdiv_status pdiv_divergence_gaussian(const void* mean_u, const void* var_u, const void* mean_v,
+                                     const void* var_v, pdiv_dtype in_dtype, int64_t ny,
+                                     int64_t nx, double dx, double dy, float* div_mean,
+                                     float* div_var, pdiv_stream stream) {
+  g_last_error.clear();
+  PDIV_NONNULL(mean_u);
+  PDIV_NONNULL(var_u);
+  PDIV_NONNULL(mean_v);
+  PDIV_NONNULL(var_v);
+  PDIV_NONNULL(div_mean);
+  PDIV_NONNULL(div_var);
+  PDIV_TRY(check_dtype(in_dtype, "in_dtype"));
+  PDIV_TRY(check_grid(ny, nx));
+  PDIV_TRY(check_spacing(dx, dy));
+  return device_status(launch_divergence(mean_u, var_u, mean_v, var_v, in_dtype, ny, nx,
+                                         make_coef(dx, dy), div_mean, div_var,
+                                         static_cast<hipStream_t>(stream)),
+                       "divergence launch");
+}
+
+pdiv_status pdiv_lcp(const float* div_mean, const float* div_var, int64_t ny, int64_t nx,
+                     const float* isovalues_host, int32_t n_iso, float* lcp,
+                     pdiv_stream stream) {
+  g_last_error.clear();
+  PDIV_NONNULL(div_mean);
+  PDIV_NONNULL(div_var);
+  PDIV_NONNULL(lcp);
+  PDIV_TRY(check_grid(ny, nx));
+  PDIV_TRY(check_iso(isovalues_host, n_iso));
+  return lcp_chunks(false, div_mean, div_var, nullptr, nullptr, PDIV_F32, ny, nx, 1.0, 1.0,
+                    isovalues_host, n_iso, lcp, static_cast<hipStream_t>(stream));
+}
+
+pdiv_status pdiv_lcp_from_moments(const void* mean_u, const void* var_u, const void* mean_v,
+                                  const void* var_v, pdiv_dtype in_dtype, int64_t ny,
+                                  int64_t nx, double dx, double dy,
+                                  const float* isovalues_host, int32_t n_iso, float* lcp,
+                                  pdiv_stream stream) {
+  g_last_error.clear();
+  PDIV_NONNULL(mean_u);
+  PDIV_NONNULL(var_u);
+  PDIV_NONNULL(mean_v);
+  PDIV_NONNULL(var_v);
+  PDIV_NONNULL(lcp);
+  PDIV_TRY(check_dtype(in_dtype, "in_dtype"));
+  PDIV_TRY(check_grid(ny, nx));
+  PDIV_TRY(check_spacing(dx, dy));
+  PDIV_TRY(check_iso(isovalues_host, n_iso));
+  return lcp_chunks(true, mean_u, var_u, mean_v, var_v, in_dtype, ny, nx, dx, dy,
+                    isovalues_host, n_iso, lcp, static_cast<hipStream_t>(stream));
+}
+
+pdiv_status pdiv_mc_lcp(const void* mean_u, const void* var_u, const void* mean_v,
+                        const void* var_v, pdiv_dtype in_dtype, int64_t ny, int64_t nx,
+                        double dx, double dy, const float* isovalues_host, int32_t n_iso,
+                        int64_t n_samples, uint64_t seed, float* lcp, pdiv_stream stream) {
+  g_last_error.clear();
+  PDIV_NONNULL(mean_u);
+  PDIV_NONNULL(var_u);
+  PDIV_NONNULL(mean_v);
+  PDIV_NONNULL(var_v);
+  PDIV_NONNULL(lcp);
+  PDIV_TRY(check_dtype(in_dtype, "in_dtype"));
+  PDIV_TRY(check_grid(ny, nx));
+  PDIV_TRY(check_spacing(dx, dy));
+  PDIV_TRY(check_iso(isovalues_host, n_iso));
+  if (ny * nx >= (int64_t(1) << 32))
+    return invalid("Monte Carlo needs ny*nx < 2^32 (point index is a 32-bit counter word)");
+  if (n_samples < 1 || n_samples >= (int64_t(1) << 31))
+    return invalid("n_samples must be in [1, 2^31) (got %lld)", (long long)n_samples);
+  const StencilCoef k = make_coef(dx, dy);
+  const int64_t plane = (ny - 1) * (nx - 1);
+  for (int32_t k0 = 0; k0 < n_iso; k0 += kIsoChunk) {
+    const int kc = (n_iso - k0) < kIsoChunk ? (n_iso - k0) : kIsoChunk;
+    IsoChunk c;
+    for (int q = 0; q < kIsoChunk; ++q) c.c[q] = isovalues_host[k0 + (q < kc ? q : kc - 1)];
+    hipError_t e = launch_mc(mean_u, var_u, mean_v, var_v, in_dtype, ny, nx, k, c, kc,
+                             n_samples, seed, lcp + k0 * plane,
+                             static_cast<hipStream_t>(stream));
+    if (e != hipSuccess) return device_status(e, "Monte Carlo launch");
+  }
+  return PDIV_OK;
+}
+
+pdiv_status pdiv_mc_sample_field(const void* mean_u, const void* var_u, const void* mean_v,
+                                 const void* var_v, pdiv_dtype in_dtype, int64_t ny, int64_t nx,
+                                 int64_t sample, uint64_t seed, float* u_s, float* v_s,
+                                 pdiv_stream stream) {
+  g_last_error.clear();
+  PDIV_NONNULL(mean_u);
+  PDIV_NONNULL(var_u);
+  PDIV_NONNULL(mean_v);
+  PDIV_NONNULL(var_v);
+  PDIV_NONNULL(u_s);
+  PDIV_NONNULL(v_s);
+  PDIV_TRY(check_dtype(in_dtype, "in_dtype"));
+  PDIV_TRY(check_grid(ny, nx));
+  if (ny * nx >= (int64_t(1) << 32)) return invalid("ny*nx must be < 2^32");
+  if (sample < 0 || sample >= (int64_t(1) << 31)) return invalid("sample out of range");
+  return device_status(launch_mc_sample(mean_u, var_u, mean_v, var_v, in_dtype, ny, nx, sample,
+                                        seed, u_s, v_s, static_cast<hipStream_t>(stream)),
+                       "sample launch");
+}
+
+}  // extern "C"

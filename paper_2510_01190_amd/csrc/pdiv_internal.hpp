@@ -1,0 +1,57 @@
+// Host-side interface between the C ABI (pdiv_api.hip) and the kernel files.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "../../include/pdiv.h"
+
+namespace pdiv {
+
+// Isovalues of one launch, passed by value in the kernel arguments so that
+// every wave reads them from scalar registers.
+constexpr int kIsoChunk = 16;
+struct IsoChunk {
+  float c[kIsoChunk];
+};
+
+// Finite-difference coefficients of Eq. 1-3 in float32: m = 1/(2h) inside,
+// 1/h on the boundary; v = m^2.
+struct StencilCoef {
+  float cxm_in, cxv_in, cxm_bd, cxv_bd;
+  float cym_in, cyv_in, cym_bd, cyv_bd;
+};
+StencilCoef make_coef(double dx, double dy);
+
+// Tile shape of the column-walking LCP kernels: one wave covers 64 vertex
+// columns (63 cells) of a band of `band_rows` cell rows.
+struct LcpShape {
+  int band_rows;
+};
+LcpShape default_lcp_shape(int64_t ny, int64_t nx, int n_iso);
+
+hipError_t launch_moments(const void* u, const void* v, pdiv_dtype in_dtype, int64_t m,
+                          int64_t n_points, int64_t stride, int ddof, void* mu, void* vu,
+                          void* mv, void* vv, pdiv_dtype out_dtype, hipStream_t s);
+
+hipError_t launch_divergence(const void* mu, const void* vu, const void* mv, const void* vv,
+                             pdiv_dtype dt, int64_t ny, int64_t nx, const StencilCoef& k,
+                             float* dmean, float* dvar, hipStream_t s);
+
+// LCP for isovalues [k0, k0+kc) (kc <= 16): from divergence Gaussians
+// (fused = false, planes dmean/dvar as float) or from moments (fused = true).
+hipError_t launch_lcp(bool fused, const void* p0, const void* p1, const void* p2,
+                      const void* p3, pdiv_dtype dt, int64_t ny, int64_t nx,
+                      const StencilCoef& k, const IsoChunk& iso, int kc, float* lcp_k0,
+                      LcpShape shape, hipStream_t s);
+
+hipError_t launch_mc(const void* mu, const void* vu, const void* mv, const void* vv,
+                     pdiv_dtype dt, int64_t ny, int64_t nx, const StencilCoef& k,
+                     const IsoChunk& iso, int kc, int64_t n_samples, uint64_t seed,
+                     float* lcp_k0, hipStream_t s);
+
+hipError_t launch_mc_sample(const void* mu, const void* vu, const void* mv, const void* vv,
+                            pdiv_dtype dt, int64_t ny, int64_t nx, int64_t sample,
+                            uint64_t seed, float* us, float* vs, hipStream_t s);
+
+}  // namespace pdiv

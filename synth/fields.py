@@ -144,13 +144,13 @@ def gen_moments(ny: int, nx: int, seed: int, n_features: int | None = None,
 
 
 def gen_ensemble(ny: int, nx: int, n_members: int, seed: int, n_features: int = 40,
-                 std=(0.1, 1.5), dtype=np.float32):
+                 std=(0.1, 1.5), dtype=np.float32, width=(5.0, 20.0)):
     """Ensemble members u_m = u_base + su * eps_m, v_m = v_base + sv * eps'_m,
     eps i.i.d. N(0,1), m = 1..M; spread maps su, sv vary smoothly in [std].
     Returns dict with u_members, v_members of shape [M][ny][nx] in dtype, the
     base field, the spread maps and the features."""
     rng = np.random.default_rng(seed)
-    feats = gen_features(rng, ny, nx, n_features)
+    feats = gen_features(rng, ny, nx, n_features, width=width)
     ub, vb = mean_field(feats, ny, nx)
     su = smooth_std_map(np.random.default_rng(seed + 1000), ny, nx, std[0], std[1])
     sv = smooth_std_map(np.random.default_rng(seed + 2000), ny, nx, std[0], std[1])
@@ -178,9 +178,10 @@ def config_c1():
 
 
 def config_c2(n_members: int = 50):
-    """721x1440 ensemble of 50 FP32 members, 40 features, spread in [0.1,1.5];
-    8 isovalues at divergence quantiles 1/9..8/9; MC 1000 samples."""
-    e = gen_ensemble(721, 1440, n_members, SEED_BASE + 2, n_features=40)
+    """721x1440 ensemble of 50 FP32 members, 40 features of width U[20,100] grid
+    units (wide enough to cover the domain), spread in [0.1,1.5]; 8 isovalues
+    at divergence quantiles 1/9..8/9; MC 1000 samples."""
+    e = gen_ensemble(721, 1440, n_members, SEED_BASE + 2, n_features=40, width=(20.0, 100.0))
     div = analytic_divergence(e["features"], 721, 1440)
     e.update(isovalues=quantile_isovalues(div, np.arange(1, 9) / 9.0), n_samples=1000,
              name="c2_721x1440_m50_k8")

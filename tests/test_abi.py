@@ -1,0 +1,129 @@
+"""C-ABI checks that need no GPU: the library loads, exports every symbol that
+include/pdiv.h declares, and rejects bad arguments synchronously (before any
+device work) with PDIV_ERR_INVALID and a message."""
+
+import ctypes
+import os
+import re
+
+import numpy as np
+import pytest
+
+import paper_2510_01190_amd as P
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADER = os.path.join(ROOT, "include", "pdiv.h")
+INVALID = 1
+
+pytestmark = pytest.mark.skipif(not os.path.exists(P.LIB_PATH), reason="libpdiv.so not built")
+
+
+def _declared():
+    text = open(HEADER).read()
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    return sorted(set(re.findall(r"\b(pdiv_[a-z0-9_]+)\s*\(", text)))
+
+
+def test_header_declares_the_core_calls():
+    names = _declared()
+    for core in ("pdiv_moments", "pdiv_divergence_gaussian", "pdiv_lcp", "pdiv_mc_lcp"):
+        assert core in names
+
+
+def test_every_declared_symbol_is_exported():
+    L = P.lib()
+    for name in _declared():
+        assert hasattr(L, name), name
+    assert set(_declared()) == set(P.EXPORTS)
+
+
+def test_version_and_status_strings():
+    L = P.lib()
+    assert L.pdiv_version().decode().count(".") == 2
+    assert L.pdiv_status_string(0) == b"ok"
+    assert L.pdiv_status_string(1) == b"invalid argument"
+
+
+FAKE = ctypes.c_void_p(0x1000)  # never dereferenced: validation fails first
+NUL = ctypes.c_void_p(0)
+
+
+def _iso(vals):
+    a = np.asarray(vals, np.float32)
+    return a, a.ctypes.data_as(ctypes.POINTER(ctypes.c_float))
+
+
+def _expect_invalid(status, fragment):
+    assert status == INVALID
+    assert fragment in P.lib().pdiv_last_error().decode()
+
+
+def test_lcp_rejects_bad_arguments():
+    L = P.lib()
+    keep, ip = _iso([0.1, 0.2])
+    _expect_invalid(L.pdiv_lcp(FAKE, FAKE, 1, 8, ip, 2, FAKE, NUL), "at least 2x2")
+    _expect_invalid(L.pdiv_lcp(FAKE, FAKE, 8, 1, ip, 2, FAKE, NUL), "at least 2x2")
+    _expect_invalid(L.pdiv_lcp(NUL, FAKE, 8, 8, ip, 2, FAKE, NUL), "div_mean is NULL")
+    _expect_invalid(L.pdiv_lcp(FAKE, FAKE, 8, 8, ip, 2, NUL, NUL), "lcp is NULL")
+    _expect_invalid(L.pdiv_lcp(FAKE, FAKE, 8, 8, ip, 0, FAKE, NUL), "n_iso")
+    _expect_invalid(L.pdiv_lcp(FAKE, FAKE, 8, 8, ip, 257, FAKE, NUL), "n_iso")
+    _expect_invalid(L.pdiv_lcp(FAKE, FAKE, 8, 8, None, 2, FAKE, NUL), "isovalues_host")
+    _expect_invalid(L.pdiv_lcp(FAKE, FAKE, 1 << 22, 8, ip, 2, FAKE, NUL), "too large")
+
+
+def test_fused_and_divergence_reject_bad_spacing_and_dtype():
+    L = P.lib()
+    keep, ip = _iso([0.0])
+    for dx, dy in ((0.0, 1.0), (1.0, -2.0), (float("nan"), 1.0), (1.0, float("inf"))):
+        _expect_invalid(L.pdiv_lcp_from_moments(FAKE, FAKE, FAKE, FAKE, 0, 8, 8, dx, dy, ip, 1,
+                                                FAKE, NUL), "dx and dy")
+        _expect_invalid(L.pdiv_divergence_gaussian(FAKE, FAKE, FAKE, FAKE, 0, 8, 8, dx, dy,
+                                                   FAKE, FAKE, NUL), "dx and dy")
+    _expect_invalid(L.pdiv_lcp_from_moments(FAKE, FAKE, FAKE, FAKE, 7, 8, 8, 1.0, 1.0, ip, 1,
+                                            FAKE, NUL), "dtype")
+    _expect_invalid(L.pdiv_divergence_gaussian(FAKE, NUL, FAKE, FAKE, 0, 8, 8, 1.0, 1.0, FAKE,
+                                               FAKE, NUL), "var_u is NULL")
+
+
+def test_moments_rejects_bad_arguments():
+    L = P.lib()
+    _expect_invalid(L.pdiv_moments(FAKE, FAKE, 0, 1, 4, 4, 0, 1, FAKE, FAKE, FAKE, FAKE, 0, NUL),
+                    "n_members")
+    _expect_invalid(L.pdiv_moments(FAKE, FAKE, 0, 5, 4, 4, 0, 2, FAKE, FAKE, FAKE, FAKE, 0, NUL),
+                    "ddof")
+    _expect_invalid(L.pdiv_moments(FAKE, FAKE, 0, 5, 4, 4, 15, 1, FAKE, FAKE, FAKE, FAKE, 0, NUL),
+                    "member_stride")
+    _expect_invalid(L.pdiv_moments(FAKE, FAKE, 0, 5, 4, 4, 0, 1, FAKE, FAKE, NUL, FAKE, 0, NUL),
+                    "mean_v is NULL")
+    _expect_invalid(L.pdiv_moments(FAKE, FAKE, 0, 5, 4, 4, 0, 1, FAKE, FAKE, FAKE, FAKE, 9, NUL),
+                    "out_dtype")
+
+
+def test_mc_rejects_bad_arguments():
+    L = P.lib()
+    keep, ip = _iso([0.0])
+    _expect_invalid(L.pdiv_mc_lcp(FAKE, FAKE, FAKE, FAKE, 0, 8, 8, 1.0, 1.0, ip, 1, 0, 1, FAKE,
+                                  NUL), "n_samples")
+    _expect_invalid(L.pdiv_mc_lcp(FAKE, FAKE, FAKE, FAKE, 0, 8, 8, 1.0, 1.0, ip, 1, 1 << 31, 1,
+                                  FAKE, NUL), "n_samples")
+    _expect_invalid(L.pdiv_mc_lcp(FAKE, FAKE, FAKE, FAKE, 0, 1 << 21, 1 << 11, 1.0, 1.0, ip, 1,
+                                  10, 1, FAKE, NUL), "2^32")
+    _expect_invalid(L.pdiv_mc_sample_field(FAKE, FAKE, FAKE, FAKE, 0, 8, 8, -1, 1, FAKE, FAKE,
+                                           NUL), "sample")
+
+
+def test_error_message_is_per_thread():
+    import threading
+    L = P.lib()
+    keep, ip = _iso([0.0])
+    assert L.pdiv_lcp(FAKE, FAKE, 1, 8, ip, 1, FAKE, NUL) == INVALID
+    seen = {}
+
+    def other():
+        seen["msg"] = L.pdiv_last_error().decode()
+
+    t = threading.Thread(target=other)
+    t.start()
+    t.join()
+    assert seen["msg"] == ""
+    assert "2x2" in L.pdiv_last_error().decode()

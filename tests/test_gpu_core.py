@@ -1,0 +1,234 @@
+"""GPU parity of the closed-form path (moments, Eq. 2-3, LCP, fused) against the
+FP64 oracle, through the C ABI.  Oracle inputs are the values the GPU actually
+received (storage dtype upcast exactly), so these tests measure the kernels'
+float32 arithmetic; the end-to-end storage error is measured at full size in
+test_gpu_fullsize.py."""
+
+import numpy as np
+import pytest
+import torch
+
+import oracle as O
+import paper_2510_01190_amd as P
+import synth
+from gpu_util import U32, dev, err_report, host64, moments_dev, stored64
+
+pytestmark = pytest.mark.gpu
+
+LCP_TOL = 1e-5  # absolute LCP error bar for float32 storage
+
+
+def _field(ny, nx, seed, sigma=(0.05, 0.5)):
+    return synth.gen_moments(ny, nx, seed, sigma=sigma)
+
+
+def _div_tol(mu_u, mu_v, dx, dy):
+    # |err(mean)| <= 4u (|a|+|b|) c_x + 4u (|a'|+|b'|) c_y with c = 1/dx on the boundary
+    return 8.0 * U32 * (np.abs(mu_u).max() / dx + np.abs(mu_v).max() / dy) + 1e-30
+
+
+SHAPES = [(2, 2), (2, 3), (3, 2), (2, 200), (200, 2), (64, 64), (65, 127), (130, 190),
+          (97, 4034), (4100, 70)]
+
+
+@pytest.mark.parametrize("dt", ["f32", "f16", "bf16"])
+@pytest.mark.parametrize("shape", SHAPES)
+def test_divergence_gaussian_parity(shape, dt):
+    ny, nx = shape
+    f = _field(ny, nx, seed=ny * 1000 + nx)
+    dx, dy = 0.75, 1.5
+    ts = moments_dev(f, dt)
+    dm, dv = P.divergence_gaussian(*ts, dx=dx, dy=dy)
+    mu_u, var_u, mu_v, var_v = stored64(ts)
+    rm, rv = O.divergence_gaussian(mu_u, var_u, mu_v, var_v, dx, dy)
+    gm, gv = host64(dm), host64(dv)
+    assert np.max(np.abs(gm - rm)) <= _div_tol(mu_u, mu_v, dx, dy)
+    assert np.max(np.abs(gv - rv) / rv) <= 6.0 * U32
+
+
+@pytest.mark.parametrize("shape", SHAPES)
+@pytest.mark.parametrize("k", [1, 5, 17])
+def test_lcp_parity(shape, k):
+    ny, nx = shape
+    f = _field(ny, nx, seed=7 + ny + nx)
+    ts = moments_dev(f)
+    dm, dv = P.divergence_gaussian(*ts)
+    rng = np.random.default_rng(k)
+    div = synth.analytic_divergence(f["features"], ny, nx)
+    iso = synth.quantile_isovalues(div, rng.uniform(0.02, 0.98, k))
+    L = P.lcp(dm, dv, iso)
+    ref = O.lcp(host64(dm), host64(dv), iso)
+    e = err_report(host64(L), ref)
+    assert e["max_abs"] <= LCP_TOL, e
+    # the fused kernel gives bitwise the same maps
+    Lf = P.lcp_from_moments(*ts, iso)
+    assert torch.equal(L, Lf)
+
+
+@pytest.mark.parametrize("dt", ["f32", "f16", "bf16"])
+def test_fused_parity_all_dtypes(dt):
+    ny, nx = 257, 300
+    f = _field(ny, nx, seed=11, sigma=(0.01, 1.0))
+    ts = moments_dev(f, dt)
+    iso = np.array([-0.2, -0.01, 0.0, 0.003, 0.05, 0.3], np.float32)
+    L = P.lcp_from_moments(*ts, iso, dx=1.0, dy=1.0)
+    rm, rv = O.divergence_gaussian(*stored64(ts), 1.0, 1.0)
+    ref = O.lcp(rm, rv, iso)
+    e = err_report(host64(L), ref)
+    assert e["max_abs"] <= LCP_TOL, e
+
+
+def test_relative_accuracy_near_zero_and_one():
+    """Cells with tiny LCP keep their relative accuracy (cancellation-free
+    combination); cells near 1 are within a few float32 ulps of 1."""
+    ny, nx = 300, 301
+    f = _field(ny, nx, seed=12, sigma=(0.01, 0.3))
+    ts = moments_dev(f)
+    dm, dv = P.divergence_gaussian(*ts)
+    div = synth.analytic_divergence(f["features"], ny, nx)
+    iso = synth.quantile_isovalues(div, [0.01, 0.3, 0.5, 0.7, 0.99])
+    L = host64(P.lcp(dm, dv, iso))
+    ref = O.lcp(host64(dm), host64(dv), iso)
+    small = (ref >= 1e-30) & (ref < 1e-3)
+    assert small.sum() > 1000
+    rel = np.abs(L[small] - ref[small]) / ref[small]
+    assert rel.max() <= 1e-4, rel.max()
+    big = ref > 1 - 1e-3
+    assert big.sum() > 100
+    assert np.max(np.abs(L[big] - ref[big])) <= 4 * U32
+
+
+def test_zero_variance_is_exact_crossing_indicator():
+    ny, nx = 70, 90
+    f = _field(ny, nx, seed=13)
+    ts = moments_dev(f)
+    dm, _ = P.divergence_gaussian(*ts)
+    zero = torch.zeros_like(dm)
+    m = host64(dm)
+    iso = np.array([np.float32(m[5, 5]), np.float32(m[40, 17]), 0.0, 0.01], np.float32)
+    L = P.lcp(dm, zero, iso)
+    ref = O.lcp(m, np.zeros_like(m), iso)
+    assert np.array_equal(host64(L), ref)
+
+
+def test_mixed_deterministic_corners_and_nan():
+    ny, nx = 40, 41
+    f = _field(ny, nx, seed=14)
+    ts = moments_dev(f)
+    dm, dv = P.divergence_gaussian(*ts)
+    dv[::3, ::2] = 0.0  # deterministic corners mixed with random ones
+    dm[20, 20] = float("nan")
+    iso = np.array([0.0, 0.02], np.float32)
+    L = host64(P.lcp(dm, dv, iso))
+    ref = O.lcp(host64(dm), host64(dv), iso)
+    nan_ref = np.isnan(ref)
+    assert np.array_equal(np.isnan(L), nan_ref) and nan_ref.sum() == 2 * 4
+    ok = ~nan_ref
+    assert np.max(np.abs(L[ok] - ref[ok])) <= LCP_TOL
+
+
+def test_far_isovalues_vanish():
+    f = _field(50, 60, seed=15)
+    ts = moments_dev(f)
+    dm, dv = P.divergence_gaussian(*ts)
+    hi = float(dm.max() + 12 * dv.max().sqrt())
+    lo = float(dm.min() - 12 * dv.max().sqrt())
+    L = host64(P.lcp(dm, dv, [hi, lo]))
+    assert L.max() <= 1e-30
+
+
+def test_many_isovalues_chunking():
+    ny, nx = 33, 70
+    f = _field(ny, nx, seed=16)
+    ts = moments_dev(f)
+    iso = np.linspace(-0.3, 0.3, 256).astype(np.float32)
+    L = P.lcp_from_moments(*ts, iso)
+    ref = O.lcp(*O.divergence_gaussian(*stored64(ts), 1.0, 1.0), iso)
+    assert err_report(host64(L), ref)["max_abs"] <= LCP_TOL
+
+
+# --------------------------------------------------------------------------
+# moments
+# --------------------------------------------------------------------------
+
+def _moment_tols(x, m):
+    # Welford in float32: mean error <= ~2 M u max|x|; variance relative <= ~4 M u
+    return 2.0 * m * U32 * np.abs(x).max(), 4.0 * m * U32
+
+
+@pytest.mark.parametrize("m,shape", [(2, (1, 1)), (3, (5, 7)), (15, (68, 68)), (20, (50, 61)),
+                                     (50, (33, 129))])
+@pytest.mark.parametrize("ddof", [0, 1])
+def test_moments_parity(m, shape, ddof):
+    ny, nx = shape
+    e = synth.gen_ensemble(ny, nx, m, seed=m + ny, n_features=2, dtype=np.float32)
+    u = torch.from_numpy(e["u_members"]).cuda()
+    v = torch.from_numpy(e["v_members"]).cuda()
+    got = [host64(t) for t in P.moments(u, v, ddof=ddof)]
+    ref = O.moments(e["u_members"].astype(np.float64), e["v_members"].astype(np.float64), ddof)
+    for g, r, x in ((got[0], ref[0], e["u_members"]), (got[2], ref[2], e["v_members"])):
+        ta, _ = _moment_tols(x, m)
+        assert np.max(np.abs(g - r)) <= ta
+    _, tr = _moment_tols(e["u_members"], m)
+    for g, r in ((got[1], ref[1]), (got[3], ref[3])):
+        assert np.max(np.abs(g - r) / np.maximum(r, 1e-30)) <= tr + 2 * U32
+
+
+@pytest.mark.parametrize("in_dt,out_dt", [("f16", "f32"), ("bf16", "f32"), ("f32", "f16"),
+                                          ("f32", "bf16")])
+def test_moments_dtypes(in_dt, out_dt):
+    from gpu_util import TORCH_DT
+    m, ny, nx = 20, 30, 45
+    e = synth.gen_ensemble(ny, nx, m, seed=3, n_features=2, dtype=np.float32)
+    u = torch.from_numpy(e["u_members"]).to(TORCH_DT[in_dt]).cuda()
+    v = torch.from_numpy(e["v_members"]).to(TORCH_DT[in_dt]).cuda()
+    got = P.moments(u, v, ddof=1, out_dtype=TORCH_DT[out_dt])
+    assert all(t.dtype == TORCH_DT[out_dt] for t in got)
+    ref = O.moments(host64(u), host64(v), 1)
+    # reference rounded to the output dtype exactly as the kernel's store rounds
+    for g, r in zip(got, ref):
+        rr = host64(torch.from_numpy(r).to(torch.float32).to(TORCH_DT[out_dt]))
+        tol = 1e-5 * np.abs(r).max() if out_dt == "f32" else 0.0
+        # one output ulp of disagreement is allowed where float32 rounding sits
+        # next to a 16-bit rounding boundary
+        ulp = np.abs(rr) * (2.0 ** -10 if out_dt == "f16" else 2.0 ** -7)
+        if out_dt == "f16":
+            ulp = np.maximum(ulp, 2.0 ** -24)  # float16 subnormal spacing
+        assert np.all(np.abs(host64(g) - rr) <= np.maximum(tol, ulp) + 1e-30)
+
+
+def test_moments_member_stride_and_ragged_tail():
+    m, ny, nx = 7, 9, 11  # n = 99 points: not a multiple of 4
+    rng = np.random.default_rng(5)
+    buf = rng.normal(1.0, 0.3, (m, 128)).astype(np.float32)  # stride 128 > 99
+    ub = torch.from_numpy(buf).cuda()
+    vb = torch.from_numpy(buf[::-1].copy()).cuda()
+    outs = [torch.empty((ny, nx), device="cuda") for _ in range(4)]
+    L = P.lib()
+    import ctypes
+    st = L.pdiv_moments(ctypes.c_void_p(ub.data_ptr()), ctypes.c_void_p(vb.data_ptr()), 0, m, ny, nx,
+                        128, 1, *[ctypes.c_void_p(o.data_ptr()) for o in outs], 0,
+                        ctypes.c_void_p(torch.cuda.current_stream().cuda_stream))
+    assert st == 0
+    torch.cuda.synchronize()
+    x = buf[:, :99].astype(np.float64).reshape(m, ny, nx)
+    y = buf[::-1][:, :99].astype(np.float64).reshape(m, ny, nx)
+    ref = O.moments(x, y, 1)
+    for g, r in zip(outs, ref):
+        assert np.max(np.abs(host64(g) - r)) <= 1e-6 * max(1.0, np.abs(r).max())
+
+
+def test_pipeline_fit_divergence_lcp():
+    """Ensemble -> moments -> fused LCP against the oracle fed with the members."""
+    m, ny, nx = 20, 100, 140
+    e = synth.gen_ensemble(ny, nx, m, seed=21, n_features=6, dtype=np.float32,
+                           width=(10.0, 40.0))
+    u = torch.from_numpy(e["u_members"]).cuda()
+    v = torch.from_numpy(e["v_members"]).cuda()
+    mom = P.moments(u, v, ddof=1)
+    div = synth.analytic_divergence(e["features"], ny, nx)
+    iso = synth.quantile_isovalues(div, [0.1, 0.5, 0.9])
+    L = host64(P.lcp_from_moments(*mom, iso))
+    ref = O.lcp(*O.divergence_gaussian(*O.moments(e["u_members"], e["v_members"], 1), 1.0, 1.0),
+                iso)
+    assert err_report(L, ref)["max_abs"] <= LCP_TOL

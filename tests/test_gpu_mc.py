@@ -1,0 +1,83 @@
+"""GPU parity of the Monte Carlo comparison path against the oracle.
+
+The random numbers are pinned exactly: both sides implement Philox4x32-10 and
+the same counter layout, so the GPU's sample fields must match the oracle's
+up to the float32 evaluation of the Box-Muller transform.  The crossing
+counts are then compared with the oracle's float32-precision MC (the decision
+is taken in the kernel's precision): they agree except for samples whose
+corner divergence lies within a few float32 ulps of the isovalue."""
+
+import numpy as np
+import pytest
+
+import oracle as O
+import paper_2510_01190_amd as P
+import synth
+from gpu_util import U32, host64, moments_dev, stored64
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.mark.parametrize("dt", ["f32", "bf16"])
+@pytest.mark.parametrize("sample", [0, 1, 2, 777])
+def test_sample_field_matches_oracle(sample, dt):
+    ny, nx = 90, 131
+    f = synth.gen_moments(ny, nx, seed=31)
+    ts = moments_dev(f, dt)
+    seed = 0x1234_5678_9ABC_DEF0
+    us, vs = P.mc_sample_field(*ts, sample=sample, seed=seed)
+    mu_u, var_u, mu_v, var_v = stored64(ts)
+    ru, rv = O.mc_sample_field(mu_u, var_u, mu_v, var_v, sample, seed)
+    for g, r, mu, var in ((host64(us), ru, mu_u, var_u), (host64(vs), rv, mu_v, var_v)):
+        sd = np.sqrt(var)
+        z = (r - mu) / sd
+        tight = 4 * U32 * np.abs(mu) + sd * 1e-5 * (1.0 + np.abs(z))
+        err = np.abs(g - r)
+        assert np.mean(err <= tight) >= 0.9999
+        assert np.all(err <= 4 * U32 * np.abs(mu) + 1e-3 * sd)
+
+
+@pytest.mark.parametrize("shape,k,s", [((37, 45), 3, 301), ((2, 2), 1, 64), ((2, 70), 2, 50),
+                                       ((70, 2), 2, 50), ((66, 130), 17, 40)])
+def test_mc_counts_match_oracle(shape, k, s):
+    ny, nx = shape
+    f = synth.gen_moments(ny, nx, seed=ny + nx, sigma=(0.05, 0.5))
+    ts = moments_dev(f)
+    rng = np.random.default_rng(k)
+    iso = rng.uniform(-0.15, 0.15, k).astype(np.float32)
+    seed = 987654321 + k
+    g = host64(P.mc_lcp(*ts, iso, n_samples=s, seed=seed))
+    r = O.mc_lcp(*stored64(ts), 1.0, 1.0, iso, s, seed, precision="f32")
+    flips = np.abs(np.rint(g * s) - np.rint(r * s))
+    assert flips.sum() <= 5 + 1e-5 * flips.size * s, flips.sum()
+
+
+def test_mc_converges_to_closed_form_on_interior_cells():
+    """Interior cells: exact independence, so the MC estimate is within
+    sampling error of the closed form (3 SE per cell, chi-square aggregate)."""
+    c = synth.config_c1()
+    ts = moments_dev(c)
+    S = c["n_samples"]
+    iso = c["isovalues"]
+    E = host64(P.mc_lcp(*ts, iso, n_samples=S, seed=2025))
+    L = host64(P.lcp_from_moments(*ts, iso))
+    ny, nx = c["ny"], c["nx"]
+    inner = np.zeros((ny - 1, nx - 1), bool)
+    inner[1:ny - 2, 1:nx - 2] = True
+    inner = np.broadcast_to(inner, L.shape)
+    se = np.sqrt(np.maximum(L * (1 - L), 1.0 / S) / S)
+    z = (np.abs(E - L) / se)[inner]
+    assert np.mean(z > 3.0 + 1.0 / (S * se[inner])) <= 0.01
+    assert np.mean(z ** 2) < 1.2
+
+
+def test_mc_zero_variance_is_deterministic():
+    ny, nx = 40, 50
+    f = synth.gen_moments(ny, nx, seed=5)
+    f["var_u"] = np.zeros_like(f["var_u"])
+    f["var_v"] = np.zeros_like(f["var_v"])
+    ts = moments_dev(f)
+    iso = np.array([-0.05, 0.0, 0.05], np.float32)
+    g = host64(P.mc_lcp(*ts, iso, n_samples=10, seed=1))
+    r = O.mc_lcp(*stored64(ts), 1.0, 1.0, iso, 10, 1, precision="f32")
+    assert np.array_equal(g, r)
