@@ -1,14 +1,17 @@
 // Divergence Gaussians (Eq. 2-3) and the closed-form level-crossing
 // probability (Section 3.1), standalone and fused.
 //
-// Column-walking tiles: a wave owns 64 consecutive vertex columns, i.e. the 63
-// cells between them, over a band of cell rows.  Lane L holds vertex column
-// x0 + L and walks down the band one vertex row at a time.  For each isovalue
-// it evaluates the corner tail once per vertex and row, pairs it with the
-// previous row's (vertical pair, kept in registers) and takes the right-hand
-// pair of the cell from lane L+1 by a lane shuffle; lane 63 only feeds lane
-// 62.  Each LCP value is stored once, coalesced across the wave (64
-// consecutive floats of one output row), with a non-temporal store.
+// Column-walking tiles: a wave owns 128 consecutive vertex columns, i.e. the
+// 127 cells between them, over a band of cell rows.  Lane L holds vertex
+// columns x0 + 2L and x0 + 2L + 1 and walks down the band one vertex row at a
+// time.  For each isovalue it evaluates each corner's tail once per row,
+// pairs it with the previous row's (vertical pairs, kept in registers) and
+// forms its two cells: the left one from its own two columns, the right one
+// with the first column of lane L+1, fetched by a lane shuffle.  Lane 63's
+// right cell belongs to the next strip and is not stored.  The kernel is
+// bound by the per-(corner, isovalue) tail and per-(cell, isovalue) combine
+// arithmetic and by the LCP stores, which are written once with
+// non-temporal stores (the maps are not re-read by this kernel).
 #include "pdiv_device.hpp"
 #include "pdiv_internal.hpp"
 
@@ -38,31 +41,34 @@ LcpShape default_lcp_shape(int64_t ny, int64_t nx, int n_iso) {
 namespace {
 
 constexpr int kWave = 64;
-constexpr int kCellsPerWave = kWave - 1;
+constexpr int kColsPerLane = 2;
+constexpr int kCellsPerWave = kWave * kColsPerLane - 1;
 constexpr int kBlock = 256;
 constexpr int kWavesPerBlock = kBlock / kWave;
 
 // Divergence Gaussian of vertex (x, j) from the moment planes, with the
-// one-sided differences of Eq. 1 on the boundary.
+// one-sided differences of Eq. 1 on the boundary.  Row pointers are formed
+// from the row index first so that, when j is uniform across the wave, the
+// address is a scalar base plus a 32-bit per-lane column offset.
 template <typename T>
 __device__ __forceinline__ DivGauss vertex_from_moments(const T* __restrict__ mu,
                                                         const T* __restrict__ vu,
                                                         const T* __restrict__ mv,
                                                         const T* __restrict__ vv, int ny,
-                                                        int nx, int x, int j,
+                                                        int nx, uint32_t x, int j,
                                                         const StencilCoef& k) {
-  const int xl = x > 0 ? x - 1 : 0;
-  const int xr = x < nx - 1 ? x + 1 : nx - 1;
+  const uint32_t xl = x > 0 ? x - 1 : 0;
+  const uint32_t xr = x < uint32_t(nx - 1) ? x + 1 : uint32_t(nx - 1);
   const int yl = j > 0 ? j - 1 : 0;
   const int yr = j < ny - 1 ? j + 1 : ny - 1;
-  const bool bx = (x == 0) | (x == nx - 1);
+  const bool bx = (x == 0) | (x == uint32_t(nx - 1));
   const bool by = (j == 0) | (j == ny - 1);
-  const int64_t row = static_cast<int64_t>(j) * nx;
-  return div_gauss(ld(mu, row + xl), ld(mu, row + xr), ld(vu, row + xl), ld(vu, row + xr),
-                   ld(mv, static_cast<int64_t>(yl) * nx + x),
-                   ld(mv, static_cast<int64_t>(yr) * nx + x),
-                   ld(vv, static_cast<int64_t>(yl) * nx + x),
-                   ld(vv, static_cast<int64_t>(yr) * nx + x), bx ? k.cxm_bd : k.cxm_in,
+  const int64_t r0 = static_cast<int64_t>(j) * nx;
+  const int64_t rl = static_cast<int64_t>(yl) * nx;
+  const int64_t rr = static_cast<int64_t>(yr) * nx;
+  return div_gauss(to_f32(*at(mu + r0, xl)), to_f32(*at(mu + r0, xr)), to_f32(*at(vu + r0, xl)),
+                   to_f32(*at(vu + r0, xr)), to_f32(*at(mv + rl, x)), to_f32(*at(mv + rr, x)),
+                   to_f32(*at(vv + rl, x)), to_f32(*at(vv + rr, x)), bx ? k.cxm_bd : k.cxm_in,
                    bx ? k.cxv_bd : k.cxv_in, by ? k.cym_bd : k.cym_in,
                    by ? k.cyv_bd : k.cyv_in);
 }
@@ -81,7 +87,7 @@ __global__ __launch_bounds__(kBlock) void divergence_kernel(const T* __restrict_
   if (x >= nx) return;
   const int j1 = min(j0 + rows_per_thread, ny);
   for (int j = j0; j < j1; ++j) {
-    DivGauss g = vertex_from_moments(mu, vu, mv, vv, ny, nx, x, j, k);
+    DivGauss g = vertex_from_moments(mu, vu, mv, vv, ny, nx, uint32_t(x), j, k);
     const int64_t o = static_cast<int64_t>(j) * nx + x;
     __builtin_nontemporal_store(g.mean, dmean + o);
     __builtin_nontemporal_store(g.var, dvar + o);
@@ -91,15 +97,15 @@ __global__ __launch_bounds__(kBlock) void divergence_kernel(const T* __restrict_
 template <bool FUSED, typename T>
 __device__ __forceinline__ Corner load_corner(const T* __restrict__ p0, const T* __restrict__ p1,
                                               const T* __restrict__ p2,
-                                              const T* __restrict__ p3, int ny, int nx, int x,
-                                              int j, const StencilCoef& k) {
+                                              const T* __restrict__ p3, int ny, int nx,
+                                              uint32_t x, int j, const StencilCoef& k) {
   if constexpr (FUSED) {
     return make_corner(vertex_from_moments(p0, p1, p2, p3, ny, nx, x, j, k));
   } else {
-    const int64_t o = static_cast<int64_t>(j) * nx + x;
+    const int64_t r0 = static_cast<int64_t>(j) * nx;
     DivGauss g;
-    g.mean = ld(p0, o);
-    g.var = ld(p1, o);
+    g.mean = to_f32(*at(p0 + r0, x));
+    g.var = to_f32(*at(p1 + r0, x));
     return make_corner(g);
   }
 }
@@ -113,6 +119,38 @@ __device__ __forceinline__ Pair pair_from_right(const Pair& p) {
   return r;
 }
 
+// One vertex row step: corners of row j+1 for the lane's two columns, their
+// pairs with row j (prev_*), the lane's two cells for every isovalue; the new
+// corners replace the old ones in next_*.
+template <int KC, bool FUSED, typename T>
+__device__ __forceinline__ void row_step(const T* __restrict__ p0, const T* __restrict__ p1,
+                                         const T* __restrict__ p2, const T* __restrict__ p3,
+                                         int ny, int nx, const StencilCoef& k,
+                                         const IsoChunk& iso, float* __restrict__ out,
+                                         int64_t plane, int j, uint32_t xa_c, uint32_t xb_c,
+                                         uint32_t xa, bool store_a, bool store_b,
+                                         const AB (&prev_a)[KC], const AB (&prev_b)[KC],
+                                         AB (&next_a)[KC], AB (&next_b)[KC]) {
+  const Corner ca = load_corner<FUSED>(p0, p1, p2, p3, ny, nx, xa_c, j + 1, k);
+  const Corner cb = load_corner<FUSED>(p0, p1, p2, p3, ny, nx, xb_c, j + 1, k);
+  float* __restrict__ orow = out + static_cast<int64_t>(j) * (nx - 1);
+#pragma unroll
+  for (int q = 0; q < KC; ++q) {
+    const AB cur_a = corner_probs(ca, iso.c[q]);
+    const AB cur_b = corner_probs(cb, iso.c[q]);
+    const Pair pa = make_pair(prev_a[q], cur_a);
+    const Pair pb = make_pair(prev_b[q], cur_b);
+    const Pair right = pair_from_right(pa);
+    const float l0 = cell_lcp(pa, pb, cur_a.below);
+    const float l1 = cell_lcp(pb, right, cur_b.below);
+    const RowWriter w(orow + q * plane);
+    if (store_a) w.put(l0, xa * 4u);
+    if (store_b) w.put(l1, xa * 4u + 4u);
+    next_a[q] = cur_a;
+    next_b[q] = cur_b;
+  }
+}
+
 template <int KC, bool FUSED, typename T>
 __global__ __launch_bounds__(kBlock) void lcp_kernel(const T* __restrict__ p0,
                                                      const T* __restrict__ p1,
@@ -122,36 +160,41 @@ __global__ __launch_bounds__(kBlock) void lcp_kernel(const T* __restrict__ p0,
                                                      float* __restrict__ out, int64_t plane,
                                                      int band_rows, int n_strips,
                                                      int n_bands) {
-  const int lane = threadIdx.x & 63;
-  const int wave = blockIdx.x * kWavesPerBlock + (threadIdx.x >> 6);
+  const uint32_t lane = threadIdx.x & 63;
+  // the wave index is uniform: row indices and row base pointers stay scalar
+  const int wave = __builtin_amdgcn_readfirstlane(blockIdx.x * kWavesPerBlock +
+                                                  (threadIdx.x >> 6));
   const int strip = wave % n_strips;
   const int band = wave / n_strips;
-  if (band >= n_bands) return;  // uniform per wave
-  const int x = strip * kCellsPerWave + lane;
-  const int xc = x < nx ? x : nx - 1;  // lanes past the edge load a valid column
-  const bool store = (lane < kCellsPerWave) & (x < nx - 1);
-  const int ncx = nx - 1;
+  if (band >= n_bands) return;
+  const uint32_t xa = uint32_t(strip * kCellsPerWave) + kColsPerLane * lane;  // first column
+  const uint32_t xb = xa + 1;                                                 // second column
+  const uint32_t last = uint32_t(nx - 1);
+  const uint32_t xa_c = xa < last ? xa : last;  // columns past the edge load a valid column
+  const uint32_t xb_c = xb < last ? xb : last;
+  const bool store_a = xa < last;
+  const bool store_b = (lane < kWave - 1) & (xb < last);
   const int j0 = band * band_rows;
   const int j1 = min(j0 + band_rows, ny - 1);
 
-  AB prev[KC];
+  AB ra[KC], rb[KC], sa[KC], sb[KC];
   {
-    const Corner c = load_corner<FUSED>(p0, p1, p2, p3, ny, nx, xc, j0, k);
-#pragma unroll
-    for (int q = 0; q < KC; ++q) prev[q] = corner_probs(c, iso.c[q]);
-  }
-  for (int j = j0; j < j1; ++j) {
-    const Corner c = load_corner<FUSED>(p0, p1, p2, p3, ny, nx, xc, j + 1, k);
-    float* orow = out + static_cast<int64_t>(j) * ncx + x;
+    const Corner ca = load_corner<FUSED>(p0, p1, p2, p3, ny, nx, xa_c, j0, k);
+    const Corner cb = load_corner<FUSED>(p0, p1, p2, p3, ny, nx, xb_c, j0, k);
 #pragma unroll
     for (int q = 0; q < KC; ++q) {
-      const AB cur = corner_probs(c, iso.c[q]);
-      const Pair left = make_pair(prev[q], cur);
-      const Pair right = pair_from_right(left);
-      const float l = cell_lcp(left, right);
-      if (store) __builtin_nontemporal_store(l, orow + q * plane);
-      prev[q] = cur;
+      ra[q] = corner_probs(ca, iso.c[q]);
+      rb[q] = corner_probs(cb, iso.c[q]);
     }
+  }
+  // two rows per trip so the carried corners alternate between two register
+  // sets instead of being copied
+  for (int j = j0; j < j1; j += 2) {
+    row_step<KC, FUSED>(p0, p1, p2, p3, ny, nx, k, iso, out, plane, j, xa_c, xb_c, xa,
+                        store_a, store_b, ra, rb, sa, sb);
+    if (j + 1 < j1)
+      row_step<KC, FUSED>(p0, p1, p2, p3, ny, nx, k, iso, out, plane, j + 1, xa_c, xb_c, xa,
+                          store_a, store_b, sa, sb, ra, rb);
   }
 }
 
@@ -176,12 +219,11 @@ hipError_t launch_any(const void* p0, const void* p1, const void* p2, const void
                       int nx, const StencilCoef& k, const IsoChunk& iso, int kc, float* out,
                       LcpShape shape, hipStream_t s) {
   switch (kc) {
-#define PDIV_KC(N) \
-  case N: return launch_kc<N, FUSED, T>(p0, p1, p2, p3, ny, nx, k, iso, out, shape, s);
-    PDIV_KC(1) PDIV_KC(2) PDIV_KC(3) PDIV_KC(4) PDIV_KC(5) PDIV_KC(6) PDIV_KC(7) PDIV_KC(8)
-    PDIV_KC(9) PDIV_KC(10) PDIV_KC(11) PDIV_KC(12) PDIV_KC(13) PDIV_KC(14) PDIV_KC(15)
-    PDIV_KC(16)
-#undef PDIV_KC
+    case 1: return launch_kc<1, FUSED, T>(p0, p1, p2, p3, ny, nx, k, iso, out, shape, s);
+    case 2: return launch_kc<2, FUSED, T>(p0, p1, p2, p3, ny, nx, k, iso, out, shape, s);
+    case 4: return launch_kc<4, FUSED, T>(p0, p1, p2, p3, ny, nx, k, iso, out, shape, s);
+    case 8: return launch_kc<8, FUSED, T>(p0, p1, p2, p3, ny, nx, k, iso, out, shape, s);
+    case 16: return launch_kc<16, FUSED, T>(p0, p1, p2, p3, ny, nx, k, iso, out, shape, s);
   }
   return hipErrorInvalidValue;
 }

@@ -38,15 +38,16 @@ pdiv_status device_status(hipError_t e, const char* what) {
   return PDIV_ERR_DEVICE;
 }
 
-// Grid limits of the kernels' launch geometry: nx <= 2^30, ny <= 2^21.
-constexpr int64_t kMaxNx = int64_t(1) << 30;
+// Grid limits of the kernels' launch geometry: nx <= 2^29 (a row's byte
+// offset fits in 32 bits), ny <= 2^21.
+constexpr int64_t kMaxNx = int64_t(1) << 29;
 constexpr int64_t kMaxNy = int64_t(1) << 21;
 
 pdiv_status check_grid(int64_t ny, int64_t nx) {
   if (ny < 2 || nx < 2) return invalid("grid must be at least 2x2 (got ny=%lld nx=%lld)",
                                        (long long)ny, (long long)nx);
   if (nx > kMaxNx || ny > kMaxNy)
-    return invalid("grid too large (ny=%lld > 2^21 or nx=%lld > 2^30)", (long long)ny,
+    return invalid("grid too large (ny=%lld > 2^21 or nx=%lld > 2^29)", (long long)ny,
                    (long long)nx);
   return PDIV_OK;
 }
@@ -87,13 +88,16 @@ pdiv_status lcp_chunks(bool fused, const void* p0, const void* p1, const void* p
   const StencilCoef k = make_coef(dx, dy);
   const int64_t plane = (ny - 1) * (nx - 1);
   const LcpShape shape = default_lcp_shape(ny, nx, n_iso);
-  for (int32_t k0 = 0; k0 < n_iso; k0 += kIsoChunk) {
-    const int kc = (n_iso - k0) < kIsoChunk ? (n_iso - k0) : kIsoChunk;
+  // chunks of 16, 8, 4, 2, 1 isovalues (the kernel is instantiated for these)
+  for (int32_t k0 = 0; k0 < n_iso;) {
+    const int left = n_iso - k0;
+    const int kc = left >= 16 ? 16 : left >= 8 ? 8 : left >= 4 ? 4 : left >= 2 ? 2 : 1;
     IsoChunk c;
     for (int q = 0; q < kIsoChunk; ++q) c.c[q] = iso_host[k0 + (q < kc ? q : kc - 1)];
     hipError_t e = launch_lcp(fused, p0, p1, p2, p3, dt, ny, nx, k, c, kc, lcp + k0 * plane,
                               shape, s);
     if (e != hipSuccess) return device_status(e, "LCP launch");
+    k0 += kc;
   }
   return PDIV_OK;
 }

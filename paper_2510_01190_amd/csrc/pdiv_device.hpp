@@ -5,6 +5,10 @@
 #include <hip/hip_fp16.h>
 #include <stdint.h>
 
+#include <type_traits>
+
+#include "tail_coeffs.hpp"
+
 namespace pdiv {
 
 // ---------------------------------------------------------------------------
@@ -46,6 +50,32 @@ __device__ __forceinline__ float ld(const T* __restrict__ p, int64_t i) {
   return to_f32(p[i]);
 }
 
+// Element idx of a row that starts at `row`, addressed as row + 32-bit byte
+// offset: with a wave-uniform row pointer this is a scalar base plus a
+// per-lane 32-bit offset, with no 64-bit address arithmetic per lane.
+// Rows are at most 2^29 elements, so the byte offset fits in 32 bits.
+template <typename T>
+__device__ __forceinline__ T* at(T* row, uint32_t idx) {
+  using B = typename std::conditional<std::is_const<T>::value, const char, char>::type;
+  return reinterpret_cast<T*>(reinterpret_cast<B*>(row) + idx * uint32_t(sizeof(T)));
+}
+
+// Streaming float store through a buffer resource: `row` is wave-uniform (the
+// descriptor lives in scalar registers), `byte_off` the per-lane offset.  The
+// store is non-temporal.  Descriptor word 3 is the raw 32-bit buffer format
+// of gfx9-family targets; the record count is unbounded (offsets stay inside
+// the row by construction).
+struct RowWriter {
+  __amdgpu_buffer_rsrc_t r;
+  __device__ __forceinline__ explicit RowWriter(float* row)
+      : r(__builtin_amdgcn_make_buffer_rsrc(row, 0, -1, 0x00020000)) {}
+  __device__ __forceinline__ void put(float v, uint32_t byte_off) const {
+    constexpr int kNonTemporal = 2;
+    __builtin_amdgcn_raw_buffer_store_b32(__float_as_uint(v), r, static_cast<int>(byte_off), 0,
+                                          kNonTemporal);
+  }
+};
+
 // ---------------------------------------------------------------------------
 // Eq. 2 and Eq. 3 at one vertex (Section 3.1).  The caller supplies the two
 // U neighbours along x and the two V neighbours along y, already clamped at
@@ -78,37 +108,58 @@ __device__ __forceinline__ DivGauss div_gauss(float mu_xl, float mu_xr, float va
 //
 // For a corner X ~ N(mu, var) and isovalue c the corner is above with
 // probability a = P(X >= c) and below with b = P(X < c) = 1 - a.  Only the
-// smaller of the two is evaluated directly, t = erfc(|c - mu| / (sigma sqrt 2))/2
-// <= 1/2; the larger is 1 - t, which has no cancellation since it is >= 1/2.
-// A corner with var == 0 is deterministic (t = 0, above iff mu >= c).
+// smaller of the two is evaluated directly, Q = erfc(|mu - c| / (sigma sqrt 2))/2
+// <= 1/2; the larger is 1 - Q, which has no cancellation since it is >= 1/2.
+//
+// Q comes from gauss_tail_scaled(): a branch-free fit (see gen_tail.py)
+//   t = 1/(1 + KP y'),  Q = t 2^(-y'^2 + C(t)),  y' = |mu - c| sqrt(log2 e)/(sigma sqrt 2),
+// one reciprocal, one base-2 exponential and nine fused multiply-adds.
+// A corner with var == 0 is deterministic: its tail argument is made +inf
+// (t = 0, Q = 0), so it is above iff mu >= c, at no extra cost per isovalue.
 // ---------------------------------------------------------------------------
+__device__ __forceinline__ float gauss_tail_scaled(float y) {
+  const float t = __builtin_amdgcn_rcpf(fmaf(tail::KP, y, 1.0f));
+  float p = tail::C7;
+  p = fmaf(p, t, tail::C6);
+  p = fmaf(p, t, tail::C5);
+  p = fmaf(p, t, tail::C4);
+  p = fmaf(p, t, tail::C3);
+  p = fmaf(p, t, tail::C2);
+  p = fmaf(p, t, tail::C1);
+  p = fmaf(p, t, tail::C0);
+  return t * __builtin_amdgcn_exp2f(fmaf(-y, y, p));
+}
+
 struct Corner {
   float mean;  // mu
-  float r;     // 1 / (sigma sqrt 2); 0 for a deterministic corner
-  bool det;    // var == 0
+  float rs;    // sqrt(log2 e) / (sigma sqrt 2); 0 for a deterministic corner
+  float z0;    // 0, or +inf for a deterministic corner
 };
 
 __device__ __forceinline__ Corner make_corner(DivGauss g) {
+  constexpr float kTwoLn2 = 1.38629436112f;  // 2 ln 2 = 2 / log2(e)
   Corner c;
   c.mean = g.mean;
-  c.det = (g.var == 0.0f);
+  const bool det = (g.var == 0.0f);
   // rsqrt of a negative variance is NaN, which then propagates to the LCP
-  c.r = c.det ? 0.0f : __frsqrt_rn(2.0f * g.var);
+  c.rs = det ? 0.0f : rsqrtf(g.var * kTwoLn2);
+  c.z0 = det ? __builtin_inff() : 0.0f;
   return c;
 }
 
 struct AB {
-  float a, b;  // P(above), P(below)
+  float a, b;   // P(above), P(below)
+  bool below;   // mu < c
 };
 
 __device__ __forceinline__ AB corner_probs(const Corner& k, float c) {
-  float y = fabsf((c - k.mean) * k.r);
-  float t = k.det ? 0.0f : 0.5f * erfcf(y);
-  bool above = (k.mean >= c);
-  float s = 1.0f - t;
+  const float d = k.mean - c;  // mu == c gives +0: above, the >= rule
+  const float q = gauss_tail_scaled(fmaf(fabsf(d), k.rs, k.z0));
+  const float s = 1.0f - q;
   AB p;
-  p.a = above ? s : t;
-  p.b = above ? t : s;
+  p.below = d < 0.0f;
+  p.a = p.below ? q : s;
+  p.b = p.below ? s : q;
   return p;
 }
 
@@ -131,15 +182,18 @@ __device__ __forceinline__ Pair make_pair(AB lo, AB hi) {
 
 // LCP of the cell made of the left pair L and the right pair R:
 //   A = Pa_L Pa_R (all above), 1 - A = Qa_L + Pa_L Qa_R, same for B (all below);
-//   LCP = (1 - A) - B if A >= B, else (1 - B) - A.
-// If A >= B some corner has a >= b, hence B <= b_k = min(a_k, b_k) <= LCP, so
-// the subtraction loses at most a bit: relative accuracy holds near 0.
-__device__ __forceinline__ float cell_lcp(const Pair& L, const Pair& R) {
-  float A = L.pa * R.pa;
-  float B = L.pb * R.pb;
-  float oneMinusA = fmaf(L.pa, R.qa, L.qa);
-  float oneMinusB = fmaf(L.pb, R.qb, L.qb);
-  return (A >= B) ? (oneMinusA - B) : (oneMinusB - A);
+//   LCP = (1 - A) - B if some corner is above, else (1 - B) - A.
+// `ref_below` is the side of any one corner of the cell.  For every corner k,
+// LCP >= min(a_k, b_k) (fix the other three corners: the all-same-side mass is
+// at most max(a_k, b_k)).  If corner k is above, B <= b_k <= LCP, so
+// (1 - A) - B subtracts at most half of 1 - A and keeps its relative accuracy
+// near 0; symmetrically when it is below.
+__device__ __forceinline__ float cell_lcp(const Pair& L, const Pair& R, bool ref_below) {
+  const float A = L.pa * R.pa;
+  const float B = L.pb * R.pb;
+  const float oneMinusA = fmaf(L.pa, R.qa, L.qa);
+  const float oneMinusB = fmaf(L.pb, R.qb, L.qb);
+  return ref_below ? (oneMinusB - A) : (oneMinusA - B);
 }
 
 // ---------------------------------------------------------------------------
