@@ -230,6 +230,14 @@ pdiv_status pdiv_server_stats(pdiv_server srv, pdiv_server_stats_t* out);
 pdiv_status pdiv_server_destroy(pdiv_server srv);
 
 /* ------------------------------------------------------------------------
+ * Tuning
+ * ------------------------------------------------------------------------ */
+/* Cell rows per wave band of the closed-form LCP kernels (pdiv_lcp,
+ * pdiv_lcp_from_moments), process-wide; 0 restores the built-in choice.
+ * Results do not depend on it.  Returns PDIV_ERR_INVALID outside [0, 4096]. */
+pdiv_status pdiv_set_lcp_band_rows(int32_t rows);
+
+/* ------------------------------------------------------------------------
  * Status
  * ------------------------------------------------------------------------ */
 const char* pdiv_status_string(pdiv_status s);

@@ -81,6 +81,7 @@ _SIGS = {
     "pdiv_server_wait": [_p, _u64, _i64, _c.POINTER(_c.c_int)],
     "pdiv_server_stats": [_p, _c.POINTER(ServerStats)],
     "pdiv_server_destroy": [_p],
+    "pdiv_set_lcp_band_rows": [_i32],
 }
 EXPORTS = list(_SIGS) + ["pdiv_status_string", "pdiv_last_error", "pdiv_version"]
 
@@ -154,6 +155,11 @@ def _moment_ptrs(mean_u, var_u, mean_v, var_v):
     ptrs = [_dev(t, n, (ny, nx), dt) for t, n in
             ((mean_u, "mean_u"), (var_u, "var_u"), (mean_v, "mean_v"), (var_v, "var_v"))]
     return ptrs, ny, nx, _dtype_code(mean_u)
+
+
+def set_lcp_band_rows(rows: int):
+    """Cell rows per wave band of the closed-form LCP kernels (0 = built-in choice)."""
+    _check(lib().pdiv_set_lcp_band_rows(rows))
 
 
 def moments(u_members, v_members, ddof: int = 1, out_dtype=None):

@@ -1,19 +1,10 @@
 // Divergence Gaussians (Eq. 2-3) and the closed-form level-crossing
-// probability (Section 3.1), standalone and fused.
-//
-// Column-walking tiles: a wave owns 128 consecutive vertex columns, i.e. the
-// 127 cells between them, over a band of cell rows.  Lane L holds vertex
-// columns x0 + 2L and x0 + 2L + 1 and walks down the band one vertex row at a
-// time.  For each isovalue it evaluates each corner's tail once per row,
-// pairs it with the previous row's (vertical pairs, kept in registers) and
-// forms its two cells: the left one from its own two columns, the right one
-// with the first column of lane L+1, fetched by a lane shuffle.  Lane 63's
-// right cell belongs to the next strip and is not stored.  The kernel is
-// bound by the per-(corner, isovalue) tail and per-(cell, isovalue) combine
-// arithmetic and by the LCP stores, which are written once with
-// non-temporal stores (the maps are not re-read by this kernel).
-#include "pdiv_device.hpp"
-#include "pdiv_internal.hpp"
+// probability (Section 3.1), standalone and fused, for one field.  The tile
+// walk itself lives in lcp_tile.hpp; here a grid of waves covers the field's
+// strips x bands, one tile per wave.
+#include <atomic>
+
+#include "lcp_tile.hpp"
 
 namespace pdiv {
 
@@ -30,48 +21,23 @@ StencilCoef make_coef(double dx, double dy) {
   return k;
 }
 
+static std::atomic<int> g_band_rows_override{0};
+
+void set_band_rows_override(int rows) { g_band_rows_override.store(rows); }
+
 LcpShape default_lcp_shape(int64_t ny, int64_t nx, int n_iso) {
   (void)nx;
   (void)n_iso;
   LcpShape s;
-  s.band_rows = ny > 4096 ? 64 : 32;
+  const int o = g_band_rows_override.load();
+  s.band_rows = o > 0 ? o : (ny > 4096 ? 64 : 32);
   return s;
 }
 
 namespace {
 
-constexpr int kWave = 64;
-constexpr int kColsPerLane = 2;
-constexpr int kCellsPerWave = kWave * kColsPerLane - 1;
 constexpr int kBlock = 256;
 constexpr int kWavesPerBlock = kBlock / kWave;
-
-// Divergence Gaussian of vertex (x, j) from the moment planes, with the
-// one-sided differences of Eq. 1 on the boundary.  Row pointers are formed
-// from the row index first so that, when j is uniform across the wave, the
-// address is a scalar base plus a 32-bit per-lane column offset.
-template <typename T>
-__device__ __forceinline__ DivGauss vertex_from_moments(const T* __restrict__ mu,
-                                                        const T* __restrict__ vu,
-                                                        const T* __restrict__ mv,
-                                                        const T* __restrict__ vv, int ny,
-                                                        int nx, uint32_t x, int j,
-                                                        const StencilCoef& k) {
-  const uint32_t xl = x > 0 ? x - 1 : 0;
-  const uint32_t xr = x < uint32_t(nx - 1) ? x + 1 : uint32_t(nx - 1);
-  const int yl = j > 0 ? j - 1 : 0;
-  const int yr = j < ny - 1 ? j + 1 : ny - 1;
-  const bool bx = (x == 0) | (x == uint32_t(nx - 1));
-  const bool by = (j == 0) | (j == ny - 1);
-  const int64_t r0 = static_cast<int64_t>(j) * nx;
-  const int64_t rl = static_cast<int64_t>(yl) * nx;
-  const int64_t rr = static_cast<int64_t>(yr) * nx;
-  return div_gauss(to_f32(*at(mu + r0, xl)), to_f32(*at(mu + r0, xr)), to_f32(*at(vu + r0, xl)),
-                   to_f32(*at(vu + r0, xr)), to_f32(*at(mv + rl, x)), to_f32(*at(mv + rr, x)),
-                   to_f32(*at(vv + rl, x)), to_f32(*at(vv + rr, x)), bx ? k.cxm_bd : k.cxm_in,
-                   bx ? k.cxv_bd : k.cxv_in, by ? k.cym_bd : k.cym_in,
-                   by ? k.cyv_bd : k.cyv_in);
-}
 
 template <typename T>
 __global__ __launch_bounds__(kBlock) void divergence_kernel(const T* __restrict__ mu,
@@ -86,68 +52,14 @@ __global__ __launch_bounds__(kBlock) void divergence_kernel(const T* __restrict_
   const int j0 = (blockIdx.y * kWavesPerBlock + (threadIdx.x >> 6)) * rows_per_thread;
   if (x >= nx) return;
   const int j1 = min(j0 + rows_per_thread, ny);
+  const Col c = make_col(uint32_t(x), nx);
   for (int j = j0; j < j1; ++j) {
-    DivGauss g = vertex_from_moments(mu, vu, mv, vv, ny, nx, uint32_t(x), j, k);
+    Raw<true> r;
+    load_raw(r, mu, vu, mv, vv, ny, nx, c.x, c.xl, c.xr, j);
+    const DivGauss g = raw_div(r, c.bx, j, ny, k);
     const int64_t o = static_cast<int64_t>(j) * nx + x;
     __builtin_nontemporal_store(g.mean, dmean + o);
     __builtin_nontemporal_store(g.var, dvar + o);
-  }
-}
-
-template <bool FUSED, typename T>
-__device__ __forceinline__ Corner load_corner(const T* __restrict__ p0, const T* __restrict__ p1,
-                                              const T* __restrict__ p2,
-                                              const T* __restrict__ p3, int ny, int nx,
-                                              uint32_t x, int j, const StencilCoef& k) {
-  if constexpr (FUSED) {
-    return make_corner(vertex_from_moments(p0, p1, p2, p3, ny, nx, x, j, k));
-  } else {
-    const int64_t r0 = static_cast<int64_t>(j) * nx;
-    DivGauss g;
-    g.mean = to_f32(*at(p0 + r0, x));
-    g.var = to_f32(*at(p1 + r0, x));
-    return make_corner(g);
-  }
-}
-
-__device__ __forceinline__ Pair pair_from_right(const Pair& p) {
-  Pair r;
-  r.pa = __shfl_down(p.pa, 1, kWave);
-  r.qa = __shfl_down(p.qa, 1, kWave);
-  r.pb = __shfl_down(p.pb, 1, kWave);
-  r.qb = __shfl_down(p.qb, 1, kWave);
-  return r;
-}
-
-// One vertex row step: corners of row j+1 for the lane's two columns, their
-// pairs with row j (prev_*), the lane's two cells for every isovalue; the new
-// corners replace the old ones in next_*.
-template <int KC, bool FUSED, typename T>
-__device__ __forceinline__ void row_step(const T* __restrict__ p0, const T* __restrict__ p1,
-                                         const T* __restrict__ p2, const T* __restrict__ p3,
-                                         int ny, int nx, const StencilCoef& k,
-                                         const IsoChunk& iso, float* __restrict__ out,
-                                         int64_t plane, int j, uint32_t xa_c, uint32_t xb_c,
-                                         uint32_t xa, bool store_a, bool store_b,
-                                         const AB (&prev_a)[KC], const AB (&prev_b)[KC],
-                                         AB (&next_a)[KC], AB (&next_b)[KC]) {
-  const Corner ca = load_corner<FUSED>(p0, p1, p2, p3, ny, nx, xa_c, j + 1, k);
-  const Corner cb = load_corner<FUSED>(p0, p1, p2, p3, ny, nx, xb_c, j + 1, k);
-  float* __restrict__ orow = out + static_cast<int64_t>(j) * (nx - 1);
-#pragma unroll
-  for (int q = 0; q < KC; ++q) {
-    const AB cur_a = corner_probs(ca, iso.c[q]);
-    const AB cur_b = corner_probs(cb, iso.c[q]);
-    const Pair pa = make_pair(prev_a[q], cur_a);
-    const Pair pb = make_pair(prev_b[q], cur_b);
-    const Pair right = pair_from_right(pa);
-    const float l0 = cell_lcp(pa, pb, cur_a.below);
-    const float l1 = cell_lcp(pb, right, cur_b.below);
-    const RowWriter w(orow + q * plane);
-    if (store_a) w.put(l0, xa * 4u);
-    if (store_b) w.put(l1, xa * 4u + 4u);
-    next_a[q] = cur_a;
-    next_b[q] = cur_b;
   }
 }
 
@@ -160,42 +72,15 @@ __global__ __launch_bounds__(kBlock) void lcp_kernel(const T* __restrict__ p0,
                                                      float* __restrict__ out, int64_t plane,
                                                      int band_rows, int n_strips,
                                                      int n_bands) {
-  const uint32_t lane = threadIdx.x & 63;
   // the wave index is uniform: row indices and row base pointers stay scalar
   const int wave = __builtin_amdgcn_readfirstlane(blockIdx.x * kWavesPerBlock +
                                                   (threadIdx.x >> 6));
   const int strip = wave % n_strips;
   const int band = wave / n_strips;
   if (band >= n_bands) return;
-  const uint32_t xa = uint32_t(strip * kCellsPerWave) + kColsPerLane * lane;  // first column
-  const uint32_t xb = xa + 1;                                                 // second column
-  const uint32_t last = uint32_t(nx - 1);
-  const uint32_t xa_c = xa < last ? xa : last;  // columns past the edge load a valid column
-  const uint32_t xb_c = xb < last ? xb : last;
-  const bool store_a = xa < last;
-  const bool store_b = (lane < kWave - 1) & (xb < last);
   const int j0 = band * band_rows;
-  const int j1 = min(j0 + band_rows, ny - 1);
-
-  AB ra[KC], rb[KC], sa[KC], sb[KC];
-  {
-    const Corner ca = load_corner<FUSED>(p0, p1, p2, p3, ny, nx, xa_c, j0, k);
-    const Corner cb = load_corner<FUSED>(p0, p1, p2, p3, ny, nx, xb_c, j0, k);
-#pragma unroll
-    for (int q = 0; q < KC; ++q) {
-      ra[q] = corner_probs(ca, iso.c[q]);
-      rb[q] = corner_probs(cb, iso.c[q]);
-    }
-  }
-  // two rows per trip so the carried corners alternate between two register
-  // sets instead of being copied
-  for (int j = j0; j < j1; j += 2) {
-    row_step<KC, FUSED>(p0, p1, p2, p3, ny, nx, k, iso, out, plane, j, xa_c, xb_c, xa,
-                        store_a, store_b, ra, rb, sa, sb);
-    if (j + 1 < j1)
-      row_step<KC, FUSED>(p0, p1, p2, p3, ny, nx, k, iso, out, plane, j + 1, xa_c, xb_c, xa,
-                          store_a, store_b, sa, sb, ra, rb);
-  }
+  lcp_tile<KC, FUSED>(p0, p1, p2, p3, ny, nx, k, iso, KC, out, plane, strip, j0,
+                      min(j0 + band_rows, ny - 1));
 }
 
 template <int KC, bool FUSED, typename T>

@@ -1,0 +1,205 @@
+// Column-walking tile of the closed-form LCP (Eq. 2-3 and the level-crossing
+// probability of Section 3.1), shared by the single-field kernel and the
+// batched persistent kernel so that both give bitwise the same maps.
+//
+// A wave owns 127 vertex columns x0..x0+126, i.e. the 126 cells between
+// them, over a band of cell rows.  Lane L holds two vertex columns, A = x0 + L
+// and B = x0 + 63 + L (lane 63's A column repeats lane 0's B column), and
+// walks down the band one vertex row at a time.  For each isovalue it
+// evaluates each corner's tail once per row, pairs it with the previous row's
+// (vertical pairs, kept in registers) and forms the cells (A, A+1) and
+// (B, B+1), taking the right-hand pairs from lane L+1 by lane shuffles.  Lanes
+// 0..62 store; each of the two stores writes 63 consecutive cells of one
+// output row, which keeps the write stream contiguous (stride-2 lane patterns
+// through buffer stores cost a factor of three in write bandwidth).  The next
+// row's input loads are issued before the current row is computed.
+#pragma once
+
+#include "pdiv_device.hpp"
+#include "pdiv_internal.hpp"
+
+namespace pdiv {
+
+constexpr int kWave = 64;
+constexpr int kHalf = kWave - 1;          // cells per half-strip
+constexpr int kCellsPerWave = 2 * kHalf;  // 126
+
+// The values one vertex reads: for the fused path the U neighbours along x
+// and the V neighbours along y of Eq. 2-3 (boundary-clamped), for the
+// two-step path its divergence mean and variance.  Loading them is split from
+// using them so that the next row's loads are in flight while the current
+// row is computed.
+template <bool FUSED>
+struct Raw;
+template <>
+struct Raw<true> {
+  float mu_l, mu_r, vu_l, vu_r, mv_l, mv_r, vv_l, vv_r;
+};
+template <>
+struct Raw<false> {
+  float mean, var;
+};
+
+// Row pointers are formed from the (wave-uniform) row index first, so each
+// load is a scalar base plus a 32-bit per-lane column offset.
+template <typename T>
+__device__ __forceinline__ void load_raw(Raw<true>& r, const T* __restrict__ mu,
+                                         const T* __restrict__ vu, const T* __restrict__ mv,
+                                         const T* __restrict__ vv, int ny, int nx, uint32_t x,
+                                         uint32_t xl, uint32_t xr, int j) {
+  const int yl = j > 0 ? j - 1 : 0;
+  const int yr = j < ny - 1 ? j + 1 : ny - 1;
+  const int64_t r0 = static_cast<int64_t>(j) * nx;
+  const int64_t rl = static_cast<int64_t>(yl) * nx;
+  const int64_t rr = static_cast<int64_t>(yr) * nx;
+  r.mu_l = to_f32(*at(mu + r0, xl));
+  r.mu_r = to_f32(*at(mu + r0, xr));
+  r.vu_l = to_f32(*at(vu + r0, xl));
+  r.vu_r = to_f32(*at(vu + r0, xr));
+  r.mv_l = to_f32(*at(mv + rl, x));
+  r.mv_r = to_f32(*at(mv + rr, x));
+  r.vv_l = to_f32(*at(vv + rl, x));
+  r.vv_r = to_f32(*at(vv + rr, x));
+}
+
+template <typename T>
+__device__ __forceinline__ void load_raw(Raw<false>& r, const T* __restrict__ dm,
+                                         const T* __restrict__ dv, const T* __restrict__,
+                                         const T* __restrict__, int, int nx, uint32_t x,
+                                         uint32_t, uint32_t, int j) {
+  const int64_t r0 = static_cast<int64_t>(j) * nx;
+  r.mean = to_f32(*at(dm + r0, x));
+  r.var = to_f32(*at(dv + r0, x));
+}
+
+// Eq. 2-3 at vertex (x, j) with the one-sided differences of Eq. 1 on the
+// boundary (bx: x is a boundary column; j decides the y boundary).
+__device__ __forceinline__ DivGauss raw_div(const Raw<true>& r, bool bx, int j, int ny,
+                                            const StencilCoef& k) {
+  const bool by = (j == 0) | (j == ny - 1);
+  return div_gauss(r.mu_l, r.mu_r, r.vu_l, r.vu_r, r.mv_l, r.mv_r, r.vv_l, r.vv_r,
+                   bx ? k.cxm_bd : k.cxm_in, bx ? k.cxv_bd : k.cxv_in,
+                   by ? k.cym_bd : k.cym_in, by ? k.cyv_bd : k.cyv_in);
+}
+__device__ __forceinline__ DivGauss raw_div(const Raw<false>& r, bool, int, int,
+                                            const StencilCoef&) {
+  DivGauss g;
+  g.mean = r.mean;
+  g.var = r.var;
+  return g;
+}
+
+// Neighbour columns of x for the x differences, clamped at the boundary.
+struct Col {
+  uint32_t x, xl, xr;
+  bool bx;
+};
+__device__ __forceinline__ Col make_col(uint32_t x, int nx) {
+  const uint32_t last = uint32_t(nx - 1);
+  Col c;
+  c.x = x;
+  c.xl = x > 0 ? x - 1 : 0;
+  c.xr = x < last ? x + 1 : last;
+  c.bx = (x == 0) | (x == last);
+  return c;
+}
+
+__device__ __forceinline__ Pair pair_from_right(const Pair& p) {
+  Pair r;
+  r.pa = __shfl_down(p.pa, 1, kWave);
+  r.qa = __shfl_down(p.qa, 1, kWave);
+  r.pb = __shfl_down(p.pb, 1, kWave);
+  r.qb = __shfl_down(p.qb, 1, kWave);
+  return r;
+}
+
+// One vertex row step: the corners of row j+1 (from raw values loaded one
+// step earlier) for the lane's two columns, their pairs with row j (prev_*),
+// and the lane's two cells for every isovalue; the new corners go to next_*.
+// xa is the lane's A column; its B column is xa + 63.
+template <int KC, bool FUSED>
+__device__ __forceinline__ void row_step(const Raw<FUSED>& raw_a, const Raw<FUSED>& raw_b,
+                                         const Col& ca_col, const Col& cb_col, int ny, int nx,
+                                         const StencilCoef& k, const IsoChunk& iso,
+                                         int n_store, float* __restrict__ out, int64_t plane,
+                                         int j,
+                                         uint32_t xa, bool store_a, bool store_b,
+                                         const AB (&prev_a)[KC], const AB (&prev_b)[KC],
+                                         AB (&next_a)[KC], AB (&next_b)[KC]) {
+  const Corner ca = make_corner(raw_div(raw_a, ca_col.bx, j + 1, ny, k));
+  const Corner cb = make_corner(raw_div(raw_b, cb_col.bx, j + 1, ny, k));
+  float* __restrict__ orow = out + static_cast<int64_t>(j) * (nx - 1);
+#pragma unroll
+  for (int q = 0; q < KC; ++q) {
+    const AB cur_a = corner_probs(ca, iso.c[q]);
+    const AB cur_b = corner_probs(cb, iso.c[q]);
+    const Pair pa = make_pair(prev_a[q], cur_a);
+    const Pair pb = make_pair(prev_b[q], cur_b);
+    const float l0 = cell_lcp(pa, pair_from_right(pa), cur_a.below);
+    const float l1 = cell_lcp(pb, pair_from_right(pb), cur_b.below);
+    if (q < n_store) {
+      const RowWriter w(orow + q * plane);
+      if (store_a) w.put(l0, xa * 4u);
+      if (store_b) w.put(l1, (xa + kHalf) * 4u);
+    }
+    next_a[q] = cur_a;
+    next_b[q] = cur_b;
+  }
+}
+
+// One tile: cell columns [x0, x0+126) of strip `strip` (x0 = 126 strip),
+// cell rows [j0, j1), for the KC isovalues in `iso`; only the first n_store
+// isovalue planes are written (a batch pads its isovalue set to KC).  Must be
+// called with wave-uniform arguments by all 64 lanes of a wave.
+template <int KC, bool FUSED, typename T>
+__device__ __forceinline__ void lcp_tile(const T* __restrict__ p0, const T* __restrict__ p1,
+                                         const T* __restrict__ p2, const T* __restrict__ p3,
+                                         int ny, int nx, const StencilCoef& k,
+                                         const IsoChunk& iso, int n_store,
+                                         float* __restrict__ out, int64_t plane, int strip,
+                                         int j0, int j1) {
+  const uint32_t lane = threadIdx.x & 63;
+  const uint32_t xa = uint32_t(strip * kCellsPerWave) + lane;  // A column
+  const uint32_t xb = xa + kHalf;                               // B column
+  const uint32_t last = uint32_t(nx - 1);
+  const Col ca = make_col(xa < last ? xa : last, nx);  // columns past the edge load a
+  const Col cb = make_col(xb < last ? xb : last, nx);  // valid column and store nothing
+  const bool store_a = (lane < kHalf) & (xa < last);
+  const bool store_b = (lane < kHalf) & (xb < last);
+
+  AB ra[KC], rb[KC], sa[KC], sb[KC];
+  Raw<FUSED> xa0, xb0, xa1, xb1;
+  load_raw(xa0, p0, p1, p2, p3, ny, nx, ca.x, ca.xl, ca.xr, j0);
+  load_raw(xb0, p0, p1, p2, p3, ny, nx, cb.x, cb.xl, cb.xr, j0);
+  load_raw(xa1, p0, p1, p2, p3, ny, nx, ca.x, ca.xl, ca.xr, j0 + 1);
+  load_raw(xb1, p0, p1, p2, p3, ny, nx, cb.x, cb.xl, cb.xr, j0 + 1);
+  {
+    const Corner c0 = make_corner(raw_div(xa0, ca.bx, j0, ny, k));
+    const Corner c1 = make_corner(raw_div(xb0, cb.bx, j0, ny, k));
+#pragma unroll
+    for (int q = 0; q < KC; ++q) {
+      ra[q] = corner_probs(c0, iso.c[q]);
+      rb[q] = corner_probs(c1, iso.c[q]);
+    }
+  }
+  // Two rows per trip: the carried corners alternate between two register
+  // sets, and the raw loads of row j+2 are issued before row j+1 is computed.
+  for (int j = j0; j < j1; j += 2) {
+    if (j + 2 <= j1) {
+      load_raw(xa0, p0, p1, p2, p3, ny, nx, ca.x, ca.xl, ca.xr, j + 2);
+      load_raw(xb0, p0, p1, p2, p3, ny, nx, cb.x, cb.xl, cb.xr, j + 2);
+    }
+    row_step<KC, FUSED>(xa1, xb1, ca, cb, ny, nx, k, iso, n_store, out, plane, j, ca.x,
+                        store_a, store_b, ra, rb, sa, sb);
+    if (j + 1 < j1) {
+      if (j + 3 <= j1) {
+        load_raw(xa1, p0, p1, p2, p3, ny, nx, ca.x, ca.xl, ca.xr, j + 3);
+        load_raw(xb1, p0, p1, p2, p3, ny, nx, cb.x, cb.xl, cb.xr, j + 3);
+      }
+      row_step<KC, FUSED>(xa0, xb0, ca, cb, ny, nx, k, iso, n_store, out, plane, j + 1, ca.x,
+                          store_a, store_b, sa, sb, ra, rb);
+    }
+  }
+}
+
+}  // namespace pdiv

@@ -110,6 +110,13 @@ extern "C" {
 
 const char* pdiv_version(void) { return "0.1.0"; }
 
+pdiv_status pdiv_set_lcp_band_rows(int32_t rows) {
+  g_last_error.clear();
+  if (rows < 0 || rows > 4096) return invalid("band rows must be in [0, 4096] (got %d)", rows);
+  set_band_rows_override(rows);
+  return PDIV_OK;
+}
+
 const char* pdiv_last_error(void) { return g_last_error.c_str(); }
 
 const char* pdiv_status_string(pdiv_status s) {

@@ -4,9 +4,18 @@
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
+#include <string>
+
 #include "../../include/pdiv.h"
 
 namespace pdiv {
+
+// Message of the last failing call on this thread (pdiv_last_error).
+extern thread_local std::string g_last_error;
+// Records a message and returns PDIV_ERR_INVALID.
+pdiv_status invalid(const char* fmt, ...);
+// PDIV_OK for hipSuccess; otherwise records the HIP error and returns PDIV_ERR_DEVICE.
+pdiv_status device_status(hipError_t e, const char* what);
 
 // Isovalues of one launch, passed by value in the kernel arguments so that
 // every wave reads them from scalar registers.
@@ -29,6 +38,7 @@ struct LcpShape {
   int band_rows;
 };
 LcpShape default_lcp_shape(int64_t ny, int64_t nx, int n_iso);
+void set_band_rows_override(int rows);
 
 hipError_t launch_moments(const void* u, const void* v, pdiv_dtype in_dtype, int64_t m,
                           int64_t n_points, int64_t stride, int ddof, void* mu, void* vu,

@@ -127,3 +127,24 @@ def test_error_message_is_per_thread():
     t.join()
     assert seen["msg"] == ""
     assert "2x2" in L.pdiv_last_error().decode()
+
+
+def test_batch_rejects_bad_fields():
+    L = P.lib()
+    iso_dev = FAKE
+    good = P._Field(FAKE, FAKE, FAKE, FAKE, 8, 8, 1.0, 1.0, iso_dev, 4, FAKE)
+    out = ctypes.c_void_p()
+    for bad, frag in (
+        (P._Field(FAKE, FAKE, FAKE, FAKE, 8, 8, 1.0, 1.0, iso_dev, 17, FAKE), "n_iso"),
+        (P._Field(FAKE, FAKE, FAKE, FAKE, 1, 8, 1.0, 1.0, iso_dev, 4, FAKE), "bad grid"),
+        (P._Field(NUL, FAKE, FAKE, FAKE, 8, 8, 1.0, 1.0, iso_dev, 4, FAKE), "NULL"),
+        (P._Field(FAKE, FAKE, FAKE, FAKE, 8, 8, 0.0, 1.0, iso_dev, 4, FAKE), "dx and dy"),
+    ):
+        arr = (P._Field * 2)(good, bad)
+        _expect_invalid(L.pdiv_batch_create(arr, 2, 0, 0, NUL, ctypes.byref(out)), frag)
+        assert out.value is None
+    arr = (P._Field * 1)(good)
+    _expect_invalid(L.pdiv_batch_create(arr, 0, 0, 0, NUL, ctypes.byref(out)), "n_fields")
+    _expect_invalid(L.pdiv_batch_create(arr, 1, 5, 0, NUL, ctypes.byref(out)), "dtype")
+    _expect_invalid(L.pdiv_batch_create(arr, 1, 0, 8, NUL, ctypes.byref(out)), "flags")
+    _expect_invalid(L.pdiv_batch_launch(NUL, NUL), "batch is NULL")

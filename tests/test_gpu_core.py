@@ -4,6 +4,7 @@ received (storage dtype upcast exactly), so these tests measure the kernels'
 float32 arithmetic; the end-to-end storage error is measured at full size in
 test_gpu_fullsize.py."""
 
+import mpmath
 import numpy as np
 import pytest
 import torch
@@ -90,11 +91,28 @@ def test_relative_accuracy_near_zero_and_one():
     div = synth.analytic_divergence(f["features"], ny, nx)
     iso = synth.quantile_isovalues(div, [0.01, 0.3, 0.5, 0.7, 0.99])
     L = host64(P.lcp(dm, dv, iso))
-    ref = O.lcp(host64(dm), host64(dv), iso)
-    small = (ref >= 1e-30) & (ref < 1e-3)
+    m, v = host64(dm), host64(dv)
+    ref = O.lcp(m, v, iso)
+    # the FP64 oracle evaluates 1 - A - B literally (absolute error ~1e-16), so
+    # it is a relative reference only down to ~1e-9
+    small = (ref >= 1e-9) & (ref < 1e-3)
     assert small.sum() > 1000
     rel = np.abs(L[small] - ref[small]) / ref[small]
     assert rel.max() <= 1e-4, rel.max()
+    # deeper cells: 40-digit evaluation of the same definition on a sample
+    mpmath.mp.dps = 40
+    deep = np.argwhere((ref < 1e-9) & (L > 1e-30))
+    rng = np.random.default_rng(0)
+    for k, j, i in deep[rng.choice(len(deep), min(200, len(deep)), replace=False)]:
+        c = mpmath.mpf(float(iso[k]))
+        A = mpmath.mpf(1)
+        B = mpmath.mpf(1)
+        for jj, ii in ((j, i), (j, i + 1), (j + 1, i), (j + 1, i + 1)):
+            x = (c - mpmath.mpf(float(m[jj, ii]))) / mpmath.sqrt(2 * mpmath.mpf(float(v[jj, ii])))
+            A *= mpmath.erfc(x) / 2
+            B *= mpmath.erfc(-x) / 2
+        exact = float(1 - A - B)
+        assert abs(L[k, j, i] - exact) <= 1e-4 * exact, (k, j, i, L[k, j, i], exact)
 
     ramp = np.add.outer(np.zeros(40), (np.arange(120) - 60.3) * 0.5)
     rm = torch.from_numpy(ramp.astype(np.float32)).cuda()
