@@ -12,6 +12,8 @@ namespace pdiv {
 
 // Message of the last failing call on this thread (pdiv_last_error).
 extern thread_local std::string g_last_error;
+// Records a message for pdiv_last_error.
+void set_error(const char* fmt, ...);
 // Records a message and returns PDIV_ERR_INVALID.
 pdiv_status invalid(const char* fmt, ...);
 // PDIV_OK for hipSuccess; otherwise records the HIP error and returns PDIV_ERR_DEVICE.

@@ -1,17 +1,608 @@
-// Continuous-batching server (placeholder until the server lands).
-#include "pdiv_internal.hpp"
+// Continuous-batching LCP server over device-resident fields.
+//
+// Fields arrive as host moment planes (pdiv_server_put_field): they are copied
+// into pinned staging, uploaded on an upload stream, reduced to their
+// divergence Gaussians (Eq. 2-3, 8 bytes per point) and kept resident.
+// Isovalue-slider requests (pdiv_server_submit_lcp) name a resident field and
+// 1..16 isovalues.  One worker thread runs the loop
+//   completions -> admission of new fields by HBM budget (evicting least
+//   recently used fields no request names) -> all slider requests waiting on
+//   ready fields merged into one batched launch per free slot
+// so requests that arrive while others are on the GPU join the next launch as
+// soon as a slot frees; launches overlap on n_streams compute streams.  Each
+// request's maps come from the same tile code as pdiv_lcp on the same
+// divergence Gaussians, so a result is bitwise the same alone or in the mix.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <atomic>
+#include <chrono>
+#include <cmath>
+#include <condition_variable>
+#include <cstdlib>
+#include <cstring>
+#include <deque>
+#include <map>
+#include <memory>
+#include <mutex>
+#include <string>
+#include <thread>
+#include <unordered_map>
+#include <vector>
+
+#include "batch_internal.hpp"
+
+using Clock = std::chrono::steady_clock;
+using namespace pdiv;
+
+namespace {
+
+constexpr int kMaxBatch = 512;   // slider requests per launch
+constexpr int kBandRows = 16;    // tile height of server launches
+constexpr int kMaxStreams = 8;
+
+size_t dtype_bytes(pdiv_dtype d) { return d == PDIV_F32 ? 4 : 2; }
+
+struct ServerField {
+  uint64_t id = 0;
+  int ny = 0, nx = 0;
+  double dx = 1, dy = 1;
+  float* dmean = nullptr;
+  float* dvar = nullptr;
+  size_t bytes = 0;
+  bool ready = false;
+  bool failed = false;  // its upload or divergence launch failed
+  uint64_t last_use = 0;
+  int refs = 0;  // requests (queued or in flight) that name this field
+};
+
+struct PinnedBuf {
+  void* p = nullptr;
+  size_t bytes = 0;
+  bool busy = false;
+};
+
+enum class Kind { kNew, kSlider };
+
+struct Request {
+  uint64_t ticket = 0;
+  Kind kind = Kind::kSlider;
+  uint64_t fid = 0;
+  // new field
+  PinnedBuf* host = nullptr;
+  pdiv_dtype dtype = PDIV_F32;
+  int ny = 0, nx = 0;
+  double dx = 1, dy = 1;
+  // slider
+  float iso[kIsoChunk] = {};
+  int n_iso = 0;
+  float* out = nullptr;
+  Clock::time_point t_submit;
+  pdiv_status status = PDIV_OK;
+  bool done = false;
+};
+
+struct Slot {  // descriptor table + isovalues of one slider launch
+  BatchField* dev_fields = nullptr;
+  float* dev_iso = nullptr;
+  BatchField* host_fields = nullptr;  // pinned
+  float* host_iso = nullptr;          // pinned
+  bool busy = false;
+};
+
+struct Launch {
+  hipEvent_t ev = nullptr;
+  std::vector<Request*> reqs;
+  int slot = -1;
+  void* staging = nullptr;  // device staging of a new field
+  size_t staging_bytes = 0;
+  PinnedBuf* host = nullptr;
+  double cells = 0;
+};
+
+int fault_after() {  // PDIV_FAULT=server_launch:<n>: the n-th slider launch fails (n >= 1)
+  const char* f = std::getenv("PDIV_FAULT");
+  if (!f || std::strncmp(f, "server_launch:", 14) != 0) return 0;
+  return std::atoi(f + 14);
+}
+
+double pct(std::vector<double> v, double p) {
+  if (v.empty()) return 0.0;
+  std::sort(v.begin(), v.end());
+  const double r = p * (v.size() - 1);
+  const size_t a = size_t(std::floor(r)), b = std::min(v.size() - 1, a + 1);
+  return v[a] + (v[b] - v[a]) * (r - a);
+}
+
+}  // namespace
+
+struct pdiv_server_s {
+  size_t budget = 0;
+  int n_streams = 1;
+  int device = 0;
+  hipStream_t upload = nullptr;
+  std::vector<hipStream_t> streams;
+  std::vector<Slot> slots;
+  size_t slot_bytes = 0;
+
+  std::mutex mu;
+  std::condition_variable cv_work, cv_done;
+  bool stop = false;
+  std::thread worker;
+
+  std::unordered_map<uint64_t, std::unique_ptr<ServerField>> fields;
+  std::deque<Request*> queue;
+  std::unordered_map<uint64_t, std::unique_ptr<Request>> tickets;
+  std::vector<Launch> inflight;
+  std::vector<std::unique_ptr<PinnedBuf>> pinned;
+  uint64_t next_ticket = 1;
+  uint64_t clock = 0;
+  int next_stream = 0;
+  int launches_issued = 0;
+  int fault_at = 0;
+
+  size_t resident = 0, peak = 0;
+  uint64_t done = 0, failed = 0, launches = 0;
+  double cells = 0;
+  std::vector<double> lat_new, lat_slider;
+
+  void account(int64_t delta) {
+    resident = size_t(int64_t(resident) + delta);
+    peak = std::max(peak, resident);
+  }
+
+  // --- pinned host staging (reused, released at destroy) -------------------
+  PinnedBuf* get_pinned(size_t bytes) {
+    PinnedBuf* best = nullptr;
+    for (auto& b : pinned)
+      if (!b->busy && b->bytes >= bytes && (!best || b->bytes < best->bytes)) best = b.get();
+    if (!best) {
+      auto b = std::make_unique<PinnedBuf>();
+      if (hipHostMalloc(&b->p, bytes, hipHostMallocDefault) != hipSuccess) {
+        (void)hipGetLastError();
+        return nullptr;
+      }
+      b->bytes = bytes;
+      best = b.get();
+      pinned.push_back(std::move(b));
+    }
+    best->busy = true;
+    return best;
+  }
+
+  void finish(Request* r, pdiv_status st) {
+    r->status = st;
+    r->done = true;
+    const double us =
+        std::chrono::duration<double, std::micro>(Clock::now() - r->t_submit).count();
+    if (st == PDIV_OK) {
+      ++done;
+      (r->kind == Kind::kNew ? lat_new : lat_slider).push_back(us);
+    } else {
+      ++failed;
+    }
+    auto it = fields.find(r->fid);
+    if (it != fields.end()) {
+      it->second->refs--;
+      if (r->kind == Kind::kNew && st != PDIV_OK) it->second->failed = true;
+    }
+  }
+
+  // --- worker steps (called with mu held) -----------------------------------
+  void poll_completions() {
+    for (size_t i = 0; i < inflight.size();) {
+      Launch& L = inflight[i];
+      const hipError_t q = hipEventQuery(L.ev);
+      if (q == hipErrorNotReady) {
+        ++i;
+        continue;
+      }
+      const pdiv_status st = (q == hipSuccess) ? PDIV_OK : PDIV_ERR_DEVICE;
+      for (Request* r : L.reqs) {
+        if (r->kind == Kind::kNew) {
+          auto it = fields.find(r->fid);
+          if (it != fields.end()) it->second->ready = (st == PDIV_OK);
+        }
+        finish(r, st);
+      }
+      if (st == PDIV_OK) cells += L.cells;
+      if (L.slot >= 0) slots[L.slot].busy = false;
+      if (L.staging) {
+        (void)hipFreeAsync(L.staging, upload);
+        account(-int64_t(L.staging_bytes));
+      }
+      if (L.host) L.host->busy = false;
+      (void)hipEventDestroy(L.ev);
+      inflight.erase(inflight.begin() + i);
+    }
+  }
+
+  bool evict_for(size_t need) {
+    while (resident + need > budget) {
+      ServerField* victim = nullptr;
+      for (auto& kv : fields) {
+        ServerField* f = kv.second.get();
+        if ((f->ready || f->failed) && f->refs == 0 &&
+            (!victim || f->last_use < victim->last_use))
+          victim = f;
+      }
+      if (!victim) return false;
+      if (victim->dmean) (void)hipFreeAsync(victim->dmean, upload);
+      if (victim->dvar) (void)hipFreeAsync(victim->dvar, upload);
+      account(-int64_t(victim->bytes));
+      fields.erase(victim->id);
+    }
+    return true;
+  }
+
+  void admit_new() {
+    for (auto it = queue.begin(); it != queue.end();) {
+      Request* r = *it;
+      if (r->kind != Kind::kNew) {
+        ++it;
+        continue;
+      }
+      const size_t n = size_t(r->ny) * r->nx;
+      const size_t res = 8 * n, stg = 4 * dtype_bytes(r->dtype) * n;
+      if (resident + res + stg > budget && !evict_for(res + stg)) break;  // keep FIFO order
+      ServerField* f = fields[r->fid].get();
+      Launch L;
+      hipError_t e = hipMallocAsync(reinterpret_cast<void**>(&f->dmean), 4 * n, upload);
+      e = e != hipSuccess ? e : hipMallocAsync(reinterpret_cast<void**>(&f->dvar), 4 * n, upload);
+      e = e != hipSuccess ? e : hipMallocAsync(&L.staging, stg, upload);
+      e = e != hipSuccess ? e
+                          : hipMemcpyAsync(L.staging, r->host->p, stg, hipMemcpyHostToDevice, upload);
+      const size_t pb = dtype_bytes(r->dtype) * n;
+      char* s = static_cast<char*>(L.staging);
+      if (e == hipSuccess)
+        e = launch_divergence(s, s + pb, s + 2 * pb, s + 3 * pb, r->dtype, r->ny, r->nx,
+                              make_coef(r->dx, r->dy), f->dmean, f->dvar, upload);
+      e = e != hipSuccess ? e : hipEventCreateWithFlags(&L.ev, hipEventDisableTiming);
+      e = e != hipSuccess ? e : hipEventRecord(L.ev, upload);
+      it = queue.erase(it);
+      f->bytes = res;
+      account(int64_t(res + stg));
+      if (e != hipSuccess) {
+        (void)hipGetLastError();
+        r->host->busy = false;
+        account(-int64_t(stg));
+        finish(r, PDIV_ERR_DEVICE);
+        continue;
+      }
+      L.staging_bytes = stg;
+      L.host = r->host;
+      L.reqs.push_back(r);
+      inflight.push_back(L);
+    }
+  }
+
+  void launch_sliders() {
+    while (true) {
+      int slot = -1;
+      for (size_t i = 0; i < slots.size(); ++i)
+        if (!slots[i].busy) {
+          slot = int(i);
+          break;
+        }
+      if (slot < 0) return;
+      std::vector<Request*> take;
+      for (auto it = queue.begin(); it != queue.end() && int(take.size()) < kMaxBatch;) {
+        Request* r = *it;
+        if (r->kind == Kind::kSlider) {
+          auto f = fields.find(r->fid);
+          if (f != fields.end() && f->second->failed) {  // its field never arrived
+            it = queue.erase(it);
+            finish(r, PDIV_ERR_DEVICE);
+            continue;
+          }
+          if (f != fields.end() && f->second->ready) {
+            take.push_back(r);
+            it = queue.erase(it);
+            continue;
+          }
+        }
+        ++it;
+      }
+      if (take.empty()) return;
+      Slot& S = slots[slot];
+      int kc = 1;
+      double cells_here = 0;
+      std::vector<BatchField> fv(take.size());
+      for (size_t i = 0; i < take.size(); ++i) {
+        Request* r = take[i];
+        ServerField* f = fields[r->fid].get();
+        f->last_use = ++clock;
+        BatchField& x = fv[i];
+        x = BatchField{};
+        x.p0 = f->dmean;
+        x.p1 = f->dvar;
+        x.p2 = x.p3 = nullptr;
+        x.lcp = r->out;
+        x.iso = S.dev_iso + i * kIsoChunk;
+        x.ny = f->ny;
+        x.nx = f->nx;
+        x.n_iso = r->n_iso;
+        x.plane = int64_t(f->ny - 1) * (f->nx - 1);
+        x.coef = make_coef(f->dx, f->dy);
+        std::memcpy(S.host_iso + i * kIsoChunk, r->iso, sizeof(float) * kIsoChunk);
+        kc = std::max(kc, iso_bucket(r->n_iso));
+        cells_here += double(x.plane) * r->n_iso;
+      }
+      const int64_t n_tiles = fill_tiles(fv, kBandRows);
+      std::memcpy(S.host_fields, fv.data(), sizeof(BatchField) * fv.size());
+      hipStream_t s = streams[next_stream];
+      next_stream = (next_stream + 1) % n_streams;
+      const void* kernel = batch_kernel_ptr(false, PDIV_F32, kc);
+      const int grid =
+          int(std::max<int64_t>(1, std::min<int64_t>(resident_blocks(kernel), (n_tiles + 3) / 4)));
+      Launch L;
+      L.slot = slot;
+      L.reqs = take;
+      L.cells = cells_here;
+      ++launches_issued;
+      hipError_t e = hipSuccess;
+      if (fault_at > 0 && launches_issued == fault_at) {
+        e = hipErrorLaunchFailure;  // forced from the host: nothing is enqueued
+      } else {
+        e = hipMemcpyAsync(S.dev_fields, S.host_fields, sizeof(BatchField) * fv.size(),
+                           hipMemcpyHostToDevice, s);
+        e = e != hipSuccess ? e
+                            : hipMemcpyAsync(S.dev_iso, S.host_iso,
+                                             sizeof(float) * kIsoChunk * fv.size(),
+                                             hipMemcpyHostToDevice, s);
+        e = e != hipSuccess ? e
+                            : launch_batch(kernel, S.dev_fields, int(fv.size()), n_tiles,
+                                           kBandRows, grid, s);
+        e = e != hipSuccess ? e : hipEventCreateWithFlags(&L.ev, hipEventDisableTiming);
+        e = e != hipSuccess ? e : hipEventRecord(L.ev, s);
+      }
+      if (e != hipSuccess) {
+        (void)hipGetLastError();
+        if (L.ev) (void)hipEventDestroy(L.ev);
+        for (Request* r : take) finish(r, PDIV_ERR_DEVICE);
+        continue;
+      }
+      ++launches;
+      S.busy = true;
+      inflight.push_back(L);
+    }
+  }
+
+  void run() {
+    (void)hipSetDevice(device);
+    std::unique_lock<std::mutex> lk(mu);
+    while (true) {
+      poll_completions();
+      admit_new();
+      launch_sliders();
+      cv_done.notify_all();
+      if (stop && queue.empty() && inflight.empty()) break;
+      if (inflight.empty()) {
+        if (stop && !queue.empty()) {
+          // nothing in flight and nothing admissible: fail what is left
+          for (Request* r : queue) finish(r, PDIV_ERR_BUSY);
+          queue.clear();
+          continue;
+        }
+        cv_work.wait(lk);
+      } else {
+        lk.unlock();
+        std::this_thread::sleep_for(std::chrono::microseconds(20));
+        lk.lock();
+      }
+    }
+    cv_done.notify_all();
+  }
+};
 
 extern "C" {
-pdiv_status pdiv_server_create(size_t, int32_t, pdiv_server* out) {
-  if (out) *out = nullptr;
-  return PDIV_ERR_UNSUPPORTED;
+
+pdiv_status pdiv_server_create(size_t hbm_budget, int32_t n_streams, pdiv_server* out) {
+  g_last_error.clear();
+  if (out == nullptr) return invalid("out is NULL");
+  *out = nullptr;
+  if (n_streams < 1 || n_streams > kMaxStreams)
+    return invalid("n_streams must be in [1, %d]", kMaxStreams);
+  const int n_slots = 2 * n_streams;
+  const size_t slot_bytes = kMaxBatch * (sizeof(BatchField) + sizeof(float) * kIsoChunk);
+  if (hbm_budget < size_t(n_slots) * slot_bytes + (size_t(1) << 20))
+    return invalid("hbm_budget too small (need more than %zu bytes)",
+                   size_t(n_slots) * slot_bytes + (size_t(1) << 20));
+  auto srv = std::make_unique<pdiv_server_s>();
+  srv->budget = hbm_budget;
+  srv->n_streams = n_streams;
+  srv->fault_at = fault_after();
+  hipError_t e = hipGetDevice(&srv->device);
+  e = e != hipSuccess ? e : hipStreamCreateWithFlags(&srv->upload, hipStreamNonBlocking);
+  for (int i = 0; i < n_streams && e == hipSuccess; ++i) {
+    hipStream_t s = nullptr;
+    e = hipStreamCreateWithFlags(&s, hipStreamNonBlocking);
+    if (e == hipSuccess) srv->streams.push_back(s);
+  }
+  srv->slots.resize(n_slots);
+  for (auto& S : srv->slots) {
+    if (e != hipSuccess) break;
+    e = hipMalloc(reinterpret_cast<void**>(&S.dev_fields), sizeof(BatchField) * kMaxBatch);
+    e = e != hipSuccess ? e
+                        : hipMalloc(reinterpret_cast<void**>(&S.dev_iso),
+                                    sizeof(float) * kIsoChunk * kMaxBatch);
+    e = e != hipSuccess ? e
+                        : hipHostMalloc(reinterpret_cast<void**>(&S.host_fields),
+                                        sizeof(BatchField) * kMaxBatch, hipHostMallocDefault);
+    e = e != hipSuccess ? e
+                        : hipHostMalloc(reinterpret_cast<void**>(&S.host_iso),
+                                        sizeof(float) * kIsoChunk * kMaxBatch,
+                                        hipHostMallocDefault);
+  }
+  srv->slot_bytes = size_t(n_slots) * slot_bytes;
+  srv->account(int64_t(srv->slot_bytes));
+  pdiv_server raw = srv.release();
+  if (e != hipSuccess) {
+    device_status(e, "server create");
+    pdiv_server_destroy(raw);
+    set_error("server create: %s", hipGetErrorString(e));
+    return PDIV_ERR_DEVICE;
+  }
+  raw->worker = std::thread([raw] { raw->run(); });
+  *out = raw;
+  return PDIV_OK;
 }
-pdiv_status pdiv_server_put_field(pdiv_server, uint64_t, const void*, const void*, const void*,
-                                  const void*, pdiv_dtype, int64_t, int64_t, double, double,
-                                  uint64_t*) { return PDIV_ERR_UNSUPPORTED; }
-pdiv_status pdiv_server_submit_lcp(pdiv_server, uint64_t, const float*, int32_t, float*,
-                                   uint64_t*) { return PDIV_ERR_UNSUPPORTED; }
-pdiv_status pdiv_server_wait(pdiv_server, uint64_t, int64_t, pdiv_status*) { return PDIV_ERR_UNSUPPORTED; }
-pdiv_status pdiv_server_stats(pdiv_server, pdiv_server_stats_t*) { return PDIV_ERR_UNSUPPORTED; }
-pdiv_status pdiv_server_destroy(pdiv_server) { return PDIV_ERR_UNSUPPORTED; }
+
+pdiv_status pdiv_server_put_field(pdiv_server srv, uint64_t id, const void* mean_u_host,
+                                  const void* var_u_host, const void* mean_v_host,
+                                  const void* var_v_host, pdiv_dtype dtype, int64_t ny,
+                                  int64_t nx, double dx, double dy, uint64_t* ticket) {
+  g_last_error.clear();
+  if (!srv || !mean_u_host || !var_u_host || !mean_v_host || !var_v_host || !ticket)
+    return invalid("NULL argument");
+  if (dtype != PDIV_F32 && dtype != PDIV_F16 && dtype != PDIV_BF16)
+    return invalid("unknown dtype %d", int(dtype));
+  if (ny < 2 || nx < 2 || ny > (int64_t(1) << 21) || nx > (int64_t(1) << 29))
+    return invalid("bad grid %lld x %lld", (long long)ny, (long long)nx);
+  if (!(std::isfinite(dx) && dx > 0) || !(std::isfinite(dy) && dy > 0))
+    return invalid("dx and dy must be finite and > 0");
+  const size_t n = size_t(ny) * size_t(nx), pb = dtype_bytes(dtype) * n;
+  if (8 * n + 4 * pb + srv->slot_bytes > srv->budget) {
+    set_error("field of %zu points can never fit the %zu-byte budget", n, srv->budget);
+    return PDIV_ERR_BUSY;
+  }
+  std::unique_ptr<Request> r(new Request());
+  {
+    std::lock_guard<std::mutex> g(srv->mu);
+    if (srv->stop) return invalid("server is shutting down");
+    if (srv->fields.count(id)) return invalid("field id %llu is in use", (unsigned long long)id);
+    r->host = srv->get_pinned(4 * pb);
+    if (!r->host) {
+      set_error("cannot allocate %zu bytes of pinned staging", 4 * pb);
+      return PDIV_ERR_NOMEM;
+    }
+    auto f = std::make_unique<ServerField>();
+    f->id = id;
+    f->ny = int(ny);
+    f->nx = int(nx);
+    f->dx = dx;
+    f->dy = dy;
+    f->refs = 1;
+    f->last_use = ++srv->clock;
+    srv->fields[id] = std::move(f);
+  }
+  char* h = static_cast<char*>(r->host->p);
+  std::memcpy(h, mean_u_host, pb);
+  std::memcpy(h + pb, var_u_host, pb);
+  std::memcpy(h + 2 * pb, mean_v_host, pb);
+  std::memcpy(h + 3 * pb, var_v_host, pb);
+  r->kind = Kind::kNew;
+  r->fid = id;
+  r->dtype = dtype;
+  r->ny = int(ny);
+  r->nx = int(nx);
+  r->dx = dx;
+  r->dy = dy;
+  r->t_submit = Clock::now();
+  {
+    std::lock_guard<std::mutex> g(srv->mu);
+    r->ticket = srv->next_ticket++;
+    *ticket = r->ticket;
+    srv->queue.push_back(r.get());
+    srv->tickets[r->ticket] = std::move(r);
+  }
+  srv->cv_work.notify_one();
+  return PDIV_OK;
 }
+
+pdiv_status pdiv_server_submit_lcp(pdiv_server srv, uint64_t id, const float* isovalues_host,
+                                   int32_t n_iso, float* out, uint64_t* ticket) {
+  g_last_error.clear();
+  if (!srv || !isovalues_host || !out || !ticket) return invalid("NULL argument");
+  if (n_iso < 1 || n_iso > kIsoChunk) return invalid("n_iso must be in [1, %d]", kIsoChunk);
+  std::unique_ptr<Request> r(new Request());
+  r->kind = Kind::kSlider;
+  r->fid = id;
+  r->n_iso = n_iso;
+  for (int q = 0; q < kIsoChunk; ++q) r->iso[q] = isovalues_host[q < n_iso ? q : n_iso - 1];
+  r->out = out;
+  r->t_submit = Clock::now();
+  {
+    std::lock_guard<std::mutex> g(srv->mu);
+    if (srv->stop) return invalid("server is shutting down");
+    auto f = srv->fields.find(id);
+    if (f == srv->fields.end())
+      return invalid("field id %llu is not resident", (unsigned long long)id);
+    f->second->refs++;
+    r->ticket = srv->next_ticket++;
+    *ticket = r->ticket;
+    srv->queue.push_back(r.get());
+    srv->tickets[r->ticket] = std::move(r);
+  }
+  srv->cv_work.notify_one();
+  return PDIV_OK;
+}
+
+pdiv_status pdiv_server_wait(pdiv_server srv, uint64_t ticket, int64_t timeout_us,
+                             pdiv_status* result) {
+  g_last_error.clear();
+  if (!srv || !result) return invalid("NULL argument");
+  std::unique_lock<std::mutex> lk(srv->mu);
+  auto it = srv->tickets.find(ticket);
+  if (it == srv->tickets.end()) return invalid("unknown ticket %llu", (unsigned long long)ticket);
+  Request* r = it->second.get();
+  if (timeout_us < 0) {
+    srv->cv_done.wait(lk, [&] { return r->done; });
+  } else if (!srv->cv_done.wait_for(lk, std::chrono::microseconds(timeout_us),
+                                    [&] { return r->done; })) {
+    return PDIV_ERR_TIMEOUT;
+  }
+  *result = r->status;
+  srv->tickets.erase(it);
+  return PDIV_OK;
+}
+
+pdiv_status pdiv_server_stats(pdiv_server srv, pdiv_server_stats_t* out) {
+  g_last_error.clear();
+  if (!srv || !out) return invalid("NULL argument");
+  std::lock_guard<std::mutex> g(srv->mu);
+  std::vector<double> all = srv->lat_new;
+  all.insert(all.end(), srv->lat_slider.begin(), srv->lat_slider.end());
+  out->done = srv->done;
+  out->failed = srv->failed;
+  out->launches = srv->launches;
+  out->p50_us = pct(all, 0.50);
+  out->p99_us = pct(all, 0.99);
+  out->p50_new_us = pct(srv->lat_new, 0.50);
+  out->p99_new_us = pct(srv->lat_new, 0.99);
+  out->p50_slider_us = pct(srv->lat_slider, 0.50);
+  out->p99_slider_us = pct(srv->lat_slider, 0.99);
+  out->lcp_cells = srv->cells;
+  out->resident_bytes = srv->resident;
+  out->peak_bytes = srv->peak;
+  return PDIV_OK;
+}
+
+pdiv_status pdiv_server_destroy(pdiv_server srv) {
+  g_last_error.clear();
+  if (!srv) return invalid("server is NULL");
+  {
+    std::lock_guard<std::mutex> g(srv->mu);
+    srv->stop = true;
+  }
+  srv->cv_work.notify_all();
+  if (srv->worker.joinable()) srv->worker.join();
+  for (auto& kv : srv->fields) {
+    if (kv.second->dmean) (void)hipFreeAsync(kv.second->dmean, srv->upload);
+    if (kv.second->dvar) (void)hipFreeAsync(kv.second->dvar, srv->upload);
+  }
+  if (srv->upload) (void)hipStreamSynchronize(srv->upload);
+  for (auto& S : srv->slots) {
+    if (S.dev_fields) (void)hipFree(S.dev_fields);
+    if (S.dev_iso) (void)hipFree(S.dev_iso);
+    if (S.host_fields) (void)hipHostFree(S.host_fields);
+    if (S.host_iso) (void)hipHostFree(S.host_iso);
+  }
+  for (auto& b : srv->pinned) (void)hipHostFree(b->p);
+  for (hipStream_t s : srv->streams) (void)hipStreamDestroy(s);
+  if (srv->upload) (void)hipStreamDestroy(srv->upload);
+  delete srv;
+  return PDIV_OK;
+}
+
+}  // extern "C"
