@@ -80,6 +80,167 @@ def time_launches(fn, n, torch):
     return start.elapsed_time(stop) / n / 1e3
 
 
+def batch_leg(P, synth, torch, np):
+    """512 fields of uneven size (sides log-uniform in [64, 2048]), 4 isovalues
+    each: one persistent launch (autotuned, graph-replayed) against 512
+    separate fused launches on one stream."""
+    log("batch leg: generating 512 fields")
+    F = synth.config_c4()
+    fields, outs_pf = [], []
+    for f in F:
+        d = {k: torch.from_numpy(f[k]).float().cuda() for k in ("mean_u", "var_u", "mean_v", "var_v")}
+        d["isovalues"] = torch.from_numpy(f["isovalues"]).cuda()
+        d["iso_host"] = f["isovalues"]
+        fields.append(d)
+        outs_pf.append(torch.empty((4, f["ny"] - 1, f["nx"] - 1), device="cuda"))
+    cells = sum(4 * (f["ny"] - 1) * (f["nx"] - 1) for f in F)
+    in_bytes = sum(16 * f["ny"] * f["nx"] for f in F)
+
+    def per_field():
+        for d, o in zip(fields, outs_pf):
+            P.lcp_from_moments(d["mean_u"], d["var_u"], d["mean_v"], d["var_v"], d["iso_host"], out=o)
+
+    per_field()
+    t_pf = time_launches(per_field, 3, torch)
+    log("batch leg: autotuning the persistent launch")
+    plain = P.Batch(fields, graph=False)
+    plain.launch()
+    t_plain = time_launches(plain.launch, 10, torch)
+    b = P.Batch(fields, graph=True, autotune=True)
+    b.launch()
+    t_b = time_launches(b.launch, 10, torch)
+    torch.cuda.synchronize()
+    same = all(torch.equal(o, g["lcp"]) for o, g in zip(outs_pf, b.fields))
+    info = b.info()
+    plain.close()
+    b.close()
+    return {"fields": len(F), "lcp_values": cells,
+            "per_field_launches_ms": round(t_pf * 1e3, 3),
+            "batch_ms": round(t_plain * 1e3, 3),
+            "batch_graph_autotuned_ms": round(t_b * 1e3, 3),
+            "speedup_vs_per_field": round(t_pf / t_b, 2),
+            "cells_per_s": round(cells / t_b, 1),
+            "achieved_GBs": round((in_bytes + 4 * cells) / t_b / 1e9, 1),
+            "tile": info, "bitwise_equal_to_per_field": bool(same)}
+
+
+def served_leg(P, synth, torch, np):
+    """Poisson request stream: 70% isovalue-slider requests (1-4 isovalues) on
+    resident fields, 30% new float32 square fields with sides log-uniform in
+    [256, 4096].  Capacity is measured with every request submitted at once;
+    the stream then runs at 50% and 90% of it.  The same requests handled one
+    at a time with per-request launches give the baseline."""
+    import time as _t
+    log("served leg: preparing the field pool")
+    sides = [256, 445, 776, 1351, 2353, 4096]
+    pool = {}
+    for s_ in sides:
+        f = synth.gen_moments(s_, s_, synth.SEED_BASE + 5 + s_, n_features=max(1, s_ * s_ // 65536))
+        pool[s_] = [f[k].astype(np.float32) for k in ("mean_u", "var_u", "mean_v", "var_v")]
+    budget = 24 << 30
+    n_req = 1200
+
+    def stream(rate, seed):
+        return synth.request_stream(n_req, rate, seed)
+
+    ring = {s_: [torch.empty((4, s_ - 1, s_ - 1), device="cuda") for _ in range(8)]
+            for s_ in sides}
+
+    def run(reqs, paced):
+        srv = P.Server(hbm_budget=budget, n_streams=4)
+        resident, tickets = [], []
+        last = {}  # (side, ring slot) -> ticket of the request writing it
+        used = {s_: 0 for s_ in sides}
+        next_id = 0
+        # two fields resident before the clock starts so sliders have targets
+        for s_ in (776, 2353):
+            srv.wait(srv.put_field(next_id, *pool[s_]))
+            resident.append((next_id, s_))
+            next_id += 1
+        t0 = _t.perf_counter()
+        for r in reqs:
+            if paced:
+                while _t.perf_counter() - t0 < r["t"]:
+                    pass
+            if r["kind"] == "new":
+                side = min(sides, key=lambda s_: abs(np.log(s_ / r["side"])))
+                tickets.append(srv.put_field(next_id, *pool[side]))
+                resident.append((next_id, side))
+                next_id += 1
+            else:
+                fid, side = resident[int(r["pick"] * len(resident))]
+                iso = (r["iso_u"] - 0.5).astype(np.float32) * 0.05
+                slot = used[side] % len(ring[side])
+                used[side] += 1
+                if (side, slot) in last:  # the buffer's previous writer must be done
+                    srv.wait(last.pop((side, slot)))
+                o = ring[side][slot][: len(iso)]
+                try:
+                    t = srv.submit_lcp(fid, iso, o)
+                    last[(side, slot)] = t
+                    tickets.append(t)
+                except P.PdivError:  # evicted: resubmit it as a new field
+                    tickets.append(srv.put_field(next_id, *pool[side]))
+                    resident.append((next_id, side))
+                    next_id += 1
+        for t in tickets:
+            try:
+                srv.wait(t)
+            except P.PdivError:  # already waited on when its ring slot was reused
+                pass
+        wall = _t.perf_counter() - t0
+        st = srv.stats()
+        srv.close()
+        return wall, st
+
+    reqs = stream(1e9, 11)  # back to back: capacity
+    wall, st = run(reqs, paced=False)
+    capacity = n_req / wall
+    out = {"requests": n_req, "budget_bytes": budget, "n_streams": 4,
+           "capacity_req_per_s": round(capacity, 1),
+           "capacity_lcp_cells_per_s": round(st["lcp_cells"] / wall, 1)}
+    for frac in (0.5, 0.9):
+        rate = frac * capacity
+        wall, st = run(stream(rate, 12), paced=True)
+        out[f"at_{int(frac * 100)}pct"] = {
+            "rate_req_per_s": round(rate, 1), "failed": st["failed"],
+            "p50_us": round(st["p50_us"], 1), "p99_us": round(st["p99_us"], 1),
+            "p50_slider_us": round(st["p50_slider_us"], 1),
+            "p99_slider_us": round(st["p99_slider_us"], 1),
+            "p50_new_us": round(st["p50_new_us"], 1), "p99_new_us": round(st["p99_new_us"], 1),
+            "launches": st["launches"], "peak_bytes": st["peak_bytes"],
+            "throughput_req_per_s": round(n_req / wall, 1)}
+    # baseline: the same back-to-back stream, one request at a time
+    log("served leg: one-request-at-a-time baseline")
+    res = {}
+    t0 = _t.perf_counter()
+    nid = 0
+    for s_ in (776, 2353):
+        ts = [torch.from_numpy(p).cuda() for p in pool[s_]]
+        res[nid] = (P.divergence_gaussian(*ts), s_)
+        nid += 1
+    torch.cuda.synchronize()
+    t0 = _t.perf_counter()
+    order = list(res)
+    for r in reqs:
+        if r["kind"] == "new":
+            side = min(sides, key=lambda s_: abs(np.log(s_ / r["side"])))
+            ts = [torch.from_numpy(p).cuda() for p in pool[side]]
+            res[nid] = (P.divergence_gaussian(*ts), side)
+            order.append(nid)
+            nid += 1
+        else:
+            fid = order[int(r["pick"] * len(order))]
+            (dm, dv), side = res[fid]
+            iso = (r["iso_u"] - 0.5).astype(np.float32) * 0.05
+            P.lcp(dm, dv, iso)
+        torch.cuda.synchronize()
+    base = _t.perf_counter() - t0
+    out["one_at_a_time_req_per_s"] = round(n_req / base, 1)
+    out["served_speedup_vs_one_at_a_time"] = round(capacity * base / n_req, 2)
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -89,6 +250,8 @@ def main():
     ap.add_argument("--no-mc", action="store_true")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--mc-samples", type=int, default=1000)
+    ap.add_argument("--copy-calibration", action="store_true",
+                    help="only run a plain 1 GiB device copy (HBM counter calibration)")
     args = ap.parse_args()
 
     world = int(os.environ.get("WORLD_SIZE", "1"))
@@ -105,6 +268,15 @@ def main():
 
     assert torch.cuda.is_available(), "bench.py needs a GPU"
     torch.cuda.set_device(0)
+    if args.copy_calibration:
+        n = 1 << 28  # 2^28 floats = 1 GiB read and 1 GiB written per copy
+        src = torch.rand(n, device="cuda")
+        dst = torch.empty_like(src)
+        for _ in range(3):
+            dst.copy_(src)
+        torch.cuda.synchronize()
+        print(json.dumps({"copy_bytes_read": 4 * n, "copy_bytes_written": 4 * n, "copies": 3}))
+        return
     P.lib()  # fail loudly if the library is missing
 
     log("generating the 8192x8192 field (seeded)")
@@ -228,6 +400,10 @@ def main():
         legs["pipeline_fit_then_lcp_721x1440_m50_k8"] = {"ms": round(t * 1e3, 4),
                                                         "cells_per_s": round(720 * 1439 * 8 / t, 1)}
         del u, v, outs, c2out
+        torch.cuda.empty_cache()
+        legs["batch_512_fields_k4"] = batch_leg(P, synth, torch, np)
+        torch.cuda.empty_cache()
+        legs["served_stream"] = served_leg(P, synth, torch, np)
         result["legs"] = legs
 
     if not args.no_cpu_baseline:

@@ -11,8 +11,9 @@
 // (B, B+1), taking the right-hand pairs from lane L+1 by lane shuffles.  Lanes
 // 0..62 store; each of the two stores writes 63 consecutive cells of one
 // output row, which keeps the write stream contiguous (stride-2 lane patterns
-// through buffer stores cost a factor of three in write bandwidth).  The next
-// row's input loads are issued before the current row is computed.
+// through buffer stores cost a factor of three in write bandwidth); stores
+// are masked by their buffer record range, not by branches.  The next row's
+// input loads are issued before the current row is computed.
 #pragma once
 
 #include "pdiv_device.hpp"
@@ -104,31 +105,39 @@ __device__ __forceinline__ Col make_col(uint32_t x, int nx) {
   return c;
 }
 
+// Lane L receives lane L+1's value (DPP wave_shl:1; lane 63 receives 0 and
+// stores nothing).  A register move in the vector ALU, no LDS round trip.
+__device__ __forceinline__ float from_right(float v) {
+  constexpr int kWaveShl1 = 0x130;
+  return __int_as_float(__builtin_amdgcn_mov_dpp(__float_as_int(v), kWaveShl1, 0xf, 0xf, true));
+}
+
 __device__ __forceinline__ Pair pair_from_right(const Pair& p) {
   Pair r;
-  r.pa = __shfl_down(p.pa, 1, kWave);
-  r.qa = __shfl_down(p.qa, 1, kWave);
-  r.pb = __shfl_down(p.pb, 1, kWave);
-  r.qb = __shfl_down(p.qb, 1, kWave);
+  r.pa = from_right(p.pa);
+  r.qa = from_right(p.qa);
+  r.pb = from_right(p.pb);
+  r.qb = from_right(p.qb);
   return r;
 }
 
 // One vertex row step: the corners of row j+1 (from raw values loaded one
 // step earlier) for the lane's two columns, their pairs with row j (prev_*),
 // and the lane's two cells for every isovalue; the new corners go to next_*.
-// xa is the lane's A column; its B column is xa + 63.
+// off_a, off_b are the byte offsets of the lane's two cells within a row.
 template <int KC, bool FUSED>
 __device__ __forceinline__ void row_step(const Raw<FUSED>& raw_a, const Raw<FUSED>& raw_b,
                                          const Col& ca_col, const Col& cb_col, int ny, int nx,
                                          const StencilCoef& k, const IsoChunk& iso,
                                          int n_store, float* __restrict__ out, int64_t plane,
                                          int j,
-                                         uint32_t xa, bool store_a, bool store_b,
+                                         uint32_t off_a, uint32_t off_b,
                                          const AB (&prev_a)[KC], const AB (&prev_b)[KC],
                                          AB (&next_a)[KC], AB (&next_b)[KC]) {
   const Corner ca = make_corner(raw_div(raw_a, ca_col.bx, j + 1, ny, k));
   const Corner cb = make_corner(raw_div(raw_b, cb_col.bx, j + 1, ny, k));
   float* __restrict__ orow = out + static_cast<int64_t>(j) * (nx - 1);
+  const uint32_t row_bytes = uint32_t(nx - 1) * 4u;
 #pragma unroll
   for (int q = 0; q < KC; ++q) {
     const AB cur_a = corner_probs(ca, iso.c[q]);
@@ -137,11 +146,10 @@ __device__ __forceinline__ void row_step(const Raw<FUSED>& raw_a, const Raw<FUSE
     const Pair pb = make_pair(prev_b[q], cur_b);
     const float l0 = cell_lcp(pa, pair_from_right(pa), cur_a.below);
     const float l1 = cell_lcp(pb, pair_from_right(pb), cur_b.below);
-    if (q < n_store) {
-      const RowWriter w(orow + q * plane);
-      if (store_a) w.put(l0, xa * 4u);
-      if (store_b) w.put(l1, (xa + kHalf) * 4u);
-    }
+    // planes past n_store (a batch's padding) get an empty record range
+    const RowWriter w(orow + q * plane, q < n_store ? row_bytes : 0u);
+    w.put(l0, off_a);
+    w.put(l1, off_b);
     next_a[q] = cur_a;
     next_b[q] = cur_b;
   }
@@ -164,8 +172,12 @@ __device__ __forceinline__ void lcp_tile(const T* __restrict__ p0, const T* __re
   const uint32_t last = uint32_t(nx - 1);
   const Col ca = make_col(xa < last ? xa : last, nx);  // columns past the edge load a
   const Col cb = make_col(xb < last ? xb : last, nx);  // valid column and store nothing
-  const bool store_a = (lane < kHalf) & (xa < last);
-  const bool store_b = (lane < kHalf) & (xb < last);
+  // byte offsets of the lane's two cells in an output row; lane 63 and cells
+  // past the right edge get an offset far beyond any row (rows are < 2^31
+  // bytes), so the buffer hardware drops their stores
+  constexpr uint32_t kDrop = 0x7ffffff0u;
+  const uint32_t off_a = (lane < kHalf) & (xa < last) ? xa * 4u : kDrop;
+  const uint32_t off_b = (lane < kHalf) & (xb < last) ? xb * 4u : kDrop;
 
   AB ra[KC], rb[KC], sa[KC], sb[KC];
   Raw<FUSED> xa0, xb0, xa1, xb1;
@@ -183,23 +195,31 @@ __device__ __forceinline__ void lcp_tile(const T* __restrict__ p0, const T* __re
     }
   }
   // Two rows per trip: the carried corners alternate between two register
-  // sets, and the raw loads of row j+2 are issued before row j+1 is computed.
-  for (int j = j0; j < j1; j += 2) {
-    if (j + 2 <= j1) {
-      load_raw(xa0, p0, p1, p2, p3, ny, nx, ca.x, ca.xl, ca.xr, j + 2);
-      load_raw(xb0, p0, p1, p2, p3, ny, nx, cb.x, cb.xl, cb.xr, j + 2);
-    }
-    row_step<KC, FUSED>(xa1, xb1, ca, cb, ny, nx, k, iso, n_store, out, plane, j, ca.x,
-                        store_a, store_b, ra, rb, sa, sb);
-    if (j + 1 < j1) {
-      if (j + 3 <= j1) {
-        load_raw(xa1, p0, p1, p2, p3, ny, nx, ca.x, ca.xl, ca.xr, j + 3);
-        load_raw(xb1, p0, p1, p2, p3, ny, nx, cb.x, cb.xl, cb.xr, j + 3);
-      }
-      row_step<KC, FUSED>(xa0, xb0, ca, cb, ny, nx, k, iso, n_store, out, plane, j + 1, ca.x,
-                          store_a, store_b, sa, sb, ra, rb);
-    }
+  // sets, and the raw loads of the row after next are issued before the next
+  // row is computed.  A trip has no branches (the prefetch row is clamped to
+  // the band's last row) and the first trip is peeled off the loop, so every
+  // path into the loop body has the same loads and stores in flight and the
+  // compiler waits for exactly the loads a row needs, never for the stores
+  // of the row before.  An odd last row is done after the loop.
+  auto trip = [&](int j) {
+    load_raw(xa0, p0, p1, p2, p3, ny, nx, ca.x, ca.xl, ca.xr, j + 2);
+    load_raw(xb0, p0, p1, p2, p3, ny, nx, cb.x, cb.xl, cb.xr, j + 2);
+    row_step<KC, FUSED>(xa1, xb1, ca, cb, ny, nx, k, iso, n_store, out, plane, j, off_a,
+                        off_b, ra, rb, sa, sb);
+    const int jn = min(j + 3, j1);
+    load_raw(xa1, p0, p1, p2, p3, ny, nx, ca.x, ca.xl, ca.xr, jn);
+    load_raw(xb1, p0, p1, p2, p3, ny, nx, cb.x, cb.xl, cb.xr, jn);
+    row_step<KC, FUSED>(xa0, xb0, ca, cb, ny, nx, k, iso, n_store, out, plane, j + 1, off_a,
+                        off_b, sa, sb, ra, rb);
+  };
+  int j = j0;
+  if (j + 2 <= j1) {
+    trip(j);
+    for (j += 2; j + 2 <= j1; j += 2) trip(j);
   }
+  if (j < j1)  // xa1/xb1 hold row j + 1 == j1
+    row_step<KC, FUSED>(xa1, xb1, ca, cb, ny, nx, k, iso, n_store, out, plane, j, off_a,
+                        off_b, ra, rb, sa, sb);
 }
 
 }  // namespace pdiv

@@ -61,14 +61,17 @@ __device__ __forceinline__ T* at(T* row, uint32_t idx) {
 }
 
 // Streaming float store through a buffer resource: `row` is wave-uniform (the
-// descriptor lives in scalar registers), `byte_off` the per-lane offset.  The
-// store is non-temporal.  Descriptor word 3 is the raw 32-bit buffer format
-// of gfx9-family targets; the record count is unbounded (offsets stay inside
-// the row by construction).
+// descriptor lives in scalar registers), `byte_off` the per-lane offset, and
+// the record count bounds the row: stores at byte offsets >= `bytes` are
+// dropped by the buffer hardware.  Lanes that must not store are pointed at
+// offset `bytes`, so the stores need no branch (a divergent branch around a
+// store makes the compiler wait for every outstanding memory operation,
+// stores included, before the next load can be used).  Descriptor word 3 is
+// the raw 32-bit buffer format of gfx9-family targets.  Non-temporal.
 struct RowWriter {
   __amdgpu_buffer_rsrc_t r;
-  __device__ __forceinline__ explicit RowWriter(float* row)
-      : r(__builtin_amdgcn_make_buffer_rsrc(row, 0, -1, 0x00020000)) {}
+  __device__ __forceinline__ RowWriter(float* row, uint32_t bytes)
+      : r(__builtin_amdgcn_make_buffer_rsrc(row, 0, static_cast<int>(bytes), 0x00020000)) {}
   __device__ __forceinline__ void put(float v, uint32_t byte_off) const {
     constexpr int kNonTemporal = 2;
     __builtin_amdgcn_raw_buffer_store_b32(__float_as_uint(v), r, static_cast<int>(byte_off), 0,
