@@ -125,6 +125,27 @@ __device__ __forceinline__ Pair pair_from_right(const Pair& p) {
 // step earlier) for the lane's two columns, their pairs with row j (prev_*),
 // and the lane's two cells for every isovalue; the new corners go to next_*.
 // off_a, off_b are the byte offsets of the lane's two cells within a row.
+// LCP of the cell whose left column pair is p (this lane) and whose right
+// column pair is lane L+1's p, read through the DPP operand of each
+// instruction (wave_shl:1: lane L reads lane L+1):
+//   up = (Qa + Pa Qa') - Pb Pb' = (1 - A) - B,  dn = (Qb + Pb Qb') - Pa Pa' = (1 - B) - A,
+//   LCP = below ? dn : up   (below: integer mask, all ones if the reference corner is below).
+// s_nop 1 gives the two wait states a DPP read needs after a VALU write of
+// its source register.  qa and qb are consumed in place.
+__device__ __forceinline__ float cell_lcp_dpp(Pair p, int below) {
+  float l;
+  asm volatile(
+      "s_nop 1\n\t"
+      "v_fmac_f32_dpp %1, %1, %3 wave_shl:1 row_mask:0xf bank_mask:0xf\n\t"
+      "v_fmac_f32_dpp %2, %2, %4 wave_shl:1 row_mask:0xf bank_mask:0xf\n\t"
+      "v_fmac_f32_dpp %1, -%4, %4 wave_shl:1 row_mask:0xf bank_mask:0xf\n\t"
+      "v_fmac_f32_dpp %2, -%3, %3 wave_shl:1 row_mask:0xf bank_mask:0xf\n\t"
+      "v_bfi_b32 %0, %5, %2, %1"
+      : "=v"(l), "+v"(p.qa), "+v"(p.qb)
+      : "v"(p.pa), "v"(p.pb), "v"(below));
+  return l;
+}
+
 template <int KC, bool FUSED>
 __device__ __forceinline__ void row_step(const Raw<FUSED>& raw_a, const Raw<FUSED>& raw_b,
                                          const Col& ca_col, const Col& cb_col, int ny, int nx,
@@ -144,8 +165,8 @@ __device__ __forceinline__ void row_step(const Raw<FUSED>& raw_a, const Raw<FUSE
     const AB cur_b = corner_probs(cb, iso.c[q]);
     const Pair pa = make_pair(prev_a[q], cur_a);
     const Pair pb = make_pair(prev_b[q], cur_b);
-    const float l0 = cell_lcp(pa, pair_from_right(pa), cur_a.below);
-    const float l1 = cell_lcp(pb, pair_from_right(pb), cur_b.below);
+    const float l0 = cell_lcp_dpp(pa, cur_a.below);
+    const float l1 = cell_lcp_dpp(pb, cur_b.below);
     // planes past n_store (a batch's padding) get an empty record range
     const RowWriter w(orow + q * plane, q < n_store ? row_bytes : 0u);
     w.put(l0, off_a);

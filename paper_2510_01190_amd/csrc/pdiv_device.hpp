@@ -142,7 +142,7 @@ struct Corner {
 __device__ __forceinline__ Corner make_corner(DivGauss g) {
   constexpr float kTwoLn2 = 1.38629436112f;  // 2 ln 2 = 2 / log2(e)
   Corner c;
-  c.mean = g.mean;
+  c.mean = g.mean + 0.0f;  // -0 becomes +0 (the side test reads the sign bit)
   const bool det = (g.var == 0.0f);
   // rsqrt of a negative variance is NaN, which then propagates to the LCP
   c.rs = det ? 0.0f : rsqrtf(g.var * kTwoLn2);
@@ -151,18 +151,29 @@ __device__ __forceinline__ Corner make_corner(DivGauss g) {
 }
 
 struct AB {
-  float a, b;   // P(above), P(below)
-  bool below;   // mu < c
+  float a, b;  // P(above), P(below)
+  int below;   // all ones if mu < c, else 0
 };
 
+// Bitwise select (m & x) | (~m & y), one v_bfi_b32.  Written as an
+// instruction because the compiler turns the mask expression back into a
+// compare and two conditional moves.
+__device__ __forceinline__ float bit_select(int m, float x, float y) {
+  float r;
+  asm("v_bfi_b32 %0, %1, %2, %3" : "=v"(r) : "v"(m), "v"(x), "v"(y));
+  return r;
+}
+
+// The side test reads the sign bit of d = mu - c.  make_corner stores mu + 0
+// (no -0), so mu == c gives d = +0: above, the >= rule.
 __device__ __forceinline__ AB corner_probs(const Corner& k, float c) {
-  const float d = k.mean - c;  // mu == c gives +0: above, the >= rule
+  const float d = k.mean - c;
   const float q = gauss_tail_scaled(fmaf(fabsf(d), k.rs, k.z0));
   const float s = 1.0f - q;
   AB p;
-  p.below = d < 0.0f;
-  p.a = p.below ? q : s;
-  p.b = p.below ? s : q;
+  p.below = __float_as_int(d) >> 31;
+  p.a = bit_select(p.below, q, s);
+  p.b = bit_select(p.below, s, q);
   return p;
 }
 
