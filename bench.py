@@ -34,7 +34,7 @@ METRIC = "LCP cells/sec & % HBM peak (closed form vs GPU MC) at ≤1e-5 LCP abs 
 HBM_PEAK_GBS = 8000.0
 PROFILE_TRAFFIC = os.path.join(ROOT, "profiles", "lcp_fused_8192x8192_k16_f32_traffic.txt")
 KERNEL_SRC = [os.path.join(ROOT, "paper_2510_01190_amd", "csrc", f)
-              for f in ("k_lcp.hip", "pdiv_device.hpp")]
+              for f in ("k_lcp.hip", "lcp_tile.hpp", "pdiv_device.hpp", "tail_coeffs.hpp")]
 
 
 def log(msg):

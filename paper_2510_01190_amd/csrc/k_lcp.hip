@@ -72,9 +72,14 @@ __global__ __launch_bounds__(kBlock) void lcp_kernel(const T* __restrict__ p0,
                                                      float* __restrict__ out, int64_t plane,
                                                      int band_rows, int n_strips,
                                                      int n_bands) {
+  // Blocks are dealt round-robin to the 8 XCDs (block b runs on XCD b % 8),
+  // each with its own L2.  Give each XCD a contiguous run of tiles, so that
+  // neighbouring strips, whose output rows meet inside a cache line, write
+  // that line through the same L2.  The map is a bijection on [0, gridDim.x).
+  const int nb = gridDim.x, xcd = blockIdx.x % 8, q8 = nb / 8, r8 = nb % 8;
+  const int blk = xcd * q8 + min(xcd, r8) + blockIdx.x / 8;
   // the wave index is uniform: row indices and row base pointers stay scalar
-  const int wave = __builtin_amdgcn_readfirstlane(blockIdx.x * kWavesPerBlock +
-                                                  (threadIdx.x >> 6));
+  const int wave = __builtin_amdgcn_readfirstlane(blk * kWavesPerBlock + (threadIdx.x >> 6));
   const int strip = wave % n_strips;
   const int band = wave / n_strips;
   if (band >= n_bands) return;

@@ -40,8 +40,12 @@ template <int KC, bool FUSED, typename T>
 __global__ __launch_bounds__(kBlock) void batch_kernel(const BatchField* __restrict__ fields,
                                                        int n_fields, int64_t n_tiles,
                                                        int band_rows) {
-  const int64_t wave = __builtin_amdgcn_readfirstlane(blockIdx.x * kWavesPerBlock +
-                                                      (threadIdx.x >> 6));
+  // XCD-aware order, as in the single-field kernel: block b runs on XCD b % 8,
+  // so renumber blocks to give each XCD a contiguous range of wave slots and
+  // hence runs of neighbouring tiles (their output rows share cache lines).
+  const int nb = gridDim.x, xcd = blockIdx.x % 8, q8 = nb / 8, r8 = nb % 8;
+  const int blk = xcd * q8 + min(xcd, r8) + blockIdx.x / 8;
+  const int64_t wave = __builtin_amdgcn_readfirstlane(blk * kWavesPerBlock + (threadIdx.x >> 6));
   const int64_t n_waves = int64_t(gridDim.x) * kWavesPerBlock;
   for (int64_t t = wave; t < n_tiles; t += n_waves) {
     // field of tile t: the last f with fields[f].tile_begin <= t

@@ -67,15 +67,19 @@ __device__ __forceinline__ T* at(T* row, uint32_t idx) {
 // offset `bytes`, so the stores need no branch (a divergent branch around a
 // store makes the compiler wait for every outstanding memory operation,
 // stores included, before the next load can be used).  Descriptor word 3 is
-// the raw 32-bit buffer format of gfx9-family targets.  Non-temporal.
+// the raw 32-bit buffer format of gfx9-family targets.  The stores take the
+// default (temporal) cache policy: a tile's rows start and end inside cache
+// lines that the neighbouring tile also writes, and the partial lines merge in
+// L2 only if they stay there; with the streaming policy the same store
+// pattern runs about 25% slower on gfx950.
 struct RowWriter {
   __amdgpu_buffer_rsrc_t r;
   __device__ __forceinline__ RowWriter(float* row, uint32_t bytes)
       : r(__builtin_amdgcn_make_buffer_rsrc(row, 0, static_cast<int>(bytes), 0x00020000)) {}
   __device__ __forceinline__ void put(float v, uint32_t byte_off) const {
-    constexpr int kNonTemporal = 2;
+    constexpr int kDefaultPolicy = 0;
     __builtin_amdgcn_raw_buffer_store_b32(__float_as_uint(v), r, static_cast<int>(byte_off), 0,
-                                          kNonTemporal);
+                                          kDefaultPolicy);
   }
 };
 
