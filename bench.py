@@ -139,6 +139,7 @@ def served_leg(P, synth, torch, np):
         pool[s_] = [f[k].astype(np.float32) for k in ("mean_u", "var_u", "mean_v", "var_v")]
     budget = 24 << 30
     n_req = 1200
+    n_staging = 6
 
     def stream(rate, seed):
         return synth.request_stream(n_req, rate, seed)
@@ -148,6 +149,9 @@ def served_leg(P, synth, torch, np):
 
     def run(reqs, paced):
         srv = P.Server(hbm_budget=budget, n_streams=4)
+        # pinned staging set aside before the clock starts, as the one-at-a-time
+        # baseline's runtime keeps its own staging buffers warm
+        srv.reserve_staging(max(sides) ** 2, n_staging)
         resident, tickets = [], []
         last = {}  # (side, ring slot) -> ticket of the request writing it
         used = {s_: 0 for s_ in sides}
@@ -197,6 +201,7 @@ def served_leg(P, synth, torch, np):
     wall, st = run(reqs, paced=False)
     capacity = n_req / wall
     out = {"requests": n_req, "budget_bytes": budget, "n_streams": 4,
+           "pinned_staging": f"{n_staging} x {16 * max(sides) ** 2} B reserved before timing",
            "capacity_req_per_s": round(capacity, 1),
            "capacity_lcp_cells_per_s": round(st["lcp_cells"] / wall, 1)}
     for frac in (0.5, 0.9):
@@ -286,7 +291,12 @@ def main():
     K = int(iso.size)
     mom = [torch.from_numpy(c3[k]).float().cuda() for k in ("mean_u", "var_u", "mean_v", "var_v")]
     cells = (ny - 1) * (nx - 1)
-    out = torch.empty((K, ny - 1, nx - 1), dtype=torch.float32, device="cuda")
+    # LCP maps [K][ny-1][nx-1] with each row padded to a multiple of 32 floats
+    # (8191 cells -> pitch 8192, 0.012% more memory), so every row starts on a
+    # 128-byte line and every store writes whole lines; a dense output is
+    # timed as a leg
+    out = P.empty_lcp(K, ny, nx)
+    pitch = out.stride(1)
 
     def step():
         P.lcp_from_moments(*mom, iso, out=out)
@@ -316,7 +326,8 @@ def main():
     traffic = read_traffic()
     roofline = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS,
                 "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4),
-                "traffic": traffic, "kernel": "lcp_kernel<16,true,float> (fused Eq. 2-3 + LCP)",
+                "traffic": traffic,
+                "kernel": "lcp_kernel<16,true,true,float> (fused Eq. 2-3 + LCP, line-aligned rows)",
                 "algorithmic_bytes_per_launch": alg_bytes,
                 "kernel_ms_mean": round(kern_s * 1e3, 4),
                 "kernel_ms_min": round(float(per.min()) * 1e3, 4)}
@@ -328,6 +339,7 @@ def main():
               "scaling": "weak", "vs_baseline": None, "dtype": "f32", "data": "synthetic",
               "config": {"workload": "lcp_from_moments_8192x8192_k16_f32", "ny": ny, "nx": nx,
                          "n_iso": K, "storage": "float32", "cells": cells,
+                         "output_row_pitch_floats": pitch,
                          "path": "fused divergence Gaussian (Eq. 2-3) + closed-form LCP",
                          "parallelism": "single GPU"},
               "roofline": roofline}
@@ -350,6 +362,14 @@ def main():
 
     if not args.no_legs:
         legs = {}
+        dense = torch.empty((K, ny - 1, nx - 1), device="cuda")
+        P.lcp_from_moments(*mom, iso, out=dense)
+        t = time_launches(lambda: P.lcp_from_moments(*mom, iso, out=dense), 10, torch)
+        legs["fused_f32_dense_output_rows"] = {
+            "ms": round(t * 1e3, 4), "cells_per_s": round(cells * K / t, 1),
+            "achieved_GBs": round(alg_bytes / t / 1e9, 1),
+            "bitwise_equal_to_pitched": bool(torch.equal(dense, out))}
+        del dense
         dm = torch.empty((ny, nx), device="cuda")
         dv = torch.empty_like(dm)
         out2 = torch.empty_like(out)
@@ -409,7 +429,7 @@ def main():
     if not args.no_cpu_baseline:
         import oracle as O
 
-        rows = (3328, 4864)
+        rows = (2048, 6144)
         log(f"CPU baseline: FP64 oracle on cell rows {rows[0]}..{rows[1]} (1 thread)")
         stored = [t.double().cpu().numpy() for t in mom]
         t_cpu = 0.0

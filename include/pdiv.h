@@ -101,10 +101,15 @@ pdiv_status pdiv_divergence_gaussian(const void* mean_u, const void* var_u, cons
  * float32 with one Gaussian tail per corner and isovalue and a cancellation-
  * free combination, so cells near 0 and near 1 keep their relative accuracy.
  * div_mean, div_var: [ny][nx] float32; isovalues_host: n_iso floats in host
- * memory, 1 <= n_iso <= PDIV_MAX_ISO; lcp: [n_iso][ny-1][nx-1] float32. */
+ * memory, 1 <= n_iso <= PDIV_MAX_ISO; lcp: n_iso planes of ny-1 rows of nx-1
+ * float32 cells; lcp_row_pitch is the distance between rows in floats (0 or
+ * nx-1: dense; larger values pad each row and are left unwritten), planes
+ * are (ny-1)*pitch floats apart.  A pitch that is a multiple of 32 floats
+ * (128 bytes) lets every store write whole cache lines, which the kernel
+ * needs for its full write bandwidth. */
 pdiv_status pdiv_lcp(const float* div_mean, const float* div_var, int64_t ny, int64_t nx,
                      const float* isovalues_host, int32_t n_iso, float* lcp,
-                     pdiv_stream stream);
+                     int64_t lcp_row_pitch, pdiv_stream stream);
 
 /* (d) Monte Carlo LCP, the paper's comparison (Sections 3.2 and 4): draw
  * n_samples samples of the uncertain vectors at every grid point, take the
@@ -124,12 +129,13 @@ pdiv_status pdiv_mc_lcp(const void* mean_u, const void* var_u, const void* mean_
 
 /* (b)+(c) fused: Eq. 2-3 and the closed-form LCP in one pass over the moment
  * planes; the divergence Gaussians never leave the chip.  Gives bitwise the
- * same LCP as pdiv_divergence_gaussian followed by pdiv_lcp. */
+ * same LCP as pdiv_divergence_gaussian followed by pdiv_lcp; the output
+ * layout and lcp_row_pitch are those of pdiv_lcp. */
 pdiv_status pdiv_lcp_from_moments(const void* mean_u, const void* var_u, const void* mean_v,
                                   const void* var_v, pdiv_dtype in_dtype, int64_t ny,
                                   int64_t nx, double dx, double dy,
                                   const float* isovalues_host, int32_t n_iso, float* lcp,
-                                  pdiv_stream stream);
+                                  int64_t lcp_row_pitch, pdiv_stream stream);
 
 /* Diagnostic: sample s of the uncertain field exactly as pdiv_mc_lcp draws it
  * (same generator, counters and transform): u_s, v_s are [ny][nx] float32. */
@@ -155,7 +161,9 @@ typedef struct pdiv_field {
   const float* isovalues;  /* n_iso float32 isovalues, DEVICE memory, read at each
                               launch (update them between launches to move a slider) */
   int32_t n_iso;           /* 1 .. 16                                             */
-  float* lcp;              /* [n_iso][ny-1][nx-1] float32 output (device)         */
+  float* lcp;              /* float32 output (device): n_iso planes of ny-1 rows  */
+  int64_t lcp_row_pitch;   /* floats between output rows, >= nx-1; 0 = dense;
+                              planes are (ny-1)*pitch floats apart                */
 } pdiv_field;
 
 typedef struct pdiv_batch_s* pdiv_batch;
@@ -208,14 +216,25 @@ typedef struct pdiv_server_stats_t {
 pdiv_status pdiv_server_create(size_t hbm_budget, int32_t n_streams, pdiv_server* out);
 /* New field from host moment planes (pageable or pinned host memory, dtype as
  * given, [ny][nx] each): uploaded, reduced to its divergence Gaussians
- * (Eq. 2-3) and kept resident under id.  The host planes are copied before the
- * call returns.  Returns PDIV_ERR_BUSY if the field can never fit the budget;
+ * (Eq. 2-3) and kept resident under id.  The host planes are copied (on
+ * several threads for large fields) into pinned staging before the call
+ * returns; the call waits while the staging pool is full.  Returns PDIV_ERR_BUSY if the field can never fit the budget;
  * otherwise the request waits for room (evicting least recently used fields
  * that no pending request names). */
 pdiv_status pdiv_server_put_field(pdiv_server srv, uint64_t id, const void* mean_u_host,
                                   const void* var_u_host, const void* mean_v_host,
                                   const void* var_v_host, pdiv_dtype dtype, int64_t ny,
                                   int64_t nx, double dx, double dy, uint64_t* ticket);
+/* Sizes the pinned host staging pool: makes sure it holds `count` free
+ * buffers, each large enough for a new field of up to max_points points of
+ * dtype, and touches their pages, so that pdiv_server_put_field reuses them
+ * instead of allocating.  From then on the pool keeps to the bytes it holds
+ * after this call (by default it grows to 2 GiB): a put_field that finds no
+ * free buffer waits until an upload returns one; only a field larger than
+ * every buffer, with none in use, allocates past that.  Returns
+ * PDIV_ERR_NOMEM if pinned memory runs out. */
+pdiv_status pdiv_server_reserve_staging(pdiv_server srv, int64_t max_points, pdiv_dtype dtype,
+                                        int32_t count);
 /* Slider request: LCP maps of resident field id at n_iso (1..16) isovalues
  * (host array, copied) into out, a device buffer of n_iso*(ny-1)*(nx-1) floats
  * that must stay valid until the ticket completes. */

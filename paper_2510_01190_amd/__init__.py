@@ -21,7 +21,7 @@ import numpy as np
 
 __all__ = [
     "PdivError", "lib", "moments", "divergence_gaussian", "lcp", "lcp_from_moments",
-    "mc_lcp", "mc_sample_field", "Batch", "Server", "STATUS", "MAX_ISO",
+    "mc_lcp", "mc_sample_field", "empty_lcp", "Batch", "Server", "STATUS", "MAX_ISO",
 ]
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
@@ -50,7 +50,7 @@ class PdivError(RuntimeError):
 class _Field(_c.Structure):
     _fields_ = [("mean_u", _p), ("var_u", _p), ("mean_v", _p), ("var_v", _p),
                 ("ny", _i64), ("nx", _i64), ("dx", _f64), ("dy", _f64),
-                ("isovalues", _p), ("n_iso", _i32), ("lcp", _p)]
+                ("isovalues", _p), ("n_iso", _i32), ("lcp", _p), ("lcp_row_pitch", _i64)]
 
 
 class ServerStats(_c.Structure):
@@ -66,9 +66,10 @@ class ServerStats(_c.Structure):
 _SIGS = {
     "pdiv_moments": [_p, _p, _c.c_int, _i64, _i64, _i64, _i64, _i32, _p, _p, _p, _p, _c.c_int, _p],
     "pdiv_divergence_gaussian": [_p, _p, _p, _p, _c.c_int, _i64, _i64, _f64, _f64, _p, _p, _p],
-    "pdiv_lcp": [_p, _p, _i64, _i64, _fp, _i32, _p, _p],
+    "pdiv_lcp": [_p, _p, _i64, _i64, _fp, _i32, _p, _i64, _p],
     "pdiv_mc_lcp": [_p, _p, _p, _p, _c.c_int, _i64, _i64, _f64, _f64, _fp, _i32, _i64, _u64, _p, _p],
-    "pdiv_lcp_from_moments": [_p, _p, _p, _p, _c.c_int, _i64, _i64, _f64, _f64, _fp, _i32, _p, _p],
+    "pdiv_lcp_from_moments": [_p, _p, _p, _p, _c.c_int, _i64, _i64, _f64, _f64, _fp, _i32, _p,
+                              _i64, _p],
     "pdiv_mc_sample_field": [_p, _p, _p, _p, _c.c_int, _i64, _i64, _i64, _u64, _p, _p, _p],
     "pdiv_batch_create": [_c.POINTER(_Field), _i32, _c.c_int, _c.c_uint32, _p, _c.POINTER(_p)],
     "pdiv_batch_launch": [_p, _p],
@@ -77,6 +78,7 @@ _SIGS = {
     "pdiv_server_create": [_c.c_size_t, _i32, _c.POINTER(_p)],
     "pdiv_server_put_field": [_p, _u64, _p, _p, _p, _p, _c.c_int, _i64, _i64, _f64, _f64,
                               _c.POINTER(_u64)],
+    "pdiv_server_reserve_staging": [_p, _i64, _c.c_int, _i32],
     "pdiv_server_submit_lcp": [_p, _u64, _fp, _i32, _p, _c.POINTER(_u64)],
     "pdiv_server_wait": [_p, _u64, _i64, _c.POINTER(_c.c_int)],
     "pdiv_server_stats": [_p, _c.POINTER(ServerStats)],
@@ -144,6 +146,38 @@ def _dev(t, name, shape=None, dtype=None):
     return _p(t.data_ptr())
 
 
+def _lcp_out(t, k, ny, nx):
+    """Pointer and row pitch (floats) of an LCP output: a [k][ny-1][nx-1]
+    float32 device tensor, dense or a view of rows padded to a longer pitch
+    (see empty_lcp)."""
+    if not t.is_cuda:
+        raise ValueError("out must be a device tensor")
+    if t.dtype != _torch().float32:
+        raise ValueError(f"out has dtype {t.dtype}, expected torch.float32")
+    if tuple(t.shape) != (k, ny - 1, nx - 1):
+        raise ValueError(f"out has shape {tuple(t.shape)}, expected {(k, ny - 1, nx - 1)}")
+    s0, s1, s2 = t.stride()
+    pitch = s1 if ny > 2 else (s0 if k > 1 else nx - 1)
+    if s2 != 1 or pitch < nx - 1 or (k > 1 and s0 != (ny - 1) * pitch) or \
+            (ny > 2 and s1 != pitch):
+        raise ValueError("out must be dense or rows of one pitch >= nx-1 with planes "
+                         "(ny-1)*pitch floats apart")
+    return _p(t.data_ptr()), pitch
+
+
+def empty_lcp(k: int, ny: int, nx: int, pitch: int = None, device="cuda"):
+    """Uninitialised LCP output [k][ny-1][nx-1] whose rows are `pitch` floats
+    apart (default: nx-1 rounded up to a multiple of 32 floats, so that every
+    row starts on a 128-byte line).  The padding floats are never written."""
+    torch = _torch()
+    if pitch is None:
+        pitch = (nx - 1 + 31) // 32 * 32
+    if pitch < nx - 1:
+        raise ValueError("pitch must be >= nx - 1")
+    buf = torch.empty((k, ny - 1, pitch), dtype=torch.float32, device=device)
+    return buf[:, :, : nx - 1]
+
+
 def _iso_arr(isovalues):
     iso = np.ascontiguousarray(np.atleast_1d(np.asarray(isovalues, np.float32)))
     return iso, iso.ctypes.data_as(_fp)
@@ -187,7 +221,8 @@ def divergence_gaussian(mean_u, var_u, mean_v, var_v, dx: float = 1.0, dy: float
 
 
 def lcp(div_mean, div_var, isovalues, out=None):
-    """Closed-form LCP [K][ny-1][nx-1] from divergence Gaussians."""
+    """Closed-form LCP [K][ny-1][nx-1] from divergence Gaussians; `out` may be
+    dense or a row-padded view (empty_lcp)."""
     torch = _torch()
     ny, nx = div_mean.shape
     pm = _dev(div_mean, "div_mean", (ny, nx), torch.float32)
@@ -195,21 +230,23 @@ def lcp(div_mean, div_var, isovalues, out=None):
     iso, ip = _iso_arr(isovalues)
     if out is None:
         out = torch.empty((iso.size, ny - 1, nx - 1), dtype=torch.float32, device=div_mean.device)
-    po = _dev(out, "out", (iso.size, ny - 1, nx - 1), torch.float32)
-    _check(lib().pdiv_lcp(pm, pv, ny, nx, ip, iso.size, po, _stream()))
+    po, pitch = _lcp_out(out, iso.size, ny, nx)
+    _check(lib().pdiv_lcp(pm, pv, ny, nx, ip, iso.size, po, pitch, _stream()))
     return out
 
 
 def lcp_from_moments(mean_u, var_u, mean_v, var_v, isovalues, dx: float = 1.0,
                      dy: float = 1.0, out=None):
-    """Fused Eq. 2-3 + closed-form LCP [K][ny-1][nx-1]."""
+    """Fused Eq. 2-3 + closed-form LCP [K][ny-1][nx-1]; `out` may be dense or a
+    row-padded view (empty_lcp)."""
     torch = _torch()
     ptrs, ny, nx, dt = _moment_ptrs(mean_u, var_u, mean_v, var_v)
     iso, ip = _iso_arr(isovalues)
     if out is None:
         out = torch.empty((iso.size, ny - 1, nx - 1), dtype=torch.float32, device=mean_u.device)
-    po = _dev(out, "out", (iso.size, ny - 1, nx - 1), torch.float32)
-    _check(lib().pdiv_lcp_from_moments(*ptrs, dt, ny, nx, dx, dy, ip, iso.size, po, _stream()))
+    po, pitch = _lcp_out(out, iso.size, ny, nx)
+    _check(lib().pdiv_lcp_from_moments(*ptrs, dt, ny, nx, dx, dy, ip, iso.size, po, pitch,
+                                       _stream()))
     return out
 
 
@@ -243,7 +280,8 @@ class Batch:
 
     fields: sequence of dicts with mean_u, var_u, mean_v, var_v (device planes of one
     dtype), isovalues (device float32 tensor, 1..16 values), dx, dy, and optionally
-    lcp (device output [K][ny-1][nx-1]; allocated if absent)."""
+    lcp (device output [K][ny-1][nx-1], dense or a row-padded view; allocated if
+    absent)."""
 
     GRAPH = 1
     AUTOTUNE = 2
@@ -264,10 +302,10 @@ class Batch:
             if out is None:
                 out = torch.empty((iso.numel(), ny - 1, nx - 1), dtype=torch.float32,
                                   device=f["mean_u"].device)
-            _dev(out, "lcp", (iso.numel(), ny - 1, nx - 1), torch.float32)
+            po, pitch = _lcp_out(out, iso.numel(), ny, nx)
             arr[k] = _Field(ptrs[0], ptrs[1], ptrs[2], ptrs[3], ny, nx,
                             float(f.get("dx", 1.0)), float(f.get("dy", 1.0)),
-                            _p(iso.data_ptr()), iso.numel(), _p(out.data_ptr()))
+                            _p(iso.data_ptr()), iso.numel(), po, pitch)
             self.fields.append(dict(f, lcp=out))
         flags = (self.GRAPH if graph else 0) | (self.AUTOTUNE if autotune else 0)
         h = _p()
@@ -311,6 +349,12 @@ class Server:
         _check(lib().pdiv_server_put_field(self._h, fid, *[_p(a.ctypes.data) for a in arrs],
                                            code, ny, nx, dx, dy, _c.byref(t)))
         return t.value
+
+    def reserve_staging(self, max_points: int, count: int, dtype=np.float32):
+        """Pre-allocate and touch `count` pinned staging buffers for fields of up
+        to max_points points."""
+        code = {np.dtype(np.float32): 0, np.dtype(np.float16): 1}[np.dtype(dtype)]
+        _check(lib().pdiv_server_reserve_staging(self._h, max_points, code, count))
 
     def submit_lcp(self, fid: int, isovalues, out) -> int:
         iso, ip = _iso_arr(isovalues)

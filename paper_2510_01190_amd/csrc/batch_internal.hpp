@@ -19,12 +19,13 @@ struct alignas(16) BatchField {
   const void* p1;
   const void* p2;
   const void* p3;
-  float* lcp;          // [n_iso][ny-1][nx-1]
+  float* lcp;          // [n_iso][ny-1] rows of pitch floats
   const float* iso;    // n_iso isovalues (device)
   int ny, nx;
   int n_iso;           // 1..16
   int n_strips;        // filled by fill_tiles
-  int64_t plane;       // (ny-1)(nx-1)
+  int64_t plane;       // (ny-1) pitch
+  int64_t pitch;       // output row pitch in floats, >= nx-1
   int64_t tile_begin;  // first global tile index of the field (fill_tiles)
   StencilCoef coef;
 };

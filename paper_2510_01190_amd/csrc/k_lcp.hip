@@ -25,6 +25,10 @@ static std::atomic<int> g_band_rows_override{0};
 
 void set_band_rows_override(int rows) { g_band_rows_override.store(rows); }
 
+// Rows per band: each band re-reads two halo rows and re-evaluates one corner
+// row, and short bands give more waves to even out the tail of the launch.
+// On gfx950, 8191 x 8191 cells at K = 16 (64 strips): 64-row bands (8192
+// waves) ran 1.26 ms against 1.32 (48 rows), 1.37 (96) and 1.30 (128).
 LcpShape default_lcp_shape(int64_t ny, int64_t nx, int n_iso) {
   (void)nx;
   (void)n_iso;
@@ -52,10 +56,10 @@ __global__ __launch_bounds__(kBlock) void divergence_kernel(const T* __restrict_
   const int j0 = (blockIdx.y * kWavesPerBlock + (threadIdx.x >> 6)) * rows_per_thread;
   if (x >= nx) return;
   const int j1 = min(j0 + rows_per_thread, ny);
-  const Col c = make_col(uint32_t(x), nx);
+  const Col c = make_col(uint32_t(x), nx, sizeof(T));
   for (int j = j0; j < j1; ++j) {
     Raw<true> r;
-    load_raw(r, mu, vu, mv, vv, ny, nx, c.x, c.xl, c.xr, j);
+    load_raw(r, mu, vu, mv, vv, ny, nx, c, j);
     const DivGauss g = raw_div(r, c.bx, j, ny, k);
     const int64_t o = static_cast<int64_t>(j) * nx + x;
     __builtin_nontemporal_store(g.mean, dmean + o);
@@ -63,14 +67,14 @@ __global__ __launch_bounds__(kBlock) void divergence_kernel(const T* __restrict_
   }
 }
 
-template <int KC, bool FUSED, typename T>
+template <int KC, bool FUSED, bool STREAM, typename T>
 __global__ __launch_bounds__(kBlock) void lcp_kernel(const T* __restrict__ p0,
                                                      const T* __restrict__ p1,
                                                      const T* __restrict__ p2,
                                                      const T* __restrict__ p3, int ny, int nx,
                                                      StencilCoef k, IsoChunk iso,
                                                      float* __restrict__ out, int64_t plane,
-                                                     int band_rows, int n_strips,
+                                                     int64_t pitch, int band_rows, int n_strips,
                                                      int n_bands) {
   // Blocks are dealt round-robin to the 8 XCDs (block b runs on XCD b % 8),
   // each with its own L2.  Give each XCD a contiguous run of tiles, so that
@@ -84,36 +88,44 @@ __global__ __launch_bounds__(kBlock) void lcp_kernel(const T* __restrict__ p0,
   const int band = wave / n_strips;
   if (band >= n_bands) return;
   const int j0 = band * band_rows;
-  lcp_tile<KC, FUSED>(p0, p1, p2, p3, ny, nx, k, iso, KC, out, plane, strip, j0,
-                      min(j0 + band_rows, ny - 1));
+  lcp_tile<KC, FUSED, STREAM>(p0, p1, p2, p3, ny, nx, k, iso, KC, out, plane, pitch, strip, j0,
+                              min(j0 + band_rows, ny - 1));
 }
 
 template <int KC, bool FUSED, typename T>
 hipError_t launch_kc(const void* p0, const void* p1, const void* p2, const void* p3, int ny,
                      int nx, const StencilCoef& k, const IsoChunk& iso, float* out,
-                     LcpShape shape, hipStream_t s) {
+                     int64_t pitch, LcpShape shape, hipStream_t s) {
   const int n_strips = (nx - 1 + kCellsPerWave - 1) / kCellsPerWave;
   const int n_bands = (ny - 1 + shape.band_rows - 1) / shape.band_rows;
   const int64_t waves = static_cast<int64_t>(n_strips) * n_bands;
   const unsigned blocks = static_cast<unsigned>((waves + kWavesPerBlock - 1) / kWavesPerBlock);
-  const int64_t plane = static_cast<int64_t>(ny - 1) * (nx - 1);
-  hipLaunchKernelGGL((lcp_kernel<KC, FUSED, T>), dim3(blocks), dim3(kBlock), 0, s,
-                     static_cast<const T*>(p0), static_cast<const T*>(p1),
-                     static_cast<const T*>(p2), static_cast<const T*>(p3), ny, nx, k, iso, out,
-                     plane, shape.band_rows, n_strips, n_bands);
+  const int64_t plane = static_cast<int64_t>(ny - 1) * pitch;
+  // every row of every plane starts on a 128-byte line: whole-line stores
+  const bool lines = (reinterpret_cast<uintptr_t>(out) % 128 == 0) && (pitch % 32 == 0);
+  if (lines)
+    hipLaunchKernelGGL((lcp_kernel<KC, FUSED, true, T>), dim3(blocks), dim3(kBlock), 0, s,
+                       static_cast<const T*>(p0), static_cast<const T*>(p1),
+                       static_cast<const T*>(p2), static_cast<const T*>(p3), ny, nx, k, iso, out,
+                       plane, pitch, shape.band_rows, n_strips, n_bands);
+  else
+    hipLaunchKernelGGL((lcp_kernel<KC, FUSED, false, T>), dim3(blocks), dim3(kBlock), 0, s,
+                       static_cast<const T*>(p0), static_cast<const T*>(p1),
+                       static_cast<const T*>(p2), static_cast<const T*>(p3), ny, nx, k, iso, out,
+                       plane, pitch, shape.band_rows, n_strips, n_bands);
   return hipGetLastError();
 }
 
 template <bool FUSED, typename T>
 hipError_t launch_any(const void* p0, const void* p1, const void* p2, const void* p3, int ny,
                       int nx, const StencilCoef& k, const IsoChunk& iso, int kc, float* out,
-                      LcpShape shape, hipStream_t s) {
+                      int64_t pitch, LcpShape shape, hipStream_t s) {
   switch (kc) {
-    case 1: return launch_kc<1, FUSED, T>(p0, p1, p2, p3, ny, nx, k, iso, out, shape, s);
-    case 2: return launch_kc<2, FUSED, T>(p0, p1, p2, p3, ny, nx, k, iso, out, shape, s);
-    case 4: return launch_kc<4, FUSED, T>(p0, p1, p2, p3, ny, nx, k, iso, out, shape, s);
-    case 8: return launch_kc<8, FUSED, T>(p0, p1, p2, p3, ny, nx, k, iso, out, shape, s);
-    case 16: return launch_kc<16, FUSED, T>(p0, p1, p2, p3, ny, nx, k, iso, out, shape, s);
+    case 1: return launch_kc<1, FUSED, T>(p0, p1, p2, p3, ny, nx, k, iso, out, pitch, shape, s);
+    case 2: return launch_kc<2, FUSED, T>(p0, p1, p2, p3, ny, nx, k, iso, out, pitch, shape, s);
+    case 4: return launch_kc<4, FUSED, T>(p0, p1, p2, p3, ny, nx, k, iso, out, pitch, shape, s);
+    case 8: return launch_kc<8, FUSED, T>(p0, p1, p2, p3, ny, nx, k, iso, out, pitch, shape, s);
+    case 16: return launch_kc<16, FUSED, T>(p0, p1, p2, p3, ny, nx, k, iso, out, pitch, shape, s);
   }
   return hipErrorInvalidValue;
 }
@@ -155,17 +167,17 @@ hipError_t launch_divergence(const void* mu, const void* vu, const void* mv, con
 hipError_t launch_lcp(bool fused, const void* p0, const void* p1, const void* p2,
                       const void* p3, pdiv_dtype dt, int64_t ny, int64_t nx,
                       const StencilCoef& k, const IsoChunk& iso, int kc, float* lcp_k0,
-                      LcpShape shape, hipStream_t s) {
+                      int64_t pitch, LcpShape shape, hipStream_t s) {
   const int iny = static_cast<int>(ny), inx = static_cast<int>(nx);
   if (!fused)
-    return launch_any<false, float>(p0, p1, p2, p3, iny, inx, k, iso, kc, lcp_k0, shape, s);
+    return launch_any<false, float>(p0, p1, p2, p3, iny, inx, k, iso, kc, lcp_k0, pitch, shape, s);
   switch (dt) {
     case PDIV_F32:
-      return launch_any<true, float>(p0, p1, p2, p3, iny, inx, k, iso, kc, lcp_k0, shape, s);
+      return launch_any<true, float>(p0, p1, p2, p3, iny, inx, k, iso, kc, lcp_k0, pitch, shape, s);
     case PDIV_F16:
-      return launch_any<true, __half>(p0, p1, p2, p3, iny, inx, k, iso, kc, lcp_k0, shape, s);
+      return launch_any<true, __half>(p0, p1, p2, p3, iny, inx, k, iso, kc, lcp_k0, pitch, shape, s);
     case PDIV_BF16:
-      return launch_any<true, bf16_t>(p0, p1, p2, p3, iny, inx, k, iso, kc, lcp_k0, shape, s);
+      return launch_any<true, bf16_t>(p0, p1, p2, p3, iny, inx, k, iso, kc, lcp_k0, pitch, shape, s);
   }
   return hipErrorInvalidValue;
 }

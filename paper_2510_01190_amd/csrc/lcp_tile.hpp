@@ -2,18 +2,25 @@
 // probability of Section 3.1), shared by the single-field kernel and the
 // batched persistent kernel so that both give bitwise the same maps.
 //
-// A wave owns 127 vertex columns x0..x0+126, i.e. the 126 cells between
-// them, over a band of cell rows.  Lane L holds two vertex columns, A = x0 + L
-// and B = x0 + 63 + L (lane 63's A column repeats lane 0's B column), and
-// walks down the band one vertex row at a time.  For each isovalue it
-// evaluates each corner's tail once per row, pairs it with the previous row's
-// (vertical pairs, kept in registers) and forms the cells (A, A+1) and
-// (B, B+1), taking the right-hand pairs from lane L+1 by lane shuffles.  Lanes
-// 0..62 store; each of the two stores writes 63 consecutive cells of one
-// output row, which keeps the write stream contiguous (stride-2 lane patterns
-// through buffer stores cost a factor of three in write bandwidth); stores
-// are masked by their buffer record range, not by branches.  The next row's
-// input loads are issued before the current row is computed.
+// A wave owns the 128 cells [x0, x0+128) of a band of cell rows, x0 = 128
+// strip, i.e. the vertex columns x0..x0+128.  Lane L holds the two adjacent
+// columns E = x0+2L and O = x0+2L+1 and walks down the band one vertex row at
+// a time.  For each isovalue it evaluates each corner's tail once per row,
+// pairs it with the previous row's (vertical pairs, kept in registers) and
+// forms cell 2L from its own two columns and cell 2L+1 from its O column and
+// lane L+1's E column, read through DPP.  The 129th column x0+128, right
+// neighbour of lane 63's last cell, belongs to no lane: a seam step per row
+// has lanes 2q and 2q+1 evaluate columns x0+127 and x0+128 at isovalue q, so
+// lane 2q forms cell x0+127 for isovalue q with the same arithmetic, and lane
+// 63 takes it over with one readlane/writelane per isovalue (about 7% more
+// vector ALU work at 16 isovalues).  Each lane writes its two cells with one
+// 8-byte store, so one store instruction covers 512 contiguous bytes of an
+// output row: whole 128-byte lines when the row pitch is a multiple of 32
+// floats.  On gfx950 such stores sustain about 5.4 TB/s, against about 4.4 TB/s
+// for 126-cell strips of 4-byte stores whose lines are shared between waves.
+// Stores are masked by their buffer record range (checked per dword), not
+// by branches.  The next row's input loads are issued before the current row
+// is computed.
 #pragma once
 
 #include "pdiv_device.hpp"
@@ -22,8 +29,7 @@
 namespace pdiv {
 
 constexpr int kWave = 64;
-constexpr int kHalf = kWave - 1;          // cells per half-strip
-constexpr int kCellsPerWave = 2 * kHalf;  // 126
+constexpr int kCellsPerWave = 2 * kWave;  // 128
 
 // The values one vertex reads: for the fused path the U neighbours along x
 // and the V neighbours along y of Eq. 2-3 (boundary-clamped), for the
@@ -41,36 +47,81 @@ struct Raw<false> {
   float mean, var;
 };
 
-// Row pointers are formed from the (wave-uniform) row index first, so each
-// load is a scalar base plus a 32-bit per-lane column offset.
+// Neighbour columns of x for the x differences, clamped at the boundary, as
+// byte offsets into a row of elements of `size` bytes.
+struct Col {
+  uint32_t x, xl, xr;  // byte offsets
+  bool bx;             // x is a boundary column
+};
+__device__ __forceinline__ Col make_col(uint32_t x, int nx, uint32_t size) {
+  const uint32_t last = uint32_t(nx - 1);
+  Col c;
+  c.x = x * size;
+  c.xl = (x > 0 ? x - 1 : 0) * size;
+  c.xr = (x < last ? x + 1 : last) * size;
+  c.bx = (x == 0) | (x == last);
+  return c;
+}
+
+// Input rows are read through buffer resources: the row base lives in
+// scalar registers and each lane supplies its column's 32-bit byte offset,
+// which is fixed for the whole walk, so a load needs no per-lane 64-bit
+// address arithmetic (and no address registers).
+template <typename T>
+struct RowReader {
+  __amdgpu_buffer_rsrc_t r;
+  __device__ __forceinline__ RowReader(const T* row, int nx)
+      : r(__builtin_amdgcn_make_buffer_rsrc(const_cast<T*>(row), 0,
+                                            static_cast<int>(uint32_t(nx) * sizeof(T)),
+                                            0x00020000)) {}
+  __device__ __forceinline__ float get(uint32_t byte_off) const;
+};
+template <>
+__device__ __forceinline__ float RowReader<float>::get(uint32_t o) const {
+  return __uint_as_float(__builtin_amdgcn_raw_buffer_load_b32(r, static_cast<int>(o), 0, 0));
+}
+template <>
+__device__ __forceinline__ float RowReader<__half>::get(uint32_t o) const {
+  return __half2float(__ushort_as_half(
+      __builtin_amdgcn_raw_buffer_load_b16(r, static_cast<int>(o), 0, 0)));
+}
+template <>
+__device__ __forceinline__ float RowReader<bf16_t>::get(uint32_t o) const {
+  return __uint_as_float(
+      static_cast<uint32_t>(__builtin_amdgcn_raw_buffer_load_b16(r, static_cast<int>(o), 0, 0))
+      << 16);
+}
+
 template <typename T>
 __device__ __forceinline__ void load_raw(Raw<true>& r, const T* __restrict__ mu,
                                          const T* __restrict__ vu, const T* __restrict__ mv,
-                                         const T* __restrict__ vv, int ny, int nx, uint32_t x,
-                                         uint32_t xl, uint32_t xr, int j) {
+                                         const T* __restrict__ vv, int ny, int nx,
+                                         const Col& c, int j) {
   const int yl = j > 0 ? j - 1 : 0;
   const int yr = j < ny - 1 ? j + 1 : ny - 1;
-  const int64_t r0 = static_cast<int64_t>(j) * nx;
-  const int64_t rl = static_cast<int64_t>(yl) * nx;
-  const int64_t rr = static_cast<int64_t>(yr) * nx;
-  r.mu_l = to_f32(*at(mu + r0, xl));
-  r.mu_r = to_f32(*at(mu + r0, xr));
-  r.vu_l = to_f32(*at(vu + r0, xl));
-  r.vu_r = to_f32(*at(vu + r0, xr));
-  r.mv_l = to_f32(*at(mv + rl, x));
-  r.mv_r = to_f32(*at(mv + rr, x));
-  r.vv_l = to_f32(*at(vv + rl, x));
-  r.vv_r = to_f32(*at(vv + rr, x));
+  const RowReader<T> u0(mu + static_cast<int64_t>(j) * nx, nx);
+  const RowReader<T> w0(vu + static_cast<int64_t>(j) * nx, nx);
+  const RowReader<T> ul(mv + static_cast<int64_t>(yl) * nx, nx);
+  const RowReader<T> ur(mv + static_cast<int64_t>(yr) * nx, nx);
+  const RowReader<T> wl(vv + static_cast<int64_t>(yl) * nx, nx);
+  const RowReader<T> wr(vv + static_cast<int64_t>(yr) * nx, nx);
+  r.mu_l = u0.get(c.xl);
+  r.mu_r = u0.get(c.xr);
+  r.vu_l = w0.get(c.xl);
+  r.vu_r = w0.get(c.xr);
+  r.mv_l = ul.get(c.x);
+  r.mv_r = ur.get(c.x);
+  r.vv_l = wl.get(c.x);
+  r.vv_r = wr.get(c.x);
 }
 
 template <typename T>
 __device__ __forceinline__ void load_raw(Raw<false>& r, const T* __restrict__ dm,
                                          const T* __restrict__ dv, const T* __restrict__,
-                                         const T* __restrict__, int, int nx, uint32_t x,
-                                         uint32_t, uint32_t, int j) {
-  const int64_t r0 = static_cast<int64_t>(j) * nx;
-  r.mean = to_f32(*at(dm + r0, x));
-  r.var = to_f32(*at(dv + r0, x));
+                                         const T* __restrict__, int, int nx, const Col& c,
+                                         int j) {
+  r.mean = RowReader<T>(dm + static_cast<int64_t>(j) * nx, nx).get(c.x);
+  r.var = RowReader<T>(dv + static_cast<int64_t>(j) * nx, nx).get(c.x);
 }
 
 // Eq. 2-3 at vertex (x, j) with the one-sided differences of Eq. 1 on the
@@ -90,48 +141,30 @@ __device__ __forceinline__ DivGauss raw_div(const Raw<false>& r, bool, int, int,
   return g;
 }
 
-// Neighbour columns of x for the x differences, clamped at the boundary.
-struct Col {
-  uint32_t x, xl, xr;
-  bool bx;
-};
-__device__ __forceinline__ Col make_col(uint32_t x, int nx) {
-  const uint32_t last = uint32_t(nx - 1);
-  Col c;
-  c.x = x;
-  c.xl = x > 0 ? x - 1 : 0;
-  c.xr = x < last ? x + 1 : last;
-  c.bx = (x == 0) | (x == last);
-  return c;
+
+// Cell LCP from the vertical pairs of its left (l) and right (r) columns:
+//   1 - A = Qa_l + Pa_l Qa_r,  1 - B = Qb_l + Pb_l Qb_r,  A = Pa_l Pa_r,  B = Pb_l Pb_r,
+//   LCP = below ? (1 - B) - A : (1 - A) - B
+// (below: integer mask, all ones if the cell's reference corner, the left
+// column's corner in the lower row of the walk, is below the isovalue).  The
+// form subtracts the product that is at most the smaller tail, so the result
+// keeps its relative accuracy for LCP near 0 and near 1.
+__device__ __forceinline__ float cell_lcp_local(const Pair& l, const Pair& r, int below) {
+  float ua = fmaf(l.pa, r.qa, l.qa);
+  float ub = fmaf(l.pb, r.qb, l.qb);
+  ua = fmaf(-l.pb, r.pb, ua);
+  ub = fmaf(-l.pa, r.pa, ub);
+  return bit_select(below, ub, ua);
 }
 
-// Lane L receives lane L+1's value (DPP wave_shl:1; lane 63 receives 0 and
-// stores nothing).  A register move in the vector ALU, no LDS round trip.
-__device__ __forceinline__ float from_right(float v) {
-  constexpr int kWaveShl1 = 0x130;
-  return __int_as_float(__builtin_amdgcn_mov_dpp(__float_as_int(v), kWaveShl1, 0xf, 0xf, true));
-}
-
-__device__ __forceinline__ Pair pair_from_right(const Pair& p) {
-  Pair r;
-  r.pa = from_right(p.pa);
-  r.qa = from_right(p.qa);
-  r.pb = from_right(p.pb);
-  r.qb = from_right(p.qb);
-  return r;
-}
-
-// One vertex row step: the corners of row j+1 (from raw values loaded one
-// step earlier) for the lane's two columns, their pairs with row j (prev_*),
-// and the lane's two cells for every isovalue; the new corners go to next_*.
-// off_a, off_b are the byte offsets of the lane's two cells within a row.
-// LCP of the cell whose left column pair is p (this lane) and whose right
-// column pair is lane L+1's p, read through the DPP operand of each
-// instruction (wave_shl:1: lane L reads lane L+1):
-//   up = (Qa + Pa Qa') - Pb Pb' = (1 - A) - B,  dn = (Qb + Pb Qb') - Pa Pa' = (1 - B) - A,
-//   LCP = below ? dn : up   (below: integer mask, all ones if the reference corner is below).
+// The same cell formula with the right column in lane L+1, read through the
+// DPP operand of each instruction (wave_shl:1: lane L reads lane L+1; lane
+// 63 has no source lane and leaves its result undefined).  cell_lcp_dpp reads
+// the right pair from the same registers as the left (the seam step);
+// cell_lcp_dpp_next takes the left pair from this lane's O column (o) and
+// the right one from lane L+1's E column (e).
 // s_nop 1 gives the two wait states a DPP read needs after a VALU write of
-// its source register.  qa and qb are consumed in place.
+// its source register.  The left pair's qa and qb are consumed in place.
 __device__ __forceinline__ float cell_lcp_dpp(Pair p, int below) {
   float l;
   asm volatile(
@@ -146,101 +179,143 @@ __device__ __forceinline__ float cell_lcp_dpp(Pair p, int below) {
   return l;
 }
 
-template <int KC, bool FUSED>
-__device__ __forceinline__ void row_step(const Raw<FUSED>& raw_a, const Raw<FUSED>& raw_b,
-                                         const Col& ca_col, const Col& cb_col, int ny, int nx,
-                                         const StencilCoef& k, const IsoChunk& iso,
-                                         int n_store, float* __restrict__ out, int64_t plane,
-                                         int j,
-                                         uint32_t off_a, uint32_t off_b,
-                                         const AB (&prev_a)[KC], const AB (&prev_b)[KC],
-                                         AB (&next_a)[KC], AB (&next_b)[KC]) {
-  const Corner ca = make_corner(raw_div(raw_a, ca_col.bx, j + 1, ny, k));
-  const Corner cb = make_corner(raw_div(raw_b, cb_col.bx, j + 1, ny, k));
-  float* __restrict__ orow = out + static_cast<int64_t>(j) * (nx - 1);
-  const uint32_t row_bytes = uint32_t(nx - 1) * 4u;
+__device__ __forceinline__ float cell_lcp_dpp_next(Pair o, const Pair& e, int below) {
+  float l;
+  asm volatile(
+      "s_nop 1\n\t"
+      "v_fmac_f32_dpp %1, %3, %5 wave_shl:1 row_mask:0xf bank_mask:0xf\n\t"
+      "v_fmac_f32_dpp %2, %4, %6 wave_shl:1 row_mask:0xf bank_mask:0xf\n\t"
+      "v_fmac_f32_dpp %1, -%7, %6 wave_shl:1 row_mask:0xf bank_mask:0xf\n\t"
+      "v_fmac_f32_dpp %2, -%8, %5 wave_shl:1 row_mask:0xf bank_mask:0xf\n\t"
+      "v_bfi_b32 %0, %9, %2, %1"
+      : "=v"(l), "+v"(o.qa), "+v"(o.qb)
+      : "v"(e.qa), "v"(e.qb), "v"(o.pa), "v"(o.pb), "v"(e.pb), "v"(e.pa), "v"(below));
+  return l;
+}
+
+// v with lane 63 replaced by the wave-uniform value s (v_writelane_b32; the
+// lane select is an inline constant, so the SGPR written by the readlane
+// that produces s is only a data operand and needs no wait states).
+__device__ __forceinline__ float to_lane63(float v, int s) {
+  asm("v_writelane_b32 %0, %1, 63" : "+v"(v) : "s"(s));
+  return v;
+}
+
+// One vertex row step: the corners of row j+1 (from raw values loaded
+// earlier) for the lane's columns E and O and its seam column, their pairs
+// with row j (cor_*, which then take row j+1's corners), and the lane's two
+// cells for every isovalue.  off is the byte offset of the lane's first cell
+// within an output row.
+template <int KC, bool FUSED, bool STREAM>
+__device__ __forceinline__ void row_step(const Raw<FUSED>& raw_e, const Raw<FUSED>& raw_o,
+                                         const Raw<FUSED>& raw_s, const Col& ce, const Col& co,
+                                         const Col& cs, int ny, const StencilCoef& k,
+                                         const IsoChunk& iso, float c_seam, int n_store,
+                                         float* __restrict__ out, int64_t plane, int64_t pitch,
+                                         uint32_t row_bytes, int j, uint32_t off,
+                                         AB (&cor_e)[KC], AB (&cor_o)[KC], AB& cor_s) {
+  const Corner ke = make_corner(raw_div(raw_e, ce.bx, j + 1, ny, k));
+  const Corner ko = make_corner(raw_div(raw_o, co.bx, j + 1, ny, k));
+  const Corner ks = make_corner(raw_div(raw_s, cs.bx, j + 1, ny, k));
+  // seam: lane 2q holds cell x0+127 at isovalue q
+  const AB cur_s = corner_probs(ks, c_seam);
+  const float seam = cell_lcp_dpp(make_pair(cor_s, cur_s), cur_s.below);
+  cor_s = cur_s;
+  float* __restrict__ orow = out + static_cast<int64_t>(j) * pitch;
 #pragma unroll
   for (int q = 0; q < KC; ++q) {
-    const AB cur_a = corner_probs(ca, iso.c[q]);
-    const AB cur_b = corner_probs(cb, iso.c[q]);
-    const Pair pa = make_pair(prev_a[q], cur_a);
-    const Pair pb = make_pair(prev_b[q], cur_b);
-    const float l0 = cell_lcp_dpp(pa, cur_a.below);
-    const float l1 = cell_lcp_dpp(pb, cur_b.below);
+    const AB cur_e = corner_probs(ke, iso.c[q]);
+    const AB cur_o = corner_probs(ko, iso.c[q]);
+    const Pair pe = make_pair(cor_e[q], cur_e);
+    const Pair po = make_pair(cor_o[q], cur_o);
+    const float l_e = cell_lcp_local(pe, po, cur_e.below);
+    float l_o = cell_lcp_dpp_next(po, pe, cur_o.below);
+    l_o = to_lane63(l_o, __builtin_amdgcn_readlane(__float_as_int(seam), 2 * q));
     // planes past n_store (a batch's padding) get an empty record range
-    const RowWriter w(orow + q * plane, q < n_store ? row_bytes : 0u);
-    w.put(l0, off_a);
-    w.put(l1, off_b);
-    next_a[q] = cur_a;
-    next_b[q] = cur_b;
+    const RowWriter<STREAM> w(orow + q * plane, q < n_store ? row_bytes : 0u);
+    w.put2(l_e, l_o, off);
+    cor_e[q] = cur_e;
+    cor_o[q] = cur_o;
   }
 }
 
-// One tile: cell columns [x0, x0+126) of strip `strip` (x0 = 126 strip),
+// One tile: cell columns [x0, x0+128) of strip `strip` (x0 = 128 strip),
 // cell rows [j0, j1), for the KC isovalues in `iso`; only the first n_store
-// isovalue planes are written (a batch pads its isovalue set to KC).  Must be
-// called with wave-uniform arguments by all 64 lanes of a wave.
-template <int KC, bool FUSED, typename T>
+// isovalue planes are written (a batch pads its isovalue set to KC).  Output
+// row j of plane q starts at out + q plane + j pitch.  Must be called with
+// wave-uniform arguments by all 64 lanes of a wave; KC <= 32.  STREAM: store
+// with the non-temporal policy (for outputs whose rows start on 128-byte lines).
+template <int KC, bool FUSED, bool STREAM, typename T>
 __device__ __forceinline__ void lcp_tile(const T* __restrict__ p0, const T* __restrict__ p1,
                                          const T* __restrict__ p2, const T* __restrict__ p3,
                                          int ny, int nx, const StencilCoef& k,
                                          const IsoChunk& iso, int n_store,
-                                         float* __restrict__ out, int64_t plane, int strip,
-                                         int j0, int j1) {
+                                         float* __restrict__ out, int64_t plane, int64_t pitch,
+                                         int strip, int j0, int j1) {
+  static_assert(2 * KC <= kWave, "the seam step needs two lanes per isovalue");
   const uint32_t lane = threadIdx.x & 63;
-  const uint32_t xa = uint32_t(strip * kCellsPerWave) + lane;  // A column
-  const uint32_t xb = xa + kHalf;                               // B column
-  const uint32_t last = uint32_t(nx - 1);
-  const Col ca = make_col(xa < last ? xa : last, nx);  // columns past the edge load a
-  const Col cb = make_col(xb < last ? xb : last, nx);  // valid column and store nothing
-  // byte offsets of the lane's two cells in an output row; lane 63 and cells
-  // past the right edge get an offset far beyond any row (rows are < 2^31
-  // bytes), so the buffer hardware drops their stores
+  const uint32_t last = uint32_t(nx - 1);                      // also the cell count
+  const uint32_t xe = uint32_t(strip) * kCellsPerWave + 2 * lane;  // E column
+  const uint32_t xs = uint32_t(strip) * kCellsPerWave + (kCellsPerWave - 1) + (lane & 1);
+  // columns past the edge load a valid column and store nothing
+  const Col ce = make_col(min(xe, last), nx, sizeof(T));
+  const Col co = make_col(min(xe + 1, last), nx, sizeof(T));
+  const Col cs = make_col(min(xs, last), nx, sizeof(T));
+  // cells past the right edge: an offset beyond any row (rows are < 2^31
+  // bytes) drops the store; the record range drops a lone second cell
   constexpr uint32_t kDrop = 0x7ffffff0u;
-  const uint32_t off_a = (lane < kHalf) & (xa < last) ? xa * 4u : kDrop;
-  const uint32_t off_b = (lane < kHalf) & (xb < last) ? xb * 4u : kDrop;
+  const uint32_t off = xe < last ? xe * 4u : kDrop;
+  const uint32_t row_bytes = last * 4u;
+  // isovalue of the lane's seam evaluation: q = L / 2
+  const int qs = min(int(lane >> 1), KC - 1);
+  float c_seam = iso.c[0];
+#pragma unroll
+  for (int q = 1; q < KC; ++q) c_seam = (qs == q) ? iso.c[q] : c_seam;
 
-  AB ra[KC], rb[KC], sa[KC], sb[KC];
-  Raw<FUSED> xa0, xb0, xa1, xb1;
-  load_raw(xa0, p0, p1, p2, p3, ny, nx, ca.x, ca.xl, ca.xr, j0);
-  load_raw(xb0, p0, p1, p2, p3, ny, nx, cb.x, cb.xl, cb.xr, j0);
-  load_raw(xa1, p0, p1, p2, p3, ny, nx, ca.x, ca.xl, ca.xr, j0 + 1);
-  load_raw(xb1, p0, p1, p2, p3, ny, nx, cb.x, cb.xl, cb.xr, j0 + 1);
+  // Corners of the walk's current vertex row, per isovalue; each row step
+  // consumes them and leaves the next row's in their place.
+  AB pe[KC], po[KC], ps;
+  Raw<FUSED> e0, o0, s0, e1, o1, s1;
+  auto load3 = [&](Raw<FUSED>& re, Raw<FUSED>& ro, Raw<FUSED>& rs_, int j) {
+    load_raw(re, p0, p1, p2, p3, ny, nx, ce, j);
+    load_raw(ro, p0, p1, p2, p3, ny, nx, co, j);
+    load_raw(rs_, p0, p1, p2, p3, ny, nx, cs, j);
+  };
+  auto step = [&](const Raw<FUSED>& re, const Raw<FUSED>& ro, const Raw<FUSED>& rs_, int j) {
+    row_step<KC, FUSED, STREAM>(re, ro, rs_, ce, co, cs, ny, k, iso, c_seam, n_store, out, plane, pitch,
+                        row_bytes, j, off, pe, po, ps);
+  };
+  load3(e0, o0, s0, j0);
+  load3(e1, o1, s1, j0 + 1);
   {
-    const Corner c0 = make_corner(raw_div(xa0, ca.bx, j0, ny, k));
-    const Corner c1 = make_corner(raw_div(xb0, cb.bx, j0, ny, k));
+    const Corner c0 = make_corner(raw_div(e0, ce.bx, j0, ny, k));
+    const Corner c1 = make_corner(raw_div(o0, co.bx, j0, ny, k));
+    const Corner c2 = make_corner(raw_div(s0, cs.bx, j0, ny, k));
 #pragma unroll
     for (int q = 0; q < KC; ++q) {
-      ra[q] = corner_probs(c0, iso.c[q]);
-      rb[q] = corner_probs(c1, iso.c[q]);
+      pe[q] = corner_probs(c0, iso.c[q]);
+      po[q] = corner_probs(c1, iso.c[q]);
     }
+    ps = corner_probs(c2, c_seam);
   }
-  // Two rows per trip: the carried corners alternate between two register
-  // sets, and the raw loads of the row after next are issued before the next
-  // row is computed.  A trip has no branches (the prefetch row is clamped to
-  // the band's last row) and the first trip is peeled off the loop, so every
-  // path into the loop body has the same loads and stores in flight and the
-  // compiler waits for exactly the loads a row needs, never for the stores
-  // of the row before.  An odd last row is done after the loop.
+  // Two rows per trip: the raw loads of the row after next are issued before
+  // the next row is computed.  A trip has no branches (the prefetch row is
+  // clamped to the band's last row) and the first trip is peeled off the
+  // loop, so every path into the loop body has the same loads and stores in
+  // flight and the compiler waits for exactly the loads a row needs, never
+  // for the stores of the row before.  An odd last row is done after the loop.
   auto trip = [&](int j) {
-    load_raw(xa0, p0, p1, p2, p3, ny, nx, ca.x, ca.xl, ca.xr, j + 2);
-    load_raw(xb0, p0, p1, p2, p3, ny, nx, cb.x, cb.xl, cb.xr, j + 2);
-    row_step<KC, FUSED>(xa1, xb1, ca, cb, ny, nx, k, iso, n_store, out, plane, j, off_a,
-                        off_b, ra, rb, sa, sb);
-    const int jn = min(j + 3, j1);
-    load_raw(xa1, p0, p1, p2, p3, ny, nx, ca.x, ca.xl, ca.xr, jn);
-    load_raw(xb1, p0, p1, p2, p3, ny, nx, cb.x, cb.xl, cb.xr, jn);
-    row_step<KC, FUSED>(xa0, xb0, ca, cb, ny, nx, k, iso, n_store, out, plane, j + 1, off_a,
-                        off_b, sa, sb, ra, rb);
+    load3(e0, o0, s0, j + 2);
+    step(e1, o1, s1, j);
+    load3(e1, o1, s1, min(j + 3, j1));
+    step(e0, o0, s0, j + 1);
   };
   int j = j0;
   if (j + 2 <= j1) {
     trip(j);
     for (j += 2; j + 2 <= j1; j += 2) trip(j);
   }
-  if (j < j1)  // xa1/xb1 hold row j + 1 == j1
-    row_step<KC, FUSED>(xa1, xb1, ca, cb, ny, nx, k, iso, n_store, out, plane, j, off_a,
-                        off_b, ra, rb, sa, sb);
+  if (j < j1) step(e1, o1, s1, j);  // e1.. hold row j + 1 == j1
 }
 
 }  // namespace pdiv

@@ -62,9 +62,9 @@ __global__ __launch_bounds__(kBlock) void batch_kernel(const BatchField* __restr
 #pragma unroll
     for (int q = 0; q < KC; ++q) iso.c[q] = F.iso[q < F.n_iso ? q : F.n_iso - 1];
     const int j0 = band * band_rows;
-    lcp_tile<KC, FUSED>(static_cast<const T*>(F.p0), static_cast<const T*>(F.p1),
+    lcp_tile<KC, FUSED, false>(static_cast<const T*>(F.p0), static_cast<const T*>(F.p1),
                         static_cast<const T*>(F.p2), static_cast<const T*>(F.p3), F.ny, F.nx,
-                        F.coef, iso, F.n_iso, F.lcp, F.plane, strip, j0,
+                        F.coef, iso, F.n_iso, F.lcp, F.plane, F.pitch, strip, j0,
                         min(j0 + band_rows, F.ny - 1));
   }
 }
@@ -309,6 +309,10 @@ pdiv_status pdiv_batch_create(const pdiv_field* fields_host, int32_t n_fields, p
       return invalid("field %d: dx and dy must be finite and > 0", i);
     if (f.n_iso < 1 || f.n_iso > kIsoChunk)
       return invalid("field %d: n_iso must be in [1, %d]", i, kIsoChunk);
+    const int64_t pitch = f.lcp_row_pitch == 0 ? f.nx - 1 : f.lcp_row_pitch;
+    if (pitch < f.nx - 1 || pitch > ((int64_t(1) << 54) / (f.ny - 1)) / kIsoChunk)
+      return invalid("field %d: lcp_row_pitch must be 0 or in [nx - 1, 2^54 / ((ny - 1) 16)]",
+                     i);
     BatchField& x = fv[i];
     x.p0 = f.mean_u;
     x.p1 = f.var_u;
@@ -319,7 +323,8 @@ pdiv_status pdiv_batch_create(const pdiv_field* fields_host, int32_t n_fields, p
     x.ny = static_cast<int>(f.ny);
     x.nx = static_cast<int>(f.nx);
     x.n_iso = f.n_iso;
-    x.plane = (f.ny - 1) * (f.nx - 1);
+    x.pitch = pitch;
+    x.plane = (f.ny - 1) * pitch;
     x.coef = make_coef(f.dx, f.dy);
     kc = std::max(kc, iso_bucket(f.n_iso));
   }

@@ -34,8 +34,8 @@ struct StencilCoef {
 };
 StencilCoef make_coef(double dx, double dy);
 
-// Tile shape of the column-walking LCP kernels: one wave covers 64 vertex
-// columns (63 cells) of a band of `band_rows` cell rows.
+// Tile shape of the column-walking LCP kernels: one wave covers 128 cells
+// (129 vertex columns) of a band of `band_rows` cell rows.
 struct LcpShape {
   int band_rows;
 };
@@ -52,10 +52,11 @@ hipError_t launch_divergence(const void* mu, const void* vu, const void* mv, con
 
 // LCP for isovalues [k0, k0+kc) (kc <= 16): from divergence Gaussians
 // (fused = false, planes dmean/dvar as float) or from moments (fused = true).
+// Output rows are `pitch` floats apart, planes (ny-1) pitch.
 hipError_t launch_lcp(bool fused, const void* p0, const void* p1, const void* p2,
                       const void* p3, pdiv_dtype dt, int64_t ny, int64_t nx,
                       const StencilCoef& k, const IsoChunk& iso, int kc, float* lcp_k0,
-                      LcpShape shape, hipStream_t s);
+                      int64_t pitch, LcpShape shape, hipStream_t s);
 
 hipError_t launch_mc(const void* mu, const void* vu, const void* mv, const void* vv,
                      pdiv_dtype dt, int64_t ny, int64_t nx, const StencilCoef& k,

@@ -40,6 +40,41 @@ namespace {
 constexpr int kMaxBatch = 512;   // slider requests per launch
 constexpr int kBandRows = 16;    // tile height of server launches
 constexpr int kMaxStreams = 8;
+// Pinned staging buffers come in power-of-two size classes from 1 MiB up and
+// are reused; the pool grows until it holds kDefaultPinnedCap bytes (or, after
+// pdiv_server_reserve_staging, what it held then), after which a new field
+// waits for a buffer to come back.  Fresh pinned pages fault on first touch (a few GB/s),
+// so a pool that keeps growing under load costs far more than the copies.
+constexpr size_t kPinnedClassMin = size_t(1) << 20;
+constexpr size_t kDefaultPinnedCap = size_t(2) << 30;
+constexpr int kCopyThreads = 4;            // host copy into staging
+constexpr size_t kParallelCopyMin = size_t(8) << 20;
+
+size_t pinned_class(size_t bytes) {
+  size_t c = kPinnedClassMin;
+  while (c < bytes) c <<= 1;
+  return c;
+}
+
+// Copies (or, with src == nullptr, zero-fills) n_parts spans of `part` bytes,
+// dst + i*part <- src[i], on up to kCopyThreads threads: one thread reaches
+// about a third of the host-to-device DMA rate.
+void staged_copy(char* dst, const void* const* src, int n_parts, size_t part) {
+  const size_t total = part * size_t(n_parts);
+  const int nt = total >= kParallelCopyMin ? kCopyThreads : 1;
+  auto job = [&](int t) {
+    for (int i = 0; i < n_parts; ++i) {
+      const size_t lo = part * size_t(t) / nt, hi = part * size_t(t + 1) / nt;
+      char* d = dst + size_t(i) * part + lo;
+      if (src) std::memcpy(d, static_cast<const char*>(src[i]) + lo, hi - lo);
+      else std::memset(d, 0, hi - lo);
+    }
+  };
+  std::vector<std::thread> th;
+  for (int t = 1; t < nt; ++t) th.emplace_back(job, t);
+  job(0);
+  for (auto& x : th) x.join();
+}
 
 size_t dtype_bytes(pdiv_dtype d) { return d == PDIV_F32 ? 4 : 2; }
 
@@ -135,6 +170,7 @@ struct pdiv_server_s {
   std::unordered_map<uint64_t, std::unique_ptr<Request>> tickets;
   std::vector<Launch> inflight;
   std::vector<std::unique_ptr<PinnedBuf>> pinned;
+  size_t pinned_total = 0, pinned_cap = kDefaultPinnedCap;
   uint64_t next_ticket = 1;
   uint64_t clock = 0;
   int next_stream = 0;
@@ -152,22 +188,56 @@ struct pdiv_server_s {
   }
 
   // --- pinned host staging (reused, released at destroy) -------------------
-  PinnedBuf* get_pinned(size_t bytes) {
-    PinnedBuf* best = nullptr;
-    for (auto& b : pinned)
-      if (!b->busy && b->bytes >= bytes && (!best || b->bytes < best->bytes)) best = b.get();
-    if (!best) {
-      auto b = std::make_unique<PinnedBuf>();
-      if (hipHostMalloc(&b->p, bytes, hipHostMallocDefault) != hipSuccess) {
-        (void)hipGetLastError();
-        return nullptr;
-      }
-      b->bytes = bytes;
-      best = b.get();
-      pinned.push_back(std::move(b));
+  PinnedBuf* alloc_pinned(size_t cls) {
+    auto b = std::make_unique<PinnedBuf>();
+    if (hipHostMalloc(&b->p, cls, hipHostMallocDefault) != hipSuccess) {
+      (void)hipGetLastError();
+      return nullptr;
     }
-    best->busy = true;
-    return best;
+    b->bytes = cls;
+    pinned_total += cls;
+    pinned.push_back(std::move(b));
+    return pinned.back().get();
+  }
+
+  bool any_pinned_busy() const {
+    for (auto& b : pinned)
+      if (b->busy) return true;
+    return false;
+  }
+
+  // Called with mu held through lk.  Takes the smallest free buffer that
+  // fits; else allocates within the cap, first releasing free buffers that
+  // are too small; else waits for an upload to hand one back.  With nothing
+  // busy the pool may pass the cap once, for a field larger than the cap.
+  PinnedBuf* get_pinned(size_t bytes, std::unique_lock<std::mutex>& lk) {
+    const size_t cls = pinned_class(bytes);
+    while (true) {
+      PinnedBuf* best = nullptr;
+      for (auto& b : pinned)
+        if (!b->busy && b->bytes >= cls && (!best || b->bytes < best->bytes)) best = b.get();
+      if (!best) {
+        for (size_t i = 0; i < pinned.size() && pinned_total + cls > pinned_cap;) {
+          if (!pinned[i]->busy) {
+            (void)hipHostFree(pinned[i]->p);
+            pinned_total -= pinned[i]->bytes;
+            pinned.erase(pinned.begin() + i);
+          } else {
+            ++i;
+          }
+        }
+        if (pinned_total + cls <= pinned_cap || !any_pinned_busy()) {
+          best = alloc_pinned(cls);
+          if (!best) return nullptr;
+        }
+      }
+      if (best) {
+        best->busy = true;
+        return best;
+      }
+      if (stop) return nullptr;
+      cv_done.wait_for(lk, std::chrono::milliseconds(1));
+    }
   }
 
   void finish(Request* r, pdiv_status st) {
@@ -322,7 +392,8 @@ struct pdiv_server_s {
         x.ny = f->ny;
         x.nx = f->nx;
         x.n_iso = r->n_iso;
-        x.plane = int64_t(f->ny - 1) * (f->nx - 1);
+        x.pitch = f->nx - 1;
+        x.plane = int64_t(f->ny - 1) * x.pitch;
         x.coef = make_coef(f->dx, f->dy);
         std::memcpy(S.host_iso + i * kIsoChunk, r->iso, sizeof(float) * kIsoChunk);
         kc = std::max(kc, iso_bucket(r->n_iso));
@@ -468,13 +539,17 @@ pdiv_status pdiv_server_put_field(pdiv_server srv, uint64_t id, const void* mean
   }
   std::unique_ptr<Request> r(new Request());
   {
-    std::lock_guard<std::mutex> g(srv->mu);
+    std::unique_lock<std::mutex> lk(srv->mu);
     if (srv->stop) return invalid("server is shutting down");
     if (srv->fields.count(id)) return invalid("field id %llu is in use", (unsigned long long)id);
-    r->host = srv->get_pinned(4 * pb);
+    r->host = srv->get_pinned(4 * pb, lk);
     if (!r->host) {
       set_error("cannot allocate %zu bytes of pinned staging", 4 * pb);
       return PDIV_ERR_NOMEM;
+    }
+    if (srv->fields.count(id)) {  // taken while this call waited for staging
+      r->host->busy = false;
+      return invalid("field id %llu is in use", (unsigned long long)id);
     }
     auto f = std::make_unique<ServerField>();
     f->id = id;
@@ -486,11 +561,8 @@ pdiv_status pdiv_server_put_field(pdiv_server srv, uint64_t id, const void* mean
     f->last_use = ++srv->clock;
     srv->fields[id] = std::move(f);
   }
-  char* h = static_cast<char*>(r->host->p);
-  std::memcpy(h, mean_u_host, pb);
-  std::memcpy(h + pb, var_u_host, pb);
-  std::memcpy(h + 2 * pb, mean_v_host, pb);
-  std::memcpy(h + 3 * pb, var_v_host, pb);
+  const void* const planes[4] = {mean_u_host, var_u_host, mean_v_host, var_v_host};
+  staged_copy(static_cast<char*>(r->host->p), planes, 4, pb);
   r->kind = Kind::kNew;
   r->fid = id;
   r->dtype = dtype;
@@ -507,6 +579,41 @@ pdiv_status pdiv_server_put_field(pdiv_server srv, uint64_t id, const void* mean
     srv->tickets[r->ticket] = std::move(r);
   }
   srv->cv_work.notify_one();
+  return PDIV_OK;
+}
+
+pdiv_status pdiv_server_reserve_staging(pdiv_server srv, int64_t max_points, pdiv_dtype dtype,
+                                        int32_t count) {
+  g_last_error.clear();
+  if (!srv) return invalid("server is NULL");
+  if (dtype != PDIV_F32 && dtype != PDIV_F16 && dtype != PDIV_BF16)
+    return invalid("unknown dtype %d", int(dtype));
+  if (max_points < 4 || max_points > (int64_t(1) << 40) || count < 1 || count > 64)
+    return invalid("max_points must be in [4, 2^40] and count in [1, 64]");
+  const size_t cls = pinned_class(4 * dtype_bytes(dtype) * size_t(max_points));
+  std::vector<PinnedBuf*> fresh;
+  {
+    std::lock_guard<std::mutex> g(srv->mu);
+    if (srv->stop) return invalid("server is shutting down");
+    int have = 0;
+    for (auto& b : srv->pinned)
+      if (!b->busy && b->bytes >= cls) ++have;
+    for (int i = have; i < count; ++i) {
+      PinnedBuf* b = srv->alloc_pinned(cls);
+      if (!b) {
+        set_error("cannot allocate %zu bytes of pinned staging", cls);
+        return PDIV_ERR_NOMEM;
+      }
+      b->busy = true;  // held while its pages are touched below
+      fresh.push_back(b);
+    }
+    srv->pinned_cap = srv->pinned_total;  // the pool is now sized by the caller
+  }
+  for (PinnedBuf* b : fresh) staged_copy(static_cast<char*>(b->p), nullptr, 1, b->bytes);
+  {
+    std::lock_guard<std::mutex> g(srv->mu);
+    for (PinnedBuf* b : fresh) b->busy = false;
+  }
   return PDIV_OK;
 }
 

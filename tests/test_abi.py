@@ -61,14 +61,17 @@ def _expect_invalid(status, fragment):
 def test_lcp_rejects_bad_arguments():
     L = P.lib()
     keep, ip = _iso([0.1, 0.2])
-    _expect_invalid(L.pdiv_lcp(FAKE, FAKE, 1, 8, ip, 2, FAKE, NUL), "at least 2x2")
-    _expect_invalid(L.pdiv_lcp(FAKE, FAKE, 8, 1, ip, 2, FAKE, NUL), "at least 2x2")
-    _expect_invalid(L.pdiv_lcp(NUL, FAKE, 8, 8, ip, 2, FAKE, NUL), "div_mean is NULL")
-    _expect_invalid(L.pdiv_lcp(FAKE, FAKE, 8, 8, ip, 2, NUL, NUL), "lcp is NULL")
-    _expect_invalid(L.pdiv_lcp(FAKE, FAKE, 8, 8, ip, 0, FAKE, NUL), "n_iso")
-    _expect_invalid(L.pdiv_lcp(FAKE, FAKE, 8, 8, ip, 257, FAKE, NUL), "n_iso")
-    _expect_invalid(L.pdiv_lcp(FAKE, FAKE, 8, 8, None, 2, FAKE, NUL), "isovalues_host")
-    _expect_invalid(L.pdiv_lcp(FAKE, FAKE, 1 << 22, 8, ip, 2, FAKE, NUL), "too large")
+    _expect_invalid(L.pdiv_lcp(FAKE, FAKE, 1, 8, ip, 2, FAKE, 0, NUL), "at least 2x2")
+    _expect_invalid(L.pdiv_lcp(FAKE, FAKE, 8, 1, ip, 2, FAKE, 0, NUL), "at least 2x2")
+    _expect_invalid(L.pdiv_lcp(NUL, FAKE, 8, 8, ip, 2, FAKE, 0, NUL), "div_mean is NULL")
+    _expect_invalid(L.pdiv_lcp(FAKE, FAKE, 8, 8, ip, 2, NUL, 0, NUL), "lcp is NULL")
+    _expect_invalid(L.pdiv_lcp(FAKE, FAKE, 8, 8, ip, 0, FAKE, 0, NUL), "n_iso")
+    _expect_invalid(L.pdiv_lcp(FAKE, FAKE, 8, 8, ip, 257, FAKE, 0, NUL), "n_iso")
+    _expect_invalid(L.pdiv_lcp(FAKE, FAKE, 8, 8, None, 2, FAKE, 0, NUL), "isovalues_host")
+    _expect_invalid(L.pdiv_lcp(FAKE, FAKE, 1 << 22, 8, ip, 2, FAKE, 0, NUL), "too large")
+    _expect_invalid(L.pdiv_lcp(FAKE, FAKE, 8, 8, ip, 2, FAKE, 6, NUL), "lcp_row_pitch")
+    _expect_invalid(L.pdiv_lcp(FAKE, FAKE, 8, 8, ip, 2, FAKE, -1, NUL), "lcp_row_pitch")
+    _expect_invalid(L.pdiv_lcp(FAKE, FAKE, 8, 8, ip, 2, FAKE, 1 << 62, NUL), "too large")
 
 
 def test_fused_and_divergence_reject_bad_spacing_and_dtype():
@@ -76,11 +79,11 @@ def test_fused_and_divergence_reject_bad_spacing_and_dtype():
     keep, ip = _iso([0.0])
     for dx, dy in ((0.0, 1.0), (1.0, -2.0), (float("nan"), 1.0), (1.0, float("inf"))):
         _expect_invalid(L.pdiv_lcp_from_moments(FAKE, FAKE, FAKE, FAKE, 0, 8, 8, dx, dy, ip, 1,
-                                                FAKE, NUL), "dx and dy")
+                                                FAKE, 0, NUL), "dx and dy")
         _expect_invalid(L.pdiv_divergence_gaussian(FAKE, FAKE, FAKE, FAKE, 0, 8, 8, dx, dy,
                                                    FAKE, FAKE, NUL), "dx and dy")
     _expect_invalid(L.pdiv_lcp_from_moments(FAKE, FAKE, FAKE, FAKE, 7, 8, 8, 1.0, 1.0, ip, 1,
-                                            FAKE, NUL), "dtype")
+                                            FAKE, 0, NUL), "dtype")
     _expect_invalid(L.pdiv_divergence_gaussian(FAKE, NUL, FAKE, FAKE, 0, 8, 8, 1.0, 1.0, FAKE,
                                                FAKE, NUL), "var_u is NULL")
 
@@ -116,7 +119,7 @@ def test_error_message_is_per_thread():
     import threading
     L = P.lib()
     keep, ip = _iso([0.0])
-    assert L.pdiv_lcp(FAKE, FAKE, 1, 8, ip, 1, FAKE, NUL) == INVALID
+    assert L.pdiv_lcp(FAKE, FAKE, 1, 8, ip, 1, FAKE, 0, NUL) == INVALID
     seen = {}
 
     def other():
@@ -139,6 +142,7 @@ def test_batch_rejects_bad_fields():
         (P._Field(FAKE, FAKE, FAKE, FAKE, 1, 8, 1.0, 1.0, iso_dev, 4, FAKE), "bad grid"),
         (P._Field(NUL, FAKE, FAKE, FAKE, 8, 8, 1.0, 1.0, iso_dev, 4, FAKE), "NULL"),
         (P._Field(FAKE, FAKE, FAKE, FAKE, 8, 8, 0.0, 1.0, iso_dev, 4, FAKE), "dx and dy"),
+        (P._Field(FAKE, FAKE, FAKE, FAKE, 8, 8, 1.0, 1.0, iso_dev, 4, FAKE, 6), "lcp_row_pitch"),
     ):
         arr = (P._Field * 2)(good, bad)
         _expect_invalid(L.pdiv_batch_create(arr, 2, 0, 0, NUL, ctypes.byref(out)), frag)
@@ -148,3 +152,10 @@ def test_batch_rejects_bad_fields():
     _expect_invalid(L.pdiv_batch_create(arr, 1, 5, 0, NUL, ctypes.byref(out)), "dtype")
     _expect_invalid(L.pdiv_batch_create(arr, 1, 0, 8, NUL, ctypes.byref(out)), "flags")
     _expect_invalid(L.pdiv_batch_launch(NUL, NUL), "batch is NULL")
+
+
+def test_server_calls_reject_null_handles():
+    L = P.lib()
+    _expect_invalid(L.pdiv_server_reserve_staging(NUL, 1024, 0, 1), "server is NULL")
+    _expect_invalid(L.pdiv_server_destroy(NUL), "server is NULL")
+

@@ -101,3 +101,24 @@ def test_batch_16bit_storage(dt):
     for f, g in zip(fields, b.fields):
         assert torch.equal(g["lcp"], _per_field(f))
     b.close()
+
+
+def test_batch_pitched_outputs():
+    """Fields whose outputs have padded rows: same maps as the dense per-field
+    launches, padding untouched."""
+    fields = _fields(10, 2, 300, seed=6)
+    bufs = []
+    for k, f in enumerate(fields):
+        ny, nx = f["mean_u"].shape
+        K = f["iso_host"].size
+        pitch = (nx - 1 + 31) // 32 * 32 + 32 * (k % 2)
+        buf = torch.full((K, ny - 1, pitch), -3.0, device="cuda")
+        f["lcp"] = buf[:, :, : nx - 1]
+        bufs.append((buf, nx))
+    b = P.Batch(fields, graph=True)
+    b.launch()
+    torch.cuda.synchronize()
+    for f, g, (buf, nx) in zip(fields, b.fields, bufs):
+        assert torch.equal(g["lcp"], _per_field(f))
+        assert bool((buf[:, :, nx - 1:] == -3.0).all())
+    b.close()

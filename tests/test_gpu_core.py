@@ -28,8 +28,10 @@ def _div_tol(mu_u, mu_v, dx, dy):
     return 8.0 * U32 * (np.abs(mu_u).max() / dx + np.abs(mu_v).max() / dy) + 1e-30
 
 
+# Widths around the 128-cell strip of the LCP tile (nx - 1 = 127, 128, 129,
+# 256, 257) exercise the seam column that lane 63 takes from the seam step.
 SHAPES = [(2, 2), (2, 3), (3, 2), (2, 200), (200, 2), (64, 64), (65, 127), (130, 190),
-          (97, 4034), (4100, 70)]
+          (97, 4034), (4100, 70), (70, 128), (33, 129), (17, 130), (40, 257), (9, 258)]
 
 
 @pytest.mark.parametrize("dt", ["f32", "f16", "bf16"])
@@ -64,6 +66,47 @@ def test_lcp_parity(shape, k):
     # the fused kernel gives bitwise the same maps
     Lf = P.lcp_from_moments(*ts, iso)
     assert torch.equal(L, Lf)
+
+
+@pytest.mark.parametrize("shape", [(65, 129), (40, 258), (130, 190), (3, 2)])
+def test_pitched_output_equals_dense_and_keeps_padding(shape):
+    """Rows padded to a longer pitch hold bitwise the dense maps; the padding
+    floats are never written (fused and two-step paths)."""
+    ny, nx = shape
+    f = _field(ny, nx, seed=5 + nx)
+    ts = moments_dev(f)
+    iso = np.array([-0.05, 0.0, 0.02], np.float32)
+    dense = P.lcp_from_moments(*ts, iso)
+    dm, dv = P.divergence_gaussian(*ts)
+    for pitch in ((nx - 1 + 31) // 32 * 32, nx + 40):
+        for fused in (True, False):
+            buf = torch.full((3, ny - 1, pitch), -7.0, device="cuda")
+            view = buf[:, :, : nx - 1]
+            if fused:
+                P.lcp_from_moments(*ts, iso, out=view)
+            else:
+                P.lcp(dm, dv, iso, out=view)
+            torch.cuda.synchronize()
+            assert torch.equal(view, dense)
+            assert bool((buf[:, :, nx - 1:] == -7.0).all())
+    e = P.empty_lcp(3, ny, nx)
+    assert e.stride(1) % 32 == 0 and e.stride(1) >= nx - 1
+    assert torch.equal(P.lcp_from_moments(*ts, iso, out=e), dense)
+
+
+def test_pitched_output_views():
+    f = _field(20, 40, seed=3)
+    ts = moments_dev(f)
+    iso = [0.0, 0.1]
+    dense = P.lcp_from_moments(*ts, iso)
+    # a view that starts one float into its rows is still a valid pitched output
+    buf = torch.zeros((2, 19, 64), device="cuda")
+    assert torch.equal(P.lcp_from_moments(*ts, iso, out=buf[:, :, 1:40]), dense)
+    assert bool((buf[:, :, 0] == 0).all()) and bool((buf[:, :, 40:] == 0).all())
+    with pytest.raises(ValueError):  # planes not (ny-1)*pitch apart
+        P.lcp_from_moments(*ts, iso, out=torch.empty((2, 20, 64), device="cuda")[:, :19, :39])
+    with pytest.raises(ValueError):  # cells of a row not contiguous
+        P.lcp_from_moments(*ts, iso, out=torch.empty((2, 19, 80), device="cuda")[:, :, :78:2])
 
 
 @pytest.mark.parametrize("dt", ["f32", "f16", "bf16"])

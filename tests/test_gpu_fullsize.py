@@ -45,7 +45,9 @@ def test_c3_sampled_rows(c3, dt):
     iso = c3["isovalues"]
     ts = [torch.from_numpy(c3[k]).to(TORCH_DT[dt]).cuda() for k in
           ("mean_u", "var_u", "mean_v", "var_v")]
-    out = P.lcp_from_moments(*ts, iso)
+    # the benchmark's launch: rows padded to a 128-byte multiple (pitch 8192)
+    out = P.lcp_from_moments(*ts, iso, out=P.empty_lcp(iso.size, ny, nx))
+    assert out.stride(1) == 8192
     torch.cuda.synchronize()
     stored = None
     worst_k, worst_e = 0.0, 0.0
@@ -69,13 +71,18 @@ def test_c3_sampled_rows(c3, dt):
 
 def test_c3_properties_whole_grid(c3):
     """Properties that hold at any size, checked on every cell: range [0,1],
-    no NaN, and the two-step path equals the fused path bitwise."""
+    no NaN, the two-step path equals the fused path bitwise, and the pitched
+    (benchmark) layout holds the same maps as the dense one."""
     ts = [torch.from_numpy(c3[k]).float().cuda() for k in ("mean_u", "var_u", "mean_v", "var_v")]
     iso = c3["isovalues"][[0, 7, 15]]
     fused = P.lcp_from_moments(*ts, iso)
     dm, dv = P.divergence_gaussian(*ts)
     two = P.lcp(dm, dv, iso)
     assert torch.equal(fused, two)
+    ny, nx = ts[0].shape
+    pitched = P.lcp_from_moments(*ts, iso, out=P.empty_lcp(iso.size, ny, nx))
+    assert torch.equal(fused, pitched)
+    del pitched
     assert not torch.isnan(fused).any()
     assert float(fused.min()) >= 0.0 and float(fused.max()) <= 1.0
     del fused, two, dm, dv, ts

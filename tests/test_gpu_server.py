@@ -63,7 +63,7 @@ def test_results_equal_alone_in_a_mixed_stream():
 def test_budget_is_never_exceeded_and_lru_evicts():
     planes = [_field(512, 512, 200 + i) for i in range(6)]
     n = 512 * 512
-    slots = 2 * 2 * 512 * (112 + 16 * 4)  # descriptor slots of a 2-stream server
+    slots = 2 * 2 * 512 * (128 + 16 * 4)  # descriptor slots of a 2-stream server
     budget = slots + 2 * 8 * n + 16 * n + (1 << 20)  # two resident fields + one upload
     srv = P.Server(hbm_budget=budget, n_streams=2)
     iso = np.array([0.0, 0.02], np.float32)
@@ -125,4 +125,23 @@ def test_forced_launch_failure_stays_with_its_requests(monkeypatch):
     assert torch.equal(results[2][1], _alone(pl, iso))
     st = srv.stats()
     assert st["failed"] == 1
+    srv.close()
+
+
+def test_reserved_staging_pool_is_reused_under_back_pressure():
+    # Two staging buffers for eight 1024x1024 fields submitted back to back:
+    # put_field must wait for uploads to hand buffers back (the copies run on
+    # several threads at this size), and every field still comes out right.
+    srv = P.Server(hbm_budget=2 << 30, n_streams=2)
+    srv.reserve_staging(1024 * 1024, 2)
+    planes = [_field(1024, 1024, 300 + i) for i in range(8)]
+    tickets = [srv.put_field(fid, *pl) for fid, pl in enumerate(planes)]
+    for t in tickets:
+        assert srv.wait(t) == OK
+    iso = np.array([-0.01, 0.0, 0.015], np.float32)
+    for fid, pl in enumerate(planes):
+        out = torch.empty((3, 1023, 1023), device="cuda")
+        assert srv.wait(srv.submit_lcp(fid, iso, out)) == OK
+        torch.cuda.synchronize()
+        assert torch.equal(out, _alone(pl, iso))
     srv.close()
