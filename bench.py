@@ -92,7 +92,7 @@ def batch_leg(P, synth, torch, np):
         d["isovalues"] = torch.from_numpy(f["isovalues"]).cuda()
         d["iso_host"] = f["isovalues"]
         fields.append(d)
-        outs_pf.append(torch.empty((4, f["ny"] - 1, f["nx"] - 1), device="cuda"))
+        outs_pf.append(P.empty_lcp(4, f["ny"], f["nx"]))
     cells = sum(4 * (f["ny"] - 1) * (f["nx"] - 1) for f in F)
     in_bytes = sum(16 * f["ny"] * f["nx"] for f in F)
 

@@ -182,8 +182,10 @@ pdiv_status pdiv_batch_create(const pdiv_field* fields_host, int32_t n_fields, p
                               uint32_t flags, pdiv_stream stream, pdiv_batch* out);
 /* Enqueues one pass over every field of the batch on `stream`. */
 pdiv_status pdiv_batch_launch(pdiv_batch batch, pdiv_stream stream);
-/* Tile shape chosen for the batch: rows per band and columns per lane. */
-pdiv_status pdiv_batch_info(pdiv_batch batch, int32_t* band_rows, int32_t* lane_cols,
+/* Tile shape chosen for the batch: cell rows per band, cells per wave strip
+ * (128: paired layout, for outputs whose rows all start on 128-byte lines;
+ * 126: split layout) and the number of tiles. */
+pdiv_status pdiv_batch_info(pdiv_batch batch, int32_t* band_rows, int32_t* strip_cells,
                             int64_t* n_tiles);
 /* Releases the batch (synchronises its stream first). */
 pdiv_status pdiv_batch_destroy(pdiv_batch batch);

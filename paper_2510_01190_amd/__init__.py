@@ -280,8 +280,8 @@ class Batch:
 
     fields: sequence of dicts with mean_u, var_u, mean_v, var_v (device planes of one
     dtype), isovalues (device float32 tensor, 1..16 values), dx, dy, and optionally
-    lcp (device output [K][ny-1][nx-1], dense or a row-padded view; allocated if
-    absent)."""
+    lcp (device output [K][ny-1][nx-1], dense or a row-padded view; allocated
+    row-padded (empty_lcp) if absent)."""
 
     GRAPH = 1
     AUTOTUNE = 2
@@ -299,9 +299,8 @@ class Batch:
             iso = f["isovalues"]
             _dev(iso, "isovalues", None, torch.float32)
             out = f.get("lcp")
-            if out is None:
-                out = torch.empty((iso.numel(), ny - 1, nx - 1), dtype=torch.float32,
-                                  device=f["mean_u"].device)
+            if out is None:  # rows on 128-byte lines, so either tile layout may run
+                out = empty_lcp(iso.numel(), ny, nx, device=f["mean_u"].device)
             po, pitch = _lcp_out(out, iso.numel(), ny, nx)
             arr[k] = _Field(ptrs[0], ptrs[1], ptrs[2], ptrs[3], ny, nx,
                             float(f.get("dx", 1.0)), float(f.get("dy", 1.0)),
@@ -318,7 +317,7 @@ class Batch:
     def info(self):
         a, b, c = _i32(), _i32(), _i64()
         _check(lib().pdiv_batch_info(self._h, _c.byref(a), _c.byref(b), _c.byref(c)))
-        return dict(band_rows=a.value, lane_cols=b.value, n_tiles=c.value)
+        return dict(band_rows=a.value, strip_cells=b.value, n_tiles=c.value)
 
     def close(self):
         if getattr(self, "_h", None):

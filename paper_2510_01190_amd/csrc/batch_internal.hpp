@@ -31,10 +31,14 @@ struct alignas(16) BatchField {
 };
 
 int iso_bucket(int n);
-// Kernel for a batch: fused (moments of dtype dt) or two-step (float planes).
-const void* batch_kernel_ptr(bool fused, pdiv_dtype dt, int kc);
-// Sets n_strips and tile_begin for band_rows-row bands; returns the tile count.
-int64_t fill_tiles(std::vector<BatchField>& f, int band_rows);
+// Kernel for a batch: fused (moments of dtype dt) or two-step (float planes),
+// paired or split tile layout.
+const void* batch_kernel_ptr(bool fused, pdiv_dtype dt, int kc, bool paired);
+// Every field's output rows start on 128-byte lines (the paired layout's need).
+bool all_rows_on_lines(const std::vector<BatchField>& f);
+// Sets n_strips and tile_begin for band_rows-row bands of the layout's strips;
+// returns the tile count.
+int64_t fill_tiles(std::vector<BatchField>& f, int band_rows, bool paired);
 // Blocks of the kernel resident on the whole device at once.
 int resident_blocks(const void* kernel);
 hipError_t launch_batch(const void* kernel, const BatchField* dev_fields, int n_fields,

@@ -27,15 +27,23 @@ void set_band_rows_override(int rows) { g_band_rows_override.store(rows); }
 
 // Rows per band: each band re-reads two halo rows and re-evaluates one corner
 // row, and short bands give more waves to even out the tail of the launch.
-// On gfx950, 8191 x 8191 cells at K = 16 (64 strips): 64-row bands (8192
-// waves) ran 1.26 ms against 1.32 (48 rows), 1.37 (96) and 1.30 (128).
+// On gfx950, 8191 x 8191 cells at K = 16: the paired tile (64 strips) ran
+// 1.26 ms with 64-row bands against 1.32 (48 rows), 1.37 (96) and 1.30 (128);
+// the split tile (65 strips, dense rows) 1.45 ms with 16-row bands against
+// 1.50 (8) and 1.55 (64).  0 in band_rows: this choice, made per layout.
 LcpShape default_lcp_shape(int64_t ny, int64_t nx, int n_iso) {
   (void)nx;
   (void)n_iso;
+  (void)ny;
   LcpShape s;
-  const int o = g_band_rows_override.load();
-  s.band_rows = o > 0 ? o : (ny > 4096 ? 64 : 32);
+  s.band_rows = g_band_rows_override.load();
   return s;
+}
+
+int band_rows_for(const LcpShape& s, int64_t ny, bool paired) {
+  if (s.band_rows > 0) return s.band_rows;
+  if (ny <= 4096) return 32;
+  return paired ? 64 : 16;
 }
 
 namespace {
@@ -67,7 +75,7 @@ __global__ __launch_bounds__(kBlock) void divergence_kernel(const T* __restrict_
   }
 }
 
-template <int KC, bool FUSED, bool STREAM, typename T>
+template <int KC, bool FUSED, bool PAIRED, typename T>
 __global__ __launch_bounds__(kBlock) void lcp_kernel(const T* __restrict__ p0,
                                                      const T* __restrict__ p1,
                                                      const T* __restrict__ p2,
@@ -88,7 +96,7 @@ __global__ __launch_bounds__(kBlock) void lcp_kernel(const T* __restrict__ p0,
   const int band = wave / n_strips;
   if (band >= n_bands) return;
   const int j0 = band * band_rows;
-  lcp_tile<KC, FUSED, STREAM>(p0, p1, p2, p3, ny, nx, k, iso, KC, out, plane, pitch, strip, j0,
+  lcp_tile<KC, FUSED, PAIRED>(p0, p1, p2, p3, ny, nx, k, iso, KC, out, plane, pitch, strip, j0,
                               min(j0 + band_rows, ny - 1));
 }
 
@@ -96,23 +104,24 @@ template <int KC, bool FUSED, typename T>
 hipError_t launch_kc(const void* p0, const void* p1, const void* p2, const void* p3, int ny,
                      int nx, const StencilCoef& k, const IsoChunk& iso, float* out,
                      int64_t pitch, LcpShape shape, hipStream_t s) {
-  const int n_strips = (nx - 1 + kCellsPerWave - 1) / kCellsPerWave;
-  const int n_bands = (ny - 1 + shape.band_rows - 1) / shape.band_rows;
+  const int64_t plane = static_cast<int64_t>(ny - 1) * pitch;
+  const bool paired = use_paired_tile(out, pitch, KC);
+  const int cells = cells_per_wave(paired);
+  const int band_rows = band_rows_for(shape, ny, paired);
+  const int n_strips = (nx - 1 + cells - 1) / cells;
+  const int n_bands = (ny - 1 + band_rows - 1) / band_rows;
   const int64_t waves = static_cast<int64_t>(n_strips) * n_bands;
   const unsigned blocks = static_cast<unsigned>((waves + kWavesPerBlock - 1) / kWavesPerBlock);
-  const int64_t plane = static_cast<int64_t>(ny - 1) * pitch;
-  // every row of every plane starts on a 128-byte line: whole-line stores
-  const bool lines = (reinterpret_cast<uintptr_t>(out) % 128 == 0) && (pitch % 32 == 0);
-  if (lines)
+  if (paired)
     hipLaunchKernelGGL((lcp_kernel<KC, FUSED, true, T>), dim3(blocks), dim3(kBlock), 0, s,
                        static_cast<const T*>(p0), static_cast<const T*>(p1),
                        static_cast<const T*>(p2), static_cast<const T*>(p3), ny, nx, k, iso, out,
-                       plane, pitch, shape.band_rows, n_strips, n_bands);
+                       plane, pitch, band_rows, n_strips, n_bands);
   else
     hipLaunchKernelGGL((lcp_kernel<KC, FUSED, false, T>), dim3(blocks), dim3(kBlock), 0, s,
                        static_cast<const T*>(p0), static_cast<const T*>(p1),
                        static_cast<const T*>(p2), static_cast<const T*>(p3), ny, nx, k, iso, out,
-                       plane, pitch, shape.band_rows, n_strips, n_bands);
+                       plane, pitch, band_rows, n_strips, n_bands);
   return hipGetLastError();
 }
 

@@ -1,26 +1,35 @@
-// Column-walking tile of the closed-form LCP (Eq. 2-3 and the level-crossing
+// Column-walking tiles of the closed-form LCP (Eq. 2-3 and the level-crossing
 // probability of Section 3.1), shared by the single-field kernel and the
-// batched persistent kernel so that both give bitwise the same maps.
+// batched persistent kernel so that both give bitwise the same maps.  A wave
+// walks a strip of cells down a band of cell rows, one vertex row at a time:
+// for each isovalue it evaluates each corner's tail once per row, pairs it
+// with the previous row's (vertical pairs, kept in registers) and forms the
+// cells from the pairs of neighbouring columns, read from the lane to the
+// right through DPP.  The next row's input loads are issued before the
+// current row is computed, and stores are masked by their buffer record range
+// (checked per dword), not by branches.  Two strip layouts, the same
+// arithmetic (so the same bits):
 //
-// A wave owns the 128 cells [x0, x0+128) of a band of cell rows, x0 = 128
-// strip, i.e. the vertex columns x0..x0+128.  Lane L holds the two adjacent
-// columns E = x0+2L and O = x0+2L+1 and walks down the band one vertex row at
-// a time.  For each isovalue it evaluates each corner's tail once per row,
-// pairs it with the previous row's (vertical pairs, kept in registers) and
-// forms cell 2L from its own two columns and cell 2L+1 from its O column and
-// lane L+1's E column, read through DPP.  The 129th column x0+128, right
-// neighbour of lane 63's last cell, belongs to no lane: a seam step per row
-// has lanes 2q and 2q+1 evaluate columns x0+127 and x0+128 at isovalue q, so
-// lane 2q forms cell x0+127 for isovalue q with the same arithmetic, and lane
-// 63 takes it over with one readlane/writelane per isovalue (about 7% more
-// vector ALU work at 16 isovalues).  Each lane writes its two cells with one
-// 8-byte store, so one store instruction covers 512 contiguous bytes of an
-// output row: whole 128-byte lines when the row pitch is a multiple of 32
-// floats.  On gfx950 such stores sustain about 5.4 TB/s, against about 4.4 TB/s
-// for 126-cell strips of 4-byte stores whose lines are shared between waves.
-// Stores are masked by their buffer record range (checked per dword), not
-// by branches.  The next row's input loads are issued before the current row
-// is computed.
+// Paired (lcp_tile_paired), for outputs whose rows start on 128-byte lines: a
+// wave owns the 128 cells [x0, x0+128), x0 = 128 strip, i.e. vertex columns
+// x0..x0+128.  Lane L holds the adjacent columns E = x0+2L and O = x0+2L+1,
+// forms cell 2L from its own two columns and cell 2L+1 from O and lane L+1's
+// E, and writes both with one 8-byte store: one store instruction covers 512
+// contiguous bytes, whole lines.  The 129th column x0+128, right neighbour of
+// lane 63's last cell, belongs to no lane: a seam step per row has lanes 2q
+// and 2q+1 evaluate columns x0+127 and x0+128 at isovalue q, lane 2q forms
+// cell x0+127 for isovalue q with the same arithmetic, and lane 63 takes it
+// over with one readlane/writelane per isovalue (about 7% more vector ALU
+// work at 16 isovalues).  On gfx950 such stores sustain about 5.4 TB/s.
+//
+// Split (lcp_tile_split), for any other output: a wave owns 127 vertex
+// columns, the 126 cells [x0, x0+126), x0 = 126 strip.  Lane L holds columns
+// A = x0+L and B = x0+63+L (lane 63's A repeats lane 0's B), forms cells
+// (A, A+1) and (B, B+1) with the right pair from lane L+1, and lanes 0..62
+// write 63 consecutive cells per store.  No seam step; rows that start
+// inside a line cap the store rate near 4.4 TB/s for either layout, so the
+// cheaper tile wins there (and at few isovalues, where the seam step costs
+// up to 15%).
 #pragma once
 
 #include "pdiv_device.hpp"
@@ -29,7 +38,12 @@
 namespace pdiv {
 
 constexpr int kWave = 64;
-constexpr int kCellsPerWave = 2 * kWave;  // 128
+constexpr int kPairedCells = 2 * kWave;     // 128 cells per wave
+constexpr int kSplitHalf = kWave - 1;       // 63 cells per half-strip
+constexpr int kSplitCells = 2 * kSplitHalf; // 126 cells per wave
+__host__ __device__ constexpr int cells_per_wave(bool paired) {
+  return paired ? kPairedCells : kSplitCells;
+}
 
 // The values one vertex reads: for the fused path the U neighbours along x
 // and the V neighbours along y of Eq. 2-3 (boundary-clamped), for the
@@ -201,13 +215,13 @@ __device__ __forceinline__ float to_lane63(float v, int s) {
   return v;
 }
 
-// One vertex row step: the corners of row j+1 (from raw values loaded
+// Paired layout, one vertex row step: the corners of row j+1 (from raw values loaded
 // earlier) for the lane's columns E and O and its seam column, their pairs
 // with row j (cor_*, which then take row j+1's corners), and the lane's two
 // cells for every isovalue.  off is the byte offset of the lane's first cell
 // within an output row.
 template <int KC, bool FUSED, bool STREAM>
-__device__ __forceinline__ void row_step(const Raw<FUSED>& raw_e, const Raw<FUSED>& raw_o,
+__device__ __forceinline__ void row_step_paired(const Raw<FUSED>& raw_e, const Raw<FUSED>& raw_o,
                                          const Raw<FUSED>& raw_s, const Col& ce, const Col& co,
                                          const Col& cs, int ny, const StencilCoef& k,
                                          const IsoChunk& iso, float c_seam, int n_store,
@@ -239,14 +253,14 @@ __device__ __forceinline__ void row_step(const Raw<FUSED>& raw_e, const Raw<FUSE
   }
 }
 
-// One tile: cell columns [x0, x0+128) of strip `strip` (x0 = 128 strip),
+// Paired tile: cell columns [x0, x0+128) of strip `strip` (x0 = 128 strip),
 // cell rows [j0, j1), for the KC isovalues in `iso`; only the first n_store
 // isovalue planes are written (a batch pads its isovalue set to KC).  Output
 // row j of plane q starts at out + q plane + j pitch.  Must be called with
 // wave-uniform arguments by all 64 lanes of a wave; KC <= 32.  STREAM: store
 // with the non-temporal policy (for outputs whose rows start on 128-byte lines).
 template <int KC, bool FUSED, bool STREAM, typename T>
-__device__ __forceinline__ void lcp_tile(const T* __restrict__ p0, const T* __restrict__ p1,
+__device__ __forceinline__ void lcp_tile_paired(const T* __restrict__ p0, const T* __restrict__ p1,
                                          const T* __restrict__ p2, const T* __restrict__ p3,
                                          int ny, int nx, const StencilCoef& k,
                                          const IsoChunk& iso, int n_store,
@@ -255,8 +269,8 @@ __device__ __forceinline__ void lcp_tile(const T* __restrict__ p0, const T* __re
   static_assert(2 * KC <= kWave, "the seam step needs two lanes per isovalue");
   const uint32_t lane = threadIdx.x & 63;
   const uint32_t last = uint32_t(nx - 1);                      // also the cell count
-  const uint32_t xe = uint32_t(strip) * kCellsPerWave + 2 * lane;  // E column
-  const uint32_t xs = uint32_t(strip) * kCellsPerWave + (kCellsPerWave - 1) + (lane & 1);
+  const uint32_t xe = uint32_t(strip) * kPairedCells + 2 * lane;  // E column
+  const uint32_t xs = uint32_t(strip) * kPairedCells + (kPairedCells - 1) + (lane & 1);
   // columns past the edge load a valid column and store nothing
   const Col ce = make_col(min(xe, last), nx, sizeof(T));
   const Col co = make_col(min(xe + 1, last), nx, sizeof(T));
@@ -282,7 +296,7 @@ __device__ __forceinline__ void lcp_tile(const T* __restrict__ p0, const T* __re
     load_raw(rs_, p0, p1, p2, p3, ny, nx, cs, j);
   };
   auto step = [&](const Raw<FUSED>& re, const Raw<FUSED>& ro, const Raw<FUSED>& rs_, int j) {
-    row_step<KC, FUSED, STREAM>(re, ro, rs_, ce, co, cs, ny, k, iso, c_seam, n_store, out, plane, pitch,
+    row_step_paired<KC, FUSED, STREAM>(re, ro, rs_, ce, co, cs, ny, k, iso, c_seam, n_store, out, plane, pitch,
                         row_bytes, j, off, pe, po, ps);
   };
   load3(e0, o0, s0, j0);
@@ -316,6 +330,118 @@ __device__ __forceinline__ void lcp_tile(const T* __restrict__ p0, const T* __re
     for (j += 2; j + 2 <= j1; j += 2) trip(j);
   }
   if (j < j1) step(e1, o1, s1, j);  // e1.. hold row j + 1 == j1
+}
+
+// Split layout, one vertex row step: the corners of row j+1 for the lane's
+// columns A and B, their pairs with row j (cor_*, which then take row j+1's
+// corners), and the lane's two cells for every isovalue; off_a, off_b are the
+// byte offsets of the lane's cells within an output row.
+template <int KC, bool FUSED>
+__device__ __forceinline__ void row_step_split(const Raw<FUSED>& raw_a, const Raw<FUSED>& raw_b,
+                                               const Col& ca, const Col& cb, int ny,
+                                               const StencilCoef& k, const IsoChunk& iso,
+                                               int n_store, float* __restrict__ out,
+                                               int64_t plane, int64_t pitch, uint32_t row_bytes,
+                                               int j, uint32_t off_a, uint32_t off_b,
+                                               AB (&cor_a)[KC], AB (&cor_b)[KC]) {
+  const Corner ka = make_corner(raw_div(raw_a, ca.bx, j + 1, ny, k));
+  const Corner kb = make_corner(raw_div(raw_b, cb.bx, j + 1, ny, k));
+  float* __restrict__ orow = out + static_cast<int64_t>(j) * pitch;
+#pragma unroll
+  for (int q = 0; q < KC; ++q) {
+    const AB cur_a = corner_probs(ka, iso.c[q]);
+    const AB cur_b = corner_probs(kb, iso.c[q]);
+    const float l0 = cell_lcp_dpp(make_pair(cor_a[q], cur_a), cur_a.below);
+    const float l1 = cell_lcp_dpp(make_pair(cor_b[q], cur_b), cur_b.below);
+    // planes past n_store (a batch's padding) get an empty record range
+    const RowWriter<false> w(orow + q * plane, q < n_store ? row_bytes : 0u);
+    w.put(l0, off_a);
+    w.put(l1, off_b);
+    cor_a[q] = cur_a;
+    cor_b[q] = cur_b;
+  }
+}
+
+// Split tile: cell columns [x0, x0+126) of strip `strip` (x0 = 126 strip),
+// cell rows [j0, j1); arguments as for lcp_tile_paired.
+template <int KC, bool FUSED, typename T>
+__device__ __forceinline__ void lcp_tile_split(const T* __restrict__ p0, const T* __restrict__ p1,
+                                               const T* __restrict__ p2, const T* __restrict__ p3,
+                                               int ny, int nx, const StencilCoef& k,
+                                               const IsoChunk& iso, int n_store,
+                                               float* __restrict__ out, int64_t plane,
+                                               int64_t pitch, int strip, int j0, int j1) {
+  const uint32_t lane = threadIdx.x & 63;
+  const uint32_t xa = uint32_t(strip) * kSplitCells + lane;  // A column
+  const uint32_t xb = xa + kSplitHalf;                        // B column
+  const uint32_t last = uint32_t(nx - 1);
+  const Col ca = make_col(min(xa, last), nx, sizeof(T));  // columns past the edge load a
+  const Col cb = make_col(min(xb, last), nx, sizeof(T));  // valid column, store nothing
+  // lane 63 and cells past the right edge get an offset beyond any row
+  constexpr uint32_t kDrop = 0x7ffffff0u;
+  const uint32_t off_a = (lane < kSplitHalf) & (xa < last) ? xa * 4u : kDrop;
+  const uint32_t off_b = (lane < kSplitHalf) & (xb < last) ? xb * 4u : kDrop;
+  const uint32_t row_bytes = last * 4u;
+
+  AB pa[KC], pb[KC];
+  Raw<FUSED> a0, b0, a1, b1;
+  load_raw(a0, p0, p1, p2, p3, ny, nx, ca, j0);
+  load_raw(b0, p0, p1, p2, p3, ny, nx, cb, j0);
+  load_raw(a1, p0, p1, p2, p3, ny, nx, ca, j0 + 1);
+  load_raw(b1, p0, p1, p2, p3, ny, nx, cb, j0 + 1);
+  {
+    const Corner c0 = make_corner(raw_div(a0, ca.bx, j0, ny, k));
+    const Corner c1 = make_corner(raw_div(b0, cb.bx, j0, ny, k));
+#pragma unroll
+    for (int q = 0; q < KC; ++q) {
+      pa[q] = corner_probs(c0, iso.c[q]);
+      pb[q] = corner_probs(c1, iso.c[q]);
+    }
+  }
+  auto step = [&](const Raw<FUSED>& ra, const Raw<FUSED>& rb, int j) {
+    row_step_split<KC, FUSED>(ra, rb, ca, cb, ny, k, iso, n_store, out, plane, pitch,
+                              row_bytes, j, off_a, off_b, pa, pb);
+  };
+  // two rows per trip, as in the paired tile
+  auto trip = [&](int j) {
+    load_raw(a0, p0, p1, p2, p3, ny, nx, ca, j + 2);
+    load_raw(b0, p0, p1, p2, p3, ny, nx, cb, j + 2);
+    step(a1, b1, j);
+    const int jn = min(j + 3, j1);
+    load_raw(a1, p0, p1, p2, p3, ny, nx, ca, jn);
+    load_raw(b1, p0, p1, p2, p3, ny, nx, cb, jn);
+    step(a0, b0, j + 1);
+  };
+  int j = j0;
+  if (j + 2 <= j1) {
+    trip(j);
+    for (j += 2; j + 2 <= j1; j += 2) trip(j);
+  }
+  if (j < j1) step(a1, b1, j);  // a1/b1 hold row j + 1 == j1
+}
+
+// Layout choice: the paired tile when every output row starts on a 128-byte
+// line (base aligned, pitch a multiple of 32 floats) and there are at least 8
+// isovalues, so that the seam step costs under 8% of the row's arithmetic.
+inline bool use_paired_tile(const float* out, int64_t pitch, int kc) {
+  return (reinterpret_cast<uintptr_t>(out) % 128 == 0) && (pitch % 32 == 0) && kc >= 8;
+}
+
+// The tile of layout PAIRED (paired tiles store non-temporally: their rows
+// start on 128-byte lines).
+template <int KC, bool FUSED, bool PAIRED, typename T>
+__device__ __forceinline__ void lcp_tile(const T* __restrict__ p0, const T* __restrict__ p1,
+                                         const T* __restrict__ p2, const T* __restrict__ p3,
+                                         int ny, int nx, const StencilCoef& k,
+                                         const IsoChunk& iso, int n_store,
+                                         float* __restrict__ out, int64_t plane, int64_t pitch,
+                                         int strip, int j0, int j1) {
+  if constexpr (PAIRED)
+    lcp_tile_paired<KC, FUSED, true>(p0, p1, p2, p3, ny, nx, k, iso, n_store, out, plane, pitch,
+                                     strip, j0, j1);
+  else
+    lcp_tile_split<KC, FUSED>(p0, p1, p2, p3, ny, nx, k, iso, n_store, out, plane, pitch, strip,
+                              j0, j1);
 }
 
 }  // namespace pdiv

@@ -36,7 +36,7 @@ namespace {
 constexpr int kBlock = 256;
 constexpr int kWavesPerBlock = kBlock / kWave;
 
-template <int KC, bool FUSED, typename T>
+template <int KC, bool FUSED, bool PAIRED, typename T>
 __global__ __launch_bounds__(kBlock) void batch_kernel(const BatchField* __restrict__ fields,
                                                        int n_fields, int64_t n_tiles,
                                                        int band_rows) {
@@ -62,21 +62,32 @@ __global__ __launch_bounds__(kBlock) void batch_kernel(const BatchField* __restr
 #pragma unroll
     for (int q = 0; q < KC; ++q) iso.c[q] = F.iso[q < F.n_iso ? q : F.n_iso - 1];
     const int j0 = band * band_rows;
-    lcp_tile<KC, FUSED, false>(static_cast<const T*>(F.p0), static_cast<const T*>(F.p1),
+    lcp_tile<KC, FUSED, PAIRED>(static_cast<const T*>(F.p0), static_cast<const T*>(F.p1),
                         static_cast<const T*>(F.p2), static_cast<const T*>(F.p3), F.ny, F.nx,
                         F.coef, iso, F.n_iso, F.lcp, F.plane, F.pitch, strip, j0,
                         min(j0 + band_rows, F.ny - 1));
   }
 }
 
-template <bool FUSED, typename T>
+template <bool FUSED, bool PAIRED, typename T>
 const void* kernel_for(int kc) {
   switch (kc) {
-    case 1: return reinterpret_cast<const void*>(&batch_kernel<1, FUSED, T>);
-    case 2: return reinterpret_cast<const void*>(&batch_kernel<2, FUSED, T>);
-    case 4: return reinterpret_cast<const void*>(&batch_kernel<4, FUSED, T>);
-    case 8: return reinterpret_cast<const void*>(&batch_kernel<8, FUSED, T>);
-    case 16: return reinterpret_cast<const void*>(&batch_kernel<16, FUSED, T>);
+    case 1: return reinterpret_cast<const void*>(&batch_kernel<1, FUSED, PAIRED, T>);
+    case 2: return reinterpret_cast<const void*>(&batch_kernel<2, FUSED, PAIRED, T>);
+    case 4: return reinterpret_cast<const void*>(&batch_kernel<4, FUSED, PAIRED, T>);
+    case 8: return reinterpret_cast<const void*>(&batch_kernel<8, FUSED, PAIRED, T>);
+    case 16: return reinterpret_cast<const void*>(&batch_kernel<16, FUSED, PAIRED, T>);
+  }
+  return nullptr;
+}
+
+template <bool PAIRED>
+const void* kernel_for_dtype(bool fused, pdiv_dtype dt, int kc) {
+  if (!fused) return kernel_for<false, PAIRED, float>(kc);
+  switch (dt) {
+    case PDIV_F32: return kernel_for<true, PAIRED, float>(kc);
+    case PDIV_F16: return kernel_for<true, PAIRED, __half>(kc);
+    case PDIV_BF16: return kernel_for<true, PAIRED, bf16_t>(kc);
   }
   return nullptr;
 }
@@ -85,20 +96,21 @@ const void* kernel_for(int kc) {
 
 int iso_bucket(int n) { return n <= 1 ? 1 : n <= 2 ? 2 : n <= 4 ? 4 : n <= 8 ? 8 : 16; }
 
-const void* batch_kernel_ptr(bool fused, pdiv_dtype dt, int kc) {
-  if (!fused) return kernel_for<false, float>(kc);
-  switch (dt) {
-    case PDIV_F32: return kernel_for<true, float>(kc);
-    case PDIV_F16: return kernel_for<true, __half>(kc);
-    case PDIV_BF16: return kernel_for<true, bf16_t>(kc);
-  }
-  return nullptr;
+const void* batch_kernel_ptr(bool fused, pdiv_dtype dt, int kc, bool paired) {
+  return paired ? kernel_for_dtype<true>(fused, dt, kc) : kernel_for_dtype<false>(fused, dt, kc);
 }
 
-int64_t fill_tiles(std::vector<BatchField>& f, int band_rows) {
+bool all_rows_on_lines(const std::vector<BatchField>& f) {
+  for (auto& x : f)
+    if (reinterpret_cast<uintptr_t>(x.lcp) % 128 != 0 || x.pitch % 32 != 0) return false;
+  return true;
+}
+
+int64_t fill_tiles(std::vector<BatchField>& f, int band_rows, bool paired) {
+  const int cells = cells_per_wave(paired);
   int64_t t = 0;
   for (auto& x : f) {
-    x.n_strips = static_cast<int>((x.nx - 1 + kCellsPerWave - 1) / kCellsPerWave);
+    x.n_strips = static_cast<int>((x.nx - 1 + cells - 1) / cells);
     const int n_bands = (x.ny - 1 + band_rows - 1) / band_rows;
     x.tile_begin = t;
     t += int64_t(x.n_strips) * n_bands;
@@ -138,6 +150,10 @@ struct pdiv_batch_s {
   int64_t n_tiles = 0;
   int band_rows = 16;
   int grid = 1;
+  bool paired = false;      // tile layout (paired needs every output row on a line)
+  bool lines = false;       // every field's output rows start on 128-byte lines
+  pdiv_dtype dtype = PDIV_F32;
+  int kc = 1;
   hipGraph_t graph = nullptr;
   hipGraphExec_t exec = nullptr;
   hipStream_t capture = nullptr;
@@ -147,13 +163,17 @@ struct pdiv_batch_s {
 namespace {
 
 // Autotune cache: in memory for the process, and in a JSON file when
-// PDIV_TUNE_CACHE names one.  Key: dtype, isovalue bucket, fused, and the
-// size class (log2 of total cells, log2 of the mean field side).
+// PDIV_TUNE_CACHE names one.  Key: dtype, isovalue bucket, whether the
+// outputs are line-aligned, and the size class (log2 of total cells, log2 of
+// the mean field side).  Value: band rows, grid multiplier, tile layout.
+struct Tune {
+  int band_rows, grid_mult, paired;
+};
 std::mutex g_tune_mu;
-std::map<std::string, std::pair<int, int>> g_tune;
+std::map<std::string, Tune> g_tune;
 bool g_tune_loaded = false;
 
-std::string tune_key(pdiv_dtype dt, int kc, const std::vector<BatchField>& f) {
+std::string tune_key(pdiv_dtype dt, int kc, bool lines, const std::vector<BatchField>& f) {
   double cells = 0, side = 0;
   for (auto& x : f) {
     cells += double(x.ny - 1) * double(x.nx - 1);
@@ -161,8 +181,8 @@ std::string tune_key(pdiv_dtype dt, int kc, const std::vector<BatchField>& f) {
   }
   side /= std::max<size_t>(1, f.size());
   std::ostringstream o;
-  o << "gfx950/batch/dt" << int(dt) << "/k" << kc << "/c" << int(std::log2(cells + 1)) << "/s"
-    << int(std::log2(side + 1));
+  o << "gfx950/batch/dt" << int(dt) << "/k" << kc << "/l" << int(lines) << "/c"
+    << int(std::log2(cells + 1)) << "/s" << int(std::log2(side + 1));
   return o.str();
 }
 
@@ -173,13 +193,14 @@ void tune_load() {
   if (!path) return;
   std::ifstream in(path);
   std::string line;
-  // one entry per line: "key": [band_rows, grid_mult],
+  // one entry per line: "key": [band_rows, grid_mult, paired],
   while (std::getline(in, line)) {
     const size_t a = line.find('"'), b = line.find('"', a + 1), c = line.find('[', b);
     if (a == std::string::npos || b == std::string::npos || c == std::string::npos) continue;
-    int br = 0, gm = 0;
-    if (std::sscanf(line.c_str() + c, "[%d, %d]", &br, &gm) == 2 && br > 0 && gm > 0)
-      g_tune[line.substr(a + 1, b - a - 1)] = {br, gm};
+    int br = 0, gm = 0, pr = 0;
+    if (std::sscanf(line.c_str() + c, "[%d, %d, %d]", &br, &gm, &pr) == 3 && br > 0 && gm > 0 &&
+        (pr == 0 || pr == 1))
+      g_tune[line.substr(a + 1, b - a - 1)] = {br, gm, pr};
   }
 }
 
@@ -190,8 +211,8 @@ void tune_save() {
   out << "{\n";
   size_t i = 0;
   for (auto& e : g_tune)
-    out << "  \"" << e.first << "\": [" << e.second.first << ", " << e.second.second << "]"
-        << (++i < g_tune.size() ? "," : "") << "\n";
+    out << "  \"" << e.first << "\": [" << e.second.band_rows << ", " << e.second.grid_mult
+        << ", " << e.second.paired << "]" << (++i < g_tune.size() ? "," : "") << "\n";
   out << "}\n";
 }
 
@@ -221,63 +242,71 @@ void release(pdiv_batch b) {
   delete b;
 }
 
+// Sets the batch's layout and band height and fills its tile table.
+void shape(pdiv_batch b, bool paired, int band_rows) {
+  b->paired = paired;
+  b->kernel = batch_kernel_ptr(true, b->dtype, b->kc, paired);
+  b->band_rows = band_rows;
+  b->n_tiles = fill_tiles(b->fields, band_rows, paired);
+}
+
 // Times the candidate shapes on the batch itself (the launches write the
-// batch's own outputs) and keeps the fastest.
-pdiv_status autotune(pdiv_batch b, pdiv_dtype dt, int kc, hipStream_t s) {
-  const std::string key = tune_key(dt, kc, b->fields);
+// batch's own outputs) and keeps the fastest: band rows x grid size, and both
+// tile layouts when every output row starts on a line.
+pdiv_status autotune(pdiv_batch b, hipStream_t s) {
+  const std::string key = tune_key(b->dtype, b->kc, b->lines, b->fields);
   {
     std::lock_guard<std::mutex> g(g_tune_mu);
     tune_load();
     auto it = g_tune.find(key);
-    if (it != g_tune.end()) {
-      b->band_rows = it->second.first;
-      b->n_tiles = fill_tiles(b->fields, b->band_rows);
-      b->grid = std::max(1, resident_blocks(b->kernel) * it->second.second / 2);
+    if (it != g_tune.end() && (b->lines || !it->second.paired)) {
+      shape(b, it->second.paired != 0, it->second.band_rows);
+      b->grid = std::max(1, resident_blocks(b->kernel) * it->second.grid_mult / 2);
       return upload(b);
     }
   }
   hipEvent_t e0, e1;
   if (hipEventCreate(&e0) != hipSuccess || hipEventCreate(&e1) != hipSuccess)
     return device_status(hipGetLastError(), "autotune events");
-  const int base = resident_blocks(b->kernel);
   float best = 1e30f;
-  int best_br = 16, best_gm = 2;
+  Tune win{16, 2, 0};
   pdiv_status st = PDIV_OK;
-  for (int br : {8, 16, 32, 64}) {
-    b->n_tiles = fill_tiles(b->fields, br);
-    if ((st = upload(b)) != PDIV_OK) break;
-    for (int gm : {1, 2, 4}) {  // grid = gm/2 x resident capacity
-      const int grid = std::max(1, base * gm / 2);
-      hipError_t e = launch_batch(b->kernel, b->dev, int(b->fields.size()), b->n_tiles, br,
-                                  grid, s);  // warm
-      e = e != hipSuccess ? e : hipEventRecord(e0, s);
-      for (int r = 0; r < 3 && e == hipSuccess; ++r)
-        e = launch_batch(b->kernel, b->dev, int(b->fields.size()), b->n_tiles, br, grid, s);
-      e = e != hipSuccess ? e : hipEventRecord(e1, s);
-      e = e != hipSuccess ? e : hipEventSynchronize(e1);
-      float ms = 0;
-      e = e != hipSuccess ? e : hipEventElapsedTime(&ms, e0, e1);
-      if (e != hipSuccess) {
-        st = device_status(e, "autotune launch");
-        break;
+  for (int paired = 0; paired <= (b->lines ? 1 : 0) && st == PDIV_OK; ++paired) {
+    for (int br : {8, 16, 32, 64}) {
+      shape(b, paired != 0, br);
+      const int base = resident_blocks(b->kernel);
+      if ((st = upload(b)) != PDIV_OK) break;
+      for (int gm : {1, 2, 4}) {  // grid = gm/2 x resident capacity
+        const int grid = std::max(1, base * gm / 2);
+        hipError_t e = launch_batch(b->kernel, b->dev, int(b->fields.size()), b->n_tiles, br,
+                                    grid, s);  // warm
+        e = e != hipSuccess ? e : hipEventRecord(e0, s);
+        for (int r = 0; r < 3 && e == hipSuccess; ++r)
+          e = launch_batch(b->kernel, b->dev, int(b->fields.size()), b->n_tiles, br, grid, s);
+        e = e != hipSuccess ? e : hipEventRecord(e1, s);
+        e = e != hipSuccess ? e : hipEventSynchronize(e1);
+        float ms = 0;
+        e = e != hipSuccess ? e : hipEventElapsedTime(&ms, e0, e1);
+        if (e != hipSuccess) {
+          st = device_status(e, "autotune launch");
+          break;
+        }
+        if (ms < best) {
+          best = ms;
+          win = {br, gm, paired};
+        }
       }
-      if (ms < best) {
-        best = ms;
-        best_br = br;
-        best_gm = gm;
-      }
+      if (st != PDIV_OK) break;
     }
-    if (st != PDIV_OK) break;
   }
   (void)hipEventDestroy(e0);
   (void)hipEventDestroy(e1);
   if (st != PDIV_OK) return st;
-  b->band_rows = best_br;
-  b->n_tiles = fill_tiles(b->fields, best_br);
-  b->grid = std::max(1, base * best_gm / 2);
+  shape(b, win.paired != 0, win.band_rows);
+  b->grid = std::max(1, resident_blocks(b->kernel) * win.grid_mult / 2);
   {
     std::lock_guard<std::mutex> g(g_tune_mu);
-    g_tune[key] = {best_br, best_gm};
+    g_tune[key] = win;
     tune_save();
   }
   return upload(b);
@@ -330,14 +359,15 @@ pdiv_status pdiv_batch_create(const pdiv_field* fields_host, int32_t n_fields, p
   }
   pdiv_batch b = new pdiv_batch_s();
   b->fields = std::move(fv);
-  b->kernel = batch_kernel_ptr(true, dtype, kc);
+  b->dtype = dtype;
+  b->kc = kc;
+  b->lines = all_rows_on_lines(b->fields);
   hipStream_t s = static_cast<hipStream_t>(stream);
   pdiv_status st = PDIV_OK;
   if (flags & PDIV_BATCH_AUTOTUNE) {
-    st = autotune(b, dtype, kc, s);
+    st = autotune(b, s);
   } else {
-    b->band_rows = 16;
-    b->n_tiles = fill_tiles(b->fields, b->band_rows);
+    shape(b, b->lines && kc >= 8, 16);
     b->grid = resident_blocks(b->kernel);
     st = upload(b);
   }
@@ -376,12 +406,12 @@ pdiv_status pdiv_batch_launch(pdiv_batch b, pdiv_stream stream) {
   return device_status(e, "batch launch");
 }
 
-pdiv_status pdiv_batch_info(pdiv_batch b, int32_t* band_rows, int32_t* lane_cols,
+pdiv_status pdiv_batch_info(pdiv_batch b, int32_t* band_rows, int32_t* strip_cells,
                             int64_t* n_tiles) {
   g_last_error.clear();
   if (b == nullptr) return invalid("batch is NULL");
   if (band_rows) *band_rows = b->band_rows;
-  if (lane_cols) *lane_cols = 2;
+  if (strip_cells) *strip_cells = cells_per_wave(b->paired);
   if (n_tiles) *n_tiles = b->n_tiles;
   return PDIV_OK;
 }

@@ -34,8 +34,9 @@ struct StencilCoef {
 };
 StencilCoef make_coef(double dx, double dy);
 
-// Tile shape of the column-walking LCP kernels: one wave covers 128 cells
-// (129 vertex columns) of a band of `band_rows` cell rows.
+// Tile shape of the column-walking LCP kernels: one wave covers a strip of
+// 128 (paired layout) or 126 cells (split layout) over a band of `band_rows`
+// cell rows; 0 lets the launcher choose per layout.
 struct LcpShape {
   int band_rows;
 };

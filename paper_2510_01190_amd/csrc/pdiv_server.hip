@@ -399,11 +399,12 @@ struct pdiv_server_s {
         kc = std::max(kc, iso_bucket(r->n_iso));
         cells_here += double(x.plane) * r->n_iso;
       }
-      const int64_t n_tiles = fill_tiles(fv, kBandRows);
+      const bool paired = kc >= 8 && all_rows_on_lines(fv);
+      const int64_t n_tiles = fill_tiles(fv, kBandRows, paired);
       std::memcpy(S.host_fields, fv.data(), sizeof(BatchField) * fv.size());
       hipStream_t s = streams[next_stream];
       next_stream = (next_stream + 1) % n_streams;
-      const void* kernel = batch_kernel_ptr(false, PDIV_F32, kc);
+      const void* kernel = batch_kernel_ptr(false, PDIV_F32, kc, paired);
       const int grid =
           int(std::max<int64_t>(1, std::min<int64_t>(resident_blocks(kernel), (n_tiles + 3) / 4)));
       Launch L;

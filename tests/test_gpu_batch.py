@@ -122,3 +122,26 @@ def test_batch_pitched_outputs():
         assert torch.equal(g["lcp"], _per_field(f))
         assert bool((buf[:, :, nx - 1:] == -3.0).all())
     b.close()
+
+
+def test_autotuned_batch_with_line_aligned_outputs(tmp_path, monkeypatch):
+    """With every output row on a 128-byte line the autotuner also times the
+    paired tile layout; whichever it keeps, the maps are the per-field ones,
+    and a second batch reads the choice back from the cache file."""
+    monkeypatch.setenv("PDIV_TUNE_CACHE", str(tmp_path / "tune.json"))
+    fields = _fields(24, 40, 400, seed=9, kmax=16)
+    for f in fields:
+        ny, nx = f["mean_u"].shape
+        f["lcp"] = P.empty_lcp(f["iso_host"].size, ny, nx)
+    b = P.Batch(fields, graph=True, autotune=True)
+    b.launch()
+    torch.cuda.synchronize()
+    info = b.info()
+    assert info["strip_cells"] in (126, 128)
+    for f, g in zip(fields, b.fields):
+        assert torch.equal(g["lcp"], _per_field(f))
+    b.close()
+    assert "/l1/" in (tmp_path / "tune.json").read_text()
+    b2 = P.Batch(fields, graph=False, autotune=True)
+    assert b2.info() == info
+    b2.close()

@@ -68,19 +68,25 @@ def test_lcp_parity(shape, k):
     assert torch.equal(L, Lf)
 
 
-@pytest.mark.parametrize("shape", [(65, 129), (40, 258), (130, 190), (3, 2)])
+@pytest.mark.parametrize("shape", [(65, 129), (40, 258), (130, 190), (3, 2), (33, 128),
+                                   (17, 130), (9, 257), (70, 4034)])
 def test_pitched_output_equals_dense_and_keeps_padding(shape):
     """Rows padded to a longer pitch hold bitwise the dense maps; the padding
-    floats are never written (fused and two-step paths)."""
+    floats are never written (fused and two-step paths).  Nine isovalues run
+    as a chunk of 8, which takes the paired tile when the rows start on
+    128-byte lines, and a chunk of 1 (split tile): the dense maps come from the
+    split tile only, so this also checks that the two layouts agree bit for
+    bit, seam column included."""
     ny, nx = shape
     f = _field(ny, nx, seed=5 + nx)
     ts = moments_dev(f)
-    iso = np.array([-0.05, 0.0, 0.02], np.float32)
+    iso = np.array([-0.05, -0.02, -0.01, 0.0, 0.004, 0.01, 0.02, 0.03, 0.06], np.float32)
+    K = iso.size
     dense = P.lcp_from_moments(*ts, iso)
     dm, dv = P.divergence_gaussian(*ts)
     for pitch in ((nx - 1 + 31) // 32 * 32, nx + 40):
         for fused in (True, False):
-            buf = torch.full((3, ny - 1, pitch), -7.0, device="cuda")
+            buf = torch.full((K, ny - 1, pitch), -7.0, device="cuda")
             view = buf[:, :, : nx - 1]
             if fused:
                 P.lcp_from_moments(*ts, iso, out=view)
@@ -89,9 +95,11 @@ def test_pitched_output_equals_dense_and_keeps_padding(shape):
             torch.cuda.synchronize()
             assert torch.equal(view, dense)
             assert bool((buf[:, :, nx - 1:] == -7.0).all())
-    e = P.empty_lcp(3, ny, nx)
+    e = P.empty_lcp(K, ny, nx)
     assert e.stride(1) % 32 == 0 and e.stride(1) >= nx - 1
     assert torch.equal(P.lcp_from_moments(*ts, iso, out=e), dense)
+    ref = O.lcp(host64(dm), host64(dv), iso)
+    assert err_report(host64(e), ref)["max_abs"] <= LCP_TOL
 
 
 def test_pitched_output_views():
