@@ -215,22 +215,19 @@ __device__ __forceinline__ float to_lane63(float v, int s) {
   return v;
 }
 
-// Paired layout, one vertex row step: the corners of row j+1 (from raw values loaded
-// earlier) for the lane's columns E and O and its seam column, their pairs
-// with row j (cor_*, which then take row j+1's corners), and the lane's two
-// cells for every isovalue.  off is the byte offset of the lane's first cell
-// within an output row.
-template <int KC, bool FUSED, bool STREAM>
-__device__ __forceinline__ void row_step_paired(const Raw<FUSED>& raw_e, const Raw<FUSED>& raw_o,
-                                         const Raw<FUSED>& raw_s, const Col& ce, const Col& co,
-                                         const Col& cs, int ny, const StencilCoef& k,
-                                         const IsoChunk& iso, float c_seam, int n_store,
-                                         float* __restrict__ out, int64_t plane, int64_t pitch,
-                                         uint32_t row_bytes, int j, uint32_t off,
-                                         AB (&cor_e)[KC], AB (&cor_o)[KC], AB& cor_s) {
-  const Corner ke = make_corner(raw_div(raw_e, ce.bx, j + 1, ny, k));
-  const Corner ko = make_corner(raw_div(raw_o, co.bx, j + 1, ny, k));
-  const Corner ks = make_corner(raw_div(raw_s, cs.bx, j + 1, ny, k));
+// Paired layout, the cells of one row step: given the corners of row j+1 for
+// the lane's columns E and O and its seam column, their pairs with row j
+// (cor_*, which then take row j+1's corners), and the lane's two cells for
+// every isovalue.  off is the byte offset of the lane's first cell within an
+// output row.
+template <int KC, bool STREAM>
+__device__ __forceinline__ void row_cells_paired(const Corner& ke, const Corner& ko,
+                                                 const Corner& ks, const IsoChunk& iso,
+                                                 float c_seam, int n_store,
+                                                 float* __restrict__ out, int64_t plane,
+                                                 int64_t pitch, uint32_t row_bytes, int j,
+                                                 uint32_t off, AB (&cor_e)[KC], AB (&cor_o)[KC],
+                                                 AB& cor_s) {
   // seam: lane 2q holds cell x0+127 at isovalue q
   const AB cur_s = corner_probs(ks, c_seam);
   const float seam = cell_lcp_dpp(make_pair(cor_s, cur_s), cur_s.below);
@@ -250,7 +247,29 @@ __device__ __forceinline__ void row_step_paired(const Raw<FUSED>& raw_e, const R
     w.put2(l_e, l_o, off);
     cor_e[q] = cur_e;
     cor_o[q] = cur_o;
+    // Keep the isovalues in order: left alone the scheduler evaluates the
+    // tails of later isovalues early and holds them, which costs 25 VGPRs
+    // and the third wave per SIMD.
+    __builtin_amdgcn_sched_barrier(0);
   }
+}
+
+// Paired layout, one vertex row step from raw values loaded earlier.
+template <int KC, bool FUSED, bool STREAM>
+__device__ __forceinline__ void row_step_paired(const Raw<FUSED>& raw_e, const Raw<FUSED>& raw_o,
+                                                const Raw<FUSED>& raw_s, const Col& ce,
+                                                const Col& co, const Col& cs, int ny,
+                                                const StencilCoef& k, const IsoChunk& iso,
+                                                float c_seam, int n_store,
+                                                float* __restrict__ out, int64_t plane,
+                                                int64_t pitch, uint32_t row_bytes, int j,
+                                                uint32_t off, AB (&cor_e)[KC], AB (&cor_o)[KC],
+                                                AB& cor_s) {
+  row_cells_paired<KC, STREAM>(make_corner(raw_div(raw_e, ce.bx, j + 1, ny, k)),
+                               make_corner(raw_div(raw_o, co.bx, j + 1, ny, k)),
+                               make_corner(raw_div(raw_s, cs.bx, j + 1, ny, k)), iso, c_seam,
+                               n_store, out, plane, pitch, row_bytes, j, off, cor_e, cor_o,
+                               cor_s);
 }
 
 // Paired tile: cell columns [x0, x0+128) of strip `strip` (x0 = 128 strip),
@@ -332,6 +351,175 @@ __device__ __forceinline__ void lcp_tile_paired(const T* __restrict__ p0, const 
   if (j < j1) step(e1, o1, s1, j);  // e1.. hold row j + 1 == j1
 }
 
+// ---------------------------------------------------------------------------
+// Paired tile with float32 moment planes: input rows staged through LDS.
+//
+// The fused tile needs, per vertex row, the four moment planes over the strip's
+// columns x0-1 .. x0+129 (x differences and the seam).  Instead of per-lane
+// loads into registers, each row is copied once into a per-wave LDS ring by
+// direct memory-to-LDS loads (buffer_load ... lds: 64 lanes x 4 bytes per
+// instruction, 9 instructions per row), kRingRows - 3 = 2 row steps ahead of
+// its first use, and the stencil values are read from LDS.  This takes the
+// in-flight rows out of the vector registers (three waves per SIMD instead of
+// two) and deepens the prefetch.  Slot layout (floats): array a (mu, var_u,
+// mv, var_v) index i = column - (x0 - 1), i < 128 at 128 a + i, i in
+// 128..130 at 512 + 16 a + (i - 128).
+//
+// The compiler does not order these loads with later LDS reads, so each step
+// waits explicitly (s_waitcnt vmcnt) for the one row it is about to read.
+// Every step issues the same memory operations in the same order (9 row
+// loads, then KC stores), so the count of operations issued after a given row
+// load is a constant: a row read at step j was loaded at step j - 2, followed
+// by 2 KC + 18 operations (KC <= 16 keeps this within the counter's 63).
+// ---------------------------------------------------------------------------
+constexpr int kRingRows = 5;
+constexpr int kSlotFloats = 4 * 128 + 64;
+constexpr int kTileWaves = 4;  // waves per block of the kernels that run tiles
+
+typedef __attribute__((address_space(3))) float lds_float;
+typedef __attribute__((address_space(3))) char lds_char;
+
+template <int N>
+__device__ __forceinline__ void wait_vmcnt() {
+  asm volatile("s_waitcnt vmcnt(%0)" ::"n"(N) : "memory");
+}
+
+// byte offset in a slot of array a at index i (column x0 - 1 + i), i < 131
+__device__ __forceinline__ uint32_t slot_off(uint32_t a, uint32_t i) {
+  return i < 128 ? (a * 128 + i) * 4 : (512 + a * 16 + (i - 128)) * 4;
+}
+
+__device__ __forceinline__ float lds_at(const lds_char* base, uint32_t off) {
+  return *reinterpret_cast<const lds_float*>(base + off);
+}
+
+template <int KC, bool STREAM>
+__device__ __forceinline__ void lcp_tile_paired_lds(const float* __restrict__ mu,
+                                                    const float* __restrict__ vu,
+                                                    const float* __restrict__ mv,
+                                                    const float* __restrict__ vv, int ny, int nx,
+                                                    const StencilCoef& k, const IsoChunk& iso,
+                                                    int n_store, float* __restrict__ out,
+                                                    int64_t plane, int64_t pitch, int strip,
+                                                    int j0, int j1) {
+  static_assert(2 * KC <= kWave && KC <= 16, "seam lanes and the wait count");
+  __shared__ float ring_block[kTileWaves * kRingRows * kSlotFloats];
+  const uint32_t lane = threadIdx.x & 63;
+  const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+  lds_float* ring = (lds_float*)(ring_block) + wave * (kRingRows * kSlotFloats);
+  const int last = nx - 1;
+  const int x0 = strip * kPairedCells;
+  // row loads: lane L of chunk c reads column x0 - 1 + 64 c + L (clamped)
+  const uint32_t voff0 = uint32_t(min(max(x0 - 1 + int(lane), 0), last)) * 4u;
+  const uint32_t voff1 = uint32_t(min(max(x0 + 63 + int(lane), 0), last)) * 4u;
+  // tail load: lane 16 a + t reads array a at index 128 + t (t < 3 used)
+  const uint32_t ta = lane >> 4;
+  const float* tbase = ta == 0 ? mu : ta == 1 ? vu : ta == 2 ? mv : vv;
+  const float* tail_src = tbase + min(max(x0 + 127 + int(lane & 15), 0), last);
+  const uint32_t rb = uint32_t(nx) * 4u;
+
+  auto load_row = [&](int rho) {  // logical row rho = vertex row j0 - 1 + rho, clamped
+    const int y = min(max(j0 - 1 + rho, 0), ny - 1);
+    lds_float* slot = ring + (rho % kRingRows) * kSlotFloats;
+    const int64_t ro = static_cast<int64_t>(y) * nx;
+    const float* planes[4] = {mu, vu, mv, vv};
+#pragma unroll
+    for (int a = 0; a < 4; ++a) {
+      const __amdgpu_buffer_rsrc_t r = __builtin_amdgcn_make_buffer_rsrc(
+          const_cast<float*>(planes[a] + ro), 0, static_cast<int>(rb), 0x00020000);
+      __builtin_amdgcn_raw_ptr_buffer_load_lds(r, slot + a * 128, 4, voff0, 0, 0, 0);
+      __builtin_amdgcn_raw_ptr_buffer_load_lds(r, slot + a * 128 + 64, 4, voff1, 0, 0, 0);
+    }
+    __builtin_amdgcn_global_load_lds(tail_src + ro, slot + 512, 4, 0, 0);
+  };
+
+  // per lane: indices of columns E = x0 + 2L, O = E + 1, seam S = x0+127+(L&1)
+  const uint32_t ie = 2 * lane + 1, io = ie + 1, is = 128 + (lane & 1);
+  const uint32_t m_el = slot_off(0, ie - 1), m_er = slot_off(0, ie + 1);
+  const uint32_t m_ol = slot_off(0, io - 1), m_or = slot_off(0, io + 1);
+  const uint32_t m_sl = slot_off(0, is - 1), m_sr = slot_off(0, is + 1);
+  const uint32_t w_el = slot_off(1, ie - 1), w_er = slot_off(1, ie + 1);
+  const uint32_t w_ol = slot_off(1, io - 1), w_or = slot_off(1, io + 1);
+  const uint32_t w_sl = slot_off(1, is - 1), w_sr = slot_off(1, is + 1);
+  const uint32_t n_e = slot_off(2, ie), n_o = slot_off(2, io), n_s = slot_off(2, is);
+  const uint32_t z_e = slot_off(3, ie), z_o = slot_off(3, io), z_s = slot_off(3, is);
+  const uint32_t xe = uint32_t(x0) + 2 * lane, xs = uint32_t(x0) + 127 + (lane & 1);
+  const uint32_t ulast = uint32_t(last);
+  const bool be = (min(xe, ulast) == 0) | (min(xe, ulast) == ulast);
+  const bool bo = (min(xe + 1, ulast) == ulast);
+  const bool bs = (min(xs, ulast) == ulast);
+  constexpr uint32_t kDrop = 0x7ffffff0u;
+  const uint32_t off = xe < ulast ? xe * 4u : kDrop;
+  const uint32_t row_bytes = ulast * 4u;
+  const int qs = min(int(lane >> 1), KC - 1);
+  float c_seam = iso.c[0];
+#pragma unroll
+  for (int q = 1; q < KC; ++q) c_seam = (qs == q) ? iso.c[q] : c_seam;
+
+  // corners of vertex row r = j0 - 1 + rho (slots rho - 1, rho, rho + 1)
+  struct C3 {
+    Corner e, o, s;
+  };
+  auto corners = [&](int rho, int r) {
+    const lds_char* up = reinterpret_cast<const lds_char*>(ring + ((rho - 1) % kRingRows) * kSlotFloats);
+    const lds_char* at = reinterpret_cast<const lds_char*>(ring + (rho % kRingRows) * kSlotFloats);
+    const lds_char* dn = reinterpret_cast<const lds_char*>(ring + ((rho + 1) % kRingRows) * kSlotFloats);
+    const bool by = (r == 0) | (r == ny - 1);
+    const float cym = by ? k.cym_bd : k.cym_in, cyv = by ? k.cyv_bd : k.cyv_in;
+    auto one = [&](uint32_t ml, uint32_t mr, uint32_t wl, uint32_t wr, uint32_t n, uint32_t z,
+                   bool bx) {
+      return make_corner(div_gauss(lds_at(at, ml), lds_at(at, mr), lds_at(at, wl), lds_at(at, wr),
+                                   lds_at(up, n), lds_at(dn, n), lds_at(up, z), lds_at(dn, z),
+                                   bx ? k.cxm_bd : k.cxm_in, bx ? k.cxv_bd : k.cxv_in, cym, cyv));
+    };
+    C3 c;
+    c.e = one(m_el, m_er, w_el, w_er, n_e, z_e, be);
+    c.o = one(m_ol, m_or, w_ol, w_or, n_o, z_o, bo);
+    c.s = one(m_sl, m_sr, w_sl, w_sr, n_s, z_s, bs);
+    return c;
+  };
+
+  AB pe[KC], po[KC], ps;
+#pragma unroll
+  for (int rho = 0; rho < kRingRows; ++rho) load_row(rho);
+  wait_vmcnt<18>();  // rows 0..2 are in LDS (rows 3 and 4 may still be in flight)
+  {
+    const C3 c = corners(1, j0);
+#pragma unroll
+    for (int q = 0; q < KC; ++q) {
+      pe[q] = corner_probs(c.e, iso.c[q]);
+      po[q] = corner_probs(c.o, iso.c[q]);
+    }
+    ps = corner_probs(c.s, c_seam);
+  }
+  // Cell row j: corners of vertex row j + 1 = logical row j - j0 + 2, which
+  // needs logical rows up to j - j0 + 3; the load issued first is row
+  // j - j0 + 5, for the step two rows on.
+  auto step = [&](int j) {
+    const int rho = j - j0 + 2;
+    load_row(rho + 3);
+    return rho;
+  };
+  auto cells = [&](int j, int rho) {
+    const C3 c = corners(rho, j + 1);
+    row_cells_paired<KC, STREAM>(c.e, c.o, c.s, iso, c_seam, n_store, out, plane, pitch,
+                                 row_bytes, j, off, pe, po, ps);
+  };
+  int j = j0;
+  // The first two rows read rows loaded before the loop, with fewer
+  // operations issued after them: wait as in the prologue (stricter).
+  for (; j < j1 && j < j0 + 2; ++j) {
+    const int rho = step(j);
+    wait_vmcnt<18>();
+    cells(j, rho);
+  }
+  for (; j < j1; ++j) {
+    const int rho = step(j);
+    wait_vmcnt<2 * KC + 18>();
+    cells(j, rho);
+  }
+}
+
 // Split layout, one vertex row step: the corners of row j+1 for the lane's
 // columns A and B, their pairs with row j (cor_*, which then take row j+1's
 // corners), and the lane's two cells for every isovalue; off_a, off_b are the
@@ -379,8 +567,8 @@ __device__ __forceinline__ void lcp_tile_split(const T* __restrict__ p0, const T
   const Col cb = make_col(min(xb, last), nx, sizeof(T));  // valid column, store nothing
   // lane 63 and cells past the right edge get an offset beyond any row
   constexpr uint32_t kDrop = 0x7ffffff0u;
-  const uint32_t off_a = (lane < kSplitHalf) & (xa < last) ? xa * 4u : kDrop;
-  const uint32_t off_b = (lane < kSplitHalf) & (xb < last) ? xb * 4u : kDrop;
+  const uint32_t off_a = ((lane < kSplitHalf) & (xa < last)) ? xa * 4u : kDrop;
+  const uint32_t off_b = ((lane < kSplitHalf) & (xb < last)) ? xb * 4u : kDrop;
   const uint32_t row_bytes = last * 4u;
 
   AB pa[KC], pb[KC];
@@ -436,7 +624,10 @@ __device__ __forceinline__ void lcp_tile(const T* __restrict__ p0, const T* __re
                                          const IsoChunk& iso, int n_store,
                                          float* __restrict__ out, int64_t plane, int64_t pitch,
                                          int strip, int j0, int j1) {
-  if constexpr (PAIRED)
+  if constexpr (PAIRED && FUSED && std::is_same<T, float>::value)
+    lcp_tile_paired_lds<KC, true>(p0, p1, p2, p3, ny, nx, k, iso, n_store, out, plane, pitch,
+                                  strip, j0, j1);
+  else if constexpr (PAIRED)
     lcp_tile_paired<KC, FUSED, true>(p0, p1, p2, p3, ny, nx, k, iso, n_store, out, plane, pitch,
                                      strip, j0, j1);
   else
