@@ -518,6 +518,11 @@ __device__ __forceinline__ void lcp_tile_paired_lds(const float* __restrict__ mu
     wait_vmcnt<2 * KC + 18>();
     cells(j, rho);
   }
+  // The loads of rows past the band are still in flight.  Let them land
+  // before the ring is reused (the batch kernel's next tile writes the same
+  // slots) or released with the wave: only the last step's KC stores, issued
+  // after the last load, may remain outstanding.
+  wait_vmcnt<KC>();
 }
 
 // Split layout, one vertex row step: the corners of row j+1 for the lane's
