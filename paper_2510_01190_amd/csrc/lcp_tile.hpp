@@ -352,7 +352,7 @@ __device__ __forceinline__ void lcp_tile_paired(const T* __restrict__ p0, const 
 }
 
 // ---------------------------------------------------------------------------
-// Paired tile with float32 moment planes: input rows staged through LDS.
+// Paired tile, fused: input rows staged through LDS.
 //
 // The fused tile needs, per vertex row, the four moment planes over the strip's
 // columns x0-1 .. x0+129 (x differences and the seam).  Instead of per-lane
@@ -361,9 +361,11 @@ __device__ __forceinline__ void lcp_tile_paired(const T* __restrict__ p0, const 
 // instruction, 9 instructions per row), kRingRows - 3 = 2 row steps ahead of
 // its first use, and the stencil values are read from LDS.  This takes the
 // in-flight rows out of the vector registers (three waves per SIMD instead of
-// two) and deepens the prefetch.  Slot layout (floats): array a (mu, var_u,
+// two) and deepens the prefetch.  Slot layout (dwords): array a (mu, var_u,
 // mv, var_v) index i = column - (x0 - 1), i < 128 at 128 a + i, i in
-// 128..130 at 512 + 16 a + (i - 128).
+// 128..130 at 512 + 16 a + (i - 128).  A 16-bit element loads the same way
+// (each lane still writes one dword, the value zero-extended), so the layout
+// does not depend on the storage type.
 //
 // The compiler does not order these loads with later LDS reads, so each step
 // waits explicitly (s_waitcnt vmcnt) for the one row it is about to read.
@@ -389,15 +391,44 @@ __device__ __forceinline__ uint32_t slot_off(uint32_t a, uint32_t i) {
   return i < 128 ? (a * 128 + i) * 4 : (512 + a * 16 + (i - 128)) * 4;
 }
 
-__device__ __forceinline__ float lds_at(const lds_char* base, uint32_t off) {
-  return *reinterpret_cast<const lds_float*>(base + off);
+typedef __attribute__((address_space(3))) uint32_t lds_u32;
+
+// One memory-to-LDS load of an element of B bytes per lane (the builtins
+// take the size as a literal).
+template <int B>
+__device__ __forceinline__ void load_to_lds(__amdgpu_buffer_rsrc_t r, lds_float* dst,
+                                            uint32_t voff) {
+  if constexpr (B == 4)
+    __builtin_amdgcn_raw_ptr_buffer_load_lds(r, dst, 4, voff, 0, 0, 0);
+  else
+    __builtin_amdgcn_raw_ptr_buffer_load_lds(r, dst, 2, voff, 0, 0, 0);
+}
+template <int B, typename T>
+__device__ __forceinline__ void load_to_lds(const T* src, lds_float* dst) {
+  if constexpr (B == 4)
+    __builtin_amdgcn_global_load_lds(src, dst, 4, 0, 0);
+  else
+    __builtin_amdgcn_global_load_lds(src, dst, 2, 0, 0);
 }
 
-template <int KC, bool STREAM>
-__device__ __forceinline__ void lcp_tile_paired_lds(const float* __restrict__ mu,
-                                                    const float* __restrict__ vu,
-                                                    const float* __restrict__ mv,
-                                                    const float* __restrict__ vv, int ny, int nx,
+// ring entry at byte offset off as float32 (a 16-bit element sits in the low
+// half of its dword)
+template <typename T>
+__device__ __forceinline__ float lds_at(const lds_char* base, uint32_t off) {
+  const uint32_t w = *reinterpret_cast<const lds_u32*>(base + off);
+  if constexpr (std::is_same<T, float>::value)
+    return __uint_as_float(w);
+  else if constexpr (std::is_same<T, __half>::value)
+    return __half2float(__ushort_as_half(static_cast<unsigned short>(w)));
+  else
+    return __uint_as_float(w << 16);
+}
+
+template <int KC, bool STREAM, typename T>
+__device__ __forceinline__ void lcp_tile_paired_lds(const T* __restrict__ mu,
+                                                    const T* __restrict__ vu,
+                                                    const T* __restrict__ mv,
+                                                    const T* __restrict__ vv, int ny, int nx,
                                                     const StencilCoef& k, const IsoChunk& iso,
                                                     int n_store, float* __restrict__ out,
                                                     int64_t plane, int64_t pitch, int strip,
@@ -410,27 +441,28 @@ __device__ __forceinline__ void lcp_tile_paired_lds(const float* __restrict__ mu
   const int last = nx - 1;
   const int x0 = strip * kPairedCells;
   // row loads: lane L of chunk c reads column x0 - 1 + 64 c + L (clamped)
-  const uint32_t voff0 = uint32_t(min(max(x0 - 1 + int(lane), 0), last)) * 4u;
-  const uint32_t voff1 = uint32_t(min(max(x0 + 63 + int(lane), 0), last)) * 4u;
+  constexpr uint32_t kSize = sizeof(T);
+  const uint32_t voff0 = uint32_t(min(max(x0 - 1 + int(lane), 0), last)) * kSize;
+  const uint32_t voff1 = uint32_t(min(max(x0 + 63 + int(lane), 0), last)) * kSize;
   // tail load: lane 16 a + t reads array a at index 128 + t (t < 3 used)
   const uint32_t ta = lane >> 4;
-  const float* tbase = ta == 0 ? mu : ta == 1 ? vu : ta == 2 ? mv : vv;
-  const float* tail_src = tbase + min(max(x0 + 127 + int(lane & 15), 0), last);
-  const uint32_t rb = uint32_t(nx) * 4u;
+  const T* tbase = ta == 0 ? mu : ta == 1 ? vu : ta == 2 ? mv : vv;
+  const T* tail_src = tbase + min(max(x0 + 127 + int(lane & 15), 0), last);
+  const uint32_t rb = uint32_t(nx) * kSize;
 
   auto load_row = [&](int rho) {  // logical row rho = vertex row j0 - 1 + rho, clamped
     const int y = min(max(j0 - 1 + rho, 0), ny - 1);
     lds_float* slot = ring + (rho % kRingRows) * kSlotFloats;
     const int64_t ro = static_cast<int64_t>(y) * nx;
-    const float* planes[4] = {mu, vu, mv, vv};
+    const T* planes[4] = {mu, vu, mv, vv};
 #pragma unroll
     for (int a = 0; a < 4; ++a) {
       const __amdgpu_buffer_rsrc_t r = __builtin_amdgcn_make_buffer_rsrc(
-          const_cast<float*>(planes[a] + ro), 0, static_cast<int>(rb), 0x00020000);
-      __builtin_amdgcn_raw_ptr_buffer_load_lds(r, slot + a * 128, 4, voff0, 0, 0, 0);
-      __builtin_amdgcn_raw_ptr_buffer_load_lds(r, slot + a * 128 + 64, 4, voff1, 0, 0, 0);
+          const_cast<T*>(planes[a] + ro), 0, static_cast<int>(rb), 0x00020000);
+      load_to_lds<sizeof(T)>(r, slot + a * 128, voff0);
+      load_to_lds<sizeof(T)>(r, slot + a * 128 + 64, voff1);
     }
-    __builtin_amdgcn_global_load_lds(tail_src + ro, slot + 512, 4, 0, 0);
+    load_to_lds<sizeof(T)>(tail_src + ro, slot + 512);
   };
 
   // per lane: indices of columns E = x0 + 2L, O = E + 1, seam S = x0+127+(L&1)
@@ -468,8 +500,9 @@ __device__ __forceinline__ void lcp_tile_paired_lds(const float* __restrict__ mu
     const float cym = by ? k.cym_bd : k.cym_in, cyv = by ? k.cyv_bd : k.cyv_in;
     auto one = [&](uint32_t ml, uint32_t mr, uint32_t wl, uint32_t wr, uint32_t n, uint32_t z,
                    bool bx) {
-      return make_corner(div_gauss(lds_at(at, ml), lds_at(at, mr), lds_at(at, wl), lds_at(at, wr),
-                                   lds_at(up, n), lds_at(dn, n), lds_at(up, z), lds_at(dn, z),
+      return make_corner(div_gauss(lds_at<T>(at, ml), lds_at<T>(at, mr), lds_at<T>(at, wl),
+                                   lds_at<T>(at, wr), lds_at<T>(up, n), lds_at<T>(dn, n),
+                                   lds_at<T>(up, z), lds_at<T>(dn, z),
                                    bx ? k.cxm_bd : k.cxm_in, bx ? k.cxv_bd : k.cxv_in, cym, cyv));
     };
     C3 c;
@@ -629,7 +662,7 @@ __device__ __forceinline__ void lcp_tile(const T* __restrict__ p0, const T* __re
                                          const IsoChunk& iso, int n_store,
                                          float* __restrict__ out, int64_t plane, int64_t pitch,
                                          int strip, int j0, int j1) {
-  if constexpr (PAIRED && FUSED && std::is_same<T, float>::value)
+  if constexpr (PAIRED && FUSED)
     lcp_tile_paired_lds<KC, true>(p0, p1, p2, p3, ny, nx, k, iso, n_store, out, plane, pitch,
                                   strip, j0, j1);
   else if constexpr (PAIRED)
