@@ -215,10 +215,20 @@ __device__ __forceinline__ float to_lane63(float v, int s) {
   return v;
 }
 
+// Corner probabilities carried from one vertex row to the next, per
+// isovalue: the lane's columns E and O and its seam column (paired layout).
+template <int KC>
+struct PairedCarry {
+  AB e[KC], o[KC], s;
+};
+
 // Paired layout, the cells of one row step: given the corners of row j+1 for
 // the lane's columns E and O and its seam column, their pairs with row j
-// (cor_*, which then take row j+1's corners), and the lane's two cells for
-// every isovalue.  off is the byte offset of the lane's first cell within an
+// (prev_*; row j+1's corner probabilities go to next_*), and the lane's two
+// cells for every isovalue.  prev and next may be the same set (updated in
+// place: a register move per carried value and row, since the old and new
+// values are live together) or two sets that the walk alternates (no moves,
+// more registers).  off is the byte offset of the lane's first cell within an
 // output row.
 template <int KC, bool STREAM>
 __device__ __forceinline__ void row_cells_paired(const Corner& ke, const Corner& ko,
@@ -226,27 +236,29 @@ __device__ __forceinline__ void row_cells_paired(const Corner& ke, const Corner&
                                                  float c_seam, int n_store,
                                                  float* __restrict__ out, int64_t plane,
                                                  int64_t pitch, uint32_t row_bytes, int j,
-                                                 uint32_t off, AB (&cor_e)[KC], AB (&cor_o)[KC],
-                                                 AB& cor_s) {
+                                                 uint32_t off, const AB (&prev_e)[KC],
+                                                 const AB (&prev_o)[KC], const AB& prev_s,
+                                                 AB (&next_e)[KC], AB (&next_o)[KC],
+                                                 AB& next_s) {
   // seam: lane 2q holds cell x0+127 at isovalue q
   const AB cur_s = corner_probs(ks, c_seam);
-  const float seam = cell_lcp_dpp(make_pair(cor_s, cur_s), cur_s.below);
-  cor_s = cur_s;
+  const float seam = cell_lcp_dpp(make_pair(prev_s, cur_s), cur_s.below);
+  next_s = cur_s;
   float* __restrict__ orow = out + static_cast<int64_t>(j) * pitch;
 #pragma unroll
   for (int q = 0; q < KC; ++q) {
     const AB cur_e = corner_probs(ke, iso.c[q]);
     const AB cur_o = corner_probs(ko, iso.c[q]);
-    const Pair pe = make_pair(cor_e[q], cur_e);
-    const Pair po = make_pair(cor_o[q], cur_o);
+    const Pair pe = make_pair(prev_e[q], cur_e);
+    const Pair po = make_pair(prev_o[q], cur_o);
     const float l_e = cell_lcp_local(pe, po, cur_e.below);
     float l_o = cell_lcp_dpp_next(po, pe, cur_o.below);
     l_o = to_lane63(l_o, __builtin_amdgcn_readlane(__float_as_int(seam), 2 * q));
     // planes past n_store (a batch's padding) get an empty record range
     const RowWriter<STREAM> w(orow + q * plane, q < n_store ? row_bytes : 0u);
     w.put2(l_e, l_o, off);
-    cor_e[q] = cur_e;
-    cor_o[q] = cur_o;
+    next_e[q] = cur_e;
+    next_o[q] = cur_o;
     // Keep the isovalues in order: left alone the scheduler evaluates the
     // tails of later isovalues early and holds them, which costs 25 VGPRs
     // and the third wave per SIMD.
@@ -263,13 +275,14 @@ __device__ __forceinline__ void row_step_paired(const Raw<FUSED>& raw_e, const R
                                                 float c_seam, int n_store,
                                                 float* __restrict__ out, int64_t plane,
                                                 int64_t pitch, uint32_t row_bytes, int j,
-                                                uint32_t off, AB (&cor_e)[KC], AB (&cor_o)[KC],
-                                                AB& cor_s) {
+                                                uint32_t off, const AB (&prev_e)[KC],
+                                                const AB (&prev_o)[KC], const AB& prev_s,
+                                                AB (&next_e)[KC], AB (&next_o)[KC], AB& next_s) {
   row_cells_paired<KC, STREAM>(make_corner(raw_div(raw_e, ce.bx, j + 1, ny, k)),
                                make_corner(raw_div(raw_o, co.bx, j + 1, ny, k)),
                                make_corner(raw_div(raw_s, cs.bx, j + 1, ny, k)), iso, c_seam,
-                               n_store, out, plane, pitch, row_bytes, j, off, cor_e, cor_o,
-                               cor_s);
+                               n_store, out, plane, pitch, row_bytes, j, off, prev_e, prev_o,
+                               prev_s, next_e, next_o, next_s);
 }
 
 // Paired tile: cell columns [x0, x0+128) of strip `strip` (x0 = 128 strip),
@@ -305,18 +318,19 @@ __device__ __forceinline__ void lcp_tile_paired(const T* __restrict__ p0, const 
 #pragma unroll
   for (int q = 1; q < KC; ++q) c_seam = (qs == q) ? iso.c[q] : c_seam;
 
-  // Corners of the walk's current vertex row, per isovalue; each row step
-  // consumes them and leaves the next row's in their place.
-  AB pe[KC], po[KC], ps;
+  // corner probabilities of the walk's current vertex row, two alternating sets
+  PairedCarry<KC> ca, cb;
   Raw<FUSED> e0, o0, s0, e1, o1, s1;
   auto load3 = [&](Raw<FUSED>& re, Raw<FUSED>& ro, Raw<FUSED>& rs_, int j) {
     load_raw(re, p0, p1, p2, p3, ny, nx, ce, j);
     load_raw(ro, p0, p1, p2, p3, ny, nx, co, j);
     load_raw(rs_, p0, p1, p2, p3, ny, nx, cs, j);
   };
-  auto step = [&](const Raw<FUSED>& re, const Raw<FUSED>& ro, const Raw<FUSED>& rs_, int j) {
-    row_step_paired<KC, FUSED, STREAM>(re, ro, rs_, ce, co, cs, ny, k, iso, c_seam, n_store, out, plane, pitch,
-                        row_bytes, j, off, pe, po, ps);
+  auto step = [&](const Raw<FUSED>& re, const Raw<FUSED>& ro, const Raw<FUSED>& rs_, int j,
+                  const PairedCarry<KC>& prev, PairedCarry<KC>& next) {
+    row_step_paired<KC, FUSED, STREAM>(re, ro, rs_, ce, co, cs, ny, k, iso, c_seam, n_store,
+                                       out, plane, pitch, row_bytes, j, off, prev.e, prev.o,
+                                       prev.s, next.e, next.o, next.s);
   };
   load3(e0, o0, s0, j0);
   load3(e1, o1, s1, j0 + 1);
@@ -326,10 +340,10 @@ __device__ __forceinline__ void lcp_tile_paired(const T* __restrict__ p0, const 
     const Corner c2 = make_corner(raw_div(s0, cs.bx, j0, ny, k));
 #pragma unroll
     for (int q = 0; q < KC; ++q) {
-      pe[q] = corner_probs(c0, iso.c[q]);
-      po[q] = corner_probs(c1, iso.c[q]);
+      ca.e[q] = corner_probs(c0, iso.c[q]);
+      ca.o[q] = corner_probs(c1, iso.c[q]);
     }
-    ps = corner_probs(c2, c_seam);
+    ca.s = corner_probs(c2, c_seam);
   }
   // Two rows per trip: the raw loads of the row after next are issued before
   // the next row is computed.  A trip has no branches (the prefetch row is
@@ -339,16 +353,16 @@ __device__ __forceinline__ void lcp_tile_paired(const T* __restrict__ p0, const 
   // for the stores of the row before.  An odd last row is done after the loop.
   auto trip = [&](int j) {
     load3(e0, o0, s0, j + 2);
-    step(e1, o1, s1, j);
+    step(e1, o1, s1, j, ca, cb);
     load3(e1, o1, s1, min(j + 3, j1));
-    step(e0, o0, s0, j + 1);
+    step(e0, o0, s0, j + 1, cb, ca);
   };
   int j = j0;
   if (j + 2 <= j1) {
     trip(j);
     for (j += 2; j + 2 <= j1; j += 2) trip(j);
   }
-  if (j < j1) step(e1, o1, s1, j);  // e1.. hold row j + 1 == j1
+  if (j < j1) step(e1, o1, s1, j, ca, cb);  // e1.. hold row j + 1 == j1
 }
 
 // ---------------------------------------------------------------------------
@@ -512,7 +526,10 @@ __device__ __forceinline__ void lcp_tile_paired_lds(const T* __restrict__ mu,
     return c;
   };
 
-  AB pe[KC], po[KC], ps;
+  // One carried set, updated in place: two alternating sets, as in the
+  // register tiles, save the per-row register moves but need 25 more VGPRs
+  // here, which costs the third wave per SIMD (measured slower).
+  PairedCarry<KC> ca;
 #pragma unroll
   for (int rho = 0; rho < kRingRows; ++rho) load_row(rho);
   wait_vmcnt<18>();  // rows 0..2 are in LDS (rows 3 and 4 may still be in flight)
@@ -520,10 +537,10 @@ __device__ __forceinline__ void lcp_tile_paired_lds(const T* __restrict__ mu,
     const C3 c = corners(1, j0);
 #pragma unroll
     for (int q = 0; q < KC; ++q) {
-      pe[q] = corner_probs(c.e, iso.c[q]);
-      po[q] = corner_probs(c.o, iso.c[q]);
+      ca.e[q] = corner_probs(c.e, iso.c[q]);
+      ca.o[q] = corner_probs(c.o, iso.c[q]);
     }
-    ps = corner_probs(c.s, c_seam);
+    ca.s = corner_probs(c.s, c_seam);
   }
   // Cell row j: corners of vertex row j + 1 = logical row j - j0 + 2, which
   // needs logical rows up to j - j0 + 3; the load issued first is row
@@ -536,7 +553,7 @@ __device__ __forceinline__ void lcp_tile_paired_lds(const T* __restrict__ mu,
   auto cells = [&](int j, int rho) {
     const C3 c = corners(rho, j + 1);
     row_cells_paired<KC, STREAM>(c.e, c.o, c.s, iso, c_seam, n_store, out, plane, pitch,
-                                 row_bytes, j, off, pe, po, ps);
+                                 row_bytes, j, off, ca.e, ca.o, ca.s, ca.e, ca.o, ca.s);
   };
   int j = j0;
   // The first two rows read rows loaded before the loop, with fewer
@@ -569,7 +586,8 @@ __device__ __forceinline__ void row_step_split(const Raw<FUSED>& raw_a, const Ra
                                                int n_store, float* __restrict__ out,
                                                int64_t plane, int64_t pitch, uint32_t row_bytes,
                                                int j, uint32_t off_a, uint32_t off_b,
-                                               AB (&cor_a)[KC], AB (&cor_b)[KC]) {
+                                               const AB (&prev_a)[KC], const AB (&prev_b)[KC],
+                                               AB (&next_a)[KC], AB (&next_b)[KC]) {
   const Corner ka = make_corner(raw_div(raw_a, ca.bx, j + 1, ny, k));
   const Corner kb = make_corner(raw_div(raw_b, cb.bx, j + 1, ny, k));
   float* __restrict__ orow = out + static_cast<int64_t>(j) * pitch;
@@ -577,14 +595,14 @@ __device__ __forceinline__ void row_step_split(const Raw<FUSED>& raw_a, const Ra
   for (int q = 0; q < KC; ++q) {
     const AB cur_a = corner_probs(ka, iso.c[q]);
     const AB cur_b = corner_probs(kb, iso.c[q]);
-    const float l0 = cell_lcp_dpp(make_pair(cor_a[q], cur_a), cur_a.below);
-    const float l1 = cell_lcp_dpp(make_pair(cor_b[q], cur_b), cur_b.below);
+    const float l0 = cell_lcp_dpp(make_pair(prev_a[q], cur_a), cur_a.below);
+    const float l1 = cell_lcp_dpp(make_pair(prev_b[q], cur_b), cur_b.below);
     // planes past n_store (a batch's padding) get an empty record range
     const RowWriter<false> w(orow + q * plane, q < n_store ? row_bytes : 0u);
     w.put(l0, off_a);
     w.put(l1, off_b);
-    cor_a[q] = cur_a;
-    cor_b[q] = cur_b;
+    next_a[q] = cur_a;
+    next_b[q] = cur_b;
   }
 }
 
@@ -609,7 +627,7 @@ __device__ __forceinline__ void lcp_tile_split(const T* __restrict__ p0, const T
   const uint32_t off_b = ((lane < kSplitHalf) & (xb < last)) ? xb * 4u : kDrop;
   const uint32_t row_bytes = last * 4u;
 
-  AB pa[KC], pb[KC];
+  AB pa[KC], pb[KC], qa[KC], qb[KC];  // two alternating sets
   Raw<FUSED> a0, b0, a1, b1;
   load_raw(a0, p0, p1, p2, p3, ny, nx, ca, j0);
   load_raw(b0, p0, p1, p2, p3, ny, nx, cb, j0);
@@ -624,26 +642,27 @@ __device__ __forceinline__ void lcp_tile_split(const T* __restrict__ p0, const T
       pb[q] = corner_probs(c1, iso.c[q]);
     }
   }
-  auto step = [&](const Raw<FUSED>& ra, const Raw<FUSED>& rb, int j) {
+  auto step = [&](const Raw<FUSED>& ra, const Raw<FUSED>& rb, int j, const AB (&prev_a)[KC],
+                  const AB (&prev_b)[KC], AB (&next_a)[KC], AB (&next_b)[KC]) {
     row_step_split<KC, FUSED>(ra, rb, ca, cb, ny, k, iso, n_store, out, plane, pitch,
-                              row_bytes, j, off_a, off_b, pa, pb);
+                              row_bytes, j, off_a, off_b, prev_a, prev_b, next_a, next_b);
   };
   // two rows per trip, as in the paired tile
   auto trip = [&](int j) {
     load_raw(a0, p0, p1, p2, p3, ny, nx, ca, j + 2);
     load_raw(b0, p0, p1, p2, p3, ny, nx, cb, j + 2);
-    step(a1, b1, j);
+    step(a1, b1, j, pa, pb, qa, qb);
     const int jn = min(j + 3, j1);
     load_raw(a1, p0, p1, p2, p3, ny, nx, ca, jn);
     load_raw(b1, p0, p1, p2, p3, ny, nx, cb, jn);
-    step(a0, b0, j + 1);
+    step(a0, b0, j + 1, qa, qb, pa, pb);
   };
   int j = j0;
   if (j + 2 <= j1) {
     trip(j);
     for (j += 2; j + 2 <= j1; j += 2) trip(j);
   }
-  if (j < j1) step(a1, b1, j);  // a1/b1 hold row j + 1 == j1
+  if (j < j1) step(a1, b1, j, pa, pb, qa, qb);  // a1/b1 hold row j + 1 == j1
 }
 
 // Layout choice: the paired tile when every output row starts on a 128-byte
