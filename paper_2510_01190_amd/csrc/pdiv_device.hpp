@@ -161,8 +161,15 @@ __device__ __forceinline__ Corner make_corner(DivGauss g) {
   Corner c;
   c.mean = g.mean + 0.0f;  // -0 becomes +0 (the side test reads the sign bit)
   const bool det = (g.var == 0.0f);
-  // rsqrt of a negative variance is NaN, which then propagates to the LCP
-  c.rs = det ? 0.0f : rsqrtf(g.var * kTwoLn2);
+  // The hardware reciprocal square root (rsqrtf wraps it in a rescaling of
+  // tiny arguments that costs five more instructions per corner and row).
+  // For normal arguments the result is the same; an argument too small for
+  // it gives +inf, clamped to the largest float so that |mu - c| = 0 still
+  // gives a tail argument of 0, not NaN.  A negative variance gives NaN,
+  // which the clamp keeps and which then propagates to the LCP.
+  const float r = __builtin_amdgcn_rsqf(g.var * kTwoLn2);
+  constexpr float kMax = 3.40282347e38f;
+  c.rs = det ? 0.0f : (r > kMax ? kMax : r);
   c.z0 = det ? __builtin_inff() : 0.0f;
   return c;
 }
