@@ -372,24 +372,28 @@ __device__ __forceinline__ void lcp_tile_paired(const T* __restrict__ p0, const 
 // columns x0-1 .. x0+129 (x differences and the seam).  Instead of per-lane
 // loads into registers, each row is copied once into a per-wave LDS ring by
 // direct memory-to-LDS loads (buffer_load ... lds: 64 lanes x 4 bytes per
-// instruction, 9 instructions per row), kRingRows - 3 = 2 row steps ahead of
+// instruction, 3 per plane and row), kRingRows - 3 = 2 row steps ahead of
 // its first use, and the stencil values are read from LDS.  This takes the
 // in-flight rows out of the vector registers (three waves per SIMD instead of
 // two) and deepens the prefetch.  Slot layout (dwords): array a (mu, var_u,
-// mv, var_v) index i = column - (x0 - 1), i < 128 at 128 a + i, i in
-// 128..130 at 512 + 16 a + (i - 128).  A 16-bit element loads the same way
+// mv, var_v) index i = column - (x0 - 1) at 132 a + i, i < 131; the third
+// load of a plane runs on lanes 0..2 only.  With one stride per plane, a
+// lane reads every plane at one base address plus immediate offsets.  A
+// 16-bit element loads the same way
 // (each lane still writes one dword, the value zero-extended), so the layout
 // does not depend on the storage type.
 //
 // The compiler does not order these loads with later LDS reads, so each step
 // waits explicitly (s_waitcnt vmcnt) for the one row it is about to read.
-// Every step issues the same memory operations in the same order (9 row
+// Every step issues the same memory operations in the same order (12 row
 // loads, then KC stores), so the count of operations issued after a given row
 // load is a constant: a row read at step j was loaded at step j - 2, followed
-// by 2 KC + 18 operations (KC <= 16 keeps this within the counter's 63).
+// by 2 KC + 24 operations (KC <= 16 keeps this within the counter's 63).
 // ---------------------------------------------------------------------------
 constexpr int kRingRows = 5;
-constexpr int kSlotFloats = 4 * 128 + 64;
+constexpr int kPlaneStride = 132;  // dwords per plane in a slot (131 used)
+constexpr int kSlotFloats = 4 * kPlaneStride;
+constexpr int kRowLoads = 12;      // memory-to-LDS loads per staged row
 constexpr int kTileWaves = 4;  // waves per block of the kernels that run tiles
 
 typedef __attribute__((address_space(3))) float lds_float;
@@ -400,10 +404,6 @@ __device__ __forceinline__ void wait_vmcnt() {
   asm volatile("s_waitcnt vmcnt(%0)" ::"n"(N) : "memory");
 }
 
-// byte offset in a slot of array a at index i (column x0 - 1 + i), i < 131
-__device__ __forceinline__ uint32_t slot_off(uint32_t a, uint32_t i) {
-  return i < 128 ? (a * 128 + i) * 4 : (512 + a * 16 + (i - 128)) * 4;
-}
 
 typedef __attribute__((address_space(3))) uint32_t lds_u32;
 
@@ -416,13 +416,6 @@ __device__ __forceinline__ void load_to_lds(__amdgpu_buffer_rsrc_t r, lds_float*
     __builtin_amdgcn_raw_ptr_buffer_load_lds(r, dst, 4, voff, 0, 0, 0);
   else
     __builtin_amdgcn_raw_ptr_buffer_load_lds(r, dst, 2, voff, 0, 0, 0);
-}
-template <int B, typename T>
-__device__ __forceinline__ void load_to_lds(const T* src, lds_float* dst) {
-  if constexpr (B == 4)
-    __builtin_amdgcn_global_load_lds(src, dst, 4, 0, 0);
-  else
-    __builtin_amdgcn_global_load_lds(src, dst, 2, 0, 0);
 }
 
 // ring entry at byte offset off as float32 (a 16-bit element sits in the low
@@ -447,7 +440,7 @@ __device__ __forceinline__ void lcp_tile_paired_lds(const T* __restrict__ mu,
                                                     int n_store, float* __restrict__ out,
                                                     int64_t plane, int64_t pitch, int strip,
                                                     int j0, int j1) {
-  static_assert(2 * KC <= kWave && KC <= 16, "seam lanes and the wait count");
+  static_assert(2 * KC <= kWave && 2 * (kRowLoads + KC) <= 63, "seam lanes and the wait count");
   __shared__ float ring_block[kTileWaves * kRingRows * kSlotFloats];
   const uint32_t lane = threadIdx.x & 63;
   const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
@@ -458,10 +451,7 @@ __device__ __forceinline__ void lcp_tile_paired_lds(const T* __restrict__ mu,
   constexpr uint32_t kSize = sizeof(T);
   const uint32_t voff0 = uint32_t(min(max(x0 - 1 + int(lane), 0), last)) * kSize;
   const uint32_t voff1 = uint32_t(min(max(x0 + 63 + int(lane), 0), last)) * kSize;
-  // tail load: lane 16 a + t reads array a at index 128 + t (t < 3 used)
-  const uint32_t ta = lane >> 4;
-  const T* tbase = ta == 0 ? mu : ta == 1 ? vu : ta == 2 ? mv : vv;
-  const T* tail_src = tbase + min(max(x0 + 127 + int(lane & 15), 0), last);
+  const uint32_t voff2 = uint32_t(min(max(x0 + 127 + int(lane), 0), last)) * kSize;
   const uint32_t rb = uint32_t(nx) * kSize;
 
   auto load_row = [&](int rho) {  // logical row rho = vertex row j0 - 1 + rho, clamped
@@ -473,27 +463,23 @@ __device__ __forceinline__ void lcp_tile_paired_lds(const T* __restrict__ mu,
     for (int a = 0; a < 4; ++a) {
       const __amdgpu_buffer_rsrc_t r = __builtin_amdgcn_make_buffer_rsrc(
           const_cast<T*>(planes[a] + ro), 0, static_cast<int>(rb), 0x00020000);
-      load_to_lds<sizeof(T)>(r, slot + a * 128, voff0);
-      load_to_lds<sizeof(T)>(r, slot + a * 128 + 64, voff1);
+      load_to_lds<sizeof(T)>(r, slot + a * kPlaneStride, voff0);
+      load_to_lds<sizeof(T)>(r, slot + a * kPlaneStride + 64, voff1);
+      // indices 128..130 only: lanes 3.. would write into the next plane
+      if (lane < 3) load_to_lds<sizeof(T)>(r, slot + a * kPlaneStride + 128, voff2);
     }
-    load_to_lds<sizeof(T)>(tail_src + ro, slot + 512);
   };
 
   // per lane: indices of columns E = x0 + 2L, O = E + 1, seam S = x0+127+(L&1)
-  const uint32_t ie = 2 * lane + 1, io = ie + 1, is = 128 + (lane & 1);
-  const uint32_t m_el = slot_off(0, ie - 1), m_er = slot_off(0, ie + 1);
-  const uint32_t m_ol = slot_off(0, io - 1), m_or = slot_off(0, io + 1);
-  const uint32_t m_sl = slot_off(0, is - 1), m_sr = slot_off(0, is + 1);
-  const uint32_t w_el = slot_off(1, ie - 1), w_er = slot_off(1, ie + 1);
-  const uint32_t w_ol = slot_off(1, io - 1), w_or = slot_off(1, io + 1);
-  const uint32_t w_sl = slot_off(1, is - 1), w_sr = slot_off(1, is + 1);
-  const uint32_t n_e = slot_off(2, ie), n_o = slot_off(2, io), n_s = slot_off(2, is);
-  const uint32_t z_e = slot_off(3, ie), z_o = slot_off(3, io), z_s = slot_off(3, is);
+  // byte offsets: plane a at a * kPlaneStride * 4, index i at 4 i
+  const uint32_t ie = 2 * lane + 1, is = 128 + (lane & 1);
+  const uint32_t be = ie * 4, bs = is * 4;
+  constexpr uint32_t kP = kPlaneStride * 4;
   const uint32_t xe = uint32_t(x0) + 2 * lane, xs = uint32_t(x0) + 127 + (lane & 1);
   const uint32_t ulast = uint32_t(last);
-  const bool be = (min(xe, ulast) == 0) | (min(xe, ulast) == ulast);
-  const bool bo = (min(xe + 1, ulast) == ulast);
-  const bool bs = (min(xs, ulast) == ulast);
+  const bool bx_e = (min(xe, ulast) == 0) | (min(xe, ulast) == ulast);
+  const bool bx_o = (min(xe + 1, ulast) == ulast);
+  const bool bx_s = (min(xs, ulast) == ulast);
   constexpr uint32_t kDrop = 0x7ffffff0u;
   const uint32_t off = xe < ulast ? xe * 4u : kDrop;
   const uint32_t row_bytes = ulast * 4u;
@@ -512,17 +498,19 @@ __device__ __forceinline__ void lcp_tile_paired_lds(const T* __restrict__ mu,
     const lds_char* dn = reinterpret_cast<const lds_char*>(ring + ((rho + 1) % kRingRows) * kSlotFloats);
     const bool by = (r == 0) | (r == ny - 1);
     const float cym = by ? k.cym_bd : k.cym_in, cyv = by ? k.cyv_bd : k.cyv_in;
-    auto one = [&](uint32_t ml, uint32_t mr, uint32_t wl, uint32_t wr, uint32_t n, uint32_t z,
-                   bool bx) {
-      return make_corner(div_gauss(lds_at<T>(at, ml), lds_at<T>(at, mr), lds_at<T>(at, wl),
-                                   lds_at<T>(at, wr), lds_at<T>(up, n), lds_at<T>(dn, n),
-                                   lds_at<T>(up, z), lds_at<T>(dn, z),
+    // column at byte offset b: U neighbours at b -/+ 4 (planes 0, 1), V at b
+    // in the rows above and below (planes 2, 3)
+    auto one = [&](uint32_t b, bool bx) {
+      return make_corner(div_gauss(lds_at<T>(at, b - 4), lds_at<T>(at, b + 4),
+                                   lds_at<T>(at, b - 4 + kP), lds_at<T>(at, b + 4 + kP),
+                                   lds_at<T>(up, b + 2 * kP), lds_at<T>(dn, b + 2 * kP),
+                                   lds_at<T>(up, b + 3 * kP), lds_at<T>(dn, b + 3 * kP),
                                    bx ? k.cxm_bd : k.cxm_in, bx ? k.cxv_bd : k.cxv_in, cym, cyv));
     };
     C3 c;
-    c.e = one(m_el, m_er, w_el, w_er, n_e, z_e, be);
-    c.o = one(m_ol, m_or, w_ol, w_or, n_o, z_o, bo);
-    c.s = one(m_sl, m_sr, w_sl, w_sr, n_s, z_s, bs);
+    c.e = one(be, bx_e);
+    c.o = one(be + 4, bx_o);
+    c.s = one(bs, bx_s);
     return c;
   };
 
@@ -532,7 +520,7 @@ __device__ __forceinline__ void lcp_tile_paired_lds(const T* __restrict__ mu,
   PairedCarry<KC> ca;
 #pragma unroll
   for (int rho = 0; rho < kRingRows; ++rho) load_row(rho);
-  wait_vmcnt<18>();  // rows 0..2 are in LDS (rows 3 and 4 may still be in flight)
+  wait_vmcnt<2 * kRowLoads>();  // rows 0..2 are in LDS (rows 3 and 4 may be in flight)
   {
     const C3 c = corners(1, j0);
 #pragma unroll
@@ -560,12 +548,12 @@ __device__ __forceinline__ void lcp_tile_paired_lds(const T* __restrict__ mu,
   // operations issued after them: wait as in the prologue (stricter).
   for (; j < j1 && j < j0 + 2; ++j) {
     const int rho = step(j);
-    wait_vmcnt<18>();
+    wait_vmcnt<2 * kRowLoads>();
     cells(j, rho);
   }
   for (; j < j1; ++j) {
     const int rho = step(j);
-    wait_vmcnt<2 * KC + 18>();
+    wait_vmcnt<2 * (kRowLoads + KC)>();
     cells(j, rho);
   }
   // The loads of rows past the band are still in flight.  Let them land
