@@ -514,10 +514,9 @@ __device__ __forceinline__ void lcp_tile_paired_lds(const T* __restrict__ mu,
     return c;
   };
 
-  // One carried set, updated in place: two alternating sets, as in the
-  // register tiles, save the per-row register moves but need 25 more VGPRs
-  // here, which costs the third wave per SIMD (measured slower).
-  PairedCarry<KC> ca;
+  // Two alternating carried sets, as in the register tiles (a single set
+  // updated in place costs 64 register moves per row at K = 16).
+  PairedCarry<KC> ca, cb;
 #pragma unroll
   for (int rho = 0; rho < kRingRows; ++rho) load_row(rho);
   wait_vmcnt<2 * kRowLoads>();  // rows 0..2 are in LDS (rows 3 and 4 may be in flight)
@@ -538,23 +537,38 @@ __device__ __forceinline__ void lcp_tile_paired_lds(const T* __restrict__ mu,
     load_row(rho + 3);
     return rho;
   };
-  auto cells = [&](int j, int rho) {
+  auto cells = [&](int j, int rho, const PairedCarry<KC>& p, PairedCarry<KC>& n) {
     const C3 c = corners(rho, j + 1);
     row_cells_paired<KC, STREAM>(c.e, c.o, c.s, iso, c_seam, n_store, out, plane, pitch,
-                                 row_bytes, j, off, ca.e, ca.o, ca.s, ca.e, ca.o, ca.s);
+                                 row_bytes, j, off, p.e, p.o, p.s, n.e, n.o, n.s);
   };
-  int j = j0;
   // The first two rows read rows loaded before the loop, with fewer
-  // operations issued after them: wait as in the prologue (stricter).
-  for (; j < j1 && j < j0 + 2; ++j) {
-    const int rho = step(j);
+  // operations issued after them: wait as in the prologue (stricter).  Then
+  // two rows per trip, the carried sets alternating; an odd last row after.
+  int j = j0;
+  if (j < j1) {
+    const int r0 = step(j);
     wait_vmcnt<2 * kRowLoads>();
-    cells(j, rho);
+    cells(j, r0, ca, cb);
+    if (++j < j1) {
+      const int r1 = step(j);
+      wait_vmcnt<2 * kRowLoads>();
+      cells(j, r1, cb, ca);
+      ++j;
+    }
   }
-  for (; j < j1; ++j) {
-    const int rho = step(j);
+  for (; j + 2 <= j1; j += 2) {
+    const int r0 = step(j);
     wait_vmcnt<2 * (kRowLoads + KC)>();
-    cells(j, rho);
+    cells(j, r0, ca, cb);
+    const int r1 = step(j + 1);
+    wait_vmcnt<2 * (kRowLoads + KC)>();
+    cells(j + 1, r1, cb, ca);
+  }
+  if (j < j1) {
+    const int r0 = step(j);
+    wait_vmcnt<2 * (kRowLoads + KC)>();
+    cells(j, r0, ca, cb);
   }
   // The loads of rows past the band are still in flight.  Let them land
   // before the ring is reused (the batch kernel's next tile writes the same
