@@ -327,7 +327,7 @@ def main():
     roofline = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS,
                 "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4),
                 "traffic": traffic,
-                "kernel": "lcp_kernel<16,true,true,float> (fused Eq. 2-3 + LCP, line-aligned rows)",
+                "kernel": "lcp_kernel_paired<16,true,float> (fused Eq. 2-3 + LCP, line-aligned rows)",
                 "algorithmic_bytes_per_launch": alg_bytes,
                 "kernel_ms_mean": round(kern_s * 1e3, 4),
                 "kernel_ms_min": round(float(per.min()) * 1e3, 4)}
