@@ -310,3 +310,29 @@ def test_pipeline_fit_divergence_lcp():
     ref = O.lcp(*O.divergence_gaussian(*O.moments(e["u_members"], e["v_members"], 1), 1.0, 1.0),
                 iso)
     assert err_report(L, ref)["max_abs"] <= LCP_TOL
+
+
+@pytest.mark.parametrize("dt", ["f32", "f16", "bf16"])
+def test_band_height_does_not_change_the_maps(dt):
+    """Every band height gives bitwise the maps of the default choice, for the
+    split tile (dense rows) and the LDS-staged paired tile (rows on 128-byte
+    lines, chunks of 8 isovalues): bands of 1..7 rows exercise the walk's
+    peeled first rows, its odd last row and the ring's reuse."""
+    ny, nx = 61, 300
+    f = _field(ny, nx, seed=77)
+    ts = moments_dev(f, dt)
+    iso = np.linspace(-0.08, 0.08, 9).astype(np.float32)
+    P.set_lcp_band_rows(0)
+    dense_ref = P.lcp_from_moments(*ts, iso)
+    paired_ref = P.lcp_from_moments(*ts, iso, out=P.empty_lcp(iso.size, ny, nx))
+    assert torch.equal(dense_ref, paired_ref)
+    try:
+        for rows in (1, 2, 3, 4, 5, 6, 7, 13, 64):
+            P.set_lcp_band_rows(rows)
+            dense = P.lcp_from_moments(*ts, iso)
+            paired = P.lcp_from_moments(*ts, iso, out=P.empty_lcp(iso.size, ny, nx))
+            torch.cuda.synchronize()
+            assert torch.equal(dense, dense_ref), rows
+            assert torch.equal(paired, dense_ref), rows
+    finally:
+        P.set_lcp_band_rows(0)
