@@ -101,15 +101,19 @@ pdiv_status pdiv_divergence_gaussian(const void* mean_u, const void* var_u, cons
  * float32 with one Gaussian tail per corner and isovalue and a cancellation-
  * free combination, so cells near 0 and near 1 keep their relative accuracy.
  * div_mean, div_var: [ny][nx] float32; isovalues_host: n_iso floats in host
- * memory, 1 <= n_iso <= PDIV_MAX_ISO; lcp: n_iso planes of ny-1 rows of nx-1
- * float32 cells; lcp_row_pitch is the distance between rows in floats (0 or
- * nx-1: dense; larger values pad each row and are left unwritten), planes
- * are (ny-1)*pitch floats apart.  A pitch that is a multiple of 32 floats
- * (128 bytes) lets every store write whole cache lines, which the kernel
- * needs for its full write bandwidth. */
+ * memory, 1 <= n_iso <= PDIV_MAX_ISO; lcp: n_iso maps of ny-1 rows of nx-1
+ * float32 cells, cell (q, j, i) at lcp[q*plane_stride + j*row_pitch + i].
+ * lcp_row_pitch: floats between rows (0: nx-1, dense; larger values pad the
+ * rows, and padding is never written).  lcp_plane_stride: floats between maps
+ * (0: (ny-1)*row_pitch); maps may also be interleaved by rows (plane stride
+ * >= nx-1 and row pitch >= n_iso*plane stride, i.e. a [ny-1][n_iso][pitch]
+ * buffer); layouts whose maps overlap are rejected.  When the row pitch and
+ * plane stride are multiples of 32 floats and lcp is 128-byte aligned, every
+ * store writes whole cache lines, which the kernel needs for its full write
+ * bandwidth; rows interleaved by isovalue write faster still on gfx950. */
 pdiv_status pdiv_lcp(const float* div_mean, const float* div_var, int64_t ny, int64_t nx,
                      const float* isovalues_host, int32_t n_iso, float* lcp,
-                     int64_t lcp_row_pitch, pdiv_stream stream);
+                     int64_t lcp_row_pitch, int64_t lcp_plane_stride, pdiv_stream stream);
 
 /* (d) Monte Carlo LCP, the paper's comparison (Sections 3.2 and 4): draw
  * n_samples samples of the uncertain vectors at every grid point, take the
@@ -130,12 +134,13 @@ pdiv_status pdiv_mc_lcp(const void* mean_u, const void* var_u, const void* mean_
 /* (b)+(c) fused: Eq. 2-3 and the closed-form LCP in one pass over the moment
  * planes; the divergence Gaussians never leave the chip.  Gives bitwise the
  * same LCP as pdiv_divergence_gaussian followed by pdiv_lcp; the output
- * layout and lcp_row_pitch are those of pdiv_lcp. */
+ * layout (lcp_row_pitch, lcp_plane_stride) is that of pdiv_lcp. */
 pdiv_status pdiv_lcp_from_moments(const void* mean_u, const void* var_u, const void* mean_v,
                                   const void* var_v, pdiv_dtype in_dtype, int64_t ny,
                                   int64_t nx, double dx, double dy,
                                   const float* isovalues_host, int32_t n_iso, float* lcp,
-                                  int64_t lcp_row_pitch, pdiv_stream stream);
+                                  int64_t lcp_row_pitch, int64_t lcp_plane_stride,
+                                  pdiv_stream stream);
 
 /* Diagnostic: sample s of the uncertain field exactly as pdiv_mc_lcp draws it
  * (same generator, counters and transform): u_s, v_s are [ny][nx] float32. */
@@ -162,8 +167,8 @@ typedef struct pdiv_field {
                               launch (update them between launches to move a slider) */
   int32_t n_iso;           /* 1 .. 16                                             */
   float* lcp;              /* float32 output (device): n_iso planes of ny-1 rows  */
-  int64_t lcp_row_pitch;   /* floats between output rows, >= nx-1; 0 = dense;
-                              planes are (ny-1)*pitch floats apart                */
+  int64_t lcp_row_pitch;   /* output layout as for pdiv_lcp: floats between rows */
+  int64_t lcp_plane_stride;/* ... and between maps (0 = (ny-1)*row pitch)         */
 } pdiv_field;
 
 typedef struct pdiv_batch_s* pdiv_batch;

@@ -50,7 +50,8 @@ class PdivError(RuntimeError):
 class _Field(_c.Structure):
     _fields_ = [("mean_u", _p), ("var_u", _p), ("mean_v", _p), ("var_v", _p),
                 ("ny", _i64), ("nx", _i64), ("dx", _f64), ("dy", _f64),
-                ("isovalues", _p), ("n_iso", _i32), ("lcp", _p), ("lcp_row_pitch", _i64)]
+                ("isovalues", _p), ("n_iso", _i32), ("lcp", _p), ("lcp_row_pitch", _i64),
+                ("lcp_plane_stride", _i64)]
 
 
 class ServerStats(_c.Structure):
@@ -66,10 +67,10 @@ class ServerStats(_c.Structure):
 _SIGS = {
     "pdiv_moments": [_p, _p, _c.c_int, _i64, _i64, _i64, _i64, _i32, _p, _p, _p, _p, _c.c_int, _p],
     "pdiv_divergence_gaussian": [_p, _p, _p, _p, _c.c_int, _i64, _i64, _f64, _f64, _p, _p, _p],
-    "pdiv_lcp": [_p, _p, _i64, _i64, _fp, _i32, _p, _i64, _p],
+    "pdiv_lcp": [_p, _p, _i64, _i64, _fp, _i32, _p, _i64, _i64, _p],
     "pdiv_mc_lcp": [_p, _p, _p, _p, _c.c_int, _i64, _i64, _f64, _f64, _fp, _i32, _i64, _u64, _p, _p],
     "pdiv_lcp_from_moments": [_p, _p, _p, _p, _c.c_int, _i64, _i64, _f64, _f64, _fp, _i32, _p,
-                              _i64, _p],
+                              _i64, _i64, _p],
     "pdiv_mc_sample_field": [_p, _p, _p, _p, _c.c_int, _i64, _i64, _i64, _u64, _p, _p, _p],
     "pdiv_batch_create": [_c.POINTER(_Field), _i32, _c.c_int, _c.c_uint32, _p, _c.POINTER(_p)],
     "pdiv_batch_launch": [_p, _p],
@@ -147,9 +148,10 @@ def _dev(t, name, shape=None, dtype=None):
 
 
 def _lcp_out(t, k, ny, nx):
-    """Pointer and row pitch (floats) of an LCP output: a [k][ny-1][nx-1]
-    float32 device tensor, dense or a view of rows padded to a longer pitch
-    (see empty_lcp)."""
+    """Pointer, row pitch and plane stride (floats) of an LCP output: a
+    [k][ny-1][nx-1] float32 device tensor whose cells are contiguous within a
+    row -- dense, or a strided view such as empty_lcp returns.  The library
+    checks that the maps do not overlap."""
     if not t.is_cuda:
         raise ValueError("out must be a device tensor")
     if t.dtype != _torch().float32:
@@ -157,23 +159,32 @@ def _lcp_out(t, k, ny, nx):
     if tuple(t.shape) != (k, ny - 1, nx - 1):
         raise ValueError(f"out has shape {tuple(t.shape)}, expected {(k, ny - 1, nx - 1)}")
     s0, s1, s2 = t.stride()
-    pitch = s1 if ny > 2 else (s0 if k > 1 else nx - 1)
-    if s2 != 1 or pitch < nx - 1 or (k > 1 and s0 != (ny - 1) * pitch) or \
-            (ny > 2 and s1 != pitch):
-        raise ValueError("out must be dense or rows of one pitch >= nx-1 with planes "
-                         "(ny-1)*pitch floats apart")
-    return _p(t.data_ptr()), pitch
+    if s2 != 1 and nx > 2:
+        raise ValueError("out: the cells of a row must be contiguous")
+    # a single row or map: its stride is free in torch; keep it if it is one
+    pitch = s1 if (ny > 2 or s1 >= nx - 1) else nx - 1
+    plane = s0 if k > 1 else 0
+    if pitch < nx - 1 or (k > 1 and plane < 1):
+        raise ValueError("out: rows or maps overlap")
+    return _p(t.data_ptr()), pitch, plane
 
 
-def empty_lcp(k: int, ny: int, nx: int, pitch: int = None, device="cuda"):
+def empty_lcp(k: int, ny: int, nx: int, pitch: int = None, interleave_rows: bool = False,
+              device="cuda"):
     """Uninitialised LCP output [k][ny-1][nx-1] whose rows are `pitch` floats
-    apart (default: nx-1 rounded up to a multiple of 32 floats, so that every
-    row starts on a 128-byte line).  The padding floats are never written."""
+    long (default: nx-1 rounded up to a multiple of 32 floats, so that every
+    row starts on a 128-byte line); padding floats are never written.
+    interleave_rows: the k maps' rows j are adjacent in memory (a
+    [ny-1][k][pitch] buffer viewed as [k][ny-1][nx-1]), the layout the
+    kernels write fastest on gfx950."""
     torch = _torch()
     if pitch is None:
         pitch = (nx - 1 + 31) // 32 * 32
     if pitch < nx - 1:
         raise ValueError("pitch must be >= nx - 1")
+    if interleave_rows:
+        buf = torch.empty((ny - 1, k, pitch), dtype=torch.float32, device=device)
+        return buf.permute(1, 0, 2)[:, :, : nx - 1]
     buf = torch.empty((k, ny - 1, pitch), dtype=torch.float32, device=device)
     return buf[:, :, : nx - 1]
 
@@ -230,8 +241,8 @@ def lcp(div_mean, div_var, isovalues, out=None):
     iso, ip = _iso_arr(isovalues)
     if out is None:
         out = torch.empty((iso.size, ny - 1, nx - 1), dtype=torch.float32, device=div_mean.device)
-    po, pitch = _lcp_out(out, iso.size, ny, nx)
-    _check(lib().pdiv_lcp(pm, pv, ny, nx, ip, iso.size, po, pitch, _stream()))
+    po, pitch, plane = _lcp_out(out, iso.size, ny, nx)
+    _check(lib().pdiv_lcp(pm, pv, ny, nx, ip, iso.size, po, pitch, plane, _stream()))
     return out
 
 
@@ -244,9 +255,9 @@ def lcp_from_moments(mean_u, var_u, mean_v, var_v, isovalues, dx: float = 1.0,
     iso, ip = _iso_arr(isovalues)
     if out is None:
         out = torch.empty((iso.size, ny - 1, nx - 1), dtype=torch.float32, device=mean_u.device)
-    po, pitch = _lcp_out(out, iso.size, ny, nx)
+    po, pitch, plane = _lcp_out(out, iso.size, ny, nx)
     _check(lib().pdiv_lcp_from_moments(*ptrs, dt, ny, nx, dx, dy, ip, iso.size, po, pitch,
-                                       _stream()))
+                                       plane, _stream()))
     return out
 
 
@@ -301,10 +312,10 @@ class Batch:
             out = f.get("lcp")
             if out is None:  # rows on 128-byte lines, so either tile layout may run
                 out = empty_lcp(iso.numel(), ny, nx, device=f["mean_u"].device)
-            po, pitch = _lcp_out(out, iso.numel(), ny, nx)
+            po, pitch, plane = _lcp_out(out, iso.numel(), ny, nx)
             arr[k] = _Field(ptrs[0], ptrs[1], ptrs[2], ptrs[3], ny, nx,
                             float(f.get("dx", 1.0)), float(f.get("dy", 1.0)),
-                            _p(iso.data_ptr()), iso.numel(), po, pitch)
+                            _p(iso.data_ptr()), iso.numel(), po, pitch, plane)
             self.fields.append(dict(f, lcp=out))
         flags = (self.GRAPH if graph else 0) | (self.AUTOTUNE if autotune else 0)
         h = _p()

@@ -126,9 +126,8 @@ __global__ __launch_bounds__(kBlock) void lcp_kernel_split(
 template <int KC, bool FUSED, typename T>
 hipError_t launch_kc(const void* p0, const void* p1, const void* p2, const void* p3, int ny,
                      int nx, const StencilCoef& k, const IsoChunk& iso, float* out,
-                     int64_t pitch, LcpShape shape, hipStream_t s) {
-  const int64_t plane = static_cast<int64_t>(ny - 1) * pitch;
-  const bool paired = use_paired_tile(out, pitch, KC);
+                     int64_t pitch, int64_t plane, LcpShape shape, hipStream_t s) {
+  const bool paired = use_paired_tile(out, pitch, plane, KC);
   const int cells = cells_per_wave(paired);
   const int band_rows = band_rows_for(shape, ny, paired);
   const int n_strips = (nx - 1 + cells - 1) / cells;
@@ -151,13 +150,13 @@ hipError_t launch_kc(const void* p0, const void* p1, const void* p2, const void*
 template <bool FUSED, typename T>
 hipError_t launch_any(const void* p0, const void* p1, const void* p2, const void* p3, int ny,
                       int nx, const StencilCoef& k, const IsoChunk& iso, int kc, float* out,
-                      int64_t pitch, LcpShape shape, hipStream_t s) {
+                      int64_t pitch, int64_t plane, LcpShape shape, hipStream_t s) {
   switch (kc) {
-    case 1: return launch_kc<1, FUSED, T>(p0, p1, p2, p3, ny, nx, k, iso, out, pitch, shape, s);
-    case 2: return launch_kc<2, FUSED, T>(p0, p1, p2, p3, ny, nx, k, iso, out, pitch, shape, s);
-    case 4: return launch_kc<4, FUSED, T>(p0, p1, p2, p3, ny, nx, k, iso, out, pitch, shape, s);
-    case 8: return launch_kc<8, FUSED, T>(p0, p1, p2, p3, ny, nx, k, iso, out, pitch, shape, s);
-    case 16: return launch_kc<16, FUSED, T>(p0, p1, p2, p3, ny, nx, k, iso, out, pitch, shape, s);
+    case 1: return launch_kc<1, FUSED, T>(p0, p1, p2, p3, ny, nx, k, iso, out, pitch, plane, shape, s);
+    case 2: return launch_kc<2, FUSED, T>(p0, p1, p2, p3, ny, nx, k, iso, out, pitch, plane, shape, s);
+    case 4: return launch_kc<4, FUSED, T>(p0, p1, p2, p3, ny, nx, k, iso, out, pitch, plane, shape, s);
+    case 8: return launch_kc<8, FUSED, T>(p0, p1, p2, p3, ny, nx, k, iso, out, pitch, plane, shape, s);
+    case 16: return launch_kc<16, FUSED, T>(p0, p1, p2, p3, ny, nx, k, iso, out, pitch, plane, shape, s);
   }
   return hipErrorInvalidValue;
 }
@@ -199,17 +198,17 @@ hipError_t launch_divergence(const void* mu, const void* vu, const void* mv, con
 hipError_t launch_lcp(bool fused, const void* p0, const void* p1, const void* p2,
                       const void* p3, pdiv_dtype dt, int64_t ny, int64_t nx,
                       const StencilCoef& k, const IsoChunk& iso, int kc, float* lcp_k0,
-                      int64_t pitch, LcpShape shape, hipStream_t s) {
+                      int64_t pitch, int64_t plane, LcpShape shape, hipStream_t s) {
   const int iny = static_cast<int>(ny), inx = static_cast<int>(nx);
   if (!fused)
-    return launch_any<false, float>(p0, p1, p2, p3, iny, inx, k, iso, kc, lcp_k0, pitch, shape, s);
+    return launch_any<false, float>(p0, p1, p2, p3, iny, inx, k, iso, kc, lcp_k0, pitch, plane, shape, s);
   switch (dt) {
     case PDIV_F32:
-      return launch_any<true, float>(p0, p1, p2, p3, iny, inx, k, iso, kc, lcp_k0, pitch, shape, s);
+      return launch_any<true, float>(p0, p1, p2, p3, iny, inx, k, iso, kc, lcp_k0, pitch, plane, shape, s);
     case PDIV_F16:
-      return launch_any<true, __half>(p0, p1, p2, p3, iny, inx, k, iso, kc, lcp_k0, pitch, shape, s);
+      return launch_any<true, __half>(p0, p1, p2, p3, iny, inx, k, iso, kc, lcp_k0, pitch, plane, shape, s);
     case PDIV_BF16:
-      return launch_any<true, bf16_t>(p0, p1, p2, p3, iny, inx, k, iso, kc, lcp_k0, pitch, shape, s);
+      return launch_any<true, bf16_t>(p0, p1, p2, p3, iny, inx, k, iso, kc, lcp_k0, pitch, plane, shape, s);
   }
   return hipErrorInvalidValue;
 }

@@ -668,10 +668,12 @@ __device__ __forceinline__ void lcp_tile_split(const T* __restrict__ p0, const T
 }
 
 // Layout choice: the paired tile when every output row starts on a 128-byte
-// line (base aligned, pitch a multiple of 32 floats) and there are at least 8
-// isovalues, so that the seam step costs under 8% of the row's arithmetic.
-inline bool use_paired_tile(const float* out, int64_t pitch, int kc) {
-  return (reinterpret_cast<uintptr_t>(out) % 128 == 0) && (pitch % 32 == 0) && kc >= 8;
+// line (base aligned, row pitch and plane stride multiples of 32 floats) and
+// there are at least 8 isovalues, so that the seam step costs under 8% of the
+// row's arithmetic.
+inline bool use_paired_tile(const float* out, int64_t pitch, int64_t plane, int kc) {
+  return (reinterpret_cast<uintptr_t>(out) % 128 == 0) && (pitch % 32 == 0) &&
+         (plane % 32 == 0) && kc >= 8;
 }
 
 // The tile of layout PAIRED (paired tiles store non-temporally: their rows

@@ -70,17 +70,29 @@ pdiv_status check_iso(const float* iso, int32_t n) {
   return PDIV_OK;
 }
 
-// Output row pitch in floats: 0 means dense (nx - 1); otherwise at least
-// nx - 1, and the whole output, n_iso planes of (ny - 1) pitch floats, must
-// stay below 2^56 bytes.
-pdiv_status check_pitch(int64_t pitch, int64_t ny, int64_t nx, int32_t n_iso, int64_t* out) {
-  if (pitch == 0) pitch = nx - 1;
-  if (pitch < nx - 1)
-    return invalid("lcp_row_pitch must be 0 or >= nx - 1 (got %lld, nx=%lld)", (long long)pitch,
-                   (long long)nx);
-  if (pitch > ((int64_t(1) << 54) / (ny - 1)) / n_iso)
-    return invalid("lcp_row_pitch %lld is too large", (long long)pitch);
-  *out = pitch;
+pdiv_status check_layout(int64_t row_pitch, int64_t plane_stride, int64_t ny, int64_t nx,
+                         int32_t n_iso, OutLayout* out) {
+  const int64_t cells = nx - 1, rows = ny - 1;
+  const int64_t pitch = row_pitch == 0 ? cells : row_pitch;
+  if (pitch < cells || pitch > (int64_t(1) << 52))
+    return invalid("lcp_row_pitch must be 0 or in [nx - 1, 2^52] (got %lld, nx=%lld)",
+                   (long long)row_pitch, (long long)nx);
+  const int64_t plane = plane_stride == 0 ? rows * pitch : plane_stride;
+  if (plane < 0 || plane > (int64_t(1) << 52))
+    return invalid("lcp_plane_stride must be 0 or in [1, 2^52] (got %lld)",
+                   (long long)plane_stride);
+  const bool apart = plane >= rows * pitch;
+  const bool interleaved = plane >= cells && pitch >= int64_t(n_iso) * plane;
+  if (!apart && !interleaved)
+    return invalid("lcp_plane_stride %lld with lcp_row_pitch %lld makes the %d maps of "
+                   "%lld x %lld cells overlap", (long long)plane, (long long)pitch, n_iso,
+                   (long long)rows, (long long)cells);
+  // last element: (n_iso - 1) plane + (rows - 1) pitch + cells - 1
+  const double last = double(n_iso - 1) * double(plane) + double(rows - 1) * double(pitch) +
+                      double(cells);
+  if (last * 4.0 >= double(int64_t(1) << 56)) return invalid("LCP output layout is too large");
+  out->pitch = pitch;
+  out->plane = plane;
   return PDIV_OK;
 }
 
@@ -98,9 +110,9 @@ pdiv_status check_pitch(int64_t pitch, int64_t ny, int64_t nx, int32_t n_iso, in
 pdiv_status lcp_chunks(bool fused, const void* p0, const void* p1, const void* p2,
                        const void* p3, pdiv_dtype dt, int64_t ny, int64_t nx, double dx,
                        double dy, const float* iso_host, int32_t n_iso, float* lcp,
-                       int64_t pitch, hipStream_t s) {
+                       OutLayout lo, hipStream_t s) {
   const StencilCoef k = make_coef(dx, dy);
-  const int64_t plane = (ny - 1) * pitch;
+  const int64_t plane = lo.plane;
   const LcpShape shape = default_lcp_shape(ny, nx, n_iso);
   // chunks of 16, 8, 4, 2, 1 isovalues (the kernel is instantiated for these)
   for (int32_t k0 = 0; k0 < n_iso;) {
@@ -109,7 +121,7 @@ pdiv_status lcp_chunks(bool fused, const void* p0, const void* p1, const void* p
     IsoChunk c;
     for (int q = 0; q < kIsoChunk; ++q) c.c[q] = iso_host[k0 + (q < kc ? q : kc - 1)];
     hipError_t e = launch_lcp(fused, p0, p1, p2, p3, dt, ny, nx, k, c, kc, lcp + k0 * plane,
-                              pitch, shape, s);
+                              lo.pitch, plane, shape, s);
     if (e != hipSuccess) return device_status(e, "LCP launch");
     k0 += kc;
   }
@@ -196,24 +208,25 @@ pdiv_status pdiv_divergence_gaussian(const void* mean_u, const void* var_u, cons
 
 pdiv_status pdiv_lcp(const float* div_mean, const float* div_var, int64_t ny, int64_t nx,
                      const float* isovalues_host, int32_t n_iso, float* lcp,
-                     int64_t lcp_row_pitch, pdiv_stream stream) {
+                     int64_t lcp_row_pitch, int64_t lcp_plane_stride, pdiv_stream stream) {
   g_last_error.clear();
   PDIV_NONNULL(div_mean);
   PDIV_NONNULL(div_var);
   PDIV_NONNULL(lcp);
   PDIV_TRY(check_grid(ny, nx));
   PDIV_TRY(check_iso(isovalues_host, n_iso));
-  int64_t pitch = 0;
-  PDIV_TRY(check_pitch(lcp_row_pitch, ny, nx, n_iso, &pitch));
+  OutLayout lo;
+  PDIV_TRY(check_layout(lcp_row_pitch, lcp_plane_stride, ny, nx, n_iso, &lo));
   return lcp_chunks(false, div_mean, div_var, nullptr, nullptr, PDIV_F32, ny, nx, 1.0, 1.0,
-                    isovalues_host, n_iso, lcp, pitch, static_cast<hipStream_t>(stream));
+                    isovalues_host, n_iso, lcp, lo, static_cast<hipStream_t>(stream));
 }
 
 pdiv_status pdiv_lcp_from_moments(const void* mean_u, const void* var_u, const void* mean_v,
                                   const void* var_v, pdiv_dtype in_dtype, int64_t ny,
                                   int64_t nx, double dx, double dy,
                                   const float* isovalues_host, int32_t n_iso, float* lcp,
-                                  int64_t lcp_row_pitch, pdiv_stream stream) {
+                                  int64_t lcp_row_pitch, int64_t lcp_plane_stride,
+                                  pdiv_stream stream) {
   g_last_error.clear();
   PDIV_NONNULL(mean_u);
   PDIV_NONNULL(var_u);
@@ -224,10 +237,10 @@ pdiv_status pdiv_lcp_from_moments(const void* mean_u, const void* var_u, const v
   PDIV_TRY(check_grid(ny, nx));
   PDIV_TRY(check_spacing(dx, dy));
   PDIV_TRY(check_iso(isovalues_host, n_iso));
-  int64_t pitch = 0;
-  PDIV_TRY(check_pitch(lcp_row_pitch, ny, nx, n_iso, &pitch));
+  OutLayout lo;
+  PDIV_TRY(check_layout(lcp_row_pitch, lcp_plane_stride, ny, nx, n_iso, &lo));
   return lcp_chunks(true, mean_u, var_u, mean_v, var_v, in_dtype, ny, nx, dx, dy,
-                    isovalues_host, n_iso, lcp, pitch, static_cast<hipStream_t>(stream));
+                    isovalues_host, n_iso, lcp, lo, static_cast<hipStream_t>(stream));
 }
 
 pdiv_status pdiv_mc_lcp(const void* mean_u, const void* var_u, const void* mean_v,

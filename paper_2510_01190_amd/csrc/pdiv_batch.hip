@@ -102,7 +102,8 @@ const void* batch_kernel_ptr(bool fused, pdiv_dtype dt, int kc, bool paired) {
 
 bool all_rows_on_lines(const std::vector<BatchField>& f) {
   for (auto& x : f)
-    if (reinterpret_cast<uintptr_t>(x.lcp) % 128 != 0 || x.pitch % 32 != 0) return false;
+    if (reinterpret_cast<uintptr_t>(x.lcp) % 128 != 0 || x.pitch % 32 != 0 || x.plane % 32 != 0)
+      return false;
   return true;
 }
 
@@ -338,10 +339,9 @@ pdiv_status pdiv_batch_create(const pdiv_field* fields_host, int32_t n_fields, p
       return invalid("field %d: dx and dy must be finite and > 0", i);
     if (f.n_iso < 1 || f.n_iso > kIsoChunk)
       return invalid("field %d: n_iso must be in [1, %d]", i, kIsoChunk);
-    const int64_t pitch = f.lcp_row_pitch == 0 ? f.nx - 1 : f.lcp_row_pitch;
-    if (pitch < f.nx - 1 || pitch > ((int64_t(1) << 54) / (f.ny - 1)) / kIsoChunk)
-      return invalid("field %d: lcp_row_pitch must be 0 or in [nx - 1, 2^54 / ((ny - 1) 16)]",
-                     i);
+    OutLayout lo;
+    if (check_layout(f.lcp_row_pitch, f.lcp_plane_stride, f.ny, f.nx, f.n_iso, &lo) != PDIV_OK)
+      return invalid("field %d: %s", i, std::string(pdiv_last_error()).c_str());
     BatchField& x = fv[i];
     x.p0 = f.mean_u;
     x.p1 = f.var_u;
@@ -352,8 +352,8 @@ pdiv_status pdiv_batch_create(const pdiv_field* fields_host, int32_t n_fields, p
     x.ny = static_cast<int>(f.ny);
     x.nx = static_cast<int>(f.nx);
     x.n_iso = f.n_iso;
-    x.pitch = pitch;
-    x.plane = (f.ny - 1) * pitch;
+    x.pitch = lo.pitch;
+    x.plane = lo.plane;
     x.coef = make_coef(f.dx, f.dy);
     kc = std::max(kc, iso_bucket(f.n_iso));
   }

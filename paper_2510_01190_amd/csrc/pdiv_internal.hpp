@@ -34,6 +34,18 @@ struct StencilCoef {
 };
 StencilCoef make_coef(double dx, double dy);
 
+// Output layout of the LCP maps in floats: row pitch (0: dense, nx - 1; else
+// >= nx - 1) and plane stride (0: (ny - 1) row pitch).  The maps may be apart
+// (plane stride >= (ny - 1) row pitch) or interleaved by rows (plane stride
+// >= nx - 1 and row pitch >= n_iso plane stride); any other pair makes maps
+// overlap.  check_layout validates (PDIV_ERR_INVALID with a message) and
+// resolves the zeros.
+struct OutLayout {
+  int64_t pitch, plane;
+};
+pdiv_status check_layout(int64_t row_pitch, int64_t plane_stride, int64_t ny, int64_t nx,
+                         int32_t n_iso, OutLayout* out);
+
 // Tile shape of the column-walking LCP kernels: one wave covers a strip of
 // 128 (paired layout) or 126 cells (split layout) over a band of `band_rows`
 // cell rows; 0 lets the launcher choose per layout.
@@ -53,11 +65,11 @@ hipError_t launch_divergence(const void* mu, const void* vu, const void* mv, con
 
 // LCP for isovalues [k0, k0+kc) (kc <= 16): from divergence Gaussians
 // (fused = false, planes dmean/dvar as float) or from moments (fused = true).
-// Output rows are `pitch` floats apart, planes (ny-1) pitch.
+// Output rows are `pitch` floats apart, planes `plane` floats.
 hipError_t launch_lcp(bool fused, const void* p0, const void* p1, const void* p2,
                       const void* p3, pdiv_dtype dt, int64_t ny, int64_t nx,
                       const StencilCoef& k, const IsoChunk& iso, int kc, float* lcp_k0,
-                      int64_t pitch, LcpShape shape, hipStream_t s);
+                      int64_t pitch, int64_t plane, LcpShape shape, hipStream_t s);
 
 hipError_t launch_mc(const void* mu, const void* vu, const void* mv, const void* vv,
                      pdiv_dtype dt, int64_t ny, int64_t nx, const StencilCoef& k,

@@ -61,17 +61,21 @@ def _expect_invalid(status, fragment):
 def test_lcp_rejects_bad_arguments():
     L = P.lib()
     keep, ip = _iso([0.1, 0.2])
-    _expect_invalid(L.pdiv_lcp(FAKE, FAKE, 1, 8, ip, 2, FAKE, 0, NUL), "at least 2x2")
-    _expect_invalid(L.pdiv_lcp(FAKE, FAKE, 8, 1, ip, 2, FAKE, 0, NUL), "at least 2x2")
-    _expect_invalid(L.pdiv_lcp(NUL, FAKE, 8, 8, ip, 2, FAKE, 0, NUL), "div_mean is NULL")
-    _expect_invalid(L.pdiv_lcp(FAKE, FAKE, 8, 8, ip, 2, NUL, 0, NUL), "lcp is NULL")
-    _expect_invalid(L.pdiv_lcp(FAKE, FAKE, 8, 8, ip, 0, FAKE, 0, NUL), "n_iso")
-    _expect_invalid(L.pdiv_lcp(FAKE, FAKE, 8, 8, ip, 257, FAKE, 0, NUL), "n_iso")
-    _expect_invalid(L.pdiv_lcp(FAKE, FAKE, 8, 8, None, 2, FAKE, 0, NUL), "isovalues_host")
-    _expect_invalid(L.pdiv_lcp(FAKE, FAKE, 1 << 22, 8, ip, 2, FAKE, 0, NUL), "too large")
-    _expect_invalid(L.pdiv_lcp(FAKE, FAKE, 8, 8, ip, 2, FAKE, 6, NUL), "lcp_row_pitch")
-    _expect_invalid(L.pdiv_lcp(FAKE, FAKE, 8, 8, ip, 2, FAKE, -1, NUL), "lcp_row_pitch")
-    _expect_invalid(L.pdiv_lcp(FAKE, FAKE, 8, 8, ip, 2, FAKE, 1 << 62, NUL), "too large")
+    _expect_invalid(L.pdiv_lcp(FAKE, FAKE, 1, 8, ip, 2, FAKE, 0, 0, NUL), "at least 2x2")
+    _expect_invalid(L.pdiv_lcp(FAKE, FAKE, 8, 1, ip, 2, FAKE, 0, 0, NUL), "at least 2x2")
+    _expect_invalid(L.pdiv_lcp(NUL, FAKE, 8, 8, ip, 2, FAKE, 0, 0, NUL), "div_mean is NULL")
+    _expect_invalid(L.pdiv_lcp(FAKE, FAKE, 8, 8, ip, 2, NUL, 0, 0, NUL), "lcp is NULL")
+    _expect_invalid(L.pdiv_lcp(FAKE, FAKE, 8, 8, ip, 0, FAKE, 0, 0, NUL), "n_iso")
+    _expect_invalid(L.pdiv_lcp(FAKE, FAKE, 8, 8, ip, 257, FAKE, 0, 0, NUL), "n_iso")
+    _expect_invalid(L.pdiv_lcp(FAKE, FAKE, 8, 8, None, 2, FAKE, 0, 0, NUL), "isovalues_host")
+    _expect_invalid(L.pdiv_lcp(FAKE, FAKE, 1 << 22, 8, ip, 2, FAKE, 0, 0, NUL), "too large")
+    _expect_invalid(L.pdiv_lcp(FAKE, FAKE, 8, 8, ip, 2, FAKE, 6, 0, NUL), "lcp_row_pitch")
+    _expect_invalid(L.pdiv_lcp(FAKE, FAKE, 8, 8, ip, 2, FAKE, -1, 0, NUL), "lcp_row_pitch")
+    _expect_invalid(L.pdiv_lcp(FAKE, FAKE, 8, 8, ip, 2, FAKE, 1 << 62, 0, NUL), "lcp_row_pitch")
+    # maps that overlap: plane stride between a row and a map, or rows too short
+    _expect_invalid(L.pdiv_lcp(FAKE, FAKE, 8, 8, ip, 2, FAKE, 7, 20, NUL), "overlap")
+    _expect_invalid(L.pdiv_lcp(FAKE, FAKE, 8, 8, ip, 2, FAKE, 10, 7, NUL), "overlap")
+    _expect_invalid(L.pdiv_lcp(FAKE, FAKE, 8, 8, ip, 2, FAKE, 0, -5, NUL), "lcp_plane_stride")
 
 
 def test_fused_and_divergence_reject_bad_spacing_and_dtype():
@@ -79,11 +83,11 @@ def test_fused_and_divergence_reject_bad_spacing_and_dtype():
     keep, ip = _iso([0.0])
     for dx, dy in ((0.0, 1.0), (1.0, -2.0), (float("nan"), 1.0), (1.0, float("inf"))):
         _expect_invalid(L.pdiv_lcp_from_moments(FAKE, FAKE, FAKE, FAKE, 0, 8, 8, dx, dy, ip, 1,
-                                                FAKE, 0, NUL), "dx and dy")
+                                                FAKE, 0, 0, NUL), "dx and dy")
         _expect_invalid(L.pdiv_divergence_gaussian(FAKE, FAKE, FAKE, FAKE, 0, 8, 8, dx, dy,
                                                    FAKE, FAKE, NUL), "dx and dy")
     _expect_invalid(L.pdiv_lcp_from_moments(FAKE, FAKE, FAKE, FAKE, 7, 8, 8, 1.0, 1.0, ip, 1,
-                                            FAKE, 0, NUL), "dtype")
+                                            FAKE, 0, 0, NUL), "dtype")
     _expect_invalid(L.pdiv_divergence_gaussian(FAKE, NUL, FAKE, FAKE, 0, 8, 8, 1.0, 1.0, FAKE,
                                                FAKE, NUL), "var_u is NULL")
 
@@ -119,7 +123,7 @@ def test_error_message_is_per_thread():
     import threading
     L = P.lib()
     keep, ip = _iso([0.0])
-    assert L.pdiv_lcp(FAKE, FAKE, 1, 8, ip, 1, FAKE, 0, NUL) == INVALID
+    assert L.pdiv_lcp(FAKE, FAKE, 1, 8, ip, 1, FAKE, 0, 0, NUL) == INVALID
     seen = {}
 
     def other():

@@ -112,15 +112,19 @@ def test_batch_pitched_outputs():
         ny, nx = f["mean_u"].shape
         K = f["iso_host"].size
         pitch = (nx - 1 + 31) // 32 * 32 + 32 * (k % 2)
-        buf = torch.full((K, ny - 1, pitch), -3.0, device="cuda")
-        f["lcp"] = buf[:, :, : nx - 1]
+        if k % 3 == 2:  # maps interleaved by rows
+            buf = torch.full((ny - 1, K, pitch), -3.0, device="cuda")
+            f["lcp"] = buf.permute(1, 0, 2)[:, :, : nx - 1]
+        else:
+            buf = torch.full((K, ny - 1, pitch), -3.0, device="cuda")
+            f["lcp"] = buf[:, :, : nx - 1]
         bufs.append((buf, nx))
     b = P.Batch(fields, graph=True)
     b.launch()
     torch.cuda.synchronize()
     for f, g, (buf, nx) in zip(fields, b.fields, bufs):
         assert torch.equal(g["lcp"], _per_field(f))
-        assert bool((buf[:, :, nx - 1:] == -3.0).all())
+        assert bool((buf[..., nx - 1:] == -3.0).all())
     b.close()
 
 

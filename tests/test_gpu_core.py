@@ -98,6 +98,18 @@ def test_pitched_output_equals_dense_and_keeps_padding(shape):
     e = P.empty_lcp(K, ny, nx)
     assert e.stride(1) % 32 == 0 and e.stride(1) >= nx - 1
     assert torch.equal(P.lcp_from_moments(*ts, iso, out=e), dense)
+    # maps interleaved by rows ([ny-1][K][pitch] buffer), padded and odd pitches
+    for pitch in ((nx - 1 + 31) // 32 * 32, nx + 3):
+        buf = torch.full((ny - 1, K, pitch), -7.0, device="cuda")
+        view = buf.permute(1, 0, 2)[:, :, : nx - 1]
+        P.lcp_from_moments(*ts, iso, out=view)
+        torch.cuda.synchronize()
+        assert torch.equal(view, dense)
+        assert bool((buf[:, :, nx - 1:] == -7.0).all())
+        P.lcp(dm, dv, iso, out=view)
+        assert torch.equal(view, dense)
+    assert torch.equal(P.lcp_from_moments(*ts, iso, out=P.empty_lcp(K, ny, nx,
+                                                                   interleave_rows=True)), dense)
     ref = O.lcp(host64(dm), host64(dv), iso)
     assert err_report(host64(e), ref)["max_abs"] <= LCP_TOL
 
@@ -111,10 +123,15 @@ def test_pitched_output_views():
     buf = torch.zeros((2, 19, 64), device="cuda")
     assert torch.equal(P.lcp_from_moments(*ts, iso, out=buf[:, :, 1:40]), dense)
     assert bool((buf[:, :, 0] == 0).all()) and bool((buf[:, :, 40:] == 0).all())
-    with pytest.raises(ValueError):  # planes not (ny-1)*pitch apart
-        P.lcp_from_moments(*ts, iso, out=torch.empty((2, 20, 64), device="cuda")[:, :19, :39])
+    # maps further apart than their rows need (a gap between maps) are fine
+    gap = torch.zeros((2, 20, 64), device="cuda")
+    assert torch.equal(P.lcp_from_moments(*ts, iso, out=gap[:, :19, :39]), dense)
+    assert bool((gap[:, 19, :] == 0).all())
     with pytest.raises(ValueError):  # cells of a row not contiguous
         P.lcp_from_moments(*ts, iso, out=torch.empty((2, 19, 80), device="cuda")[:, :, :78:2])
+    with pytest.raises(P.PdivError):  # maps overlap (the library checks the strides)
+        P.lcp_from_moments(*ts, iso, out=torch.empty((20, 50), device="cuda")
+                           .as_strided((2, 19, 39), (20, 50, 1)))
 
 
 @pytest.mark.parametrize("dt", ["f32", "f16", "bf16"])
