@@ -45,9 +45,10 @@ def test_c3_sampled_rows(c3, dt):
     iso = c3["isovalues"]
     ts = [torch.from_numpy(c3[k]).to(TORCH_DT[dt]).cuda() for k in
           ("mean_u", "var_u", "mean_v", "var_v")]
-    # the benchmark's launch: rows padded to a 128-byte multiple (pitch 8192)
-    out = P.lcp_from_moments(*ts, iso, out=P.empty_lcp(iso.size, ny, nx))
-    assert out.stride(1) == 8192
+    # the benchmark's launch: rows padded to a 128-byte multiple (pitch 8192),
+    # the 16 maps' rows j adjacent in memory
+    out = P.lcp_from_moments(*ts, iso, out=P.empty_lcp(iso.size, ny, nx, interleave_rows=True))
+    assert out.stride(2) == 1 and out.stride(0) == 8192 and out.stride(1) == 8192 * iso.size
     torch.cuda.synchronize()
     stored = None
     worst_k, worst_e = 0.0, 0.0
@@ -72,7 +73,8 @@ def test_c3_sampled_rows(c3, dt):
 def test_c3_properties_whole_grid(c3):
     """Properties that hold at any size, checked on every cell: range [0,1],
     no NaN, the two-step path equals the fused path bitwise, and the pitched
-    (benchmark) layout holds the same maps as the dense one."""
+    planar and row-interleaved (benchmark) layouts hold the same maps as the
+    dense one."""
     ts = [torch.from_numpy(c3[k]).float().cuda() for k in ("mean_u", "var_u", "mean_v", "var_v")]
     iso = c3["isovalues"][[0, 7, 15]]
     fused = P.lcp_from_moments(*ts, iso)
@@ -80,9 +82,11 @@ def test_c3_properties_whole_grid(c3):
     two = P.lcp(dm, dv, iso)
     assert torch.equal(fused, two)
     ny, nx = ts[0].shape
-    pitched = P.lcp_from_moments(*ts, iso, out=P.empty_lcp(iso.size, ny, nx))
-    assert torch.equal(fused, pitched)
-    del pitched
+    for inter in (False, True):
+        pitched = P.lcp_from_moments(*ts, iso, out=P.empty_lcp(iso.size, ny, nx,
+                                                              interleave_rows=inter))
+        assert torch.equal(fused, pitched)
+        del pitched
     assert not torch.isnan(fused).any()
     assert float(fused.min()) >= 0.0 and float(fused.max()) <= 1.0
     del fused, two, dm, dv, ts
