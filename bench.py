@@ -124,13 +124,20 @@ def batch_leg(P, synth, torch, np):
             "tile": info, "bitwise_equal_to_per_field": bool(same)}
 
 
-def served_leg(P, synth, torch, np):
-    """Poisson request stream: 70% isovalue-slider requests (1-4 isovalues) on
-    resident fields, 30% new float32 square fields with sides log-uniform in
-    [256, 4096].  Capacity is measured with every request submitted at once;
-    the stream then runs at 50% and 90% of it.  The same requests handled one
-    at a time with per-request launches give the baseline."""
+def served_leg(P, synth, torch, np, n_streams=2, fracs=(0.5, 0.9), baseline=True):
+    """Poisson request stream of 10^4 requests: 70% isovalue-slider requests
+    (1-4 isovalues) on a field already resident on the device, 30% new float32
+    square fields with sides log-uniform in [256, 4096] (drawn from six
+    pre-generated sides, 256..4096 log-spaced).  Capacity is measured with
+    every request submitted at once; the stream then runs at 50% and 90% of
+    it.  Clients are independent: new fields are put from two client threads
+    (their host copy into pinned staging takes milliseconds), sliders from the
+    main thread.  Latency is the server's, from each call to its result on the
+    device; `call_lag` is how late each call started after its arrival time.
+    The same requests handled one at a time with per-request launches, within
+    the same HBM budget, give the baseline."""
     import time as _t
+    from concurrent.futures import ThreadPoolExecutor
     log("served leg: preparing the field pool")
     sides = [256, 445, 776, 1351, 2353, 4096]
     pool = {}
@@ -138,8 +145,9 @@ def served_leg(P, synth, torch, np):
         f = synth.gen_moments(s_, s_, synth.SEED_BASE + 5 + s_, n_features=max(1, s_ * s_ // 65536))
         pool[s_] = [f[k].astype(np.float32) for k in ("mean_u", "var_u", "mean_v", "var_v")]
     budget = 24 << 30
-    n_req = 1200
+    n_req = 10000
     n_staging = 6
+    n_put_threads = 2
 
     def stream(rate, seed):
         return synth.request_stream(n_req, rate, seed)
@@ -147,46 +155,94 @@ def served_leg(P, synth, torch, np):
     ring = {s_: [torch.empty((4, s_ - 1, s_ - 1), device="cuda") for _ in range(8)]
             for s_ in sides}
 
+    def pct(v, q):
+        return round(float(np.percentile(np.asarray(v) * 1e6, q)), 1) if v else None
+
     def run(reqs, paced):
-        srv = P.Server(hbm_budget=budget, n_streams=4)
+        srv = P.Server(hbm_budget=budget, n_streams=n_streams)
         # pinned staging set aside before the clock starts, as the one-at-a-time
         # baseline's runtime keeps its own staging buffers warm
         srv.reserve_staging(max(sides) ** 2, n_staging)
-        resident, tickets = [], []
-        last = {}  # (side, ring slot) -> ticket of the request writing it
+        ready = []    # (id, side) of fields whose upload has completed
+        pending = []  # (id, side, future of the put_field ticket)
+        tickets = []
+        last = {}     # (side, ring slot) -> ticket of the slider writing it
         used = {s_: 0 for s_ in sides}
+        lag = {"slider": [], "new": []}
+        failed_puts = 0
         next_id = 0
         # two fields resident before the clock starts so sliders have targets
         for s_ in (776, 2353):
             srv.wait(srv.put_field(next_id, *pool[s_]))
-            resident.append((next_id, s_))
+            ready.append((next_id, s_))
             next_id += 1
+        puts = ThreadPoolExecutor(max_workers=n_put_threads)
         t0 = _t.perf_counter()
+
+        def put(fid, side, t_arr):
+            lag["new"].append(_t.perf_counter() - t0 - t_arr)
+            return srv.put_field(fid, *pool[side])
+
+        def refresh():
+            nonlocal failed_puts
+            keep = []
+            for fid, side, fut in pending:
+                if not fut.done():
+                    keep.append((fid, side, fut))
+                    continue
+                try:
+                    st = srv.poll(fut.result())
+                except P.PdivError:
+                    failed_puts += 1
+                    continue
+                if st is None:
+                    keep.append((fid, side, fut))
+                elif st == 0:
+                    ready.append((fid, side))
+                else:
+                    failed_puts += 1
+            pending[:] = keep
+
         for r in reqs:
             if paced:
                 while _t.perf_counter() - t0 < r["t"]:
                     pass
             if r["kind"] == "new":
                 side = min(sides, key=lambda s_: abs(np.log(s_ / r["side"])))
-                tickets.append(srv.put_field(next_id, *pool[side]))
-                resident.append((next_id, side))
+                pending.append((next_id, side, puts.submit(put, next_id, side, r["t"])))
                 next_id += 1
-            else:
-                fid, side = resident[int(r["pick"] * len(resident))]
-                iso = (r["iso_u"] - 0.5).astype(np.float32) * 0.05
+                continue
+            refresh()
+            iso = (r["iso_u"] - 0.5).astype(np.float32) * 0.05
+            while True:
+                while not ready:  # every resident field was evicted: wait for an upload
+                    if not pending:
+                        pending.append((next_id, 776, puts.submit(put, next_id, 776, r["t"])))
+                        next_id += 1
+                    refresh()
+                fid, side = ready[int(r["pick"] * len(ready))]
                 slot = used[side] % len(ring[side])
-                used[side] += 1
                 if (side, slot) in last:  # the buffer's previous writer must be done
                     srv.wait(last.pop((side, slot)))
-                o = ring[side][slot][: len(iso)]
+                if paced:
+                    lag["slider"].append(_t.perf_counter() - t0 - r["t"])
                 try:
-                    t = srv.submit_lcp(fid, iso, o)
-                    last[(side, slot)] = t
-                    tickets.append(t)
-                except P.PdivError:  # evicted: resubmit it as a new field
-                    tickets.append(srv.put_field(next_id, *pool[side]))
-                    resident.append((next_id, side))
-                    next_id += 1
+                    t = srv.submit_lcp(fid, iso, ring[side][slot][: len(iso)])
+                except P.PdivError:  # evicted since it was ready: pick another
+                    ready.remove((fid, side))
+                    if paced:
+                        lag["slider"].pop()
+                    continue
+                used[side] += 1
+                last[(side, slot)] = t
+                tickets.append(t)
+                break
+        for _, _, fut in pending:
+            try:
+                srv.wait(fut.result())
+            except P.PdivError:
+                failed_puts += 1
+        puts.shutdown()
         for t in tickets:
             try:
                 srv.wait(t)
@@ -195,43 +251,57 @@ def served_leg(P, synth, torch, np):
         wall = _t.perf_counter() - t0
         st = srv.stats()
         srv.close()
+        st["failed_puts"] = failed_puts
+        st["lag"] = lag
         return wall, st
 
     reqs = stream(1e9, 11)  # back to back: capacity
     wall, st = run(reqs, paced=False)
     capacity = n_req / wall
-    out = {"requests": n_req, "budget_bytes": budget, "n_streams": 4,
+    out = {"requests": n_req, "budget_bytes": budget, "n_streams": n_streams,
+           "client_put_threads": n_put_threads,
            "pinned_staging": f"{n_staging} x {16 * max(sides) ** 2} B reserved before timing",
            "capacity_req_per_s": round(capacity, 1),
            "capacity_lcp_cells_per_s": round(st["lcp_cells"] / wall, 1)}
-    for frac in (0.5, 0.9):
+    for frac in fracs:
         rate = frac * capacity
+        log(f"served leg: Poisson stream at {int(frac * 100)}% of capacity")
         wall, st = run(stream(rate, 12), paced=True)
+        lag = st["lag"]
         out[f"at_{int(frac * 100)}pct"] = {
-            "rate_req_per_s": round(rate, 1), "failed": st["failed"],
+            "rate_req_per_s": round(rate, 1), "failed": st["failed"] + st["failed_puts"],
             "p50_us": round(st["p50_us"], 1), "p99_us": round(st["p99_us"], 1),
             "p50_slider_us": round(st["p50_slider_us"], 1),
             "p99_slider_us": round(st["p99_slider_us"], 1),
             "p50_new_us": round(st["p50_new_us"], 1), "p99_new_us": round(st["p99_new_us"], 1),
+            "call_lag_p50_p99_slider_us": [pct(lag["slider"], 50), pct(lag["slider"], 99)],
+            "call_lag_p50_p99_new_us": [pct(lag["new"], 50), pct(lag["new"], 99)],
             "launches": st["launches"], "peak_bytes": st["peak_bytes"],
             "throughput_req_per_s": round(n_req / wall, 1)}
-    # baseline: the same back-to-back stream, one request at a time
+    if not baseline:
+        return out
+    # baseline: the same back-to-back stream, one request at a time, keeping
+    # fields resident within the same budget (oldest dropped first)
     log("served leg: one-request-at-a-time baseline")
     res = {}
-    t0 = _t.perf_counter()
     nid = 0
     for s_ in (776, 2353):
         ts = [torch.from_numpy(p).cuda() for p in pool[s_]]
         res[nid] = (P.divergence_gaussian(*ts), s_)
         nid += 1
     torch.cuda.synchronize()
+    held = sum(8 * s_ * s_ for _, s_ in res.values())
     t0 = _t.perf_counter()
     order = list(res)
     for r in reqs:
         if r["kind"] == "new":
             side = min(sides, key=lambda s_: abs(np.log(s_ / r["side"])))
+            while held + 24 * side * side > budget:
+                held -= 8 * res.pop(order.pop(0))[1] ** 2
             ts = [torch.from_numpy(p).cuda() for p in pool[side]]
             res[nid] = (P.divergence_gaussian(*ts), side)
+            held += 8 * side * side
+            del ts
             order.append(nid)
             nid += 1
         else:
@@ -241,6 +311,7 @@ def served_leg(P, synth, torch, np):
             P.lcp(dm, dv, iso)
         torch.cuda.synchronize()
     base = _t.perf_counter() - t0
+    del res
     out["one_at_a_time_req_per_s"] = round(n_req / base, 1)
     out["served_speedup_vs_one_at_a_time"] = round(capacity * base / n_req, 2)
     return out

@@ -209,7 +209,8 @@ typedef struct pdiv_server_stats_t {
   uint64_t done;            /* completed requests                                */
   uint64_t failed;          /* requests that ended with an error                 */
   uint64_t launches;        /* kernel launches issued for LCP requests           */
-  double p50_us, p99_us;    /* latency, submission -> result on device           */
+  double p50_us, p99_us;    /* latency, from the put_field / submit_lcp call to
+                               the worker seeing the result on the device      */
   double p50_new_us, p99_new_us;       /* ... for new-field requests             */
   double p50_slider_us, p99_slider_us; /* ... for slider requests                */
   double lcp_cells;         /* LCP values produced                               */
@@ -219,7 +220,11 @@ typedef struct pdiv_server_stats_t {
 
 /* hbm_budget: bytes the server may hold on the device (resident divergence
  * Gaussians, 8 B per point, plus staging of fields being uploaded).
- * n_streams: 1..8 compute streams. */
+ * n_streams: 1..8 compute streams.  Slider launches should not share a
+ * hardware queue with the upload stream, or they wait behind its host-to-device
+ * copies (milliseconds per large field): keep n_streams + 2 (the upload stream
+ * and the application's own stream) within the device's hardware queues per
+ * process (4 by default on ROCm; GPU_MAX_HW_QUEUES). */
 pdiv_status pdiv_server_create(size_t hbm_budget, int32_t n_streams, pdiv_server* out);
 /* New field from host moment planes (pageable or pinned host memory, dtype as
  * given, [ny][nx] each): uploaded, reduced to its divergence Gaussians

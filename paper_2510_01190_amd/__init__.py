@@ -31,6 +31,7 @@ MAX_ISO = 256
 STATUS = {0: "PDIV_OK", 1: "PDIV_ERR_INVALID", 2: "PDIV_ERR_UNSUPPORTED", 3: "PDIV_ERR_NOMEM",
           4: "PDIV_ERR_DEVICE", 5: "PDIV_ERR_BUSY", 6: "PDIV_ERR_TIMEOUT"}
 _DT = {"float32": 0, "float16": 1, "bfloat16": 2}
+_TIMEOUT = 6  # PDIV_ERR_TIMEOUT
 
 _c = ctypes
 _p = _c.c_void_p
@@ -376,6 +377,16 @@ class Server:
     def wait(self, ticket: int, timeout_us: int = -1) -> int:
         r = _c.c_int()
         st = lib().pdiv_server_wait(self._h, ticket, timeout_us, _c.byref(r))
+        _check(st)
+        return r.value
+
+    def poll(self, ticket: int):
+        """The request's own status (0 = done) once it has finished, which
+        retires the ticket like wait(); None while it is still running."""
+        r = _c.c_int()
+        st = lib().pdiv_server_wait(self._h, ticket, 0, _c.byref(r))
+        if st == _TIMEOUT:
+            return None
         _check(st)
         return r.value
 

@@ -155,6 +155,10 @@ struct pdiv_server_s {
   size_t budget = 0;
   int n_streams = 1;
   int device = 0;
+  // private stream-ordered pool for resident fields and upload staging; it
+  // keeps up to the budget mapped after frees, so admitting a field does not
+  // map fresh pages while the worker holds the lock
+  hipMemPool_t pool = nullptr;
   hipStream_t upload = nullptr;
   std::vector<hipStream_t> streams;
   std::vector<Slot> slots;
@@ -317,9 +321,12 @@ struct pdiv_server_s {
       if (resident + res + stg > budget && !evict_for(res + stg)) break;  // keep FIFO order
       ServerField* f = fields[r->fid].get();
       Launch L;
-      hipError_t e = hipMallocAsync(reinterpret_cast<void**>(&f->dmean), 4 * n, upload);
-      e = e != hipSuccess ? e : hipMallocAsync(reinterpret_cast<void**>(&f->dvar), 4 * n, upload);
-      e = e != hipSuccess ? e : hipMallocAsync(&L.staging, stg, upload);
+      hipError_t e =
+          hipMallocFromPoolAsync(reinterpret_cast<void**>(&f->dmean), 4 * n, pool, upload);
+      e = e != hipSuccess
+              ? e
+              : hipMallocFromPoolAsync(reinterpret_cast<void**>(&f->dvar), 4 * n, pool, upload);
+      e = e != hipSuccess ? e : hipMallocFromPoolAsync(&L.staging, stg, pool, upload);
       e = e != hipSuccess ? e
                           : hipMemcpyAsync(L.staging, r->host->p, stg, hipMemcpyHostToDevice, upload);
       const size_t pb = dtype_bytes(r->dtype) * n;
@@ -485,6 +492,14 @@ pdiv_status pdiv_server_create(size_t hbm_budget, int32_t n_streams, pdiv_server
   srv->n_streams = n_streams;
   srv->fault_at = fault_after();
   hipError_t e = hipGetDevice(&srv->device);
+  hipMemPoolProps props{};
+  props.allocType = hipMemAllocationTypePinned;
+  props.location.type = hipMemLocationTypeDevice;
+  props.location.id = srv->device;
+  e = e != hipSuccess ? e : hipMemPoolCreate(&srv->pool, &props);
+  uint64_t keep = hbm_budget;
+  e = e != hipSuccess ? e
+                      : hipMemPoolSetAttribute(srv->pool, hipMemPoolAttrReleaseThreshold, &keep);
   e = e != hipSuccess ? e : hipStreamCreateWithFlags(&srv->upload, hipStreamNonBlocking);
   for (int i = 0; i < n_streams && e == hipSuccess; ++i) {
     hipStream_t s = nullptr;
@@ -539,6 +554,9 @@ pdiv_status pdiv_server_put_field(pdiv_server srv, uint64_t id, const void* mean
     return PDIV_ERR_BUSY;
   }
   std::unique_ptr<Request> r(new Request());
+  // latency counts from the call: waiting for staging and the host copy are
+  // part of serving a new field
+  r->t_submit = Clock::now();
   {
     std::unique_lock<std::mutex> lk(srv->mu);
     if (srv->stop) return invalid("server is shutting down");
@@ -571,7 +589,6 @@ pdiv_status pdiv_server_put_field(pdiv_server srv, uint64_t id, const void* mean
   r->nx = int(nx);
   r->dx = dx;
   r->dy = dy;
-  r->t_submit = Clock::now();
   {
     std::lock_guard<std::mutex> g(srv->mu);
     r->ticket = srv->next_ticket++;
@@ -709,6 +726,7 @@ pdiv_status pdiv_server_destroy(pdiv_server srv) {
   for (auto& b : srv->pinned) (void)hipHostFree(b->p);
   for (hipStream_t s : srv->streams) (void)hipStreamDestroy(s);
   if (srv->upload) (void)hipStreamDestroy(srv->upload);
+  if (srv->pool) (void)hipMemPoolDestroy(srv->pool);
   delete srv;
   return PDIV_OK;
 }
