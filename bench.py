@@ -66,6 +66,129 @@ def read_traffic():
         return None
 
 
+def host_cpu():
+    """CPU model and the number of CPUs this process may run on."""
+    name = "unknown"
+    try:
+        for line in open("/proc/cpuinfo"):
+            if line.startswith("model name"):
+                name = line.split(":", 1)[1].strip()
+                break
+    except OSError:
+        pass
+    return {"model": name, "affinity_cpus": len(os.sched_getaffinity(0))}
+
+
+def cpu_workers():
+    """Worker processes for the all-cores CPU legs: the CPUs this process may
+    run on, at most 16 (one GPU's share of the host)."""
+    return max(1, min(16, len(os.sched_getaffinity(0))))
+
+
+def _warm(_):
+    import numpy  # noqa: F401
+    import oracle  # noqa: F401
+    return os.getpid()
+
+
+def _shared_rows(task):
+    from multiprocessing import shared_memory
+    import numpy as np
+    shm = shared_memory.SharedMemory(name=task[0])
+    arr = np.ndarray(task[1], np.float64, buffer=shm.buf)
+    return shm, [arr[q, task[2]:task[3]] for q in range(4)]
+
+
+def _oracle_band(task):
+    """Closed-form oracle on moment rows [a, b) of the shared float64 copy
+    (cell rows a+1 .. b-2); returns (LCP values, seconds)."""
+    import oracle as O
+    shm, planes = _shared_rows(task)
+    t = time.perf_counter()
+    m, vv = O.divergence_gaussian(*planes, 1.0, 1.0)
+    n = O.lcp(m[1:-1], vv[1:-1], task[4]).size
+    dt = time.perf_counter() - t
+    del planes, m, vv
+    shm.close()
+    return n, dt
+
+
+def _mc_band(task):
+    """Vector-level Monte Carlo oracle on moment rows [a, b) of the shared
+    copy, as a field of its own; returns (LCP values, seconds)."""
+    import oracle as O
+    shm, planes = _shared_rows(task)
+    t = time.perf_counter()
+    n = O.mc_lcp(*planes, 1.0, 1.0, task[4], task[5], task[6]).size
+    dt = time.perf_counter() - t
+    del planes
+    shm.close()
+    return n, dt
+
+
+def cpu_legs(stored, iso, rows, mc_rows=34, mc_samples=100, mc_target=1000):
+    """CPU legs beside the single-thread oracle: the same oracle on the same
+    cell rows spread over cpu_workers() processes, and the vector-level
+    Monte Carlo oracle (mc_samples samples on mc_rows-row bands, scaled
+    linearly to mc_target samples) on one core and on all workers.  The
+    oracle is unchanged; the processes only split the rows."""
+    import multiprocessing
+    from multiprocessing import shared_memory
+    import numpy as np
+    ny, nx = stored[0].shape
+    nw = cpu_workers()
+    lo, hi = rows[0] - 1, rows[1] + 2
+    mc_lo = lo  # Monte Carlo bands start at the top of the shared rows
+    assert mc_lo + nw * mc_rows <= hi
+    shape = (4, hi - lo, nx)
+    shm = shared_memory.SharedMemory(create=True, size=8 * 4 * (hi - lo) * nx)
+    out = {}
+    try:
+        arr = np.ndarray(shape, np.float64, buffer=shm.buf)
+        for q in range(4):
+            arr[q] = stored[q][lo:hi]
+        del arr
+        mc_task = lambda i: (shm.name, shape, i * mc_rows, (i + 1) * mc_rows, iso, mc_samples,
+                             2025 + i)
+        log(f"CPU Monte Carlo oracle, 1 thread ({mc_rows}x{nx} band, {mc_samples} samples)")
+        n1, t1 = _mc_band(mc_task(0))
+        scale = mc_target / mc_samples
+        ctx = multiprocessing.get_context("spawn")
+        with ctx.Pool(nw) as pool:
+            pool.map(_warm, range(4 * nw))  # start-up and imports outside the clock
+            log(f"CPU oracle on {nw} processes")
+            tasks = [(shm.name, shape, j0 - 1 - lo, min(j0 + 256, rows[1]) + 2 - lo, iso)
+                     for j0 in range(rows[0], rows[1], 256)]
+            t = time.perf_counter()
+            res = pool.map(_oracle_band, tasks, chunksize=1)
+            wall = time.perf_counter() - t
+            n_all = sum(r[0] for r in res)
+            out["oracle_all_cores"] = {
+                "value": round(n_all / wall, 1), "unit": "LCP cells/s", "cores": nw,
+                "kind": "oracle", "sample": f"the same cell rows in {len(tasks)} bands of 256 "
+                                            f"rows over {nw} processes ({wall:.2f} s wall)"}
+            log(f"CPU Monte Carlo oracle on {nw} processes")
+            t = time.perf_counter()
+            res = pool.map(_mc_band, [mc_task(i) for i in range(nw)], chunksize=1)
+            wall_mc = time.perf_counter() - t
+        n_mc = sum(r[0] for r in res)
+        sample = (f"{mc_rows}x{nx}-vertex bands of the same field, {len(iso)} isovalues, "
+                  f"{mc_samples} samples, time scaled x{scale:g} to {mc_target} samples")
+        out["mc_1core"] = {"value": round(n1 / (t1 * scale), 1),
+                           "unit": f"LCP cells/s at {mc_target} samples", "cores": 1,
+                           "kind": "oracle (vector-level Monte Carlo, numpy float64)",
+                           "sample": f"one band; {sample} ({t1:.1f} s)",
+                           "point_samples_per_s": round(mc_rows * nx * mc_samples / t1, 1)}
+        out["mc_all_cores"] = {"value": round(n_mc / (wall_mc * scale), 1),
+                               "unit": f"LCP cells/s at {mc_target} samples", "cores": nw,
+                               "kind": "oracle (vector-level Monte Carlo, numpy float64)",
+                               "sample": f"{nw} bands; {sample} ({wall_mc:.1f} s wall)"}
+    finally:
+        shm.close()
+        shm.unlink()
+    return out
+
+
 def time_launches(fn, n, torch):
     """Average device time of fn() over n back-to-back launches, HIP events on
     the current stream (the stream every launch is enqueued on)."""
@@ -325,6 +448,8 @@ def main():
     ap.add_argument("--no-legs", action="store_true")
     ap.add_argument("--no-mc", action="store_true")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-cpu-legs", action="store_true",
+                    help="only the single-thread oracle in the CPU baseline")
     ap.add_argument("--mc-samples", type=int, default=1000)
     ap.add_argument("--copy-calibration", action="store_true",
                     help="only run a plain 1 GiB device copy (HBM counter calibration)")
@@ -529,13 +654,35 @@ def main():
             n_cpu += ref.size
             g = out[:, j0:j1, :].double().cpu().numpy()
             worst = max(worst, float(np.max(np.abs(g - ref))))
-        result["cpu_baseline"] = {"value": round(n_cpu / t_cpu, 1), "unit": "LCP cells/s",
+        cpu = n_cpu / t_cpu
+        result["cpu_baseline"] = {"value": round(cpu, 1), "unit": "LCP cells/s",
                                   "cores": 1, "kind": "oracle",
                                   "sample": f"cell rows {rows[0]}-{rows[1] - 1} of the same "
                                             f"8192x8192 field, all {K} isovalues "
                                             f"({n_cpu} LCP values, {t_cpu:.1f} s, numpy float64)",
-                                  "gpu_speedup": round(value / (n_cpu / t_cpu), 1),
-                                  "gpu_max_abs_err_on_sample": worst}
+                                  "gpu_speedup": round(value / cpu, 1),
+                                  "gpu_max_abs_err_on_sample": worst,
+                                  "host": host_cpu()}
+        if not args.no_cpu_legs:
+            legs_cpu = cpu_legs(stored, iso, rows, mc_target=args.mc_samples)
+            result["cpu_baseline"].update(legs_cpu)
+            mc1 = legs_cpu["mc_1core"]["value"]
+            ratios = {"cpu_oracle_1core_vs_cpu_mc_1core": round(cpu / mc1, 1),
+                      "cpu_oracle_all_cores_vs_cpu_mc_1core":
+                          round(legs_cpu["oracle_all_cores"]["value"] / mc1, 1),
+                      "gpu_closed_form_vs_cpu_mc_1core": round(value / mc1, 1)}
+            if "mc" in result:
+                ratios["gpu_closed_form_vs_gpu_mc"] = result["mc"]["closed_form_speedup"]
+            # the paper's speed-ups of the closed form over serial Monte Carlo,
+            # on its own hardware and datasets (Sec. 4): context only
+            ratios["paper_context"] = {
+                "wind_serial_closed_form_vs_serial_mc": 1946,
+                "wind_openmp10_closed_form_vs_serial_mc": 9891,
+                "red_sea_serial_closed_form_vs_serial_mc": 1125.62,
+                "red_sea_openmp10_closed_form_vs_serial_mc": 10505.8,
+                "red_sea_gpu_closed_form_vs_serial_mc": 19698.37,
+                "hardware": "Apple M4 (serial and 10 threads); a GPU of the Frontier system"}
+            result["cpu_baseline"]["ratios"] = ratios
         result["accuracy"] = {"max_abs_err_vs_fp64_oracle": worst, "bar": 1e-5,
                               "within_bar": worst <= 1e-5}
 
