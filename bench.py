@@ -628,6 +628,32 @@ def main():
                           10, torch)
         legs["pipeline_fit_then_lcp_721x1440_m50_k8"] = {"ms": round(t * 1e3, 4),
                                                         "cells_per_s": round(720 * 1439 * 8 / t, 1)}
+        # the error and time curve of Sec. 4 (Fig. 4): the Monte Carlo at
+        # growing sample counts against the closed form on the fitted
+        # ensemble; a run of S samples is the prefix of any longer run with
+        # the same seed (Philox counters), and on interior cells the expected
+        # SSE is sum L(1-L)/S
+        iso2 = c2["isovalues"]
+        P.lcp_from_moments(*outs, iso2, out=c2out)
+        t_cf = time_launches(lambda: P.lcp_from_moments(*outs, iso2, out=c2out), 10, torch)
+        Lh = c2out.double().cpu().numpy()
+        inner = np.zeros((720, 1439), bool)
+        inner[1:719, 1:1438] = True  # cells 1 <= i <= nx-3, 1 <= j <= ny-3
+        var_sum = float(np.sum((Lh * (1 - Lh))[:, inner]))
+        mco = torch.empty_like(c2out)
+        curve = []
+        for S in (10, 30, 100, 300, 1000):
+            P.mc_lcp(*outs, iso2, n_samples=S, seed=2025, out=mco)
+            t = time_launches(lambda: P.mc_lcp(*outs, iso2, n_samples=S, seed=2025, out=mco), 3,
+                              torch)
+            d2 = (mco.double().cpu().numpy() - Lh) ** 2
+            curve.append({"samples": S, "ms": round(t * 1e3, 3),
+                          "sse_interior": round(float(d2[:, inner].sum()), 3),
+                          "expected_sse_interior": round(var_sum / S, 3),
+                          "sse_all_cells": round(float(d2.sum()), 3)})
+        legs["mc_error_and_time_vs_samples_721x1440_k8"] = {
+            "closed_form_ms": round(t_cf * 1e3, 4), "seed": 2025, "curve": curve}
+        del mco, d2
         del u, v, outs, c2out
         torch.cuda.empty_cache()
         legs["batch_512_fields_k4"] = batch_leg(P, synth, torch, np)

@@ -81,3 +81,25 @@ def test_mc_zero_variance_is_deterministic():
     g = host64(P.mc_lcp(*ts, iso, n_samples=10, seed=1))
     r = O.mc_lcp(*stored64(ts), 1.0, 1.0, iso, 10, 1, precision="f32")
     assert np.array_equal(g, r)
+
+
+@pytest.mark.parametrize("S", [10, 100, 1000])
+def test_mc_sse_follows_sample_count(S):
+    """The error curve of Sec. 4 (Fig. 4) on the GPU: over the interior cells
+    of a 512x512 field at 8 isovalues, the SSE of the S-sample MC against the
+    closed form has expectation sum L(1-L)/S (independent Bernoulli draws per
+    interior cell); one run lands within 5% of it (its relative spread is
+    well under 1% at this size)."""
+    ny = nx = 512
+    f = synth.gen_moments(ny, nx, seed=77, sigma=(0.05, 0.5))
+    ts = moments_dev(f)
+    iso = np.linspace(-0.15, 0.15, 8).astype(np.float32)
+    L = host64(P.lcp_from_moments(*ts, iso))
+    E = host64(P.mc_lcp(*ts, iso, n_samples=S, seed=4242))
+    inner = np.zeros((ny - 1, nx - 1), bool)
+    inner[1:ny - 2, 1:nx - 2] = True
+    inner = np.broadcast_to(inner, L.shape)
+    expected = float(np.sum((L * (1 - L))[inner])) / S
+    sse = float(np.sum(((E - L) ** 2)[inner]))
+    print(f"\n[S={S}] SSE {sse:.4g}, expected {expected:.4g}, ratio {sse / expected:.4f}")
+    assert abs(sse / expected - 1.0) < 0.05

@@ -153,3 +153,25 @@ def test_mc_f32_and_f64_agree_up_to_rare_flips():
     a = O.mc_lcp(mu_u, var_u, mu_v, var_v, 1.0, 1.0, [0.0, 0.3], S, seed=3, precision="f64")
     b = O.mc_lcp(mu_u, var_u, mu_v, var_v, 1.0, 1.0, [0.0, 0.3], S, seed=3, precision="f32")
     assert np.sum(np.abs(a - b) * S) <= 5
+
+
+@pytest.mark.parametrize("S", [8, 64])
+def test_mc_sse_follows_binomial_expectation(S):
+    """The error curve of Sec. 4 (Fig. 4): on an interior cell each sample's
+    crossing is an independent Bernoulli(LCP) draw, so the sum of squared
+    errors of the S-sample estimate has expectation sum L(1-L)/S.  Averaged
+    over 40 seeds the oracle's SSE must sit within 5% of it (the SSE of one
+    run has a relative spread of about 6% on this grid, so the mean of 40
+    runs about 1%)."""
+    rng = np.random.default_rng(11)
+    ny, nx = 24, 24
+    mu_u, mu_v = rng.normal(0, 0.3, (ny, nx)), rng.normal(0, 0.3, (ny, nx))
+    var_u, var_v = rng.uniform(0.1, 0.5, (ny, nx)) ** 2, rng.uniform(0.1, 0.5, (ny, nx)) ** 2
+    iso = [-0.05, 0.1]
+    m, v = O.divergence_gaussian(mu_u, var_u, mu_v, var_v, 1.0, 1.0)
+    L = O.lcp(m, v, iso)
+    inner = np.broadcast_to(_interior(ny, nx), L.shape)
+    expected = float(np.sum((L * (1 - L))[inner])) / S
+    sse = [float(np.sum(((O.mc_lcp(mu_u, var_u, mu_v, var_v, 1.0, 1.0, iso, S, seed) - L)
+                         ** 2)[inner])) for seed in range(100, 140)]
+    assert abs(np.mean(sse) / expected - 1.0) < 0.05
