@@ -7,7 +7,8 @@ helpers, tables or constants) and never imports it.
 
 The oracle is written from the paper (Ouermi et al., "Efficient Probabilistic
 Visualization of Local Divergence of 2D Vector Fields with Independent Gaussian
-Uncertainty"): plain, slow, obviously correct numpy in float64.
+Uncertainty"): plain, slow, obviously correct numpy in float64.  The 3D
+extension (pdiv_oracle3d) follows the paper's stated future work.
 """
 
 from .pdiv_oracle import (  # noqa: F401
@@ -21,4 +22,12 @@ from .pdiv_oracle import (  # noqa: F401
     mc_sample_field,
     mc_lcp,
     mc_lcp_vertex,
+)
+from .pdiv_oracle3d import (  # noqa: F401
+    divergence_gaussian_3d,
+    fd_divergence_3d,
+    lcp_3d,
+    crossed_3d,
+    mc_lcp_3d,
+    mc_lcp_3d_vertex,
 )

@@ -17,6 +17,8 @@ from .fields import (  # noqa: F401
     quantile_isovalues,
     smooth_std_map,
     gen_moments,
+    gen_moments_3d,
+    analytic_divergence_3d,
     gen_ensemble,
     config_c1,
     config_c2,

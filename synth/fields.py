@@ -219,6 +219,55 @@ def config_c4(n_fields: int = 512, lo: int = 64, hi: int = 2048, n_iso: int = 4)
     return fields
 
 
+def gen_moments_3d(nz: int, ny: int, nx: int, seed: int, sigma=(0.05, 0.5), n_modes: int = 6,
+                   dtype=np.float64):
+    """Independent-Gaussian 3D field: returns dict with mean_u, var_u, mean_v,
+    var_v, mean_w, var_w ([nz][ny][nx] in dtype) and the modes.  Each mean
+    component is a sum of n_modes separable waves
+        A sin(2 pi kx x/nx + px) sin(2 pi ky y/ny + py) sin(2 pi kz z/nz + pz),
+    k ~ U[1, 4] periods per axis, phases U[0, 2 pi), A ~ U[-1, 1] scaled so
+    that the component's derivative along its own axis has amplitude |A|
+    (sources, sinks and swirls at every scale of the box, with divergences of
+    order one).  Spread sigma ~ U[sigma] i.i.d. per point and component."""
+    rng = np.random.default_rng(seed)
+    n = (nx, ny, nz)
+    axes = [np.arange(m, dtype=np.float64) for m in n]  # x, y, z coordinates
+    modes = []
+    out = {}
+    for comp, own in (("u", 0), ("v", 1), ("w", 2)):
+        mean = np.zeros((nz, ny, nx), dtype)
+        for _ in range(n_modes):
+            k = rng.uniform(1.0, 4.0, 3)
+            ph = rng.uniform(0.0, 2.0 * math.pi, 3)
+            amp = rng.uniform(-1.0, 1.0) * n[own] / (2.0 * math.pi * k[own])
+            fx, fy, fz = (np.sin(2.0 * math.pi * k[a] * axes[a] / n[a] + ph[a]) for a in range(3))
+            mean += (amp * fz.astype(dtype)[:, None, None]) * (fy.astype(dtype)[None, :, None]
+                                                              * fx.astype(dtype)[None, None, :])
+            modes.append((comp, amp, tuple(k), tuple(ph)))
+        sd = rng.uniform(sigma[0], sigma[1], (nz, ny, nx)).astype(dtype)
+        out["mean_" + comp] = mean
+        out["var_" + comp] = sd * sd
+    out.update(modes=modes, nz=nz, ny=ny, nx=nx)
+    return out
+
+
+def analytic_divergence_3d(modes, nz: int, ny: int, nx: int, step: int = 1):
+    """dU/dx + dV/dy + dW/dz of gen_moments_3d's mean field, on every
+    step-th point along each axis (for picking isovalues)."""
+    n = (nx, ny, nz)
+    axes = [np.arange(0, m, step, dtype=np.float64) for m in n]
+    div = np.zeros((axes[2].size, axes[1].size, axes[0].size))
+    own = {"u": 0, "v": 1, "w": 2}
+    for comp, amp, k, ph in modes:
+        a0 = own[comp]
+        f = []
+        for a in range(3):
+            arg = 2.0 * math.pi * k[a] * axes[a] / n[a] + ph[a]
+            f.append(np.cos(arg) * 2.0 * math.pi * k[a] / n[a] if a == a0 else np.sin(arg))
+        div += amp * f[2][:, None, None] * f[1][None, :, None] * f[0][None, None, :]
+    return div
+
+
 def request_stream(n_requests: int, rate_hz: float, seed: int, frac_new: float = 0.3,
                    side=(256, 4096), n_iso=(1, 4)):
     """Poisson request stream: list of dicts with arrival time (s), kind
