@@ -247,6 +247,56 @@ def batch_leg(P, synth, torch, np):
             "tile": info, "bitwise_equal_to_per_field": bool(same)}
 
 
+def volume_leg(P, synth, torch, np, n=512):
+    """The 3D extension on an n^3 float32 field (six moment volumes): the
+    divergence Gaussian with the z term, then the 8-corner LCP at 1, 4 and
+    16 isovalues, each against its algorithmic bytes; the maps of sampled
+    cell layers against the oracle, and the oracle's own rate on one slab."""
+    import oracle as O
+    log(f"3D leg: generating the {n}^3 field (seeded)")
+    keys = ("mean_u", "var_u", "mean_v", "var_v", "mean_w", "var_w")
+    f = synth.gen_moments_3d(n, n, n, synth.SEED_BASE + 30, dtype=np.float32)
+    ts = [torch.from_numpy(f[k]).cuda() for k in keys]
+    del f
+    pts = n ** 3
+    cells = (n - 1) ** 3
+    dm, dv = P.divergence_gaussian_3d(*ts)
+    t = time_launches(lambda: P.divergence_gaussian_3d(*ts), 10, torch)
+    b = 6 * 4 * pts + 2 * 4 * pts
+    out = {"grid": [n, n, n], "storage": "float32",
+           "divergence_3d": {"ms": round(t * 1e3, 4), "algorithmic_bytes": b,
+                             "achieved_GBs": round(b / t / 1e9, 1),
+                             "frac_hbm": round(b / t / 1e9 / HBM_PEAK_GBS, 4)}}
+    del ts
+    sub = dm[::8, ::8, ::8].double().cpu().numpy()
+    for k in (1, 4, 16):
+        iso = np.quantile(sub, np.linspace(0.2, 0.8, k) if k > 1 else [0.5]).astype(np.float32)
+        o = torch.empty((k, n - 1, n - 1, n - 1), device="cuda")
+        P.lcp_3d(dm, dv, iso, out=o)
+        t = time_launches(lambda: P.lcp_3d(dm, dv, iso, out=o), 10, torch)
+        b = 8 * pts + 4 * k * cells
+        leg = {"ms": round(t * 1e3, 4), "cells_per_s": round(k * cells / t, 1),
+               "algorithmic_bytes": b, "achieved_GBs": round(b / t / 1e9, 1),
+               "frac_hbm": round(b / t / 1e9 / HBM_PEAK_GBS, 4)}
+        if k == 4:
+            worst = 0.0
+            for k0 in (0, n // 2 - 2, n - 3):
+                m = dm[k0:k0 + 3].double().cpu().numpy()
+                v = dv[k0:k0 + 3].double().cpu().numpy()
+                tc = time.perf_counter()
+                r = O.lcp_3d(m, v, iso)
+                tc = time.perf_counter() - tc
+                worst = max(worst, float(np.max(np.abs(
+                    o[:, k0:k0 + 2].double().cpu().numpy() - r))))
+            leg["max_abs_err_vs_fp64_oracle_sampled_layers"] = worst
+            leg["cpu_oracle_cells_per_s_1core"] = round(r.size / tc, 1)
+            out["two_step_k4_ms"] = round(out["divergence_3d"]["ms"] + leg["ms"], 4)
+        out[f"lcp_3d_k{k}"] = leg
+        del o
+    del dm, dv
+    return out
+
+
 def served_leg(P, synth, torch, np, n_streams=2, fracs=(0.5, 0.9), baseline=True):
     """Poisson request stream of 10^4 requests: 70% isovalue-slider requests
     (1-4 isovalues) on a field already resident on the device, 30% new float32
@@ -657,6 +707,8 @@ def main():
         del u, v, outs, c2out
         torch.cuda.empty_cache()
         legs["batch_512_fields_k4"] = batch_leg(P, synth, torch, np)
+        torch.cuda.empty_cache()
+        legs["volume_3d_512"] = volume_leg(P, synth, torch, np)
         torch.cuda.empty_cache()
         legs["served_stream"] = served_leg(P, synth, torch, np)
         result["legs"] = legs

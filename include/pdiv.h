@@ -150,6 +150,43 @@ pdiv_status pdiv_mc_sample_field(const void* mean_u, const void* var_u, const vo
                                  pdiv_stream stream);
 
 /* ------------------------------------------------------------------------
+ * 3D vector fields, the extension the paper names as future work (Section 5).
+ * Nothing in the method changes but the dimension: the divergence adds
+ * dW/dz, differenced like the other two axes, and a cell is a hexahedron.
+ * Grids are row-major [nz][ny][nx] (x fastest); 2 <= nz, ny <= 2^21,
+ * 2 <= nx <= 2^29, at most 2^40 points; larger grids are PDIV_ERR_INVALID.
+ * ------------------------------------------------------------------------ */
+
+/* Eq. 2 and Eq. 3 with the z term at every vertex: mean = sum over the three
+ * axes of the central difference of the axis's own component's means (step
+ * 2h inside, first-order one-sided with step h on the two boundary planes of
+ * that axis), variance = the sum of the squared weights times the neighbour
+ * variances.  U, V, W are the x, y, z components; their six [nz][ny][nx]
+ * planes are in_dtype (device); div_mean, div_var: [nz][ny][nx] float32
+ * (device).  dx, dy, dz: finite and > 0. */
+pdiv_status pdiv_divergence_gaussian_3d(const void* mean_u, const void* var_u,
+                                        const void* mean_v, const void* var_v,
+                                        const void* mean_w, const void* var_w,
+                                        pdiv_dtype in_dtype, int64_t nz, int64_t ny, int64_t nx,
+                                        double dx, double dy, double dz, float* div_mean,
+                                        float* div_var, pdiv_stream stream);
+
+/* Level-crossing probability of every hexahedral cell: the probability that
+ * the c-isosurface passes through a cell whose 8 corners hold independent
+ * Gaussians, 1 - prod_8 P(X >= c) - prod_8 P(X < c) (Section 3.1's formula
+ * with 8 corners; >= counts as above; a zero-variance corner is
+ * deterministic, so zero variance everywhere gives the marching-cubes
+ * crossing indicator).  Evaluated in float32 with one Gaussian tail per
+ * corner and isovalue and the cancellation-free pairwise combination.
+ * div_mean, div_var: [nz][ny][nx] float32 (device); isovalues_host: n_iso
+ * floats in host memory, 1 <= n_iso <= PDIV_MAX_ISO; lcp: dense
+ * [n_iso][nz-1][ny-1][nx-1] float32 (device), cell (i, j, k) having corners
+ * (i+a, j+b, k+c), a, b, c in {0, 1}. */
+pdiv_status pdiv_lcp_3d(const float* div_mean, const float* div_var, int64_t nz, int64_t ny,
+                        int64_t nx, const float* isovalues_host, int32_t n_iso, float* lcp,
+                        pdiv_stream stream);
+
+/* ------------------------------------------------------------------------
  * Batched launch: many independent fields of uneven size, each with its own
  * isovalues, in ONE persistent kernel (fused Eq. 2-3 + closed-form LCP).
  * The paper's GPU run is dominated by launch overhead on a small field

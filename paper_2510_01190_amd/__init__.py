@@ -69,6 +69,9 @@ _SIGS = {
     "pdiv_moments": [_p, _p, _c.c_int, _i64, _i64, _i64, _i64, _i32, _p, _p, _p, _p, _c.c_int, _p],
     "pdiv_divergence_gaussian": [_p, _p, _p, _p, _c.c_int, _i64, _i64, _f64, _f64, _p, _p, _p],
     "pdiv_lcp": [_p, _p, _i64, _i64, _fp, _i32, _p, _i64, _i64, _p],
+    "pdiv_divergence_gaussian_3d": [_p, _p, _p, _p, _p, _p, _c.c_int, _i64, _i64, _i64, _f64,
+                                    _f64, _f64, _p, _p, _p],
+    "pdiv_lcp_3d": [_p, _p, _i64, _i64, _i64, _fp, _i32, _p, _p],
     "pdiv_mc_lcp": [_p, _p, _p, _p, _c.c_int, _i64, _i64, _f64, _f64, _fp, _i32, _i64, _u64, _p, _p],
     "pdiv_lcp_from_moments": [_p, _p, _p, _p, _c.c_int, _i64, _i64, _f64, _f64, _fp, _i32, _p,
                               _i64, _i64, _p],
@@ -244,6 +247,38 @@ def lcp(div_mean, div_var, isovalues, out=None):
         out = torch.empty((iso.size, ny - 1, nx - 1), dtype=torch.float32, device=div_mean.device)
     po, pitch, plane = _lcp_out(out, iso.size, ny, nx)
     _check(lib().pdiv_lcp(pm, pv, ny, nx, ip, iso.size, po, pitch, plane, _stream()))
+    return out
+
+
+def divergence_gaussian_3d(mean_u, var_u, mean_v, var_v, mean_w, var_w, dx: float = 1.0,
+                           dy: float = 1.0, dz: float = 1.0):
+    """Eq. 2-3 with the z term for a 3D field (six [nz][ny][nx] planes of one
+    dtype): (div_mean, div_var) float32 [nz][ny][nx]."""
+    torch = _torch()
+    nz, ny, nx = mean_u.shape
+    dt = mean_u.dtype
+    ptrs = [_dev(t, n, (nz, ny, nx), dt) for t, n in
+            ((mean_u, "mean_u"), (var_u, "var_u"), (mean_v, "mean_v"), (var_v, "var_v"),
+             (mean_w, "mean_w"), (var_w, "var_w"))]
+    dm = torch.empty((nz, ny, nx), dtype=torch.float32, device=mean_u.device)
+    dv = torch.empty_like(dm)
+    _check(lib().pdiv_divergence_gaussian_3d(*ptrs, _dtype_code(mean_u), nz, ny, nx, dx, dy, dz,
+                                             _p(dm.data_ptr()), _p(dv.data_ptr()), _stream()))
+    return dm, dv
+
+
+def lcp_3d(div_mean, div_var, isovalues, out=None):
+    """8-corner LCP [K][nz-1][ny-1][nx-1] (dense) from 3D divergence Gaussians."""
+    torch = _torch()
+    nz, ny, nx = div_mean.shape
+    pm = _dev(div_mean, "div_mean", (nz, ny, nx), torch.float32)
+    pv = _dev(div_var, "div_var", (nz, ny, nx), torch.float32)
+    iso, ip = _iso_arr(isovalues)
+    shape = (iso.size, nz - 1, ny - 1, nx - 1)
+    if out is None:
+        out = torch.empty(shape, dtype=torch.float32, device=div_mean.device)
+    po = _dev(out, "out", shape, torch.float32)
+    _check(lib().pdiv_lcp_3d(pm, pv, nz, ny, nx, ip, iso.size, po, _stream()))
     return out
 
 

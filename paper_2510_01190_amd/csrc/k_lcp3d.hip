@@ -1,0 +1,253 @@
+// The path extended to 3D vector fields, the paper's stated future work
+// (Section 5): the divergence Gaussian gains the z term of Eq. 2 and Eq. 3
+// (dW/dz differenced like the other two axes), and a cell is a hexahedron
+// whose level-crossing probability is 1 - prod_8 P(above) - prod_8 P(below).
+//
+// Kernels:
+//   divergence3d_kernel  Eq. 2-3 with the z term, one vertex per lane; HBM
+//                        bound: 6 planes read, 2 written.
+//   lcp3d_kernel         8-corner LCP from the divergence Gaussians.  A wave
+//                        holds a strip of 64 vertex columns (63 cells) and LZ
+//                        consecutive cell layers k0..k0+LZ-1 and walks a band
+//                        of rows along y.  At each row it evaluates the
+//                        corner tails once for the LZ+1 z-levels it holds,
+//                        pairs them along z, joins each z-pair with the one
+//                        of the previous row (carried in registers) and
+//                        combines the resulting 4-corner column with the
+//                        right neighbour's through DPP, so every tail serves
+//                        the cells on both sides of its vertex in x, y and,
+//                        inside the wave, z.
+#include <hip/hip_runtime.h>
+
+#include "lcp_tile.hpp"
+#include "pdiv_device.hpp"
+#include "pdiv_internal.hpp"
+
+namespace pdiv {
+
+StencilCoef3 make_coef3(double dx, double dy, double dz) {
+  StencilCoef3 k;
+  k.xy = make_coef(dx, dy);
+  k.czm_in = static_cast<float>(1.0 / (2.0 * dz));
+  k.czv_in = static_cast<float>(1.0 / (4.0 * dz * dz));
+  k.czm_bd = static_cast<float>(1.0 / dz);
+  k.czv_bd = static_cast<float>(1.0 / (dz * dz));
+  return k;
+}
+
+namespace {
+
+constexpr int kBlock = 256;
+constexpr int kWavesPerBlock = kBlock / 64;
+constexpr int kRowsPerWave = 8;
+constexpr int kBandRows3 = 64;
+
+// Eq. 2-3 with the z term at one vertex; the neighbours are already clamped
+// at the boundary and the coefficients chosen (1/(2h) inside, 1/h on a
+// boundary plane).  Contraction is off so the rounding is fixed.
+__device__ __forceinline__ DivGauss div_gauss3(float mu_xl, float mu_xr, float vu_xl,
+                                               float vu_xr, float mv_yl, float mv_yr,
+                                               float vv_yl, float vv_yr, float mw_zl,
+                                               float mw_zr, float vw_zl, float vw_zr, float cxm,
+                                               float cxv, float cym, float cyv, float czm,
+                                               float czv) {
+#pragma clang fp contract(off)
+  const float mx = (mu_xr - mu_xl) * cxm;
+  const float my = (mv_yr - mv_yl) * cym;
+  const float mz = (mw_zr - mw_zl) * czm;
+  const float vx = (vu_xr + vu_xl) * cxv;
+  const float vy = (vv_yr + vv_yl) * cyv;
+  const float vz = (vw_zr + vw_zl) * czv;
+  DivGauss g;
+  g.mean = (mx + my) + mz;
+  g.var = (vx + vy) + vz;
+  return g;
+}
+
+// Grid: blocks of 4 waves; block b covers x columns 64 (b % n_xb) .. +63
+// and vertex rows r = z ny + y from kRowsPerWave (4 (b / n_xb) + wave) on.
+template <typename T>
+__global__ __launch_bounds__(kBlock) void divergence3d_kernel(
+    const T* __restrict__ mu, const T* __restrict__ vu, const T* __restrict__ mv,
+    const T* __restrict__ vv, const T* __restrict__ mw, const T* __restrict__ vw, int nz, int ny,
+    int nx, StencilCoef3 k, float* __restrict__ dmean, float* __restrict__ dvar, int n_xb) {
+  const int xb = blockIdx.x % n_xb;
+  const int rg = blockIdx.x / n_xb;
+  const int x = xb * 64 + (threadIdx.x & 63);
+  if (x >= nx) return;
+  const int64_t rows = int64_t(nz) * ny;
+  const int64_t r0 =
+      (int64_t(rg) * kWavesPerBlock + __builtin_amdgcn_readfirstlane(threadIdx.x >> 6)) *
+      kRowsPerWave;
+  const int64_t r1 = r0 + kRowsPerWave < rows ? r0 + kRowsPerWave : rows;
+  const Col c = make_col(uint32_t(x), nx, sizeof(T));
+  const int64_t plane = int64_t(ny) * nx;
+  for (int64_t r = r0; r < r1; ++r) {
+    const int z = int(r / ny);
+    const int y = int(r - int64_t(z) * ny);
+    const int yl = y > 0 ? y - 1 : 0, yr = y < ny - 1 ? y + 1 : ny - 1;
+    const int zl = z > 0 ? z - 1 : 0, zr = z < nz - 1 ? z + 1 : nz - 1;
+    const int64_t row = r * nx;
+    const int64_t row_yl = int64_t(z) * plane + int64_t(yl) * nx;
+    const int64_t row_yr = int64_t(z) * plane + int64_t(yr) * nx;
+    const int64_t row_zl = int64_t(zl) * plane + int64_t(y) * nx;
+    const int64_t row_zr = int64_t(zr) * plane + int64_t(y) * nx;
+    const RowReader<T> u0(mu + row, nx), s0(vu + row, nx);
+    const RowReader<T> v_l(mv + row_yl, nx), v_r(mv + row_yr, nx);
+    const RowReader<T> t_l(vv + row_yl, nx), t_r(vv + row_yr, nx);
+    const RowReader<T> w_l(mw + row_zl, nx), w_r(mw + row_zr, nx);
+    const RowReader<T> q_l(vw + row_zl, nx), q_r(vw + row_zr, nx);
+    const bool by = (y == 0) | (y == ny - 1);
+    const bool bz = (z == 0) | (z == nz - 1);
+    const DivGauss g = div_gauss3(
+        u0.get(c.xl), u0.get(c.xr), s0.get(c.xl), s0.get(c.xr), v_l.get(c.x), v_r.get(c.x),
+        t_l.get(c.x), t_r.get(c.x), w_l.get(c.x), w_r.get(c.x), q_l.get(c.x), q_r.get(c.x),
+        c.bx ? k.xy.cxm_bd : k.xy.cxm_in, c.bx ? k.xy.cxv_bd : k.xy.cxv_in,
+        by ? k.xy.cym_bd : k.xy.cym_in, by ? k.xy.cyv_bd : k.xy.cyv_in,
+        bz ? k.czm_bd : k.czm_in, bz ? k.czv_bd : k.czv_in);
+    __builtin_nontemporal_store(g.mean, dmean + row + x);
+    __builtin_nontemporal_store(g.var, dvar + row + x);
+  }
+}
+
+// The 8 corners of a pair of 4-corner groups (lo, hi): the products multiply
+// and 1 - prod telescopes as Q_lo + P_lo Q_hi (every term non-negative).
+__device__ __forceinline__ Pair join_pairs(const Pair& lo, const Pair& hi) {
+  Pair p;
+  p.pa = lo.pa * hi.pa;
+  p.qa = fmaf(lo.pa, hi.qa, lo.qa);
+  p.pb = lo.pb * hi.pb;
+  p.qb = fmaf(lo.pb, hi.qb, lo.qb);
+  return p;
+}
+
+// Waves: layer group g (fastest, so the waves of a block share z-levels),
+// then strip, then band.  Every lane stays active through the DPP reads:
+// lanes past the grid clamp their column and store nothing.
+template <int KC, int LZ>
+__global__ __launch_bounds__(kBlock) void lcp3d_kernel(const float* __restrict__ dm,
+                                                       const float* __restrict__ dv, int nz,
+                                                       int ny, int nx, IsoChunk iso,
+                                                       float* __restrict__ out, int64_t plane,
+                                                       int n_groups, int n_strips, int n_bands) {
+  const int wave = __builtin_amdgcn_readfirstlane(blockIdx.x * kWavesPerBlock + (threadIdx.x >> 6));
+  const int lane = threadIdx.x & 63;
+  const int grp = wave % n_groups;
+  const int rest = wave / n_groups;
+  const int strip = rest % n_strips;
+  const int band = rest / n_strips;
+  if (band >= n_bands) return;
+  const int k0 = grp * LZ;
+  const int nl = min(LZ, nz - 1 - k0);
+  const int j0 = band * kBandRows3;
+  const int j1 = min(j0 + kBandRows3, ny - 1);
+  const int x0 = strip * 63;
+  const int x = min(x0 + lane, nx - 1);
+  const bool has_cell = (lane < 63) & (x0 + lane < nx - 1);
+  const int64_t cells_x = nx - 1;
+  const int64_t layer = int64_t(ny - 1) * cells_x;
+  const int64_t vplane = int64_t(ny) * nx;
+  Pair carry[LZ][KC];
+  for (int j = j0; j <= j1; ++j) {
+    Corner c[LZ + 1];
+#pragma unroll
+    for (int l = 0; l <= LZ; ++l) {
+      const int kk = min(k0 + l, nz - 1);
+      const int64_t o = int64_t(kk) * vplane + int64_t(j) * nx + x;
+      DivGauss g;
+      g.mean = dm[o];
+      g.var = dv[o];
+      c[l] = make_corner(g);
+    }
+    const int64_t row_out = int64_t(k0) * layer + int64_t(j - 1) * cells_x + x0 + lane;
+#pragma unroll
+    for (int q = 0; q < KC; ++q) {
+      AB ab[LZ + 1];
+#pragma unroll
+      for (int l = 0; l <= LZ; ++l) ab[l] = corner_probs(c[l], iso.c[q]);
+#pragma unroll
+      for (int l = 0; l < LZ; ++l) {
+        const Pair zp = make_pair(ab[l], ab[l + 1]);
+        if (j > j0) {
+          float v = cell_lcp_dpp(join_pairs(carry[l][q], zp), ab[l].below);
+          // with 8 corners the float32 combination can land an ulp outside
+          // [0, 1] where the probability is 0 or 1; the exact value is inside,
+          // so clamping only removes error (NaN fails both tests and stays)
+          v = v < 0.0f ? 0.0f : v;
+          v = v > 1.0f ? 1.0f : v;
+          if (has_cell & (l < nl)) out[int64_t(q) * plane + row_out + int64_t(l) * layer] = v;
+        }
+        carry[l][q] = zp;
+      }
+    }
+  }
+}
+
+template <int KC, int LZ>
+hipError_t launch_lcp3d_kc(const float* dm, const float* dv, int nz, int ny, int nx,
+                           const IsoChunk& iso, float* out, int64_t plane, hipStream_t s) {
+  const int n_groups = (nz - 1 + LZ - 1) / LZ;
+  const int n_strips = (nx - 1 + 62) / 63;
+  const int n_bands = (ny - 1 + kBandRows3 - 1) / kBandRows3;
+  const int64_t waves = int64_t(n_groups) * n_strips * n_bands;
+  const int64_t blocks = (waves + kWavesPerBlock - 1) / kWavesPerBlock;
+  if (blocks > 0x7fffffff) return hipErrorInvalidConfiguration;
+  hipLaunchKernelGGL((lcp3d_kernel<KC, LZ>), dim3(unsigned(blocks)), dim3(kBlock), 0, s, dm, dv,
+                     nz, ny, nx, iso, out, plane, n_groups, n_strips, n_bands);
+  return hipGetLastError();
+}
+
+}  // namespace
+
+int64_t lcp3d_blocks(int64_t nz, int64_t ny, int64_t nx, int kc) {
+  const int lz = kc <= 4 ? 4 : kc <= 8 ? 2 : 1;
+  const int64_t waves = ((nz - 1 + lz - 1) / lz) * ((nx - 1 + 62) / 63) *
+                        ((ny - 1 + kBandRows3 - 1) / kBandRows3);
+  return (waves + kWavesPerBlock - 1) / kWavesPerBlock;
+}
+
+int64_t divergence3d_blocks(int64_t nz, int64_t ny, int64_t nx) {
+  const int64_t rows = nz * ny;
+  const int64_t groups = (rows + kWavesPerBlock * kRowsPerWave - 1) / (kWavesPerBlock * kRowsPerWave);
+  return ((nx + 63) / 64) * groups;
+}
+
+hipError_t launch_divergence3d(const void* mu, const void* vu, const void* mv, const void* vv,
+                               const void* mw, const void* vw, pdiv_dtype dt, int64_t nz,
+                               int64_t ny, int64_t nx, const StencilCoef3& k, float* dmean,
+                               float* dvar, hipStream_t s) {
+  const int n_xb = int((nx + 63) / 64);
+  const int64_t blocks = divergence3d_blocks(nz, ny, nx);
+  if (blocks > 0x7fffffff) return hipErrorInvalidConfiguration;
+  const dim3 grid{unsigned(blocks)}, block{unsigned(kBlock)};
+  const int z = int(nz), y = int(ny), x = int(nx);
+#define PDIV_DIV3(T)                                                                         \
+  hipLaunchKernelGGL(divergence3d_kernel<T>, grid, block, 0, s, static_cast<const T*>(mu),   \
+                     static_cast<const T*>(vu), static_cast<const T*>(mv),                   \
+                     static_cast<const T*>(vv), static_cast<const T*>(mw),                   \
+                     static_cast<const T*>(vw), z, y, x, k, dmean, dvar, n_xb)
+  switch (dt) {
+    case PDIV_F32: PDIV_DIV3(float); break;
+    case PDIV_F16: PDIV_DIV3(__half); break;
+    case PDIV_BF16: PDIV_DIV3(bf16_t); break;
+    default: return hipErrorInvalidValue;
+  }
+#undef PDIV_DIV3
+  return hipGetLastError();
+}
+
+hipError_t launch_lcp3d(const float* dm, const float* dv, int64_t nz, int64_t ny, int64_t nx,
+                        const IsoChunk& iso, int kc, float* out_k0, int64_t plane,
+                        hipStream_t s) {
+  const int z = int(nz), y = int(ny), x = int(nx);
+  switch (kc) {
+    case 1: return launch_lcp3d_kc<1, 4>(dm, dv, z, y, x, iso, out_k0, plane, s);
+    case 2: return launch_lcp3d_kc<2, 4>(dm, dv, z, y, x, iso, out_k0, plane, s);
+    case 4: return launch_lcp3d_kc<4, 4>(dm, dv, z, y, x, iso, out_k0, plane, s);
+    case 8: return launch_lcp3d_kc<8, 2>(dm, dv, z, y, x, iso, out_k0, plane, s);
+    case 16: return launch_lcp3d_kc<16, 1>(dm, dv, z, y, x, iso, out_k0, plane, s);
+    default: return hipErrorInvalidValue;
+  }
+}
+
+}  // namespace pdiv

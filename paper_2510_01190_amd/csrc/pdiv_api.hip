@@ -96,6 +96,19 @@ pdiv_status check_layout(int64_t row_pitch, int64_t plane_stride, int64_t ny, in
   return PDIV_OK;
 }
 
+pdiv_status check_grid3(int64_t nz, int64_t ny, int64_t nx) {
+  if (nz < 2 || ny < 2 || nx < 2)
+    return invalid("grid must be at least 2x2x2 (got nz=%lld ny=%lld nx=%lld)", (long long)nz,
+                   (long long)ny, (long long)nx);
+  if (nx > kMaxNx || ny > kMaxNy || nz > kMaxNy)
+    return invalid("grid too large (nz, ny > 2^21 or nx > 2^29)");
+  if (double(nz) * double(ny) * double(nx) > double(int64_t(1) << 40) ||
+      divergence3d_blocks(nz, ny, nx) > 0x7fffffff || lcp3d_blocks(nz, ny, nx, 1) > (1 << 29))
+    return invalid("grid of %lld x %lld x %lld points is too large for one launch",
+                   (long long)nz, (long long)ny, (long long)nx);
+  return PDIV_OK;
+}
+
 #define PDIV_TRY(expr)                \
   do {                                \
     pdiv_status st_ = (expr);         \
@@ -241,6 +254,54 @@ pdiv_status pdiv_lcp_from_moments(const void* mean_u, const void* var_u, const v
   PDIV_TRY(check_layout(lcp_row_pitch, lcp_plane_stride, ny, nx, n_iso, &lo));
   return lcp_chunks(true, mean_u, var_u, mean_v, var_v, in_dtype, ny, nx, dx, dy,
                     isovalues_host, n_iso, lcp, lo, static_cast<hipStream_t>(stream));
+}
+
+pdiv_status pdiv_divergence_gaussian_3d(const void* mean_u, const void* var_u,
+                                        const void* mean_v, const void* var_v,
+                                        const void* mean_w, const void* var_w,
+                                        pdiv_dtype in_dtype, int64_t nz, int64_t ny, int64_t nx,
+                                        double dx, double dy, double dz, float* div_mean,
+                                        float* div_var, pdiv_stream stream) {
+  g_last_error.clear();
+  PDIV_NONNULL(mean_u);
+  PDIV_NONNULL(var_u);
+  PDIV_NONNULL(mean_v);
+  PDIV_NONNULL(var_v);
+  PDIV_NONNULL(mean_w);
+  PDIV_NONNULL(var_w);
+  PDIV_NONNULL(div_mean);
+  PDIV_NONNULL(div_var);
+  PDIV_TRY(check_dtype(in_dtype, "in_dtype"));
+  PDIV_TRY(check_grid3(nz, ny, nx));
+  PDIV_TRY(check_spacing(dx, dy));
+  if (!(std::isfinite(dz) && dz > 0.0)) return invalid("dz must be finite and > 0 (got %g)", dz);
+  return device_status(launch_divergence3d(mean_u, var_u, mean_v, var_v, mean_w, var_w,
+                                           in_dtype, nz, ny, nx, make_coef3(dx, dy, dz),
+                                           div_mean, div_var, static_cast<hipStream_t>(stream)),
+                       "3D divergence launch");
+}
+
+pdiv_status pdiv_lcp_3d(const float* div_mean, const float* div_var, int64_t nz, int64_t ny,
+                        int64_t nx, const float* isovalues_host, int32_t n_iso, float* lcp,
+                        pdiv_stream stream) {
+  g_last_error.clear();
+  PDIV_NONNULL(div_mean);
+  PDIV_NONNULL(div_var);
+  PDIV_NONNULL(lcp);
+  PDIV_TRY(check_grid3(nz, ny, nx));
+  PDIV_TRY(check_iso(isovalues_host, n_iso));
+  const int64_t plane = (nz - 1) * (ny - 1) * (nx - 1);
+  for (int32_t k0 = 0; k0 < n_iso;) {
+    const int left = n_iso - k0;
+    const int kc = left >= 16 ? 16 : left >= 8 ? 8 : left >= 4 ? 4 : left >= 2 ? 2 : 1;
+    IsoChunk c;
+    for (int q = 0; q < kIsoChunk; ++q) c.c[q] = isovalues_host[k0 + (q < kc ? q : kc - 1)];
+    const hipError_t e = launch_lcp3d(div_mean, div_var, nz, ny, nx, c, kc, lcp + k0 * plane,
+                                      plane, static_cast<hipStream_t>(stream));
+    if (e != hipSuccess) return device_status(e, "3D LCP launch");
+    k0 += kc;
+  }
+  return PDIV_OK;
 }
 
 pdiv_status pdiv_mc_lcp(const void* mean_u, const void* var_u, const void* mean_v,

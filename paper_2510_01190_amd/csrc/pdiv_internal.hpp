@@ -80,4 +80,26 @@ hipError_t launch_mc_sample(const void* mu, const void* vu, const void* mv, cons
                             pdiv_dtype dt, int64_t ny, int64_t nx, int64_t sample,
                             uint64_t seed, float* us, float* vs, hipStream_t s);
 
+// 3D extension: the coefficients of the x and y differences plus z's.
+struct StencilCoef3 {
+  StencilCoef xy;
+  float czm_in, czv_in, czm_bd, czv_bd;
+};
+StencilCoef3 make_coef3(double dx, double dy, double dz);
+
+// Blocks of the 3D launches (the API rejects grids whose launch would not fit).
+int64_t divergence3d_blocks(int64_t nz, int64_t ny, int64_t nx);
+int64_t lcp3d_blocks(int64_t nz, int64_t ny, int64_t nx, int kc);
+
+hipError_t launch_divergence3d(const void* mu, const void* vu, const void* mv, const void* vv,
+                               const void* mw, const void* vw, pdiv_dtype dt, int64_t nz,
+                               int64_t ny, int64_t nx, const StencilCoef3& k, float* dmean,
+                               float* dvar, hipStream_t s);
+
+// 8-corner LCP for isovalues [k0, k0+kc) (kc in {1, 2, 4, 8, 16}) from 3D
+// divergence Gaussians; maps [kc][nz-1][ny-1][nx-1], `plane` floats apart.
+hipError_t launch_lcp3d(const float* dm, const float* dv, int64_t nz, int64_t ny, int64_t nx,
+                        const IsoChunk& iso, int kc, float* out_k0, int64_t plane,
+                        hipStream_t s);
+
 }  // namespace pdiv

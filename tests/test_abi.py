@@ -163,3 +163,26 @@ def test_server_calls_reject_null_handles():
     _expect_invalid(L.pdiv_server_reserve_staging(NUL, 1024, 0, 1), "server is NULL")
     _expect_invalid(L.pdiv_server_destroy(NUL), "server is NULL")
 
+
+
+def test_3d_calls_reject_bad_arguments():
+    L = P.lib()
+    iso, ip = _iso([0.1])
+    six = [FAKE] * 6
+    _expect_invalid(L.pdiv_divergence_gaussian_3d(*six, 0, 1, 8, 8, 1.0, 1.0, 1.0, FAKE, FAKE,
+                                                  NUL), "at least 2x2x2")
+    _expect_invalid(L.pdiv_divergence_gaussian_3d(*six, 0, 4, 8, 8, 1.0, 1.0, 0.0, FAKE, FAKE,
+                                                  NUL), "dz")
+    _expect_invalid(L.pdiv_divergence_gaussian_3d(*six, 0, 4, 8, 8, 1.0, -1.0, 1.0, FAKE, FAKE,
+                                                  NUL), "dx and dy")
+    _expect_invalid(L.pdiv_divergence_gaussian_3d(*six[:5], NUL, 0, 4, 8, 8, 1.0, 1.0, 1.0,
+                                                  FAKE, FAKE, NUL), "var_w")
+    _expect_invalid(L.pdiv_divergence_gaussian_3d(*six, 5, 4, 8, 8, 1.0, 1.0, 1.0, FAKE, FAKE,
+                                                  NUL), "dtype")
+    _expect_invalid(L.pdiv_divergence_gaussian_3d(*six, 0, 1 << 14, 1 << 14, 1 << 14, 1.0, 1.0,
+                                                  1.0, FAKE, FAKE, NUL), "too large")
+    _expect_invalid(L.pdiv_lcp_3d(FAKE, FAKE, 4, 8, 1, ip, 1, FAKE, NUL), "at least 2x2x2")
+    _expect_invalid(L.pdiv_lcp_3d(FAKE, FAKE, 4, 8, 8, ip, 0, FAKE, NUL), "n_iso")
+    _expect_invalid(L.pdiv_lcp_3d(FAKE, FAKE, 4, 8, 8, ip, 257, FAKE, NUL), "n_iso")
+    _expect_invalid(L.pdiv_lcp_3d(FAKE, FAKE, 4, 8, 8, ip, 1, NUL, NUL), "lcp")
+    _expect_invalid(L.pdiv_lcp_3d(FAKE, FAKE, 4, 1 << 22, 8, ip, 1, FAKE, NUL), "too large")

@@ -1,0 +1,134 @@
+"""GPU parity of the 3D extension (the paper's future work, Section 5)
+against the FP64 oracle: the divergence Gaussian with the z term and the
+8-corner level-crossing probability, through the C ABI."""
+
+import numpy as np
+import pytest
+import torch
+
+import oracle as O
+import paper_2510_01190_amd as P
+import synth
+from gpu_util import U32, dev, host64
+
+pytestmark = pytest.mark.gpu
+
+KEYS = ("mean_u", "var_u", "mean_v", "var_v", "mean_w", "var_w")
+LCP_TOL = 1e-5
+
+# (nz, ny, nx): one cell wide; strips of 63 cells exact and ragged; two bands
+# of 64 rows; layer counts that are and are not multiples of the layers a
+# wave carries (4, 2 or 1)
+SHAPES = [(2, 2, 2), (3, 5, 70), (9, 33, 130), (17, 40, 64), (5, 3, 127), (4, 130, 65),
+          (6, 7, 2), (2, 66, 190)]
+
+
+def _field(shape, seed, dt="f32", sigma=(0.05, 0.5)):
+    f = synth.gen_moments_3d(*shape, seed, sigma=sigma)
+    ts = [dev(f[k], dt) for k in KEYS]
+    return f, ts
+
+
+def _axis_means(st, h):
+    """The three axis terms of the oracle's mean, each alone (for the
+    rounding bound of the float32 sum)."""
+    zero = np.zeros_like(st[0])
+    parts = []
+    for a in range(3):
+        args = [zero] * 6
+        args[2 * a], args[2 * a + 1] = st[2 * a], st[2 * a + 1]
+        parts.append(O.divergence_gaussian_3d(*args, *h)[0])
+    return parts
+
+
+@pytest.mark.parametrize("dt", ["f32", "f16", "bf16"])
+@pytest.mark.parametrize("shape", SHAPES)
+def test_divergence_3d_matches_oracle(shape, dt):
+    h = (1.0, 0.5, 2.0)
+    _, ts = _field(shape, seed=sum(shape), dt=dt)
+    dm, dv = P.divergence_gaussian_3d(*ts, *h)
+    st = [host64(t) for t in ts]
+    rm, rv = O.divergence_gaussian_3d(*st, *h)
+    mx, my, mz = _axis_means(st, h)
+    # each axis term: a difference, one coefficient and one product rounded;
+    # then two additions
+    bound_m = 6 * U32 * (np.abs(mx) + np.abs(my) + np.abs(mz)) + 1e-30
+    assert np.all(np.abs(host64(dm) - rm) <= bound_m)
+    np.testing.assert_allclose(host64(dv), rv, rtol=8 * U32, atol=0)
+
+
+@pytest.mark.parametrize("k", [1, 3, 4, 8, 16, 17])
+@pytest.mark.parametrize("shape", SHAPES)
+def test_lcp_3d_matches_oracle(shape, k):
+    _, ts = _field(shape, seed=7 * sum(shape) + k)
+    dm, dv = P.divergence_gaussian_3d(*ts)
+    m64, v64 = host64(dm), host64(dv)
+    iso = np.quantile(m64, np.linspace(0.05, 0.95, k)).astype(np.float32)
+    g = host64(P.lcp_3d(dm, dv, iso))
+    r = O.lcp_3d(m64, v64, iso)
+    err = np.abs(g - r)
+    print(f"\n[{shape} K={k}] max |LCP - oracle| = {err.max():.3e}, range [{g.min():.9g}, "
+          f"{g.max():.9g}]")
+    assert err.max() <= LCP_TOL
+    assert np.all((g >= 0) & (g <= 1))
+
+
+def test_lcp_3d_end_to_end_float32():
+    """From the float64 field through float32 storage and arithmetic."""
+    shape = (9, 33, 130)
+    f, ts = _field(shape, seed=99)
+    iso = np.linspace(-0.6, 0.6, 5).astype(np.float32)
+    g = host64(P.lcp_3d(*P.divergence_gaussian_3d(*ts), iso))
+    r = O.lcp_3d(*O.divergence_gaussian_3d(*[f[k] for k in KEYS], 1.0, 1.0, 1.0), iso)
+    err = float(np.max(np.abs(g - r)))
+    print(f"\n[end to end] max |LCP - oracle(float64 field)| = {err:.3e}")
+    assert err <= LCP_TOL
+
+
+def test_zero_variance_is_marching_cubes():
+    shape = (6, 20, 70)
+    f = synth.gen_moments_3d(*shape, 5)
+    ts = [dev(f[k] if k.startswith("mean") else 0.0 * f[k]) for k in KEYS]
+    dm, dv = P.divergence_gaussian_3d(*ts)
+    assert float(dv.abs().max()) == 0.0
+    m64 = host64(dm)
+    iso = np.quantile(m64, [0.1, 0.5, 0.9]).astype(np.float32)
+    iso[1] = np.float32(m64[3, 10, 35])  # a tie at a vertex: >= counts as above
+    g = host64(P.lcp_3d(dm, dv, iso))
+    for q, c in enumerate(iso):
+        np.testing.assert_array_equal(g[q], O.crossed_3d(m64, float(c)).astype(np.float64))
+
+
+def test_nan_reaches_exactly_its_cells():
+    shape = (5, 9, 70)
+    _, ts = _field(shape, seed=3)
+    dm, dv = P.divergence_gaussian_3d(*ts)
+    dm[2, 4, 66] = float("nan")
+    g = host64(P.lcp_3d(dm, dv, [0.0, 0.3]))
+    bad = np.zeros(g.shape[1:], bool)
+    bad[1:3, 3:5, 65:67] = True
+    assert np.all(np.isnan(g[:, bad]))
+    assert not np.any(np.isnan(g[:, ~bad]))
+
+
+def test_bench_size_sampled_slabs():
+    """The benchmark's 3D workload (512^3, float32, 4 isovalues): every cell
+    in [0, 1] and finite, and slabs of cell layers at the bottom, middle and
+    top of the volume against the oracle."""
+    n = 512
+    f = synth.gen_moments_3d(n, n, n, synth.SEED_BASE + 30, dtype=np.float32)
+    ts = [torch.from_numpy(f[k]).cuda() for k in KEYS]
+    del f
+    dm, dv = P.divergence_gaussian_3d(*ts)
+    iso = np.quantile(host64(dm[::8, ::8, ::8]), [0.2, 0.4, 0.6, 0.8]).astype(np.float32)
+    out = P.lcp_3d(dm, dv, iso)
+    assert not torch.isnan(out).any()
+    assert float(out.min()) >= 0.0 and float(out.max()) <= 1.0
+    worst = 0.0
+    for k0 in (0, n // 2 - 2, n - 3):
+        m = host64(dm[k0:k0 + 3])
+        v = host64(dv[k0:k0 + 3])
+        r = O.lcp_3d(m, v, iso)
+        worst = max(worst, float(np.max(np.abs(host64(out[:, k0:k0 + 2]) - r))))
+    print(f"\n[512^3 K=4] max |LCP - oracle| on sampled slabs = {worst:.3e}")
+    assert worst <= LCP_TOL
