@@ -501,6 +501,8 @@ def main():
     ap.add_argument("--no-cpu-legs", action="store_true",
                     help="only the single-thread oracle in the CPU baseline")
     ap.add_argument("--mc-samples", type=int, default=1000)
+    ap.add_argument("--only-leg", choices=["volume_3d", "batch", "served"],
+                    help="run one leg alone and print its JSON (for profiling)")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="only run a plain 1 GiB device copy (HBM counter calibration)")
     args = ap.parse_args()
@@ -529,6 +531,10 @@ def main():
         print(json.dumps({"copy_bytes_read": 4 * n, "copy_bytes_written": 4 * n, "copies": 3}))
         return
     P.lib()  # fail loudly if the library is missing
+    if args.only_leg:
+        fn = {"volume_3d": volume_leg, "batch": batch_leg, "served": served_leg}[args.only_leg]
+        print(json.dumps(fn(P, synth, torch, np)), flush=True)
+        return
 
     log("generating the 8192x8192 field (seeded)")
     c3 = synth.config_c3()

@@ -39,8 +39,8 @@ namespace {
 
 constexpr int kBlock = 256;
 constexpr int kWavesPerBlock = kBlock / 64;
-constexpr int kRowsPerWave = 8;
-constexpr int kBandRows3 = 64;
+constexpr int kZChunk = 16;
+constexpr int kBandRows3 = 32;
 
 // Eq. 2-3 with the z term at one vertex; the neighbours are already clamped
 // at the boundary and the coefficients chosen (1/(2h) inside, 1/h on a
@@ -64,49 +64,72 @@ __device__ __forceinline__ DivGauss div_gauss3(float mu_xl, float mu_xr, float v
   return g;
 }
 
-// Grid: blocks of 4 waves; block b covers x columns 64 (b % n_xb) .. +63
-// and vertex rows r = z ny + y from kRowsPerWave (4 (b / n_xb) + wave) on.
+// Grid: blocks of 4 waves over (x block of 64 columns, 4 consecutive rows
+// y, a chunk of kZChunk slices z), x block fastest, in XCD-contiguous block
+// order (blocks are dealt round-robin to the 8 XCDs; this gives each XCD a
+// contiguous run, so blocks that share neighbour rows share an L2).  A wave
+// walks z along its row: W's values at z-1, z, z+1 stay in a three-deep
+// register window, so each is loaded once per chunk instead of once per use;
+// V's rows y-1, y+1 are those of the block's other waves (found in cache).
+// Every vertex sees the same inputs and operations as a straight evaluation
+// of Eq. 2-3 with clamped neighbours.
 template <typename T>
 __global__ __launch_bounds__(kBlock) void divergence3d_kernel(
     const T* __restrict__ mu, const T* __restrict__ vu, const T* __restrict__ mv,
     const T* __restrict__ vv, const T* __restrict__ mw, const T* __restrict__ vw, int nz, int ny,
-    int nx, StencilCoef3 k, float* __restrict__ dmean, float* __restrict__ dvar, int n_xb) {
-  const int xb = blockIdx.x % n_xb;
-  const int rg = blockIdx.x / n_xb;
+    int nx, StencilCoef3 k, float* __restrict__ dmean, float* __restrict__ dvar, int n_xb,
+    int n_yq) {
+  const int nb = gridDim.x, xcd = blockIdx.x % 8, q8 = nb / 8, r8 = nb % 8;
+  const int blk = xcd * q8 + min(xcd, r8) + blockIdx.x / 8;
+  const int xb = blk % n_xb;
+  const int rest = blk / n_xb;
+  const int y = (rest % n_yq) * kWavesPerBlock + __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+  const int z0 = (rest / n_yq) * kZChunk;
   const int x = xb * 64 + (threadIdx.x & 63);
-  if (x >= nx) return;
-  const int64_t rows = int64_t(nz) * ny;
-  const int64_t r0 =
-      (int64_t(rg) * kWavesPerBlock + __builtin_amdgcn_readfirstlane(threadIdx.x >> 6)) *
-      kRowsPerWave;
-  const int64_t r1 = r0 + kRowsPerWave < rows ? r0 + kRowsPerWave : rows;
+  if (y >= ny || x >= nx) return;
+  const int z1 = min(z0 + kZChunk, nz);
   const Col c = make_col(uint32_t(x), nx, sizeof(T));
+  const int yl = y > 0 ? y - 1 : 0, yr = y < ny - 1 ? y + 1 : ny - 1;
+  const bool by = (y == 0) | (y == ny - 1);
+  const float cym = by ? k.xy.cym_bd : k.xy.cym_in, cyv = by ? k.xy.cyv_bd : k.xy.cyv_in;
+  const float cxm = c.bx ? k.xy.cxm_bd : k.xy.cxm_in, cxv = c.bx ? k.xy.cxv_bd : k.xy.cxv_in;
   const int64_t plane = int64_t(ny) * nx;
-  for (int64_t r = r0; r < r1; ++r) {
-    const int z = int(r / ny);
-    const int y = int(r - int64_t(z) * ny);
-    const int yl = y > 0 ? y - 1 : 0, yr = y < ny - 1 ? y + 1 : ny - 1;
-    const int zl = z > 0 ? z - 1 : 0, zr = z < nz - 1 ? z + 1 : nz - 1;
-    const int64_t row = r * nx;
+  const int64_t off_y = int64_t(y) * nx;
+  auto w_at = [&](int z, float& m, float& v) {
+    const int64_t row = int64_t(z) * plane + off_y;
+    m = RowReader<T>(mw + row, nx).get(c.x);
+    v = RowReader<T>(vw + row, nx).get(c.x);
+  };
+  float wm_prev, wv_prev, wm_cur, wv_cur, wm_next, wv_next;
+  w_at(z0, wm_cur, wv_cur);
+  if (z0 > 0) {
+    w_at(z0 - 1, wm_prev, wv_prev);
+  } else {
+    wm_prev = wm_cur;
+    wv_prev = wv_cur;
+  }
+  for (int z = z0; z < z1; ++z) {
+    w_at(z < nz - 1 ? z + 1 : nz - 1, wm_next, wv_next);
+    const int64_t row = int64_t(z) * plane + off_y;
     const int64_t row_yl = int64_t(z) * plane + int64_t(yl) * nx;
     const int64_t row_yr = int64_t(z) * plane + int64_t(yr) * nx;
-    const int64_t row_zl = int64_t(zl) * plane + int64_t(y) * nx;
-    const int64_t row_zr = int64_t(zr) * plane + int64_t(y) * nx;
     const RowReader<T> u0(mu + row, nx), s0(vu + row, nx);
     const RowReader<T> v_l(mv + row_yl, nx), v_r(mv + row_yr, nx);
     const RowReader<T> t_l(vv + row_yl, nx), t_r(vv + row_yr, nx);
-    const RowReader<T> w_l(mw + row_zl, nx), w_r(mw + row_zr, nx);
-    const RowReader<T> q_l(vw + row_zl, nx), q_r(vw + row_zr, nx);
-    const bool by = (y == 0) | (y == ny - 1);
     const bool bz = (z == 0) | (z == nz - 1);
-    const DivGauss g = div_gauss3(
-        u0.get(c.xl), u0.get(c.xr), s0.get(c.xl), s0.get(c.xr), v_l.get(c.x), v_r.get(c.x),
-        t_l.get(c.x), t_r.get(c.x), w_l.get(c.x), w_r.get(c.x), q_l.get(c.x), q_r.get(c.x),
-        c.bx ? k.xy.cxm_bd : k.xy.cxm_in, c.bx ? k.xy.cxv_bd : k.xy.cxv_in,
-        by ? k.xy.cym_bd : k.xy.cym_in, by ? k.xy.cyv_bd : k.xy.cyv_in,
-        bz ? k.czm_bd : k.czm_in, bz ? k.czv_bd : k.czv_in);
+    // clamped z neighbours: (0, 1) at z = 0, (nz-2, nz-1) at z = nz-1
+    const float mzl = z > 0 ? wm_prev : wm_cur, vzl = z > 0 ? wv_prev : wv_cur;
+    const float mzr = z < nz - 1 ? wm_next : wm_cur, vzr = z < nz - 1 ? wv_next : wv_cur;
+    const DivGauss g = div_gauss3(u0.get(c.xl), u0.get(c.xr), s0.get(c.xl), s0.get(c.xr),
+                                  v_l.get(c.x), v_r.get(c.x), t_l.get(c.x), t_r.get(c.x), mzl,
+                                  mzr, vzl, vzr, cxm, cxv, cym, cyv,
+                                  bz ? k.czm_bd : k.czm_in, bz ? k.czv_bd : k.czv_in);
     __builtin_nontemporal_store(g.mean, dmean + row + x);
     __builtin_nontemporal_store(g.var, dvar + row + x);
+    wm_prev = wm_cur;
+    wv_prev = wv_cur;
+    wm_cur = wm_next;
+    wv_cur = wv_next;
   }
 }
 
@@ -121,45 +144,66 @@ __device__ __forceinline__ Pair join_pairs(const Pair& lo, const Pair& hi) {
   return p;
 }
 
-// Waves: layer group g (fastest, so the waves of a block share z-levels),
-// then strip, then band.  Every lane stays active through the DPP reads:
-// lanes past the grid clamp their column and store nothing.
+// Waves: strip (fastest), then layer group, then band, over an XCD-aware
+// block order: blocks are dealt round-robin to the 8 XCDs, each with its own
+// L2, so each XCD is given a contiguous run of blocks and the strips that
+// share an output row's cache lines write them through the same L2
+// (measured at 512^3: 1.03 ms against 1.19 ms with layer groups fastest at
+// 4 isovalues).  Every lane stays active through the DPP reads:
+// lanes past the grid clamp their column.  Loads and stores go through
+// buffer resources with a scalar row base and a per-lane byte offset; a
+// store row is sized to the strip's cells, so the buffer hardware drops the
+// stores of lane 63 and of lanes past the grid (no branch around them).
+// Each row's inputs are loaded one row ahead, so their latency overlaps the
+// previous row's arithmetic.
 template <int KC, int LZ>
 __global__ __launch_bounds__(kBlock) void lcp3d_kernel(const float* __restrict__ dm,
                                                        const float* __restrict__ dv, int nz,
                                                        int ny, int nx, IsoChunk iso,
                                                        float* __restrict__ out, int64_t plane,
                                                        int n_groups, int n_strips, int n_bands) {
-  const int wave = __builtin_amdgcn_readfirstlane(blockIdx.x * kWavesPerBlock + (threadIdx.x >> 6));
+  const int nb = gridDim.x, xcd = blockIdx.x % 8, q8 = nb / 8, r8 = nb % 8;
+  const int blk = xcd * q8 + min(xcd, r8) + blockIdx.x / 8;
+  const int wave = __builtin_amdgcn_readfirstlane(blk * kWavesPerBlock + (threadIdx.x >> 6));
   const int lane = threadIdx.x & 63;
-  const int grp = wave % n_groups;
-  const int rest = wave / n_groups;
-  const int strip = rest % n_strips;
-  const int band = rest / n_strips;
+  const int strip = wave % n_strips;
+  const int rest = wave / n_strips;
+  const int grp = rest % n_groups;
+  const int band = rest / n_groups;
   if (band >= n_bands) return;
   const int k0 = grp * LZ;
   const int nl = min(LZ, nz - 1 - k0);
   const int j0 = band * kBandRows3;
   const int j1 = min(j0 + kBandRows3, ny - 1);
   const int x0 = strip * 63;
-  const int x = min(x0 + lane, nx - 1);
-  const bool has_cell = (lane < 63) & (x0 + lane < nx - 1);
+  const uint32_t xoff = uint32_t(min(x0 + lane, nx - 1)) * 4u;
+  const uint32_t store_bytes = uint32_t(min(63, nx - 1 - x0)) * 4u;
+  const uint32_t soff = uint32_t(lane) * 4u;
   const int64_t cells_x = nx - 1;
   const int64_t layer = int64_t(ny - 1) * cells_x;
   const int64_t vplane = int64_t(ny) * nx;
+  float pm[LZ + 1], pv[LZ + 1];
+  auto load_row = [&](int j) {
+#pragma unroll
+    for (int l = 0; l <= LZ; ++l) {
+      const int64_t row = int64_t(min(k0 + l, nz - 1)) * vplane + int64_t(j) * nx;
+      pm[l] = RowReader<float>(dm + row, nx).get(xoff);
+      pv[l] = RowReader<float>(dv + row, nx).get(xoff);
+    }
+  };
+  load_row(j0);
   Pair carry[LZ][KC];
   for (int j = j0; j <= j1; ++j) {
     Corner c[LZ + 1];
 #pragma unroll
     for (int l = 0; l <= LZ; ++l) {
-      const int kk = min(k0 + l, nz - 1);
-      const int64_t o = int64_t(kk) * vplane + int64_t(j) * nx + x;
       DivGauss g;
-      g.mean = dm[o];
-      g.var = dv[o];
+      g.mean = pm[l];
+      g.var = pv[l];
       c[l] = make_corner(g);
     }
-    const int64_t row_out = int64_t(k0) * layer + int64_t(j - 1) * cells_x + x0 + lane;
+    if (j < j1) load_row(j + 1);
+    float* const row_out = out + int64_t(k0) * layer + int64_t(j - 1) * cells_x + x0;
 #pragma unroll
     for (int q = 0; q < KC; ++q) {
       AB ab[LZ + 1];
@@ -175,7 +219,9 @@ __global__ __launch_bounds__(kBlock) void lcp3d_kernel(const float* __restrict__
           // so clamping only removes error (NaN fails both tests and stays)
           v = v < 0.0f ? 0.0f : v;
           v = v > 1.0f ? 1.0f : v;
-          if (has_cell & (l < nl)) out[int64_t(q) * plane + row_out + int64_t(l) * layer] = v;
+          if (l < nl)
+            RowWriter<false>(row_out + int64_t(q) * plane + int64_t(l) * layer, store_bytes)
+                .put(v, soff);
         }
         carry[l][q] = zp;
       }
@@ -200,16 +246,15 @@ hipError_t launch_lcp3d_kc(const float* dm, const float* dv, int nz, int ny, int
 }  // namespace
 
 int64_t lcp3d_blocks(int64_t nz, int64_t ny, int64_t nx, int kc) {
-  const int lz = kc <= 4 ? 4 : kc <= 8 ? 2 : 1;
+  const int lz = kc <= 4 ? 4 : 2;
   const int64_t waves = ((nz - 1 + lz - 1) / lz) * ((nx - 1 + 62) / 63) *
                         ((ny - 1 + kBandRows3 - 1) / kBandRows3);
   return (waves + kWavesPerBlock - 1) / kWavesPerBlock;
 }
 
 int64_t divergence3d_blocks(int64_t nz, int64_t ny, int64_t nx) {
-  const int64_t rows = nz * ny;
-  const int64_t groups = (rows + kWavesPerBlock * kRowsPerWave - 1) / (kWavesPerBlock * kRowsPerWave);
-  return ((nx + 63) / 64) * groups;
+  return ((nx + 63) / 64) * ((ny + kWavesPerBlock - 1) / kWavesPerBlock) *
+         ((nz + kZChunk - 1) / kZChunk);
 }
 
 hipError_t launch_divergence3d(const void* mu, const void* vu, const void* mv, const void* vv,
@@ -217,6 +262,7 @@ hipError_t launch_divergence3d(const void* mu, const void* vu, const void* mv, c
                                int64_t ny, int64_t nx, const StencilCoef3& k, float* dmean,
                                float* dvar, hipStream_t s) {
   const int n_xb = int((nx + 63) / 64);
+  const int n_yq = int((ny + kWavesPerBlock - 1) / kWavesPerBlock);
   const int64_t blocks = divergence3d_blocks(nz, ny, nx);
   if (blocks > 0x7fffffff) return hipErrorInvalidConfiguration;
   const dim3 grid{unsigned(blocks)}, block{unsigned(kBlock)};
@@ -225,7 +271,7 @@ hipError_t launch_divergence3d(const void* mu, const void* vu, const void* mv, c
   hipLaunchKernelGGL(divergence3d_kernel<T>, grid, block, 0, s, static_cast<const T*>(mu),   \
                      static_cast<const T*>(vu), static_cast<const T*>(mv),                   \
                      static_cast<const T*>(vv), static_cast<const T*>(mw),                   \
-                     static_cast<const T*>(vw), z, y, x, k, dmean, dvar, n_xb)
+                     static_cast<const T*>(vw), z, y, x, k, dmean, dvar, n_xb, n_yq)
   switch (dt) {
     case PDIV_F32: PDIV_DIV3(float); break;
     case PDIV_F16: PDIV_DIV3(__half); break;
@@ -245,7 +291,7 @@ hipError_t launch_lcp3d(const float* dm, const float* dv, int64_t nz, int64_t ny
     case 2: return launch_lcp3d_kc<2, 4>(dm, dv, z, y, x, iso, out_k0, plane, s);
     case 4: return launch_lcp3d_kc<4, 4>(dm, dv, z, y, x, iso, out_k0, plane, s);
     case 8: return launch_lcp3d_kc<8, 2>(dm, dv, z, y, x, iso, out_k0, plane, s);
-    case 16: return launch_lcp3d_kc<16, 1>(dm, dv, z, y, x, iso, out_k0, plane, s);
+    case 16: return launch_lcp3d_kc<16, 2>(dm, dv, z, y, x, iso, out_k0, plane, s);
     default: return hipErrorInvalidValue;
   }
 }

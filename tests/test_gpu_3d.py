@@ -18,7 +18,7 @@ LCP_TOL = 1e-5
 
 # (nz, ny, nx): one cell wide; strips of 63 cells exact and ragged; two bands
 # of 64 rows; layer counts that are and are not multiples of the layers a
-# wave carries (4, 2 or 1)
+# wave carries (4 or 2)
 SHAPES = [(2, 2, 2), (3, 5, 70), (9, 33, 130), (17, 40, 64), (5, 3, 127), (4, 130, 65),
           (6, 7, 2), (2, 66, 190)]
 
