@@ -14,6 +14,8 @@ extension (pdiv_oracle3d) follows the paper's stated future work.
 from .pdiv_oracle import (  # noqa: F401
     moments,
     fd_divergence,
+    speed_gradient,
+    speed_gradient_moments,
     divergence_gaussian,
     vertex_probs,
     lcp,

@@ -12,6 +12,10 @@ field F = (U, V); U_{i+-1} means U at (i+-1, j) and V_{j+-1} means V at
 Parity status per function:
   moments            pinned (numpy mean/var, closed forms, invariants)
   fd_divergence      pinned (numpy.gradient, linear fields)
+  speed_gradient     pinned (numpy.hypot + numpy.gradient, linear speed,
+                     rotation and reflection invariance)
+  speed_gradient_moments  pinned through speed_gradient and moments, plus
+                     identical members (zero variance)
   divergence_gaussian pinned (Fig. 2 worked example, numpy.gradient, closed forms,
                       brute-force sampling)
   lcp                pinned (marching-squares limit, i.i.d. closed form, symmetry,
@@ -114,6 +118,36 @@ def divergence_gaussian(mean_u, var_u, mean_v, var_v, dx: float, dy: float):
         mean[j, :] += mu_v[hi, :] / h - mu_v[lo, :] / h
         var[j, :] += (s_v[hi, :] / h) ** 2 + (s_v[lo, :] / h) ** 2
     return mean, var
+
+
+# ---------------------------------------------------------------------------
+# (b') The Red Sea pre-stage (Section 4): for each ensemble member, the
+#      pixelwise gradient of the velocity magnitude; the gradient vectors are
+#      the field whose divergence uncertainty is analysed (sources of the
+#      gradient of speed mark vortex cores).  The paper does not give the
+#      difference scheme; the reading is Eq. 1's (central inside, first-order
+#      one-sided at the boundary), and the Gaussian fit is moments() applied
+#      to the members' gradient vectors.
+# ---------------------------------------------------------------------------
+
+def speed_gradient(u, v, dx: float, dy: float):
+    """Gradient (gx, gy) of the speed sqrt(u^2 + v^2) of one member, [ny][nx]
+    float64 each, by Eq. 1's differences."""
+    u = np.asarray(u, np.float64)
+    v = np.asarray(v, np.float64)
+    s = np.sqrt(u * u + v * v)
+    return _ddx(s, dx), _ddx(s.T, dy).T
+
+
+def speed_gradient_moments(u_members, v_members, dx: float, dy: float, ddof: int = 1):
+    """Per-point Gaussian fit of the members' speed-gradient vectors:
+    (mean_gx, var_gx, mean_gy, var_gy), [ny][nx] float64 each."""
+    gx, gy = [], []
+    for u, v in zip(u_members, v_members):
+        a, b = speed_gradient(u, v, dx, dy)
+        gx.append(a)
+        gy.append(b)
+    return moments(np.stack(gx), np.stack(gy), ddof)
 
 
 # ---------------------------------------------------------------------------
