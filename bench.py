@@ -679,6 +679,28 @@ def main():
         legs["moments_721x1440_m50_f32"] = {"ms": round(t * 1e3, 4),
                                             "achieved_GBs": round(b / t / 1e9, 1),
                                             "frac_hbm": round(b / t / 1e9 / HBM_PEAK_GBS, 4)}
+        # the Red Sea pre-stage (Sec. 4) on the same ensemble: each member's
+        # gradient of speed, fitted per point, then the fused LCP on it
+        gout = [torch.empty((721, 1440), device="cuda") for _ in range(4)]
+
+        def sgfit():
+            P.lib().pdiv_speed_gradient_moments(
+                P._p(u.data_ptr()), P._p(v.data_ptr()), 0, 50, 721, 1440, 0, 1.0, 1.0, 1,
+                *[P._p(o.data_ptr()) for o in gout], 0, P._stream())
+
+        sgfit()
+        t = time_launches(sgfit, 10, torch)
+        b = 2 * 50 * 721 * 1440 * 4 + 4 * 4 * 721 * 1440
+        gdm, _ = P.divergence_gaussian(*gout)
+        iso_g = np.quantile(gdm[::4, ::4].double().cpu().numpy(), [0.5, 0.9]).astype(np.float32)
+        del gdm
+        gl = torch.empty((2, 720, 1439), device="cuda")
+        t2 = time_launches(lambda: (sgfit(), P.lcp_from_moments(*gout, iso_g, out=gl)), 10, torch)
+        legs["speed_gradient_fit_721x1440_m50_f32"] = {
+            "ms": round(t * 1e3, 4), "achieved_GBs": round(b / t / 1e9, 1),
+            "frac_hbm": round(b / t / 1e9 / HBM_PEAK_GBS, 4),
+            "pipeline_with_lcp_k2_ms": round(t2 * 1e3, 4)}
+        del gout, gl
         c2out = torch.empty((8, 720, 1439), device="cuda")
         t = time_launches(lambda: (fit(), P.lcp_from_moments(*outs, c2["isovalues"], out=c2out)),
                           10, torch)

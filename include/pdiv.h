@@ -80,6 +80,23 @@ pdiv_status pdiv_moments(const void* u_members, const void* v_members, pdiv_dtyp
                          int32_t ddof, void* mean_u, void* var_u, void* mean_v, void* var_v,
                          pdiv_dtype out_dtype, pdiv_stream stream);
 
+/* The Red Sea pre-stage (Section 4): for every member, the pixelwise gradient
+ * of the velocity magnitude, gx = d|F|/dx and gy = d|F|/dy with |F| =
+ * sqrt(u^2 + v^2), differenced like Eq. 1 (central inside, first-order
+ * one-sided at the boundary; the paper does not state the scheme), then
+ * fitted per point over the members like pdiv_moments: mean and variance of
+ * gx and gy.  The gradient vectors are the field whose divergence
+ * uncertainty the path analyses next (pass the four outputs to
+ * pdiv_lcp_from_moments as mean_u, var_u, mean_v, var_v).  Fused: the
+ * members' speeds and gradients never reach memory.  Arguments as in
+ * pdiv_moments, plus the grid spacing dx, dy (finite, > 0); ny, nx >= 2. */
+pdiv_status pdiv_speed_gradient_moments(const void* u_members, const void* v_members,
+                                        pdiv_dtype in_dtype, int64_t n_members, int64_t ny,
+                                        int64_t nx, int64_t member_stride, double dx, double dy,
+                                        int32_t ddof, void* mean_gx, void* var_gx,
+                                        void* mean_gy, void* var_gy, pdiv_dtype out_dtype,
+                                        pdiv_stream stream);
+
 /* (b) Divergence Gaussian at every vertex: Eq. 2 (mean) and Eq. 3 (variance)
  * of Section 3.1, from the finite-difference divergence of Eq. 1.  Interior
  * vertices use the central difference; at i = 0, i = nx-1, j = 0, j = ny-1 the

@@ -69,6 +69,8 @@ _SIGS = {
     "pdiv_moments": [_p, _p, _c.c_int, _i64, _i64, _i64, _i64, _i32, _p, _p, _p, _p, _c.c_int, _p],
     "pdiv_divergence_gaussian": [_p, _p, _p, _p, _c.c_int, _i64, _i64, _f64, _f64, _p, _p, _p],
     "pdiv_lcp": [_p, _p, _i64, _i64, _fp, _i32, _p, _i64, _i64, _p],
+    "pdiv_speed_gradient_moments": [_p, _p, _c.c_int, _i64, _i64, _i64, _i64, _f64, _f64, _i32,
+                                    _p, _p, _p, _p, _c.c_int, _p],
     "pdiv_divergence_gaussian_3d": [_p, _p, _p, _p, _p, _p, _c.c_int, _i64, _i64, _i64, _f64,
                                     _f64, _f64, _p, _p, _p],
     "pdiv_lcp_3d": [_p, _p, _i64, _i64, _i64, _fp, _i32, _p, _p],
@@ -221,6 +223,23 @@ def moments(u_members, v_members, ddof: int = 1, out_dtype=None):
     pv = _dev(v_members, "v_members", (m, ny, nx), u_members.dtype)
     _check(lib().pdiv_moments(pu, pv, _dtype_code(u_members), m, ny, nx, 0, ddof,
                               *[_p(o.data_ptr()) for o in outs], _dtype_code(outs[0]), _stream()))
+    return tuple(outs)
+
+
+def speed_gradient_moments(u_members, v_members, dx: float = 1.0, dy: float = 1.0,
+                           ddof: int = 1, out_dtype=None):
+    """The Red Sea pre-stage: per member the gradient of the speed, fitted
+    over members -> (mean_gx, var_gx, mean_gy, var_gy) planes [ny][nx], ready
+    for lcp_from_moments."""
+    torch = _torch()
+    m, ny, nx = u_members.shape
+    od = out_dtype or torch.float32
+    outs = [torch.empty((ny, nx), dtype=od, device=u_members.device) for _ in range(4)]
+    pu = _dev(u_members, "u_members", (m, ny, nx))
+    pv = _dev(v_members, "v_members", (m, ny, nx), u_members.dtype)
+    _check(lib().pdiv_speed_gradient_moments(pu, pv, _dtype_code(u_members), m, ny, nx, 0, dx,
+                                             dy, ddof, *[_p(o.data_ptr()) for o in outs],
+                                             _dtype_code(outs[0]), _stream()))
     return tuple(outs)
 
 

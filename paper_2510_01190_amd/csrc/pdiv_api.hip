@@ -199,6 +199,40 @@ pdiv_status pdiv_moments(const void* u_members, const void* v_members, pdiv_dtyp
                        "moments launch");
 }
 
+pdiv_status pdiv_speed_gradient_moments(const void* u_members, const void* v_members,
+                                        pdiv_dtype in_dtype, int64_t n_members, int64_t ny,
+                                        int64_t nx, int64_t member_stride, double dx, double dy,
+                                        int32_t ddof, void* mean_gx, void* var_gx,
+                                        void* mean_gy, void* var_gy, pdiv_dtype out_dtype,
+                                        pdiv_stream stream) {
+  g_last_error.clear();
+  PDIV_NONNULL(u_members);
+  PDIV_NONNULL(v_members);
+  PDIV_NONNULL(mean_gx);
+  PDIV_NONNULL(var_gx);
+  PDIV_NONNULL(mean_gy);
+  PDIV_NONNULL(var_gy);
+  PDIV_TRY(check_dtype(in_dtype, "in_dtype"));
+  PDIV_TRY(check_dtype(out_dtype, "out_dtype"));
+  PDIV_TRY(check_grid(ny, nx));
+  PDIV_TRY(check_spacing(dx, dy));
+  if (ddof != 0 && ddof != 1) return invalid("ddof must be 0 or 1 (got %d)", ddof);
+  if (n_members <= ddof || n_members > (int64_t(1) << 30))
+    return invalid("n_members must be in (ddof, 2^30] (got %lld)", (long long)n_members);
+  const int64_t n = ny * nx;
+  if (member_stride == 0) member_stride = n;
+  if (member_stride < n)
+    return invalid("member_stride %lld < ny*nx %lld", (long long)member_stride, (long long)n);
+  if (speed_gradient_blocks(ny, nx) > (int64_t(1) << 29))
+    return invalid("grid of %lld x %lld points is too large for one launch", (long long)ny,
+                   (long long)nx);
+  return device_status(
+      launch_speed_gradient_moments(u_members, v_members, in_dtype, n_members, ny, nx,
+                                    member_stride, make_coef(dx, dy), ddof, mean_gx, var_gx,
+                                    mean_gy, var_gy, out_dtype, static_cast<hipStream_t>(stream)),
+      "speed-gradient launch");
+}
+
 pdiv_status pdiv_divergence_gaussian(const void* mean_u, const void* var_u, const void* mean_v,
                                      const void* var_v, pdiv_dtype in_dtype, int64_t ny,
                                      int64_t nx, double dx, double dy, float* div_mean,

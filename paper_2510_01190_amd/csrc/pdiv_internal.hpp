@@ -80,6 +80,15 @@ hipError_t launch_mc_sample(const void* mu, const void* vu, const void* mv, cons
                             pdiv_dtype dt, int64_t ny, int64_t nx, int64_t sample,
                             uint64_t seed, float* us, float* vs, hipStream_t s);
 
+// Red Sea pre-stage: per member the gradient of the speed by Eq. 1's
+// differences, fitted per point over the members (Welford, float32).
+int64_t speed_gradient_blocks(int64_t ny, int64_t nx);
+hipError_t launch_speed_gradient_moments(const void* u, const void* v, pdiv_dtype in_dt,
+                                         int64_t m, int64_t ny, int64_t nx, int64_t stride,
+                                         const StencilCoef& k, int ddof, void* mgx, void* vgx,
+                                         void* mgy, void* vgy, pdiv_dtype out_dt,
+                                         hipStream_t s);
+
 // 3D extension: the coefficients of the x and y differences plus z's.
 struct StencilCoef3 {
   StencilCoef xy;

@@ -186,3 +186,22 @@ def test_3d_calls_reject_bad_arguments():
     _expect_invalid(L.pdiv_lcp_3d(FAKE, FAKE, 4, 8, 8, ip, 257, FAKE, NUL), "n_iso")
     _expect_invalid(L.pdiv_lcp_3d(FAKE, FAKE, 4, 8, 8, ip, 1, NUL, NUL), "lcp")
     _expect_invalid(L.pdiv_lcp_3d(FAKE, FAKE, 4, 1 << 22, 8, ip, 1, FAKE, NUL), "too large")
+
+
+def test_speed_gradient_rejects_bad_arguments():
+    L = P.lib()
+    outs = [FAKE] * 4
+    _expect_invalid(L.pdiv_speed_gradient_moments(FAKE, FAKE, 0, 5, 1, 8, 0, 1.0, 1.0, 1, *outs, 0,
+                                                  NUL), "at least 2x2")
+    _expect_invalid(L.pdiv_speed_gradient_moments(FAKE, FAKE, 0, 1, 8, 8, 0, 1.0, 1.0, 1, *outs, 0,
+                                                  NUL), "n_members")
+    _expect_invalid(L.pdiv_speed_gradient_moments(FAKE, FAKE, 0, 5, 8, 8, 0, 1.0, 1.0, 2, *outs, 0,
+                                                  NUL), "ddof")
+    _expect_invalid(L.pdiv_speed_gradient_moments(FAKE, FAKE, 0, 5, 8, 8, 10, 1.0, 1.0, 1, *outs,
+                                                  0, NUL), "member_stride")
+    _expect_invalid(L.pdiv_speed_gradient_moments(FAKE, FAKE, 0, 5, 8, 8, 0, 0.0, 1.0, 1, *outs, 0,
+                                                  NUL), "dx and dy")
+    _expect_invalid(L.pdiv_speed_gradient_moments(FAKE, FAKE, 0, 5, 8, 8, 0, 1.0, 1.0, 1, *outs, 9,
+                                                  NUL), "out_dtype")
+    _expect_invalid(L.pdiv_speed_gradient_moments(NUL, FAKE, 0, 5, 8, 8, 0, 1.0, 1.0, 1, *outs, 0,
+                                                  NUL), "u_members")

@@ -1,0 +1,100 @@
+"""GPU parity of the Red Sea pre-stage (Section 4): the members' gradient of
+speed fitted per point, through the C ABI, against the FP64 oracle on the
+same stored members; then the path on the fitted gradient field.
+
+Tolerance, per output: each member's gradient is rounded in float32 (two
+speeds, a difference, a coefficient) with error at most
+eps = 3 u (s_lo + s_hi) c <= 3 u 2 max|F| max(c); the float32 Welford fit
+adds at most 2 M u max|g| to the mean and a relative 4 M u to the variance,
+and a perturbation eps of every member moves the variance by at most
+2 eps sqrt(var M / (M - ddof)) + 2 eps^2."""
+
+import ctypes
+
+import numpy as np
+import pytest
+import torch
+
+import oracle as O
+import paper_2510_01190_amd as P
+import synth
+from gpu_util import TORCH_DT, U32, host64
+
+pytestmark = pytest.mark.gpu
+
+
+def _check(got, ref, U, V, m, ddof, dx=1.0, dy=1.0):
+    speed = np.sqrt(U ** 2 + V ** 2).max()
+    eps = 3 * U32 * 2 * speed * max(1.0 / dx, 1.0 / dy)
+    grads = [O.speed_gradient(a, b, dx, dy) for a, b in zip(U, V)]
+    for q in (0, 2):
+        g, r, var = got[q], ref[q], ref[q + 1]
+        gmax = max(float(np.abs(t[q // 2]).max()) for t in grads)
+        assert np.max(np.abs(g - r)) <= 2 * m * U32 * gmax + eps, q
+        gv = got[q + 1]
+        tol = (4 * m * U32 * var + 2 * eps * np.sqrt(var * m / (m - ddof)) + 2 * eps ** 2
+               + 1e-30)
+        assert np.all(np.abs(gv - var) <= tol), q
+
+
+@pytest.mark.parametrize("m,shape", [(2, (2, 2)), (3, (5, 70)), (15, (68, 68)), (20, (33, 130)),
+                                     (50, (9, 200)), (4, (130, 3))])
+@pytest.mark.parametrize("ddof", [0, 1])
+def test_matches_oracle(m, shape, ddof):
+    ny, nx = shape
+    e = synth.gen_ensemble(ny, nx, m, seed=m + ny, n_features=2, dtype=np.float32)
+    U = e["u_members"].astype(np.float64)
+    V = e["v_members"].astype(np.float64)
+    u = torch.from_numpy(e["u_members"]).cuda()
+    v = torch.from_numpy(e["v_members"]).cuda()
+    got = [host64(t) for t in P.speed_gradient_moments(u, v, 1.0, 1.0, ddof)]
+    ref = O.speed_gradient_moments(U, V, 1.0, 1.0, ddof)
+    _check(got, ref, U, V, m, ddof)
+
+
+@pytest.mark.parametrize("in_dt", ["f16", "bf16"])
+def test_16bit_members(in_dt):
+    m, ny, nx = 12, 40, 100
+    e = synth.gen_ensemble(ny, nx, m, seed=5, n_features=3, dtype=np.float32)
+    u = torch.from_numpy(e["u_members"]).to(TORCH_DT[in_dt]).cuda()
+    v = torch.from_numpy(e["v_members"]).to(TORCH_DT[in_dt]).cuda()
+    U, V = host64(u), host64(v)
+    got = [host64(t) for t in P.speed_gradient_moments(u, v, 0.5, 2.0, 1)]
+    _check(got, O.speed_gradient_moments(U, V, 0.5, 2.0, 1), U, V, m, 1, 0.5, 2.0)
+
+
+def test_member_stride():
+    m, ny, nx, stride = 5, 7, 66, 500  # stride > ny*nx = 462
+    rng = np.random.default_rng(9)
+    buf_u = rng.normal(0, 1, (m, stride)).astype(np.float32)
+    buf_v = rng.normal(0, 1, (m, stride)).astype(np.float32)
+    U = buf_u[:, :ny * nx].reshape(m, ny, nx).astype(np.float64)
+    V = buf_v[:, :ny * nx].reshape(m, ny, nx).astype(np.float64)
+    ub, vb = torch.from_numpy(buf_u).cuda(), torch.from_numpy(buf_v).cuda()
+    outs = [torch.empty((ny, nx), device="cuda") for _ in range(4)]
+    st = P.lib().pdiv_speed_gradient_moments(
+        ctypes.c_void_p(ub.data_ptr()), ctypes.c_void_p(vb.data_ptr()), 0, m, ny, nx, stride, 1.0,
+        1.0, 1, *[ctypes.c_void_p(o.data_ptr()) for o in outs], 0,
+        ctypes.c_void_p(torch.cuda.current_stream().cuda_stream))
+    assert st == 0
+    _check([host64(o) for o in outs], O.speed_gradient_moments(U, V, 1.0, 1.0, 1), U, V, m, 1)
+
+
+def test_ensemble_full_size_and_the_path_on_it():
+    """The benchmark's ensemble (721 x 1440, 50 members): every point of the
+    fit against the oracle, then the fused LCP on the fitted gradient field
+    against the oracle's LCP of the same stored moments."""
+    e = synth.config_c2()
+    U = e["u_members"].astype(np.float64)
+    V = e["v_members"].astype(np.float64)
+    u = torch.from_numpy(e["u_members"]).cuda()
+    v = torch.from_numpy(e["v_members"]).cuda()
+    mom = P.speed_gradient_moments(u, v)
+    got = [host64(t) for t in mom]
+    _check(got, O.speed_gradient_moments(U, V, 1.0, 1.0, 1), U, V, 50, 1)
+    dm, dv = O.divergence_gaussian(*got, 1.0, 1.0)
+    iso = np.quantile(dm, [0.5, 0.9, 0.99]).astype(np.float32)
+    lcp = host64(P.lcp_from_moments(*mom, iso))
+    err = float(np.max(np.abs(lcp - O.lcp(dm, dv, iso))))
+    print(f"\n[721x1440x50] max |LCP - oracle| on the gradient-of-speed field = {err:.3e}")
+    assert err <= 1e-5
