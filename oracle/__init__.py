@@ -24,6 +24,8 @@ from .pdiv_oracle import (  # noqa: F401
     mc_sample_field,
     mc_lcp,
     mc_lcp_vertex,
+    marching_squares,
+    spaghetti,
 )
 from .pdiv_oracle3d import (  # noqa: F401
     divergence_gaussian_3d,

@@ -22,6 +22,10 @@ Parity status per function:
                       brute-force sampling, mpmath tails)
   philox4x32_10      pinned (published known-answer vectors, rocRAND routine)
   box_muller         pinned (closed form at chosen inputs, normality tests)
+  marching_squares   pinned (planes: every point on the exact line; circles:
+                     closed loops, every point shared by two segments; crossed
+                     cells = the zero-variance LCP indicator; saddles)
+  spaghetti          marching_squares of fd_divergence per member
   mc_lcp             pinned statistically against lcp on interior cells; a single
                      MC draw has no closed form to pin to.
 """
@@ -337,3 +341,79 @@ def mc_lcp_vertex(div_mean, div_var, isovalues, n_samples: int, seed: int):
         for k, c in enumerate(iso):
             counts[k] += _crossed(d, c)
     return counts / float(n_samples)
+
+
+# ---------------------------------------------------------------------------
+# (e) Isocontour geometry (Section 4, Figs. 1 and 3): the mean-field
+#     isocontour of the divergence and the per-member contours of a spaghetti
+#     plot, extracted by marching squares.  The paper draws these without
+#     stating the extraction; the reading is the textbook algorithm:
+#       * a corner is above iff its value >= c (the tie rule of the LCP);
+#       * case index = sum of 1, 2, 4, 8 for the corners (i,j), (i+1,j),
+#         (i+1,j+1), (i,j+1) that are above;
+#       * a crossed edge from corner P (value p) to corner Q (value q) gets
+#         the point P + t (Q - P), t = (c - p) / (q - p);
+#       * the saddle cases (two opposite corners above) are split by the
+#         cell centre value, the mean of the four corners, evaluated in
+#         float32 as ((v0 + v1) + (v2 + v3)) / 4 so that both sides take
+#         that decision in the same precision.
+#     Segments are listed cell by cell in row-major order (j, then i), each
+#     as (x0, y0, x1, y1) in grid units (x = i, y = j).
+# ---------------------------------------------------------------------------
+
+# edges: 0 bottom (i,j)-(i+1,j), 1 right (i+1,j)-(i+1,j+1),
+#        2 top (i,j+1)-(i+1,j+1), 3 left (i,j)-(i,j+1)
+_MS_SEGMENTS = {
+    0: [], 15: [],
+    1: [(3, 0)], 14: [(3, 0)],
+    2: [(0, 1)], 13: [(0, 1)],
+    4: [(1, 2)], 11: [(1, 2)],
+    8: [(2, 3)], 7: [(2, 3)],
+    3: [(3, 1)], 12: [(3, 1)],
+    6: [(0, 2)], 9: [(0, 2)],
+}
+
+
+def _ms_point(edge, i, j, v00, v10, v11, v01, c):
+    if edge == 0:
+        return i + (c - v00) / (v10 - v00), float(j)
+    if edge == 1:
+        return float(i + 1), j + (c - v10) / (v11 - v10)
+    if edge == 2:
+        return i + (c - v01) / (v11 - v01), float(j + 1)
+    return float(i), j + (c - v00) / (v01 - v00)
+
+
+def marching_squares(field, c: float):
+    """Isocontour segments [n][4] float64 of a [ny][nx] field at c."""
+    f = np.asarray(field, np.float64)
+    ny, nx = f.shape
+    segs = []
+    for j in range(ny - 1):
+        for i in range(nx - 1):
+            v00, v10, v11, v01 = f[j, i], f[j, i + 1], f[j + 1, i + 1], f[j + 1, i]
+            case = ((v00 >= c) * 1 + (v10 >= c) * 2 + (v11 >= c) * 4 + (v01 >= c) * 8)
+            if case in (5, 10):
+                f32 = np.float32
+                centre = ((f32(v00) + f32(v10)) + (f32(v11) + f32(v01))) * f32(0.25)
+                centre_above = bool(centre >= f32(c))
+                # centre on the side of corners (i,j) and (i+1,j+1) (case 5)
+                # or (i+1,j) and (i,j+1) (case 10): those corners connect
+                # through the cell and the contour cuts off the other two
+                if (case == 5) == centre_above:
+                    pairs = [(0, 1), (2, 3)]
+                else:
+                    pairs = [(3, 0), (1, 2)]
+            else:
+                pairs = _MS_SEGMENTS[int(case)]
+            for a, b in pairs:
+                x0, y0 = _ms_point(a, i, j, v00, v10, v11, v01, c)
+                x1, y1 = _ms_point(b, i, j, v00, v10, v11, v01, c)
+                segs.append((x0, y0, x1, y1))
+    return np.asarray(segs, np.float64).reshape(-1, 4)
+
+
+def spaghetti(u_members, v_members, dx: float, dy: float, c: float):
+    """Per-member isocontours of the divergence (Eq. 1) at c: list of [n][4]."""
+    return [marching_squares(fd_divergence(u, v, dx, dy), c)
+            for u, v in zip(u_members, v_members)]
