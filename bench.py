@@ -21,6 +21,7 @@ Usage: python bench.py [--steps K] [--warmup W] [--gpus 1]
 """
 
 import argparse
+import ctypes
 import hashlib
 import json
 import os
@@ -650,7 +651,25 @@ def main():
         legs["two_step_divergence_then_lcp_f32"] = {"ms": round(t * 1e3, 4),
                                                    "cells_per_s": round(cells * K / t, 1)}
         assert torch.equal(out, out2), "two-step path differs from the fused path"
-        del out2, dm, dv
+        # the mean-field isocontour (marching squares) of the divergence at
+        # the middle isovalue: count, scan and write, one call
+        c_mid = float(iso[K // 2])
+        offs = torch.empty(ny, dtype=torch.int64, device="cuda")
+        n_seg = int(P.isocontour(dm, c_mid).shape[0])
+        segs = torch.empty((max(n_seg, 1), 4), device="cuda")
+
+        def contour():
+            P.lib().pdiv_isocontour(P._p(dm.data_ptr()), ny, nx, ctypes.c_float(c_mid),
+                                    P._p(offs.data_ptr()), P._p(segs.data_ptr()), n_seg,
+                                    P._stream())
+
+        contour()
+        t = time_launches(contour, 10, torch)
+        b = 2 * 4 * ny * nx + 16 * n_seg + 16 * ny
+        legs["isocontour_8192x8192_mean_field"] = {
+            "ms": round(t * 1e3, 4), "segments": n_seg, "achieved_GBs": round(b / t / 1e9, 1),
+            "note": "count pass, row scan and write pass; bytes = field read twice + segments"}
+        del out2, dm, dv, offs, segs
         for name, dt, bpe in (("f16", torch.float16, 2), ("bf16", torch.bfloat16, 2)):
             m16 = [torch.from_numpy(c3[k]).to(dt).cuda() for k in
                    ("mean_u", "var_u", "mean_v", "var_v")]
@@ -732,6 +751,20 @@ def main():
         legs["mc_error_and_time_vs_samples_721x1440_k8"] = {
             "closed_form_ms": round(t_cf * 1e3, 4), "seed": 2025, "curve": curve}
         del mco, d2
+        # spaghetti plot: every member's divergence contour at the middle
+        # isovalue (a divergence and an isocontour per member; the binding
+        # sizes each output from a count call, so this includes 50 host
+        # synchronisations)
+        c_sp = float(c2["isovalues"][4])
+        P.spaghetti(u[:2], v[:2], c_sp)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        sp = P.spaghetti(u, v, c_sp)
+        torch.cuda.synchronize()
+        t_sp = time.perf_counter() - t0
+        legs["spaghetti_721x1440_m50"] = {"ms": round(t_sp * 1e3, 3),
+                                          "segments": int(sum(int(x.shape[0]) for x in sp))}
+        del sp
         del u, v, outs, c2out
         torch.cuda.empty_cache()
         legs["batch_512_fields_k4"] = batch_leg(P, synth, torch, np)

@@ -166,6 +166,29 @@ pdiv_status pdiv_mc_sample_field(const void* mean_u, const void* var_u, const vo
                                  int64_t sample, uint64_t seed, float* u_s, float* v_s,
                                  pdiv_stream stream);
 
+/* Isocontour geometry (Section 4's figures: the mean-field contour of the
+ * divergence and the per-member contours of a spaghetti plot) by marching
+ * squares; the paper does not state the extraction, the rules here are the
+ * textbook ones: a corner is above iff its value >= isovalue; the case index
+ * sums 1, 2, 4, 8 for the corners (i,j), (i+1,j), (i+1,j+1), (i,j+1) that
+ * are above; a crossed edge from corner value p to q gets the point at
+ * t = (isovalue - p) / (q - p) along it; the two saddle cases are split by
+ * the cell centre ((v00 + v10) + (v11 + v01)) / 4 (the two corners on the
+ * centre's side connect).  Segments (x0, y0, x1, y1) in grid units (x = i,
+ * y = j) are listed cell by cell in row-major order, so the output is
+ * deterministic.
+ * field: [ny][nx] float32 (device).  row_offsets: ny int64 (device,
+ * caller-allocated workspace and result): entry j < ny-1 receives the index
+ * of cell row j's first segment, entry ny-1 the total count.  segments:
+ * [max_segments][4] float32 (device, 16-byte aligned; may be NULL when
+ * max_segments is 0);
+ * segments past max_segments are not written, so a caller can size the
+ * buffer from a first call with max_segments = 0.  A NaN isovalue or field
+ * value never counts as above. */
+pdiv_status pdiv_isocontour(const float* field, int64_t ny, int64_t nx, float isovalue,
+                            int64_t* row_offsets, float* segments, int64_t max_segments,
+                            pdiv_stream stream);
+
 /* ------------------------------------------------------------------------
  * 3D vector fields, the extension the paper names as future work (Section 5).
  * Nothing in the method changes but the dimension: the divergence adds

@@ -71,6 +71,7 @@ _SIGS = {
     "pdiv_lcp": [_p, _p, _i64, _i64, _fp, _i32, _p, _i64, _i64, _p],
     "pdiv_speed_gradient_moments": [_p, _p, _c.c_int, _i64, _i64, _i64, _i64, _f64, _f64, _i32,
                                     _p, _p, _p, _p, _c.c_int, _p],
+    "pdiv_isocontour": [_p, _i64, _i64, _c.c_float, _p, _p, _i64, _p],
     "pdiv_divergence_gaussian_3d": [_p, _p, _p, _p, _p, _p, _c.c_int, _i64, _i64, _i64, _f64,
                                     _f64, _f64, _p, _p, _p],
     "pdiv_lcp_3d": [_p, _p, _i64, _i64, _i64, _fp, _i32, _p, _p],
@@ -266,6 +267,35 @@ def lcp(div_mean, div_var, isovalues, out=None):
         out = torch.empty((iso.size, ny - 1, nx - 1), dtype=torch.float32, device=div_mean.device)
     po, pitch, plane = _lcp_out(out, iso.size, ny, nx)
     _check(lib().pdiv_lcp(pm, pv, ny, nx, ip, iso.size, po, pitch, plane, _stream()))
+    return out
+
+
+def isocontour(field, isovalue):
+    """Marching-squares segments [n][4] (x0, y0, x1, y1) of a [ny][nx]
+    float32 field at isovalue, cell by cell in row-major order."""
+    torch = _torch()
+    ny, nx = field.shape
+    pf = _dev(field, "field", (ny, nx), torch.float32)
+    offs = torch.empty(ny, dtype=torch.int64, device=field.device)
+    c = float(np.float32(isovalue))
+    _check(lib().pdiv_isocontour(pf, ny, nx, c, _p(offs.data_ptr()), None, 0, _stream()))
+    n = int(offs[ny - 1].item())
+    segs = torch.empty((n, 4), dtype=torch.float32, device=field.device)
+    if n:
+        _check(lib().pdiv_isocontour(pf, ny, nx, c, _p(offs.data_ptr()), _p(segs.data_ptr()), n,
+                                     _stream()))
+    return segs
+
+
+def spaghetti(u_members, v_members, isovalue, dx: float = 1.0, dy: float = 1.0):
+    """Per-member isocontours of the divergence (Eq. 1, each member taken as a
+    deterministic field) at isovalue: a list of [n_m][4] segment tensors."""
+    torch = _torch()
+    zero = torch.zeros(u_members.shape[1:], dtype=u_members.dtype, device=u_members.device)
+    out = []
+    for u, v in zip(u_members, v_members):
+        d, _ = divergence_gaussian(u.contiguous(), zero, v.contiguous(), zero, dx, dy)
+        out.append(isocontour(d, isovalue))
     return out
 
 

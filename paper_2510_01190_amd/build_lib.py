@@ -18,7 +18,7 @@ OUT = os.path.join(HERE, "_build")
 LIB = os.path.join(HERE, "libpdiv.so")
 
 SOURCES = ["pdiv_api.hip", "k_moments.hip", "k_lcp.hip", "k_lcp3d.hip", "k_speed_gradient.hip",
-           "k_mc.hip", "pdiv_batch.hip", "pdiv_server.hip"]
+           "k_contour.hip", "k_mc.hip", "pdiv_batch.hip", "pdiv_server.hip"]
 
 ARCH = "gfx950"
 CFLAGS = [f"--offload-arch={ARCH}", "-O3", "-fPIC", "-std=c++17", "-Wall",

@@ -1,0 +1,173 @@
+// Isocontour geometry by marching squares: the mean-field contour of the
+// divergence and the per-member contours of a spaghetti plot (Section 4,
+// the figures' geometry).  Rules: a corner is above iff its value >= c; the
+// case index sums 1, 2, 4, 8 for the corners (i,j), (i+1,j), (i+1,j+1),
+// (i,j+1) that are above; a crossed edge from corner value p to q gets the
+// point at t = (c - p) / (q - p); the two saddle cases are split by the cell
+// centre ((v00 + v10) + (v11 + v01)) / 4.  Segments are listed cell by cell
+// in row-major order, so the output is deterministic:
+//   count  one wave per cell row: segments of the row;
+//   scan   one block: exclusive scan of the row counts, total at the end;
+//   write  one wave per cell row: each lane's segments at the row's offset
+//          plus the count of the lanes before it (ballot + prefix count).
+#include <hip/hip_runtime.h>
+
+#include "pdiv_internal.hpp"
+
+namespace pdiv {
+namespace {
+
+constexpr int kBlock = 256;
+constexpr int kWavesPerBlock = kBlock / 64;
+constexpr int kScanBlock = 1024;
+
+// Edges: 0 bottom (i,j)-(i+1,j), 1 right (i+1,j)-(i+1,j+1), 2 top
+// (i,j+1)-(i+1,j+1), 3 left (i,j)-(i,j+1).  Nibble `case` of kEdgeA / kEdgeB
+// holds the two edges of the case's segment (the saddles 5 and 10 and the
+// empty cases 0 and 15 are decided apart).
+constexpr uint64_t kEdgeA = 0x0303100220013030ull;
+constexpr uint64_t kEdgeB = 0x0011202332021100ull;
+
+struct Cell {
+  int n;       // segments: 0, 1 or 2
+  int a0, b0;  // edges of the first segment
+  int a1, b1;  // edges of the second (saddles)
+};
+
+__device__ __forceinline__ Cell classify(float v00, float v10, float v11, float v01, float c) {
+  const int cs = int(v00 >= c) | (int(v10 >= c) << 1) | (int(v11 >= c) << 2) | (int(v01 >= c) << 3);
+  Cell r;
+  r.a0 = int((kEdgeA >> (4 * cs)) & 15u);
+  r.b0 = int((kEdgeB >> (4 * cs)) & 15u);
+  r.a1 = r.b1 = 0;
+  r.n = (cs == 0 || cs == 15) ? 0 : 1;
+  if (cs == 5 || cs == 10) {
+#pragma clang fp contract(off)
+    const float centre = ((v00 + v10) + (v11 + v01)) * 0.25f;
+    // the corners on the centre's side connect through the cell; the
+    // contour cuts off the other two
+    const bool join_diag = (cs == 5) == (centre >= c);
+    r.n = 2;
+    r.a0 = join_diag ? 0 : 3;
+    r.b0 = join_diag ? 1 : 0;
+    r.a1 = join_diag ? 2 : 1;
+    r.b1 = join_diag ? 3 : 2;
+  }
+  return r;
+}
+
+__device__ __forceinline__ float2 edge_point(int e, int i, int j, float v00, float v10, float v11,
+                                             float v01, float c) {
+  switch (e) {
+    case 0: return make_float2(float(i) + (c - v00) / (v10 - v00), float(j));
+    case 1: return make_float2(float(i + 1), float(j) + (c - v10) / (v11 - v10));
+    case 2: return make_float2(float(i) + (c - v01) / (v11 - v01), float(j + 1));
+    default: return make_float2(float(i), float(j) + (c - v00) / (v01 - v00));
+  }
+}
+
+struct Corners {
+  float v00, v10, v11, v01;
+};
+
+__device__ __forceinline__ Corners corners(const float* __restrict__ f, int nx, int j, int i) {
+  const int64_t o = int64_t(j) * nx + i;
+  Corners k;
+  k.v00 = f[o];
+  k.v10 = f[o + 1];
+  k.v01 = f[o + nx];
+  k.v11 = f[o + nx + 1];
+  return k;
+}
+
+__global__ __launch_bounds__(kBlock) void contour_count_kernel(const float* __restrict__ f, int ny,
+                                                               int nx, float c,
+                                                               int64_t* __restrict__ counts) {
+  const int j = blockIdx.x * kWavesPerBlock + (threadIdx.x >> 6);
+  if (j >= ny - 1) return;
+  const int lane = threadIdx.x & 63;
+  int n = 0;
+  for (int i = lane; i < nx - 1; i += 64) {
+    const Corners k = corners(f, nx, j, i);
+    n += classify(k.v00, k.v10, k.v11, k.v01, c).n;
+  }
+#pragma unroll
+  for (int s = 32; s > 0; s >>= 1) n += __shfl_xor(n, s, 64);
+  if (lane == 0) counts[j] = n;
+}
+
+// Exclusive scan of counts[0 .. n) in place, total to counts[n]; one block.
+__global__ __launch_bounds__(kScanBlock) void contour_scan_kernel(int64_t* __restrict__ counts,
+                                                                  int n) {
+  __shared__ int64_t buf[kScanBlock];
+  int64_t carry = 0;
+  for (int base = 0; base < n; base += kScanBlock) {
+    const int t = threadIdx.x;
+    const int64_t x = base + t < n ? counts[base + t] : 0;
+    buf[t] = x;
+    __syncthreads();
+    for (int d = 1; d < kScanBlock; d <<= 1) {
+      const int64_t y = t >= d ? buf[t - d] : 0;
+      __syncthreads();
+      buf[t] += y;
+      __syncthreads();
+    }
+    if (base + t < n) counts[base + t] = carry + buf[t] - x;
+    carry += buf[kScanBlock - 1];
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) counts[n] = carry;
+}
+
+__global__ __launch_bounds__(kBlock) void contour_write_kernel(
+    const float* __restrict__ f, int ny, int nx, float c, const int64_t* __restrict__ offsets,
+    float4* __restrict__ segs, int64_t max_segs) {
+  const int j = blockIdx.x * kWavesPerBlock + (threadIdx.x >> 6);
+  if (j >= ny - 1) return;
+  const int lane = threadIdx.x & 63;
+  const uint64_t below_me = __lanemask_lt();
+  int64_t k = offsets[j];
+  // every lane walks the same number of chunks, so the ballots see the wave
+  for (int i0 = 0; i0 < nx - 1; i0 += 64) {
+    const int i = i0 + lane;
+    Cell cell;
+    cell.n = 0;
+    Corners v{0.0f, 0.0f, 0.0f, 0.0f};
+    if (i < nx - 1) {
+      v = corners(f, nx, j, i);
+      cell = classify(v.v00, v.v10, v.v11, v.v01, c);
+    }
+    const uint64_t one = __ballot(cell.n >= 1);
+    const uint64_t two = __ballot(cell.n >= 2);
+    const int64_t at = k + __popcll(one & below_me) + __popcll(two & below_me);
+    if (cell.n >= 1 && at < max_segs) {
+      const float2 p = edge_point(cell.a0, i, j, v.v00, v.v10, v.v11, v.v01, c);
+      const float2 q = edge_point(cell.b0, i, j, v.v00, v.v10, v.v11, v.v01, c);
+      segs[at] = make_float4(p.x, p.y, q.x, q.y);
+    }
+    if (cell.n >= 2 && at + 1 < max_segs) {
+      const float2 p = edge_point(cell.a1, i, j, v.v00, v.v10, v.v11, v.v01, c);
+      const float2 q = edge_point(cell.b1, i, j, v.v00, v.v10, v.v11, v.v01, c);
+      segs[at + 1] = make_float4(p.x, p.y, q.x, q.y);
+    }
+    k += __popcll(one) + __popcll(two);
+  }
+}
+
+}  // namespace
+
+hipError_t launch_isocontour(const float* field, int64_t ny, int64_t nx, float c,
+                             int64_t* row_offsets, float* segments, int64_t max_segments,
+                             hipStream_t s) {
+  const int rows = int(ny - 1);
+  const unsigned blocks = unsigned((rows + kWavesPerBlock - 1) / kWavesPerBlock);
+  hipLaunchKernelGGL(contour_count_kernel, dim3(blocks), dim3(kBlock), 0, s, field, int(ny),
+                     int(nx), c, row_offsets);
+  hipLaunchKernelGGL(contour_scan_kernel, dim3(1), dim3(kScanBlock), 0, s, row_offsets, rows);
+  hipLaunchKernelGGL(contour_write_kernel, dim3(blocks), dim3(kBlock), 0, s, field, int(ny),
+                     int(nx), c, row_offsets, reinterpret_cast<float4*>(segments),
+                     max_segments);
+  return hipGetLastError();
+}
+
+}  // namespace pdiv

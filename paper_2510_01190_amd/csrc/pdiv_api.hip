@@ -290,6 +290,23 @@ pdiv_status pdiv_lcp_from_moments(const void* mean_u, const void* var_u, const v
                     isovalues_host, n_iso, lcp, lo, static_cast<hipStream_t>(stream));
 }
 
+pdiv_status pdiv_isocontour(const float* field, int64_t ny, int64_t nx, float isovalue,
+                            int64_t* row_offsets, float* segments, int64_t max_segments,
+                            pdiv_stream stream) {
+  g_last_error.clear();
+  PDIV_NONNULL(field);
+  PDIV_NONNULL(row_offsets);
+  PDIV_TRY(check_grid(ny, nx));
+  if (max_segments < 0) return invalid("max_segments must be >= 0 (got %lld)",
+                                       (long long)max_segments);
+  if (max_segments > 0 && segments == nullptr) return invalid("segments is NULL");
+  if (max_segments > 0 && reinterpret_cast<uintptr_t>(segments) % 16 != 0)
+    return invalid("segments must be 16-byte aligned");
+  return device_status(launch_isocontour(field, ny, nx, isovalue, row_offsets, segments,
+                                         max_segments, static_cast<hipStream_t>(stream)),
+                       "isocontour launch");
+}
+
 pdiv_status pdiv_divergence_gaussian_3d(const void* mean_u, const void* var_u,
                                         const void* mean_v, const void* var_v,
                                         const void* mean_w, const void* var_w,

@@ -89,6 +89,14 @@ hipError_t launch_speed_gradient_moments(const void* u, const void* v, pdiv_dtyp
                                          void* mgy, void* vgy, pdiv_dtype out_dt,
                                          hipStream_t s);
 
+// Marching-squares isocontour of a [ny][nx] float32 field: row_offsets (ny
+// entries) receives each cell row's first segment index and the total at
+// [ny-1]; segments [max_segments][4] (x0, y0, x1, y1), the ones past
+// max_segments not written.
+hipError_t launch_isocontour(const float* field, int64_t ny, int64_t nx, float c,
+                             int64_t* row_offsets, float* segments, int64_t max_segments,
+                             hipStream_t s);
+
 // 3D extension: the coefficients of the x and y differences plus z's.
 struct StencilCoef3 {
   StencilCoef xy;

@@ -205,3 +205,17 @@ def test_speed_gradient_rejects_bad_arguments():
                                                   NUL), "out_dtype")
     _expect_invalid(L.pdiv_speed_gradient_moments(NUL, FAKE, 0, 5, 8, 8, 0, 1.0, 1.0, 1, *outs, 0,
                                                   NUL), "u_members")
+
+
+def test_isocontour_rejects_bad_arguments():
+    L = P.lib()
+    _expect_invalid(L.pdiv_isocontour(FAKE, 1, 8, ctypes.c_float(0.0), FAKE, FAKE, 4, NUL),
+                    "at least 2x2")
+    _expect_invalid(L.pdiv_isocontour(FAKE, 8, 8, ctypes.c_float(0.0), NUL, FAKE, 4, NUL),
+                    "row_offsets")
+    _expect_invalid(L.pdiv_isocontour(FAKE, 8, 8, ctypes.c_float(0.0), FAKE, NUL, 4, NUL),
+                    "segments is NULL")
+    _expect_invalid(L.pdiv_isocontour(FAKE, 8, 8, ctypes.c_float(0.0), FAKE, FAKE, -1, NUL),
+                    "max_segments")
+    _expect_invalid(L.pdiv_isocontour(FAKE, 8, 8, ctypes.c_float(0.0), FAKE,
+                                      ctypes.c_void_p(0x1004), 4, NUL), "aligned")
