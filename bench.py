@@ -251,8 +251,9 @@ def batch_leg(P, synth, torch, np):
 def volume_leg(P, synth, torch, np, n=512):
     """The 3D extension on an n^3 float32 field (six moment volumes): the
     divergence Gaussian with the z term, then the 8-corner LCP at 1, 4 and
-    16 isovalues, each against its algorithmic bytes; the maps of sampled
-    cell layers against the oracle, and the oracle's own rate on one slab."""
+    16 isovalues, and the two fused, each against its algorithmic bytes;
+    the maps of sampled cell layers against the oracle, and the oracle's own
+    rate on one slab."""
     import oracle as O
     log(f"3D leg: generating the {n}^3 field (seeded)")
     keys = ("mean_u", "var_u", "mean_v", "var_v", "mean_w", "var_w")
@@ -268,7 +269,6 @@ def volume_leg(P, synth, torch, np, n=512):
            "divergence_3d": {"ms": round(t * 1e3, 4), "algorithmic_bytes": b,
                              "achieved_GBs": round(b / t / 1e9, 1),
                              "frac_hbm": round(b / t / 1e9 / HBM_PEAK_GBS, 4)}}
-    del ts
     sub = dm[::8, ::8, ::8].double().cpu().numpy()
     for k in (1, 4, 16):
         iso = np.quantile(sub, np.linspace(0.2, 0.8, k) if k > 1 else [0.5]).astype(np.float32)
@@ -293,8 +293,15 @@ def volume_leg(P, synth, torch, np, n=512):
             leg["cpu_oracle_cells_per_s_1core"] = round(r.size / tc, 1)
             out["two_step_k4_ms"] = round(out["divergence_3d"]["ms"] + leg["ms"], 4)
         out[f"lcp_3d_k{k}"] = leg
+        # the two steps fused: the divergence volumes never reach HBM
+        P.lcp_3d_from_moments(*ts, iso, out=o)
+        t = time_launches(lambda: P.lcp_3d_from_moments(*ts, iso, out=o), 10, torch)
+        b = 6 * 4 * pts + 4 * k * cells
+        out[f"fused_3d_k{k}"] = {"ms": round(t * 1e3, 4), "cells_per_s": round(k * cells / t, 1),
+                                 "algorithmic_bytes": b, "achieved_GBs": round(b / t / 1e9, 1),
+                                 "frac_hbm": round(b / t / 1e9 / HBM_PEAK_GBS, 4)}
         del o
-    del dm, dv
+    del dm, dv, ts
     return out
 
 

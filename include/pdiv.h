@@ -226,6 +226,17 @@ pdiv_status pdiv_lcp_3d(const float* div_mean, const float* div_var, int64_t nz,
                         int64_t nx, const float* isovalues_host, int32_t n_iso, float* lcp,
                         pdiv_stream stream);
 
+/* The two 3D steps fused: Eq. 2-3 with the z term and the 8-corner LCP in
+ * one pass over the six moment volumes (the divergence Gaussians never leave
+ * the chip).  Gives bitwise the same maps as pdiv_divergence_gaussian_3d
+ * followed by pdiv_lcp_3d.  Arguments as in those two calls. */
+pdiv_status pdiv_lcp_3d_from_moments(const void* mean_u, const void* var_u, const void* mean_v,
+                                     const void* var_v, const void* mean_w, const void* var_w,
+                                     pdiv_dtype in_dtype, int64_t nz, int64_t ny, int64_t nx,
+                                     double dx, double dy, double dz,
+                                     const float* isovalues_host, int32_t n_iso, float* lcp,
+                                     pdiv_stream stream);
+
 /* ------------------------------------------------------------------------
  * Batched launch: many independent fields of uneven size, each with its own
  * isovalues, in ONE persistent kernel (fused Eq. 2-3 + closed-form LCP).

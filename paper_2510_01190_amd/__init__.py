@@ -75,6 +75,8 @@ _SIGS = {
     "pdiv_divergence_gaussian_3d": [_p, _p, _p, _p, _p, _p, _c.c_int, _i64, _i64, _i64, _f64,
                                     _f64, _f64, _p, _p, _p],
     "pdiv_lcp_3d": [_p, _p, _i64, _i64, _i64, _fp, _i32, _p, _p],
+    "pdiv_lcp_3d_from_moments": [_p, _p, _p, _p, _p, _p, _c.c_int, _i64, _i64, _i64, _f64, _f64,
+                                 _f64, _fp, _i32, _p, _p],
     "pdiv_mc_lcp": [_p, _p, _p, _p, _c.c_int, _i64, _i64, _f64, _f64, _fp, _i32, _i64, _u64, _p, _p],
     "pdiv_lcp_from_moments": [_p, _p, _p, _p, _c.c_int, _i64, _i64, _f64, _f64, _fp, _i32, _p,
                               _i64, _i64, _p],
@@ -314,6 +316,26 @@ def divergence_gaussian_3d(mean_u, var_u, mean_v, var_v, mean_w, var_w, dx: floa
     _check(lib().pdiv_divergence_gaussian_3d(*ptrs, _dtype_code(mean_u), nz, ny, nx, dx, dy, dz,
                                              _p(dm.data_ptr()), _p(dv.data_ptr()), _stream()))
     return dm, dv
+
+
+def lcp_3d_from_moments(mean_u, var_u, mean_v, var_v, mean_w, var_w, isovalues,
+                        dx: float = 1.0, dy: float = 1.0, dz: float = 1.0, out=None):
+    """Fused 3D Eq. 2-3 + 8-corner LCP [K][nz-1][ny-1][nx-1] (dense) from the
+    six [nz][ny][nx] moment volumes."""
+    torch = _torch()
+    nz, ny, nx = mean_u.shape
+    dt = mean_u.dtype
+    ptrs = [_dev(t, n, (nz, ny, nx), dt) for t, n in
+            ((mean_u, "mean_u"), (var_u, "var_u"), (mean_v, "mean_v"), (var_v, "var_v"),
+             (mean_w, "mean_w"), (var_w, "var_w"))]
+    iso, ip = _iso_arr(isovalues)
+    shape = (iso.size, nz - 1, ny - 1, nx - 1)
+    if out is None:
+        out = torch.empty(shape, dtype=torch.float32, device=mean_u.device)
+    po = _dev(out, "out", shape, torch.float32)
+    _check(lib().pdiv_lcp_3d_from_moments(*ptrs, _dtype_code(mean_u), nz, ny, nx, dx, dy, dz, ip,
+                                          iso.size, po, _stream()))
+    return out
 
 
 def lcp_3d(div_mean, div_var, isovalues, out=None):

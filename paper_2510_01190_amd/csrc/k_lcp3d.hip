@@ -156,10 +156,21 @@ __device__ __forceinline__ Pair join_pairs(const Pair& lo, const Pair& hi) {
 // stores of lane 63 and of lanes past the grid (no branch around them).
 // Each row's inputs are loaded one row ahead, so their latency overlaps the
 // previous row's arithmetic.
-template <int KC, int LZ>
-__global__ __launch_bounds__(kBlock) void lcp3d_kernel(const float* __restrict__ dm,
-                                                       const float* __restrict__ dv, int nz,
-                                                       int ny, int nx, IsoChunk iso,
+// The input planes of one launch: the two divergence volumes (dm, dv as
+// float) or, fused, the six moment volumes of type T.
+struct Planes6 {
+  const void* p[6];
+};
+
+// FUSED: each row's corners come from Eq. 2-3 with the z term evaluated on
+// the spot from the six moment volumes (the divergence never reaches HBM):
+// U's x neighbours and V's y neighbours are read directly, W once per row at
+// the levels k0-1 .. k0+LZ+1 and shared by adjacent levels; the operands and
+// their order are those of divergence3d_kernel, so the maps are bitwise the
+// two-step result.
+template <int KC, int LZ, bool FUSED, typename T>
+__global__ __launch_bounds__(kBlock) void lcp3d_kernel(Planes6 src, int nz, int ny, int nx,
+                                                       StencilCoef3 k, IsoChunk iso,
                                                        float* __restrict__ out, int64_t plane,
                                                        int n_groups, int n_strips, int n_bands) {
   const int nb = gridDim.x, xcd = blockIdx.x % 8, q8 = nb / 8, r8 = nb % 8;
@@ -183,12 +194,56 @@ __global__ __launch_bounds__(kBlock) void lcp3d_kernel(const float* __restrict__
   const int64_t layer = int64_t(ny - 1) * cells_x;
   const int64_t vplane = int64_t(ny) * nx;
   float pm[LZ + 1], pv[LZ + 1];
+  const Col col = make_col(uint32_t(min(x0 + lane, nx - 1)), nx, sizeof(T));
+  const float cxm = col.bx ? k.xy.cxm_bd : k.xy.cxm_in;
+  const float cxv = col.bx ? k.xy.cxv_bd : k.xy.cxv_in;
   auto load_row = [&](int j) {
+    if constexpr (FUSED) {
+      const T* const mu = static_cast<const T*>(src.p[0]);
+      const T* const vu = static_cast<const T*>(src.p[1]);
+      const T* const mv = static_cast<const T*>(src.p[2]);
+      const T* const vv = static_cast<const T*>(src.p[3]);
+      const T* const mw = static_cast<const T*>(src.p[4]);
+      const T* const vw = static_cast<const T*>(src.p[5]);
+      const int yl = j > 0 ? j - 1 : 0, yr = j < ny - 1 ? j + 1 : ny - 1;
+      const bool by = (j == 0) | (j == ny - 1);
+      const float cym = by ? k.xy.cym_bd : k.xy.cym_in, cyv = by ? k.xy.cyv_bd : k.xy.cyv_in;
+      // W at levels clamp(k0 - 1 + t), t = 0 .. LZ + 2: level k0 + l has its
+      // clamped z neighbours at t = l and t = l + 2
+      float wm[LZ + 3], wv[LZ + 3];
 #pragma unroll
-    for (int l = 0; l <= LZ; ++l) {
-      const int64_t row = int64_t(min(k0 + l, nz - 1)) * vplane + int64_t(j) * nx;
-      pm[l] = RowReader<float>(dm + row, nx).get(xoff);
-      pv[l] = RowReader<float>(dv + row, nx).get(xoff);
+      for (int t = 0; t < LZ + 3; ++t) {
+        const int lev = min(max(k0 - 1 + t, 0), nz - 1);
+        const int64_t row = int64_t(lev) * vplane + int64_t(j) * nx;
+        wm[t] = RowReader<T>(mw + row, nx).get(col.x);
+        wv[t] = RowReader<T>(vw + row, nx).get(col.x);
+      }
+#pragma unroll
+      for (int l = 0; l <= LZ; ++l) {
+        const int kk = min(k0 + l, nz - 1);
+        const int64_t row = int64_t(kk) * vplane + int64_t(j) * nx;
+        const int64_t row_yl = int64_t(kk) * vplane + int64_t(yl) * nx;
+        const int64_t row_yr = int64_t(kk) * vplane + int64_t(yr) * nx;
+        const RowReader<T> u0(mu + row, nx), s0(vu + row, nx);
+        const RowReader<T> v_l(mv + row_yl, nx), v_r(mv + row_yr, nx);
+        const RowReader<T> t_l(vv + row_yl, nx), t_r(vv + row_yr, nx);
+        const bool bz = (kk == 0) | (kk == nz - 1);
+        const DivGauss g = div_gauss3(
+            u0.get(col.xl), u0.get(col.xr), s0.get(col.xl), s0.get(col.xr), v_l.get(col.x),
+            v_r.get(col.x), t_l.get(col.x), t_r.get(col.x), wm[l], wm[l + 2], wv[l], wv[l + 2],
+            cxm, cxv, cym, cyv, bz ? k.czm_bd : k.czm_in, bz ? k.czv_bd : k.czv_in);
+        pm[l] = g.mean;
+        pv[l] = g.var;
+      }
+    } else {
+      const float* const dm = static_cast<const float*>(src.p[0]);
+      const float* const dv = static_cast<const float*>(src.p[1]);
+#pragma unroll
+      for (int l = 0; l <= LZ; ++l) {
+        const int64_t row = int64_t(min(k0 + l, nz - 1)) * vplane + int64_t(j) * nx;
+        pm[l] = RowReader<float>(dm + row, nx).get(xoff);
+        pv[l] = RowReader<float>(dv + row, nx).get(xoff);
+      }
     }
   };
   load_row(j0);
@@ -229,8 +284,8 @@ __global__ __launch_bounds__(kBlock) void lcp3d_kernel(const float* __restrict__
   }
 }
 
-template <int KC, int LZ>
-hipError_t launch_lcp3d_kc(const float* dm, const float* dv, int nz, int ny, int nx,
+template <int KC, int LZ, bool FUSED, typename T>
+hipError_t launch_lcp3d_kc(const Planes6& src, int nz, int ny, int nx, const StencilCoef3& k,
                            const IsoChunk& iso, float* out, int64_t plane, hipStream_t s) {
   const int n_groups = (nz - 1 + LZ - 1) / LZ;
   const int n_strips = (nx - 1 + 62) / 63;
@@ -238,8 +293,8 @@ hipError_t launch_lcp3d_kc(const float* dm, const float* dv, int nz, int ny, int
   const int64_t waves = int64_t(n_groups) * n_strips * n_bands;
   const int64_t blocks = (waves + kWavesPerBlock - 1) / kWavesPerBlock;
   if (blocks > 0x7fffffff) return hipErrorInvalidConfiguration;
-  hipLaunchKernelGGL((lcp3d_kernel<KC, LZ>), dim3(unsigned(blocks)), dim3(kBlock), 0, s, dm, dv,
-                     nz, ny, nx, iso, out, plane, n_groups, n_strips, n_bands);
+  hipLaunchKernelGGL((lcp3d_kernel<KC, LZ, FUSED, T>), dim3(unsigned(blocks)), dim3(kBlock), 0, s,
+                     src, nz, ny, nx, k, iso, out, plane, n_groups, n_strips, n_bands);
   return hipGetLastError();
 }
 
@@ -282,16 +337,41 @@ hipError_t launch_divergence3d(const void* mu, const void* vu, const void* mv, c
   return hipGetLastError();
 }
 
+namespace {
+
+template <bool FUSED, typename T>
+hipError_t launch_lcp3d_any(const Planes6& src, int64_t nz, int64_t ny, int64_t nx,
+                            const StencilCoef3& k, const IsoChunk& iso, int kc, float* out_k0,
+                            int64_t plane, hipStream_t s) {
+  const int z = int(nz), y = int(ny), x = int(nx);
+  switch (kc) {
+    case 1: return launch_lcp3d_kc<1, 4, FUSED, T>(src, z, y, x, k, iso, out_k0, plane, s);
+    case 2: return launch_lcp3d_kc<2, 4, FUSED, T>(src, z, y, x, k, iso, out_k0, plane, s);
+    case 4: return launch_lcp3d_kc<4, 4, FUSED, T>(src, z, y, x, k, iso, out_k0, plane, s);
+    case 8: return launch_lcp3d_kc<8, 2, FUSED, T>(src, z, y, x, k, iso, out_k0, plane, s);
+    case 16: return launch_lcp3d_kc<16, 2, FUSED, T>(src, z, y, x, k, iso, out_k0, plane, s);
+    default: return hipErrorInvalidValue;
+  }
+}
+
+}  // namespace
+
 hipError_t launch_lcp3d(const float* dm, const float* dv, int64_t nz, int64_t ny, int64_t nx,
                         const IsoChunk& iso, int kc, float* out_k0, int64_t plane,
                         hipStream_t s) {
-  const int z = int(nz), y = int(ny), x = int(nx);
-  switch (kc) {
-    case 1: return launch_lcp3d_kc<1, 4>(dm, dv, z, y, x, iso, out_k0, plane, s);
-    case 2: return launch_lcp3d_kc<2, 4>(dm, dv, z, y, x, iso, out_k0, plane, s);
-    case 4: return launch_lcp3d_kc<4, 4>(dm, dv, z, y, x, iso, out_k0, plane, s);
-    case 8: return launch_lcp3d_kc<8, 2>(dm, dv, z, y, x, iso, out_k0, plane, s);
-    case 16: return launch_lcp3d_kc<16, 2>(dm, dv, z, y, x, iso, out_k0, plane, s);
+  const Planes6 src{{dm, dv, nullptr, nullptr, nullptr, nullptr}};
+  return launch_lcp3d_any<false, float>(src, nz, ny, nx, StencilCoef3{}, iso, kc, out_k0, plane,
+                                        s);
+}
+
+hipError_t launch_lcp3d_fused(const void* const* planes, pdiv_dtype dt, int64_t nz, int64_t ny,
+                              int64_t nx, const StencilCoef3& k, const IsoChunk& iso, int kc,
+                              float* out_k0, int64_t plane, hipStream_t s) {
+  const Planes6 src{{planes[0], planes[1], planes[2], planes[3], planes[4], planes[5]}};
+  switch (dt) {
+    case PDIV_F32: return launch_lcp3d_any<true, float>(src, nz, ny, nx, k, iso, kc, out_k0, plane, s);
+    case PDIV_F16: return launch_lcp3d_any<true, __half>(src, nz, ny, nx, k, iso, kc, out_k0, plane, s);
+    case PDIV_BF16: return launch_lcp3d_any<true, bf16_t>(src, nz, ny, nx, k, iso, kc, out_k0, plane, s);
     default: return hipErrorInvalidValue;
   }
 }

@@ -332,6 +332,31 @@ pdiv_status pdiv_divergence_gaussian_3d(const void* mean_u, const void* var_u,
                        "3D divergence launch");
 }
 
+namespace {
+
+// Isovalue chunks of 16, 8, 4, 2, 1 for the 3D LCP launches; planes is null
+// for the two-step form (dm, dv given), else the six moment volumes.
+pdiv_status lcp3d_chunks(const float* dm, const float* dv, const void* const* planes,
+                         pdiv_dtype dt, int64_t nz, int64_t ny, int64_t nx,
+                         const StencilCoef3& k, const float* iso_host, int32_t n_iso,
+                         float* lcp, hipStream_t s) {
+  const int64_t plane = (nz - 1) * (ny - 1) * (nx - 1);
+  for (int32_t k0 = 0; k0 < n_iso;) {
+    const int left = n_iso - k0;
+    const int kc = left >= 16 ? 16 : left >= 8 ? 8 : left >= 4 ? 4 : left >= 2 ? 2 : 1;
+    IsoChunk c;
+    for (int q = 0; q < kIsoChunk; ++q) c.c[q] = iso_host[k0 + (q < kc ? q : kc - 1)];
+    const hipError_t e =
+        planes ? launch_lcp3d_fused(planes, dt, nz, ny, nx, k, c, kc, lcp + k0 * plane, plane, s)
+               : launch_lcp3d(dm, dv, nz, ny, nx, c, kc, lcp + k0 * plane, plane, s);
+    if (e != hipSuccess) return device_status(e, "3D LCP launch");
+    k0 += kc;
+  }
+  return PDIV_OK;
+}
+
+}  // namespace
+
 pdiv_status pdiv_lcp_3d(const float* div_mean, const float* div_var, int64_t nz, int64_t ny,
                         int64_t nx, const float* isovalues_host, int32_t n_iso, float* lcp,
                         pdiv_stream stream) {
@@ -341,18 +366,32 @@ pdiv_status pdiv_lcp_3d(const float* div_mean, const float* div_var, int64_t nz,
   PDIV_NONNULL(lcp);
   PDIV_TRY(check_grid3(nz, ny, nx));
   PDIV_TRY(check_iso(isovalues_host, n_iso));
-  const int64_t plane = (nz - 1) * (ny - 1) * (nx - 1);
-  for (int32_t k0 = 0; k0 < n_iso;) {
-    const int left = n_iso - k0;
-    const int kc = left >= 16 ? 16 : left >= 8 ? 8 : left >= 4 ? 4 : left >= 2 ? 2 : 1;
-    IsoChunk c;
-    for (int q = 0; q < kIsoChunk; ++q) c.c[q] = isovalues_host[k0 + (q < kc ? q : kc - 1)];
-    const hipError_t e = launch_lcp3d(div_mean, div_var, nz, ny, nx, c, kc, lcp + k0 * plane,
-                                      plane, static_cast<hipStream_t>(stream));
-    if (e != hipSuccess) return device_status(e, "3D LCP launch");
-    k0 += kc;
-  }
-  return PDIV_OK;
+  return lcp3d_chunks(div_mean, div_var, nullptr, PDIV_F32, nz, ny, nx, StencilCoef3{},
+                      isovalues_host, n_iso, lcp, static_cast<hipStream_t>(stream));
+}
+
+pdiv_status pdiv_lcp_3d_from_moments(const void* mean_u, const void* var_u, const void* mean_v,
+                                     const void* var_v, const void* mean_w, const void* var_w,
+                                     pdiv_dtype in_dtype, int64_t nz, int64_t ny, int64_t nx,
+                                     double dx, double dy, double dz,
+                                     const float* isovalues_host, int32_t n_iso, float* lcp,
+                                     pdiv_stream stream) {
+  g_last_error.clear();
+  PDIV_NONNULL(mean_u);
+  PDIV_NONNULL(var_u);
+  PDIV_NONNULL(mean_v);
+  PDIV_NONNULL(var_v);
+  PDIV_NONNULL(mean_w);
+  PDIV_NONNULL(var_w);
+  PDIV_NONNULL(lcp);
+  PDIV_TRY(check_dtype(in_dtype, "in_dtype"));
+  PDIV_TRY(check_grid3(nz, ny, nx));
+  PDIV_TRY(check_spacing(dx, dy));
+  if (!(std::isfinite(dz) && dz > 0.0)) return invalid("dz must be finite and > 0 (got %g)", dz);
+  PDIV_TRY(check_iso(isovalues_host, n_iso));
+  const void* const planes[6] = {mean_u, var_u, mean_v, var_v, mean_w, var_w};
+  return lcp3d_chunks(nullptr, nullptr, planes, in_dtype, nz, ny, nx, make_coef3(dx, dy, dz),
+                      isovalues_host, n_iso, lcp, static_cast<hipStream_t>(stream));
 }
 
 pdiv_status pdiv_mc_lcp(const void* mean_u, const void* var_u, const void* mean_v,

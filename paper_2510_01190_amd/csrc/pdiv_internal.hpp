@@ -118,5 +118,10 @@ hipError_t launch_divergence3d(const void* mu, const void* vu, const void* mv, c
 hipError_t launch_lcp3d(const float* dm, const float* dv, int64_t nz, int64_t ny, int64_t nx,
                         const IsoChunk& iso, int kc, float* out_k0, int64_t plane,
                         hipStream_t s);
+// The same from the six moment volumes (mean_u, var_u, mean_v, var_v,
+// mean_w, var_w) of type dt, Eq. 2-3 evaluated on the spot.
+hipError_t launch_lcp3d_fused(const void* const* planes, pdiv_dtype dt, int64_t nz, int64_t ny,
+                              int64_t nx, const StencilCoef3& k, const IsoChunk& iso, int kc,
+                              float* out_k0, int64_t plane, hipStream_t s);
 
 }  // namespace pdiv

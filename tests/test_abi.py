@@ -186,6 +186,16 @@ def test_3d_calls_reject_bad_arguments():
     _expect_invalid(L.pdiv_lcp_3d(FAKE, FAKE, 4, 8, 8, ip, 257, FAKE, NUL), "n_iso")
     _expect_invalid(L.pdiv_lcp_3d(FAKE, FAKE, 4, 8, 8, ip, 1, NUL, NUL), "lcp")
     _expect_invalid(L.pdiv_lcp_3d(FAKE, FAKE, 4, 1 << 22, 8, ip, 1, FAKE, NUL), "too large")
+    _expect_invalid(L.pdiv_lcp_3d_from_moments(*six, 0, 4, 8, 8, 1.0, 1.0, -2.0, ip, 1, FAKE,
+                                               NUL), "dz")
+    _expect_invalid(L.pdiv_lcp_3d_from_moments(*six, 0, 4, 8, 8, 1.0, 1.0, 1.0, ip, 0, FAKE,
+                                               NUL), "n_iso")
+    _expect_invalid(L.pdiv_lcp_3d_from_moments(*six, 3, 4, 8, 8, 1.0, 1.0, 1.0, ip, 1, FAKE,
+                                               NUL), "dtype")
+    _expect_invalid(L.pdiv_lcp_3d_from_moments(*six, 0, 2, 1, 8, 1.0, 1.0, 1.0, ip, 1, FAKE,
+                                               NUL), "at least 2x2x2")
+    _expect_invalid(L.pdiv_lcp_3d_from_moments(*six, 0, 4, 8, 8, 1.0, 1.0, 1.0, ip, 1, NUL,
+                                               NUL), "lcp")
 
 
 def test_speed_gradient_rejects_bad_arguments():

@@ -73,6 +73,21 @@ def test_lcp_3d_matches_oracle(shape, k):
     assert np.all((g >= 0) & (g <= 1))
 
 
+@pytest.mark.parametrize("dt", ["f32", "f16", "bf16"])
+@pytest.mark.parametrize("shape", SHAPES)
+def test_fused_equals_two_step(shape, dt):
+    """pdiv_lcp_3d_from_moments evaluates Eq. 2-3 on the spot with the same
+    operands as the divergence kernel: the maps are bitwise the two-step's."""
+    h = (1.0, 0.5, 2.0)
+    _, ts = _field(shape, seed=3 * sum(shape), dt=dt)
+    dm, dv = P.divergence_gaussian_3d(*ts, *h)
+    for k in (1, 4, 8, 16, 17):
+        iso = np.quantile(host64(dm), np.linspace(0.05, 0.95, k)).astype(np.float32)
+        two = P.lcp_3d(dm, dv, iso)
+        fused = P.lcp_3d_from_moments(*ts, iso, *h)
+        assert torch.equal(fused, two), (shape, dt, k)
+
+
 def test_lcp_3d_end_to_end_float32():
     """From the float64 field through float32 storage and arithmetic."""
     shape = (9, 33, 130)
@@ -122,6 +137,7 @@ def test_bench_size_sampled_slabs():
     dm, dv = P.divergence_gaussian_3d(*ts)
     iso = np.quantile(host64(dm[::8, ::8, ::8]), [0.2, 0.4, 0.6, 0.8]).astype(np.float32)
     out = P.lcp_3d(dm, dv, iso)
+    assert torch.equal(P.lcp_3d_from_moments(*ts, iso), out)
     assert not torch.isnan(out).any()
     assert float(out.min()) >= 0.0 and float(out.max()) <= 1.0
     worst = 0.0
