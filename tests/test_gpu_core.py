@@ -353,3 +353,21 @@ def test_band_height_does_not_change_the_maps(dt):
             assert torch.equal(paired, dense_ref), rows
     finally:
         P.set_lcp_band_rows(0)
+
+
+@pytest.mark.parametrize("shape", [(2, (1 << 20) + 3), ((1 << 17) + 1, 2), (3, 70001)])
+@pytest.mark.parametrize("k", [3, 16])
+def test_extreme_aspect_ratios(shape, k):
+    """One row of a million cells (many strips in one band) and one cell per
+    row over 131072 rows (many bands of one strip), dense, padded and
+    row-interleaved outputs, against the oracle."""
+    ny, nx = shape
+    rng = np.random.default_rng(ny + k)
+    f = {"mean_u": rng.normal(0, 1, shape), "var_u": rng.uniform(0.01, 0.25, shape),
+         "mean_v": rng.normal(0, 1, shape), "var_v": rng.uniform(0.01, 0.25, shape)}
+    ts = moments_dev(f)
+    iso = np.linspace(-0.8, 0.8, k).astype(np.float32)
+    ref = O.lcp(*O.divergence_gaussian(*stored64(ts), 1.0, 1.0), iso)
+    for out in (None, P.empty_lcp(k, ny, nx), P.empty_lcp(k, ny, nx, interleave_rows=True)):
+        g = host64(P.lcp_from_moments(*ts, iso, out=out))
+        assert np.max(np.abs(g - ref)) <= LCP_TOL
