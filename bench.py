@@ -190,6 +190,34 @@ def cpu_legs(stored, iso, rows, mc_rows=34, mc_samples=100, mc_target=1000):
     return out
 
 
+PROFILE_MC = os.path.join(ROOT, "profiles", "mc_8192x8192_k16_s1000_valu.txt")
+MC_SRC = [os.path.join(ROOT, "paper_2510_01190_amd", "csrc", f)
+          for f in ("k_mc.hip", "pdiv_device.hpp")]
+VALU_ISSUE_PEAK = 256 * 2.4e9  # wave64 VALU instructions/s: 1 per CU per cycle
+
+
+def read_mc_valu():
+    """Vector-ALU instructions per point-sample of the Monte Carlo kernel
+    from the committed counter summary, or None if absent or taken on other
+    kernel source."""
+    if not os.path.exists(PROFILE_MC):
+        return None
+    vals = {}
+    for line in open(PROFILE_MC):
+        if ":" in line and not line.startswith("#"):
+            k, v = line.split(":", 1)
+            vals[k.strip()] = v.strip()
+    h = hashlib.sha256()
+    for p in MC_SRC:
+        h.update(open(p, "rb").read())
+    if vals.get("kernel_source_sha256_16") != h.hexdigest()[:16]:
+        return None
+    try:
+        return float(vals["valu_wave_instructions_per_point_sample"])
+    except (KeyError, ValueError):
+        return None
+
+
 def time_launches(fn, n, torch):
     """Average device time of fn() over n back-to-back launches, HIP events on
     the current stream (the stream every launch is enqueued on)."""
@@ -303,6 +331,19 @@ def volume_leg(P, synth, torch, np, n=512):
         del o
     del dm, dv, ts
     return out
+
+
+def mc_leg(P, synth, torch, np, samples=1000):
+    """The Monte Carlo comparison alone on the 8192x8192 field at 16
+    isovalues (one launch after a short warmup launch)."""
+    c3 = synth.config_c3()
+    mom = [torch.from_numpy(c3[k]).float().cuda() for k in ("mean_u", "var_u", "mean_v", "var_v")]
+    iso = c3["isovalues"]
+    out = torch.empty((iso.size, c3["ny"] - 1, c3["nx"] - 1), device="cuda")
+    P.mc_lcp(*mom, iso, n_samples=2, seed=1, out=out)
+    t = time_launches(lambda: P.mc_lcp(*mom, iso, n_samples=samples, seed=2025, out=out), 1, torch)
+    return {"ms": round(t * 1e3, 3), "samples": samples,
+            "point_samples_per_s": round(c3["ny"] * c3["nx"] * samples / t, 1)}
 
 
 def served_leg(P, synth, torch, np, n_streams=2, fracs=(0.5, 0.9), baseline=True):
@@ -509,7 +550,7 @@ def main():
     ap.add_argument("--no-cpu-legs", action="store_true",
                     help="only the single-thread oracle in the CPU baseline")
     ap.add_argument("--mc-samples", type=int, default=1000)
-    ap.add_argument("--only-leg", choices=["volume_3d", "batch", "served"],
+    ap.add_argument("--only-leg", choices=["volume_3d", "batch", "served", "mc"],
                     help="run one leg alone and print its JSON (for profiling)")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="only run a plain 1 GiB device copy (HBM counter calibration)")
@@ -540,7 +581,8 @@ def main():
         return
     P.lib()  # fail loudly if the library is missing
     if args.only_leg:
-        fn = {"volume_3d": volume_leg, "batch": batch_leg, "served": served_leg}[args.only_leg]
+        fn = {"volume_3d": volume_leg, "batch": batch_leg, "served": served_leg,
+              "mc": mc_leg}[args.only_leg]
         print(json.dumps(fn(P, synth, torch, np)), flush=True)
         return
 
@@ -620,6 +662,13 @@ def main():
                         "ms": round(t * 1e3, 3),
                         "point_samples_per_s": round(ny * nx * S / t, 1),
                         "closed_form_speedup": round(t / kern_s, 1)}
+        ipps = read_mc_valu()
+        if ipps is not None:
+            ach = ipps * ny * nx * S / t
+            result["mc"]["roofline"] = {
+                "bound": "alu", "achieved": round(ach, 1), "peak": VALU_ISSUE_PEAK,
+                "unit": "wave64 VALU instructions/s", "frac": round(ach / VALU_ISSUE_PEAK, 4),
+                "valu_instructions_per_point_sample": ipps}
         d = (mc_out - out).double()
         result["mc"]["sse_vs_closed_form_per_map"] = round(float((d * d).sum()) / K, 3)
         del mc_out, d
