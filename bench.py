@@ -218,6 +218,16 @@ def read_mc_valu():
         return None
 
 
+def guarded(name, fn, *args, **kw):
+    """Run an optional leg; a failure is logged and recorded in its entry so
+    that the headline line is still printed."""
+    try:
+        return fn(*args, **kw)
+    except Exception as e:  # noqa: BLE001 -- any failure of a side leg
+        log(f"{name} failed: {type(e).__name__}: {e}")
+        return {"error": f"{type(e).__name__}: {e}"}
+
+
 def time_launches(fn, n, torch):
     """Average device time of fn() over n back-to-back launches, HIP events on
     the current stream (the stream every launch is enqueued on)."""
@@ -823,11 +833,11 @@ def main():
         del sp
         del u, v, outs, c2out
         torch.cuda.empty_cache()
-        legs["batch_512_fields_k4"] = batch_leg(P, synth, torch, np)
+        legs["batch_512_fields_k4"] = guarded("batch leg", batch_leg, P, synth, torch, np)
         torch.cuda.empty_cache()
-        legs["volume_3d_512"] = volume_leg(P, synth, torch, np)
+        legs["volume_3d_512"] = guarded("3D leg", volume_leg, P, synth, torch, np)
         torch.cuda.empty_cache()
-        legs["served_stream"] = served_leg(P, synth, torch, np)
+        legs["served_stream"] = guarded("served leg", served_leg, P, synth, torch, np)
         result["legs"] = legs
 
     if not args.no_cpu_baseline:
@@ -859,8 +869,10 @@ def main():
                                   "gpu_max_abs_err_on_sample": worst,
                                   "host": host_cpu()}
         if not args.no_cpu_legs:
-            legs_cpu = cpu_legs(stored, iso, rows, mc_target=args.mc_samples)
-            result["cpu_baseline"].update(legs_cpu)
+            legs_cpu = guarded("CPU legs", cpu_legs, stored, iso, rows, mc_target=args.mc_samples)
+            result["cpu_baseline"].update(legs_cpu if "error" not in legs_cpu
+                                          else {"cpu_legs_error": legs_cpu["error"]})
+        if not args.no_cpu_legs and "error" not in legs_cpu:
             mc1 = legs_cpu["mc_1core"]["value"]
             ratios = {"cpu_oracle_1core_vs_cpu_mc_1core": round(cpu / mc1, 1),
                       "cpu_oracle_all_cores_vs_cpu_mc_1core":
