@@ -189,6 +189,22 @@ pdiv_status pdiv_isocontour(const float* field, int64_t ny, int64_t nx, float is
                             int64_t* row_offsets, float* segments, int64_t max_segments,
                             pdiv_stream stream);
 
+/* Spaghetti plot in one call: the divergence of every member by Eq. 1 (each
+ * member a deterministic field; bitwise the mean of pdiv_divergence_gaussian
+ * with zero variances) into div_workspace, then every member's isocontour
+ * at isovalue, as pdiv_isocontour computes it.  u_members, v_members as in
+ * pdiv_moments; div_workspace: n_members*ny*nx float32 (device, caller-
+ * allocated); row_offsets: n_members*(ny-1) + 1 int64 (device): entry
+ * m*(ny-1) + j receives the first segment of member m's cell row j, the last
+ * entry the total, so member m's segments are
+ * [row_offsets[m*(ny-1)], row_offsets[(m+1)*(ny-1)]); segments and
+ * max_segments as in pdiv_isocontour.  n_members*ny <= 2^30. */
+pdiv_status pdiv_spaghetti(const void* u_members, const void* v_members, pdiv_dtype in_dtype,
+                           int64_t n_members, int64_t ny, int64_t nx, int64_t member_stride,
+                           double dx, double dy, float isovalue, float* div_workspace,
+                           int64_t* row_offsets, float* segments, int64_t max_segments,
+                           pdiv_stream stream);
+
 /* ------------------------------------------------------------------------
  * 3D vector fields, the extension the paper names as future work (Section 5).
  * Nothing in the method changes but the dimension: the divergence adds

@@ -72,6 +72,8 @@ _SIGS = {
     "pdiv_speed_gradient_moments": [_p, _p, _c.c_int, _i64, _i64, _i64, _i64, _f64, _f64, _i32,
                                     _p, _p, _p, _p, _c.c_int, _p],
     "pdiv_isocontour": [_p, _i64, _i64, _c.c_float, _p, _p, _i64, _p],
+    "pdiv_spaghetti": [_p, _p, _c.c_int, _i64, _i64, _i64, _i64, _f64, _f64, _c.c_float, _p, _p,
+                       _p, _i64, _p],
     "pdiv_divergence_gaussian_3d": [_p, _p, _p, _p, _p, _p, _c.c_int, _i64, _i64, _i64, _f64,
                                     _f64, _f64, _p, _p, _p],
     "pdiv_lcp_3d": [_p, _p, _i64, _i64, _i64, _fp, _i32, _p, _p],
@@ -291,14 +293,23 @@ def isocontour(field, isovalue):
 
 def spaghetti(u_members, v_members, isovalue, dx: float = 1.0, dy: float = 1.0):
     """Per-member isocontours of the divergence (Eq. 1, each member taken as a
-    deterministic field) at isovalue: a list of [n_m][4] segment tensors."""
+    deterministic field) at isovalue, in one library call: a list of [n_m][4]
+    segment tensors (views of one buffer)."""
     torch = _torch()
-    zero = torch.zeros(u_members.shape[1:], dtype=u_members.dtype, device=u_members.device)
-    out = []
-    for u, v in zip(u_members, v_members):
-        d, _ = divergence_gaussian(u.contiguous(), zero, v.contiguous(), zero, dx, dy)
-        out.append(isocontour(d, isovalue))
-    return out
+    m, ny, nx = u_members.shape
+    pu = _dev(u_members, "u_members", (m, ny, nx))
+    pv = _dev(v_members, "v_members", (m, ny, nx), u_members.dtype)
+    work = torch.empty((m, ny, nx), dtype=torch.float32, device=u_members.device)
+    offs = torch.empty(m * (ny - 1) + 1, dtype=torch.int64, device=u_members.device)
+    c = float(np.float32(isovalue))
+    args = (pu, pv, _dtype_code(u_members), m, ny, nx, 0, dx, dy, c, _p(work.data_ptr()),
+            _p(offs.data_ptr()))
+    _check(lib().pdiv_spaghetti(*args, None, 0, _stream()))
+    n = int(offs[-1].item())
+    segs = torch.empty((max(n, 1), 4), dtype=torch.float32, device=u_members.device)
+    _check(lib().pdiv_spaghetti(*args, _p(segs.data_ptr()), n, _stream()))
+    bounds = offs[::ny - 1].cpu().tolist()
+    return [segs[bounds[q]:bounds[q + 1]] for q in range(m)]
 
 
 def divergence_gaussian_3d(mean_u, var_u, mean_v, var_v, mean_w, var_w, dx: float = 1.0,

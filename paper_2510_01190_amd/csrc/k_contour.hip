@@ -12,6 +12,7 @@
 //          plus the count of the lanes before it (ballot + prefix count).
 #include <hip/hip_runtime.h>
 
+#include "pdiv_device.hpp"
 #include "pdiv_internal.hpp"
 
 namespace pdiv {
@@ -80,11 +81,16 @@ __device__ __forceinline__ Corners corners(const float* __restrict__ f, int nx, 
   return k;
 }
 
-__global__ __launch_bounds__(kBlock) void contour_count_kernel(const float* __restrict__ f, int ny,
-                                                               int nx, float c,
+// Rows r = 0 .. n_fields (ny - 1) - 1 of n_fields fields stored field_stride
+// floats apart: cell row j = r mod (ny - 1) of field r / (ny - 1).
+__global__ __launch_bounds__(kBlock) void contour_count_kernel(const float* __restrict__ f0, int ny,
+                                                               int nx, int64_t field_stride,
+                                                               int rows, float c,
                                                                int64_t* __restrict__ counts) {
-  const int j = blockIdx.x * kWavesPerBlock + (threadIdx.x >> 6);
-  if (j >= ny - 1) return;
+  const int r = blockIdx.x * kWavesPerBlock + (threadIdx.x >> 6);
+  if (r >= rows) return;
+  const int j = r % (ny - 1);
+  const float* const f = f0 + int64_t(r / (ny - 1)) * field_stride;
   const int lane = threadIdx.x & 63;
   int n = 0;
   for (int i = lane; i < nx - 1; i += 64) {
@@ -93,7 +99,7 @@ __global__ __launch_bounds__(kBlock) void contour_count_kernel(const float* __re
   }
 #pragma unroll
   for (int s = 32; s > 0; s >>= 1) n += __shfl_xor(n, s, 64);
-  if (lane == 0) counts[j] = n;
+  if (lane == 0) counts[r] = n;
 }
 
 // Exclusive scan of counts[0 .. n) in place, total to counts[n]; one block.
@@ -120,13 +126,15 @@ __global__ __launch_bounds__(kScanBlock) void contour_scan_kernel(int64_t* __res
 }
 
 __global__ __launch_bounds__(kBlock) void contour_write_kernel(
-    const float* __restrict__ f, int ny, int nx, float c, const int64_t* __restrict__ offsets,
-    float4* __restrict__ segs, int64_t max_segs) {
-  const int j = blockIdx.x * kWavesPerBlock + (threadIdx.x >> 6);
-  if (j >= ny - 1) return;
+    const float* __restrict__ f0, int ny, int nx, int64_t field_stride, int rows, float c,
+    const int64_t* __restrict__ offsets, float4* __restrict__ segs, int64_t max_segs) {
+  const int r = blockIdx.x * kWavesPerBlock + (threadIdx.x >> 6);
+  if (r >= rows) return;
+  const int j = r % (ny - 1);
+  const float* const f = f0 + int64_t(r / (ny - 1)) * field_stride;
   const int lane = threadIdx.x & 63;
   const uint64_t below_me = __lanemask_lt();
-  int64_t k = offsets[j];
+  int64_t k = offsets[r];
   // every lane walks the same number of chunks, so the ballots see the wave
   for (int i0 = 0; i0 < nx - 1; i0 += 64) {
     const int i = i0 + lane;
@@ -154,19 +162,75 @@ __global__ __launch_bounds__(kBlock) void contour_write_kernel(
   }
 }
 
+// Eq. 1 on every member of an ensemble (each member a deterministic field):
+// the x and y differences with the coefficients of Eq. 2 and its rounding,
+// so each divergence is bitwise the mean of a zero-variance Eq. 2.  Grid:
+// x blocks of 64 columns, one row per wave, members outermost.
+template <typename T>
+__global__ __launch_bounds__(kBlock) void members_divergence_kernel(
+    const T* __restrict__ u, const T* __restrict__ v, int ny, int nx, int64_t stride,
+    StencilCoef k, float* __restrict__ div, int n_xb, int rows) {
+  const int xb = blockIdx.x % n_xb;
+  const int r = (blockIdx.x / n_xb) * kWavesPerBlock + (threadIdx.x >> 6);
+  const int x = xb * 64 + (threadIdx.x & 63);
+  if (r >= rows || x >= nx) return;
+  const int m = r / ny, y = r % ny;
+  const T* const um = u + int64_t(m) * stride;
+  const T* const vm = v + int64_t(m) * stride;
+  const int xl = x > 0 ? x - 1 : 0, xr = x < nx - 1 ? x + 1 : nx - 1;
+  const int yl = y > 0 ? y - 1 : 0, yr = y < ny - 1 ? y + 1 : ny - 1;
+  const bool bx = (x == 0) | (x == nx - 1), by = (y == 0) | (y == ny - 1);
+  const float a_r = to_f32(um[int64_t(y) * nx + xr]), a_l = to_f32(um[int64_t(y) * nx + xl]);
+  const float b_r = to_f32(vm[int64_t(yr) * nx + x]), b_l = to_f32(vm[int64_t(yl) * nx + x]);
+  const float cx = bx ? k.cxm_bd : k.cxm_in, cy = by ? k.cym_bd : k.cym_in;
+  float d;
+  {
+#pragma clang fp contract(off)
+    d = (a_r - a_l) * cx + (b_r - b_l) * cy;
+  }
+  div[int64_t(m) * ny * nx + int64_t(y) * nx + x] = d;
+}
+
 }  // namespace
+
+hipError_t launch_isocontours(const float* fields, int64_t n_fields, int64_t field_stride,
+                              int64_t ny, int64_t nx, float c, int64_t* row_offsets,
+                              float* segments, int64_t max_segments, hipStream_t s) {
+  const int rows = int(n_fields * (ny - 1));
+  const unsigned blocks = unsigned((rows + kWavesPerBlock - 1) / kWavesPerBlock);
+  hipLaunchKernelGGL(contour_count_kernel, dim3(blocks), dim3(kBlock), 0, s, fields, int(ny),
+                     int(nx), field_stride, rows, c, row_offsets);
+  hipLaunchKernelGGL(contour_scan_kernel, dim3(1), dim3(kScanBlock), 0, s, row_offsets, rows);
+  hipLaunchKernelGGL(contour_write_kernel, dim3(blocks), dim3(kBlock), 0, s, fields, int(ny),
+                     int(nx), field_stride, rows, c, row_offsets,
+                     reinterpret_cast<float4*>(segments), max_segments);
+  return hipGetLastError();
+}
 
 hipError_t launch_isocontour(const float* field, int64_t ny, int64_t nx, float c,
                              int64_t* row_offsets, float* segments, int64_t max_segments,
                              hipStream_t s) {
-  const int rows = int(ny - 1);
-  const unsigned blocks = unsigned((rows + kWavesPerBlock - 1) / kWavesPerBlock);
-  hipLaunchKernelGGL(contour_count_kernel, dim3(blocks), dim3(kBlock), 0, s, field, int(ny),
-                     int(nx), c, row_offsets);
-  hipLaunchKernelGGL(contour_scan_kernel, dim3(1), dim3(kScanBlock), 0, s, row_offsets, rows);
-  hipLaunchKernelGGL(contour_write_kernel, dim3(blocks), dim3(kBlock), 0, s, field, int(ny),
-                     int(nx), c, row_offsets, reinterpret_cast<float4*>(segments),
-                     max_segments);
+  return launch_isocontours(field, 1, ny * nx, ny, nx, c, row_offsets, segments, max_segments,
+                            s);
+}
+
+hipError_t launch_members_divergence(const void* u, const void* v, pdiv_dtype dt, int64_t m,
+                                     int64_t ny, int64_t nx, int64_t stride,
+                                     const StencilCoef& k, float* div, hipStream_t s) {
+  const int n_xb = int((nx + 63) / 64);
+  const int rows = int(m * ny);
+  const unsigned blocks = unsigned(int64_t(n_xb) * ((rows + kWavesPerBlock - 1) / kWavesPerBlock));
+#define PDIV_MDIV(T)                                                                           \
+  hipLaunchKernelGGL(members_divergence_kernel<T>, dim3(blocks), dim3(kBlock), 0, s,           \
+                     static_cast<const T*>(u), static_cast<const T*>(v), int(ny), int(nx),     \
+                     stride, k, div, n_xb, rows)
+  switch (dt) {
+    case PDIV_F32: PDIV_MDIV(float); break;
+    case PDIV_F16: PDIV_MDIV(__half); break;
+    case PDIV_BF16: PDIV_MDIV(bf16_t); break;
+    default: return hipErrorInvalidValue;
+  }
+#undef PDIV_MDIV
   return hipGetLastError();
 }
 

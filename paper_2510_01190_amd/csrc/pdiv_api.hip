@@ -307,6 +307,40 @@ pdiv_status pdiv_isocontour(const float* field, int64_t ny, int64_t nx, float is
                        "isocontour launch");
 }
 
+pdiv_status pdiv_spaghetti(const void* u_members, const void* v_members, pdiv_dtype in_dtype,
+                           int64_t n_members, int64_t ny, int64_t nx, int64_t member_stride,
+                           double dx, double dy, float isovalue, float* div_workspace,
+                           int64_t* row_offsets, float* segments, int64_t max_segments,
+                           pdiv_stream stream) {
+  g_last_error.clear();
+  PDIV_NONNULL(u_members);
+  PDIV_NONNULL(v_members);
+  PDIV_NONNULL(div_workspace);
+  PDIV_NONNULL(row_offsets);
+  PDIV_TRY(check_dtype(in_dtype, "in_dtype"));
+  PDIV_TRY(check_grid(ny, nx));
+  PDIV_TRY(check_spacing(dx, dy));
+  if (n_members < 1 || n_members * ny > (int64_t(1) << 30))
+    return invalid("n_members must be >= 1 with n_members*ny <= 2^30 (got %lld)",
+                   (long long)n_members);
+  const int64_t n = ny * nx;
+  if (member_stride == 0) member_stride = n;
+  if (member_stride < n)
+    return invalid("member_stride %lld < ny*nx %lld", (long long)member_stride, (long long)n);
+  if (max_segments < 0) return invalid("max_segments must be >= 0 (got %lld)",
+                                       (long long)max_segments);
+  if (max_segments > 0 && segments == nullptr) return invalid("segments is NULL");
+  if (max_segments > 0 && reinterpret_cast<uintptr_t>(segments) % 16 != 0)
+    return invalid("segments must be 16-byte aligned");
+  const hipStream_t s = static_cast<hipStream_t>(stream);
+  hipError_t e = launch_members_divergence(u_members, v_members, in_dtype, n_members, ny, nx,
+                                           member_stride, make_coef(dx, dy), div_workspace, s);
+  e = e != hipSuccess ? e
+                      : launch_isocontours(div_workspace, n_members, n, ny, nx, isovalue,
+                                           row_offsets, segments, max_segments, s);
+  return device_status(e, "spaghetti launch");
+}
+
 pdiv_status pdiv_divergence_gaussian_3d(const void* mean_u, const void* var_u,
                                         const void* mean_v, const void* var_v,
                                         const void* mean_w, const void* var_w,

@@ -96,6 +96,15 @@ hipError_t launch_speed_gradient_moments(const void* u, const void* v, pdiv_dtyp
 hipError_t launch_isocontour(const float* field, int64_t ny, int64_t nx, float c,
                              int64_t* row_offsets, float* segments, int64_t max_segments,
                              hipStream_t s);
+// The same over n_fields fields field_stride floats apart (row_offsets:
+// n_fields (ny-1) + 1 entries, field-major).
+hipError_t launch_isocontours(const float* fields, int64_t n_fields, int64_t field_stride,
+                              int64_t ny, int64_t nx, float c, int64_t* row_offsets,
+                              float* segments, int64_t max_segments, hipStream_t s);
+// Eq. 1 of each of m members (deterministic fields) into div [m][ny][nx].
+hipError_t launch_members_divergence(const void* u, const void* v, pdiv_dtype dt, int64_t m,
+                                     int64_t ny, int64_t nx, int64_t stride,
+                                     const StencilCoef& k, float* div, hipStream_t s);
 
 // 3D extension: the coefficients of the x and y differences plus z's.
 struct StencilCoef3 {

@@ -229,3 +229,18 @@ def test_isocontour_rejects_bad_arguments():
                     "max_segments")
     _expect_invalid(L.pdiv_isocontour(FAKE, 8, 8, ctypes.c_float(0.0), FAKE,
                                       ctypes.c_void_p(0x1004), 4, NUL), "aligned")
+
+
+def test_spaghetti_rejects_bad_arguments():
+    L = P.lib()
+    c = ctypes.c_float(0.0)
+    _expect_invalid(L.pdiv_spaghetti(FAKE, FAKE, 0, 0, 8, 8, 0, 1.0, 1.0, c, FAKE, FAKE, FAKE, 4,
+                                     NUL), "n_members")
+    _expect_invalid(L.pdiv_spaghetti(FAKE, FAKE, 0, 3, 8, 8, 10, 1.0, 1.0, c, FAKE, FAKE, FAKE, 4,
+                                     NUL), "member_stride")
+    _expect_invalid(L.pdiv_spaghetti(FAKE, FAKE, 0, 3, 8, 8, 0, 1.0, 1.0, c, NUL, FAKE, FAKE, 4,
+                                     NUL), "div_workspace")
+    _expect_invalid(L.pdiv_spaghetti(FAKE, FAKE, 0, 3, 8, 8, 0, 1.0, 1.0, c, FAKE, FAKE, NUL, 4,
+                                     NUL), "segments is NULL")
+    _expect_invalid(L.pdiv_spaghetti(FAKE, FAKE, 0, 3, 1, 8, 0, 1.0, 1.0, c, FAKE, FAKE, FAKE, 4,
+                                     NUL), "at least 2x2")

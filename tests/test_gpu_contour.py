@@ -103,3 +103,18 @@ def test_spaghetti_matches_per_member_contours():
         g = host64(sp[m])
         assert g.shape == r.shape
         assert np.all(np.abs(g - r) <= 4 * U32 * (1 + np.abs(r)))
+        # one batched call gives bitwise the per-member contours
+        assert torch.equal(sp[m], P.isocontour(d, 0.02))
+
+
+@pytest.mark.parametrize("dt", ["f16", "bf16"])
+def test_spaghetti_16bit_members_and_spacing(dt):
+    from gpu_util import TORCH_DT
+    e = synth.gen_ensemble(33, 130, 4, seed=8, n_features=2, dtype=np.float32)
+    u = torch.from_numpy(e["u_members"]).to(TORCH_DT[dt]).cuda()
+    v = torch.from_numpy(e["v_members"]).to(TORCH_DT[dt]).cuda()
+    sp = P.spaghetti(u, v, -0.01, dx=0.5, dy=2.0)
+    zero = torch.zeros((33, 130), dtype=TORCH_DT[dt], device="cuda")
+    for m in range(4):
+        d, _ = P.divergence_gaussian(u[m].contiguous(), zero, v[m].contiguous(), zero, 0.5, 2.0)
+        assert torch.equal(sp[m], P.isocontour(d, -0.01))
