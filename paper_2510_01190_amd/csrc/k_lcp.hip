@@ -127,7 +127,7 @@ template <int KC, bool FUSED, typename T>
 hipError_t launch_kc(const void* p0, const void* p1, const void* p2, const void* p3, int ny,
                      int nx, const StencilCoef& k, const IsoChunk& iso, float* out,
                      int64_t pitch, int64_t plane, LcpShape shape, hipStream_t s) {
-  const bool paired = use_paired_tile(out, pitch, plane, KC);
+  const bool paired = use_paired_tile(out, pitch, plane, KC, int64_t(ny - 1) * (nx - 1));
   const int cells = cells_per_wave(paired);
   const int band_rows = band_rows_for(shape, ny, paired);
   const int n_strips = (nx - 1 + cells - 1) / cells;

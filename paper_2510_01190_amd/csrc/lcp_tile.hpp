@@ -669,11 +669,18 @@ __device__ __forceinline__ void lcp_tile_split(const T* __restrict__ p0, const T
 
 // Layout choice: the paired tile when every output row starts on a 128-byte
 // line (base aligned, row pitch and plane stride multiples of 32 floats) and
-// there are at least 8 isovalues, so that the seam step costs under 8% of the
-// row's arithmetic.
-inline bool use_paired_tile(const float* out, int64_t pitch, int64_t plane, int kc) {
+// either there are at least 8 isovalues or the map has at least 2^22 cells.
+// On large maps its whole-line stores outweigh the seam step at any
+// isovalue count (8192^2, rows interleaved, paired against split: 0.269 /
+// 0.293 ms at 1 isovalue, 0.318 / 0.360 ms at 2, 0.430 / 0.497 ms at 4;
+// 4096^2: 62 / 76 us at 1, 103 / 142 us at 4); on small maps with few
+// isovalues the launch is dominated by its fixed cost, which is lower for
+// the split tile (up to 1024^2: 16 against 24 us at 1 isovalue, 26 against
+// 35 us at 4).
+inline bool use_paired_tile(const float* out, int64_t pitch, int64_t plane, int kc,
+                            int64_t cells) {
   return (reinterpret_cast<uintptr_t>(out) % 128 == 0) && (pitch % 32 == 0) &&
-         (plane % 32 == 0) && kc >= 8;
+         (plane % 32 == 0) && (kc >= 8 || cells >= (int64_t(1) << 22));
 }
 
 // The tile of layout PAIRED (paired tiles store non-temporally: their rows

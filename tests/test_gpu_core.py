@@ -74,9 +74,9 @@ def test_pitched_output_equals_dense_and_keeps_padding(shape):
     """Rows padded to a longer pitch hold bitwise the dense maps; the padding
     floats are never written (fused and two-step paths).  Nine isovalues run
     as a chunk of 8, which takes the paired tile when the rows start on
-    128-byte lines, and a chunk of 1 (split tile): the dense maps come from the
-    split tile only, so this also checks that the two layouts agree bit for
-    bit, seam column included."""
+    128-byte lines, and a chunk of 1 (split tile on these small maps): the
+    dense maps come from the split tile only, so this also checks that the
+    two layouts agree bit for bit, seam column included."""
     ny, nx = shape
     f = _field(ny, nx, seed=5 + nx)
     ts = moments_dev(f)
