@@ -849,6 +849,13 @@ def main():
         t_cpu = 0.0
         n_cpu = 0
         worst = 0.0
+        sum_err = 0.0
+        # LCP bins of the oracle value: count, max abs error, max error
+        # relative to min(L, 1 - L) (the accuracy the stable combination keeps)
+        edges = [0.0, 1e-6, 1e-3, 0.5, 1 - 1e-3, 1 - 1e-6, 1.0 + 1e-12]
+        names = ["[0,1e-6)", "[1e-6,1e-3)", "[1e-3,0.5)", "[0.5,1-1e-3)", "[1-1e-3,1-1e-6)",
+                 "[1-1e-6,1]"]
+        bins = [{"bin": nm, "count": 0, "max_abs": 0.0, "max_rel": 0.0} for nm in names]
         for j0 in range(rows[0], rows[1], 256):
             j1 = min(j0 + 256, rows[1])
             a, b = j0 - 1, j1 + 2
@@ -858,7 +865,18 @@ def main():
             t_cpu += time.perf_counter() - t
             n_cpu += ref.size
             g = out[:, j0:j1, :].double().cpu().numpy()
-            worst = max(worst, float(np.max(np.abs(g - ref))))
+            err = np.abs(g - ref)
+            worst = max(worst, float(np.max(err)))
+            sum_err += float(err.sum())
+            side = np.minimum(ref, 1.0 - ref)
+            for q, bn in enumerate(bins):
+                sel = (ref >= edges[q]) & (ref < edges[q + 1])
+                if sel.any():
+                    bn["count"] += int(sel.sum())
+                    bn["max_abs"] = max(bn["max_abs"], float(err[sel].max()))
+                    rel = err[sel] / np.maximum(side[sel], 1e-300)
+                    bn["max_rel"] = max(bn["max_rel"], float(rel[side[sel] > 0].max())
+                                        if (side[sel] > 0).any() else 0.0)
         cpu = n_cpu / t_cpu
         result["cpu_baseline"] = {"value": round(cpu, 1), "unit": "LCP cells/s",
                                   "cores": 1, "kind": "oracle",
@@ -891,7 +909,33 @@ def main():
                 "hardware": "Apple M4 (serial and 10 threads); a GPU of the Frontier system"}
             result["cpu_baseline"]["ratios"] = ratios
         result["accuracy"] = {"max_abs_err_vs_fp64_oracle": worst, "bar": 1e-5,
-                              "within_bar": worst <= 1e-5}
+                              "within_bar": worst <= 1e-5,
+                              "mean_abs_err_vs_fp64_oracle": sum_err / n_cpu,
+                              "sample": f"cell rows {rows[0]}-{rows[1] - 1}, float32 storage, "
+                                        "oracle on the stored values",
+                              "bins_by_oracle_lcp": bins}
+        # storage precision: every storage type on one band, against the
+        # oracle on its stored values (kernel arithmetic) and on the float64
+        # field (end to end, storage rounding included)
+        a0, a1 = 4096, 4352
+        keys = ("mean_u", "var_u", "mean_v", "var_v")
+        m64, v64 = O.divergence_gaussian(*[c3[k][a0 - 1:a1 + 2] for k in keys], 1.0, 1.0)
+        ref_e2e = O.lcp(m64[1:-1], v64[1:-1], iso)
+        prec = {"sample": f"cell rows {a0}-{a1 - 1}, all {K} isovalues"}
+        for name, dt in (("f32", torch.float32), ("f16", torch.float16),
+                         ("bf16", torch.bfloat16)):
+            ts = [torch.from_numpy(c3[k]).to(dt).cuda() for k in keys]
+            g = P.lcp_from_moments(*ts, iso)[:, a0:a1, :].double().cpu().numpy()
+            st = [t[a0 - 1:a1 + 2].double().cpu().numpy() for t in ts]
+            del ts
+            ms, vs = O.divergence_gaussian(*st, 1.0, 1.0)
+            e_k = np.abs(g - O.lcp(ms[1:-1], vs[1:-1], iso))
+            e_e = np.abs(g - ref_e2e)
+            prec[name] = {"kernel_max_abs": float(e_k.max()), "kernel_mean_abs": float(e_k.mean()),
+                          "end_to_end_max_abs": float(e_e.max()),
+                          "end_to_end_mean_abs": float(e_e.mean())}
+        torch.cuda.empty_cache()
+        result["accuracy"]["storage_precision"] = prec
 
     print(json.dumps(result), flush=True)
 
