@@ -714,8 +714,22 @@ def main():
 
         two_step()
         t = time_launches(two_step, 5, torch)
-        legs["two_step_divergence_then_lcp_f32"] = {"ms": round(t * 1e3, 4),
-                                                   "cells_per_s": round(cells * K / t, 1)}
+        # each step alone: Eq. 2-3 (16 B read + 8 B written per point) and the
+        # LCP from the divergence Gaussians (8 B read per point, 4 B per value)
+        t_div = time_launches(lambda: P.lib().pdiv_divergence_gaussian(
+            *[P._p(x.data_ptr()) for x in mom], 0, ny, nx, 1.0, 1.0, P._p(dm.data_ptr()),
+            P._p(dv.data_ptr()), P._stream()), 10, torch)
+        t_lcp = time_launches(lambda: P.lcp(dm, dv, iso, out=out2), 10, torch)
+        b_div = 24 * ny * nx
+        b_lcp = 8 * ny * nx + 4 * K * cells
+        legs["two_step_divergence_then_lcp_f32"] = {
+            "ms": round(t * 1e3, 4), "cells_per_s": round(cells * K / t, 1),
+            "divergence_ms": round(t_div * 1e3, 4),
+            "divergence_achieved_GBs": round(b_div / t_div / 1e9, 1),
+            "divergence_frac_hbm": round(b_div / t_div / 1e9 / HBM_PEAK_GBS, 4),
+            "lcp_from_divergence_ms": round(t_lcp * 1e3, 4),
+            "lcp_from_divergence_achieved_GBs": round(b_lcp / t_lcp / 1e9, 1),
+            "lcp_from_divergence_frac_hbm": round(b_lcp / t_lcp / 1e9 / HBM_PEAK_GBS, 4)}
         assert torch.equal(out, out2), "two-step path differs from the fused path"
         # the mean-field isocontour (marching squares) of the divergence at
         # the middle isovalue: count, scan and write, one call

@@ -65,13 +65,38 @@ __global__ __launch_bounds__(kBlock) void divergence_kernel(const T* __restrict_
   if (x >= nx) return;
   const int j1 = min(j0 + rows_per_thread, ny);
   const Col c = make_col(uint32_t(x), nx, sizeof(T));
+  // V's values at rows clamp(j-1), j, clamp(j+1) stay in a register window
+  // along the wave's rows, so each V row is loaded once (the operands of
+  // Eq. 2-3 are those of a straight evaluation with clamped neighbours)
+  auto v_at = [&](int y, float& m, float& v) {
+    const int64_t row = static_cast<int64_t>(y) * nx;
+    m = RowReader<T>(mv + row, nx).get(c.x);
+    v = RowReader<T>(vv + row, nx).get(c.x);
+  };
+  float vm_l, vv_l, vm_c, vv_c, vm_r, vv_r;
+  v_at(j0 > 0 ? j0 - 1 : 0, vm_l, vv_l);
+  v_at(j0, vm_c, vv_c);
   for (int j = j0; j < j1; ++j) {
+    v_at(j < ny - 1 ? j + 1 : ny - 1, vm_r, vv_r);
     Raw<true> r;
-    load_raw(r, mu, vu, mv, vv, ny, nx, c, j);
+    const RowReader<T> u0(mu + static_cast<int64_t>(j) * nx, nx);
+    const RowReader<T> w0(vu + static_cast<int64_t>(j) * nx, nx);
+    r.mu_l = u0.get(c.xl);
+    r.mu_r = u0.get(c.xr);
+    r.vu_l = w0.get(c.xl);
+    r.vu_r = w0.get(c.xr);
+    r.mv_l = vm_l;
+    r.mv_r = vm_r;
+    r.vv_l = vv_l;
+    r.vv_r = vv_r;
     const DivGauss g = raw_div(r, c.bx, j, ny, k);
     const int64_t o = static_cast<int64_t>(j) * nx + x;
     __builtin_nontemporal_store(g.mean, dmean + o);
     __builtin_nontemporal_store(g.var, dvar + o);
+    vm_l = vm_c;
+    vv_l = vv_c;
+    vm_c = vm_r;
+    vv_c = vv_r;
   }
 }
 
