@@ -197,6 +197,24 @@ __global__ __launch_bounds__(kBlock) void lcp3d_kernel(Planes6 src, int nz, int 
   const Col col = make_col(uint32_t(min(x0 + lane, nx - 1)), nx, sizeof(T));
   const float cxm = col.bx ? k.xy.cxm_bd : k.xy.cxm_in;
   const float cxv = col.bx ? k.xy.cxv_bd : k.xy.cxv_in;
+  // FUSED: V at rows clamp(j-1) and j of every level, carried from row to
+  // row, so each V row is loaded once per wave
+  float vwin_m[LZ + 1][2], vwin_v[LZ + 1][2];
+  if constexpr (FUSED) {
+    const T* const mv = static_cast<const T*>(src.p[2]);
+    const T* const vv = static_cast<const T*>(src.p[3]);
+#pragma unroll
+    for (int l = 0; l <= LZ; ++l) {
+      const int kk = min(k0 + l, nz - 1);
+#pragma unroll
+      for (int h = 0; h < 2; ++h) {
+        const int y = h == 0 ? (j0 > 0 ? j0 - 1 : 0) : j0;
+        const int64_t row = int64_t(kk) * vplane + int64_t(y) * nx;
+        vwin_m[l][h] = RowReader<T>(mv + row, nx).get(col.x);
+        vwin_v[l][h] = RowReader<T>(vv + row, nx).get(col.x);
+      }
+    }
+  }
   auto load_row = [&](int j) {
     if constexpr (FUSED) {
       const T* const mu = static_cast<const T*>(src.p[0]);
@@ -205,7 +223,7 @@ __global__ __launch_bounds__(kBlock) void lcp3d_kernel(Planes6 src, int nz, int 
       const T* const vv = static_cast<const T*>(src.p[3]);
       const T* const mw = static_cast<const T*>(src.p[4]);
       const T* const vw = static_cast<const T*>(src.p[5]);
-      const int yl = j > 0 ? j - 1 : 0, yr = j < ny - 1 ? j + 1 : ny - 1;
+      const int yr = j < ny - 1 ? j + 1 : ny - 1;
       const bool by = (j == 0) | (j == ny - 1);
       const float cym = by ? k.xy.cym_bd : k.xy.cym_in, cyv = by ? k.xy.cyv_bd : k.xy.cyv_in;
       // W at levels clamp(k0 - 1 + t), t = 0 .. LZ + 2: level k0 + l has its
@@ -222,18 +240,23 @@ __global__ __launch_bounds__(kBlock) void lcp3d_kernel(Planes6 src, int nz, int 
       for (int l = 0; l <= LZ; ++l) {
         const int kk = min(k0 + l, nz - 1);
         const int64_t row = int64_t(kk) * vplane + int64_t(j) * nx;
-        const int64_t row_yl = int64_t(kk) * vplane + int64_t(yl) * nx;
         const int64_t row_yr = int64_t(kk) * vplane + int64_t(yr) * nx;
         const RowReader<T> u0(mu + row, nx), s0(vu + row, nx);
-        const RowReader<T> v_l(mv + row_yl, nx), v_r(mv + row_yr, nx);
-        const RowReader<T> t_l(vv + row_yl, nx), t_r(vv + row_yr, nx);
+        const float vmr = RowReader<T>(mv + row_yr, nx).get(col.x);
+        const float vvr = RowReader<T>(vv + row_yr, nx).get(col.x);
         const bool bz = (kk == 0) | (kk == nz - 1);
         const DivGauss g = div_gauss3(
-            u0.get(col.xl), u0.get(col.xr), s0.get(col.xl), s0.get(col.xr), v_l.get(col.x),
-            v_r.get(col.x), t_l.get(col.x), t_r.get(col.x), wm[l], wm[l + 2], wv[l], wv[l + 2],
-            cxm, cxv, cym, cyv, bz ? k.czm_bd : k.czm_in, bz ? k.czv_bd : k.czv_in);
+            u0.get(col.xl), u0.get(col.xr), s0.get(col.xl), s0.get(col.xr), vwin_m[l][0], vmr,
+            vwin_v[l][0], vvr, wm[l], wm[l + 2], wv[l], wv[l + 2], cxm, cxv, cym, cyv,
+            bz ? k.czm_bd : k.czm_in, bz ? k.czv_bd : k.czv_in);
         pm[l] = g.mean;
         pv[l] = g.var;
+        // the window moves one row: rows clamp(j), clamp(j+1) become the
+        // next row's lower and centre rows
+        vwin_m[l][0] = vwin_m[l][1];
+        vwin_v[l][0] = vwin_v[l][1];
+        vwin_m[l][1] = vmr;
+        vwin_v[l][1] = vvr;
       }
     } else {
       const float* const dm = static_cast<const float*>(src.p[0]);
