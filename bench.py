@@ -42,11 +42,23 @@ def log(msg):
     print(f"[bench] {msg}", file=sys.stderr, flush=True)
 
 
-def kernel_hash():
+def source_hash(paths):
+    """sha256 (first 16 hex digits) of source files with their comments
+    removed and whitespace collapsed: counters taken on a kernel stay valid
+    when only its comments or layout change, and go stale with any change to
+    its code."""
+    import re
     h = hashlib.sha256()
-    for p in KERNEL_SRC:
-        h.update(open(p, "rb").read())
+    for p in paths:
+        text = open(p).read()
+        text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+        text = re.sub(r"//[^\n]*", "", text)
+        h.update(" ".join(text.split()).encode())
     return h.hexdigest()[:16]
+
+
+def kernel_hash():
+    return source_hash(KERNEL_SRC)
 
 
 def read_traffic():
@@ -207,10 +219,7 @@ def read_mc_valu():
         if ":" in line and not line.startswith("#"):
             k, v = line.split(":", 1)
             vals[k.strip()] = v.strip()
-    h = hashlib.sha256()
-    for p in MC_SRC:
-        h.update(open(p, "rb").read())
-    if vals.get("kernel_source_sha256_16") != h.hexdigest()[:16]:
+    if vals.get("kernel_source_sha256_16") != source_hash(MC_SRC):
         return None
     try:
         return float(vals["valu_wave_instructions_per_point_sample"])

@@ -28,8 +28,9 @@
 // (A, A+1) and (B, B+1) with the right pair from lane L+1, and lanes 0..62
 // write 63 consecutive cells per store.  No seam step; rows that start
 // inside a line cap the store rate near 4.4 TB/s for either layout, so the
-// cheaper tile wins there (and at few isovalues, where the seam step costs
-// up to 15%).
+// cheaper tile wins there, and on small maps with few isovalues, where a
+// launch's fixed cost dominates and is lower for this tile (use_paired_tile
+// below).
 #pragma once
 
 #include "pdiv_device.hpp"
