@@ -577,8 +577,9 @@ def main():
 
     world = int(os.environ.get("WORLD_SIZE", "1"))
     if args.gpus != 1 or world != 1:
-        print("bench.py runs on exactly one GPU: the path is single-GPU in this build "
-              "(multi-GPU sharding is a design note only); use --gpus 1", file=sys.stderr)
+        print("bench.py runs on exactly one GPU: the library's path runs on one GPU "
+              "(how it would shard over several is described, not implemented); use --gpus 1",
+              file=sys.stderr)
         sys.exit(2)
 
     import numpy as np

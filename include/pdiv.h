@@ -41,7 +41,7 @@ extern "C" {
 typedef enum pdiv_status {
   PDIV_OK = 0,
   PDIV_ERR_INVALID = 1,     /* bad argument; nothing was enqueued            */
-  PDIV_ERR_UNSUPPORTED = 2, /* valid request this build cannot serve         */
+  PDIV_ERR_UNSUPPORTED = 2, /* valid request the library cannot serve       */
   PDIV_ERR_NOMEM = 3,       /* an owned allocation (batch, server) failed    */
   PDIV_ERR_DEVICE = 4,      /* HIP runtime or launch error                   */
   PDIV_ERR_BUSY = 5,        /* server: admission refused (budget or queue)   */
