@@ -51,6 +51,20 @@ namespace {
 constexpr int kBlock = 256;
 constexpr int kWavesPerBlock = kBlock / kWave;
 
+// Eq. 2-3 at every vertex.  A wave walks rows_per_thread rows of a strip of
+// columns and keeps V's rows clamp(j-1), j, clamp(j+1) in a register window,
+// so each V row is loaded once.  U's x neighbours depend on the storage:
+//   32-bit  the strip is 64 columns; each lane loads its two neighbours,
+//           which the L1 serves from the lines of the row already in flight;
+//   16-bit  the strip is 62 columns in 64 lanes (lanes 0 and 63 hold the x
+//           halo); each lane loads only its own column and takes the
+//           neighbours from the adjacent lanes through DPP, with every lane
+//           active, so no load straddles a cache line.
+// Measured at 8192^2: the DPP form takes 0.39 ms for 16-bit storage against
+// 0.55 ms with neighbour loads, but 0.49 ms for 32-bit against 0.36 ms (its
+// 62-column strips put the row segments off cache-line boundaries).  Either
+// way the operands are those of a straight evaluation with clamped
+// neighbours.
 template <typename T>
 __global__ __launch_bounds__(kBlock) void divergence_kernel(const T* __restrict__ mu,
                                                             const T* __restrict__ vu,
@@ -60,14 +74,20 @@ __global__ __launch_bounds__(kBlock) void divergence_kernel(const T* __restrict_
                                                             float* __restrict__ dmean,
                                                             float* __restrict__ dvar,
                                                             int rows_per_thread) {
-  const int x = blockIdx.x * kWave + (threadIdx.x & 63);
-  const int j0 = (blockIdx.y * kWavesPerBlock + (threadIdx.x >> 6)) * rows_per_thread;
-  if (x >= nx) return;
+  constexpr bool kDpp = sizeof(T) == 2;
+  constexpr int kStrip = kDpp ? kWave - 2 : kWave;
+  const int lane = threadIdx.x & 63;
+  const int x = int(blockIdx.x) * kStrip + lane - (kDpp ? 1 : 0);
+  // the wave index is uniform: row pointers stay scalar, and whole waves
+  // leave together, so every DPP partner lane is active
+  const int j0 =
+      __builtin_amdgcn_readfirstlane(blockIdx.y * kWavesPerBlock + (threadIdx.x >> 6)) *
+      rows_per_thread;
+  if (j0 >= ny) return;
+  if (!kDpp && x >= nx) return;
   const int j1 = min(j0 + rows_per_thread, ny);
-  const Col c = make_col(uint32_t(x), nx, sizeof(T));
-  // V's values at rows clamp(j-1), j, clamp(j+1) stay in a register window
-  // along the wave's rows, so each V row is loaded once (the operands of
-  // Eq. 2-3 are those of a straight evaluation with clamped neighbours)
+  const Col c = make_col(uint32_t(x < 0 ? 0 : min(x, nx - 1)), nx, sizeof(T));
+  const bool store = (x < nx) & (!kDpp | ((lane >= 1) & (lane <= kWave - 2)));
   auto v_at = [&](int y, float& m, float& v) {
     const int64_t row = static_cast<int64_t>(y) * nx;
     m = RowReader<T>(mv + row, nx).get(c.x);
@@ -78,21 +98,34 @@ __global__ __launch_bounds__(kBlock) void divergence_kernel(const T* __restrict_
   v_at(j0, vm_c, vv_c);
   for (int j = j0; j < j1; ++j) {
     v_at(j < ny - 1 ? j + 1 : ny - 1, vm_r, vv_r);
+    const int64_t row = static_cast<int64_t>(j) * nx;
+    const RowReader<T> u0(mu + row, nx);
+    const RowReader<T> w0(vu + row, nx);
     Raw<true> r;
-    const RowReader<T> u0(mu + static_cast<int64_t>(j) * nx, nx);
-    const RowReader<T> w0(vu + static_cast<int64_t>(j) * nx, nx);
-    r.mu_l = u0.get(c.xl);
-    r.mu_r = u0.get(c.xr);
-    r.vu_l = w0.get(c.xl);
-    r.vu_r = w0.get(c.xr);
+    if constexpr (kDpp) {
+      const float um = u0.get(c.x);
+      const float us = w0.get(c.x);
+      const float um_l = dpp_from_left(um), um_r = dpp_from_right(um);
+      const float us_l = dpp_from_left(us), us_r = dpp_from_right(us);
+      r.mu_l = x == 0 ? um : um_l;
+      r.mu_r = x == nx - 1 ? um : um_r;
+      r.vu_l = x == 0 ? us : us_l;
+      r.vu_r = x == nx - 1 ? us : us_r;
+    } else {
+      r.mu_l = u0.get(c.xl);
+      r.mu_r = u0.get(c.xr);
+      r.vu_l = w0.get(c.xl);
+      r.vu_r = w0.get(c.xr);
+    }
     r.mv_l = vm_l;
     r.mv_r = vm_r;
     r.vv_l = vv_l;
     r.vv_r = vv_r;
     const DivGauss g = raw_div(r, c.bx, j, ny, k);
-    const int64_t o = static_cast<int64_t>(j) * nx + x;
-    __builtin_nontemporal_store(g.mean, dmean + o);
-    __builtin_nontemporal_store(g.var, dvar + o);
+    if (store) {
+      __builtin_nontemporal_store(g.mean, dmean + row + x);
+      __builtin_nontemporal_store(g.var, dvar + row + x);
+    }
     vm_l = vm_c;
     vv_l = vv_c;
     vm_c = vm_r;
@@ -192,7 +225,9 @@ hipError_t launch_divergence(const void* mu, const void* vu, const void* mv, con
                              pdiv_dtype dt, int64_t ny, int64_t nx, const StencilCoef& k,
                              float* dmean, float* dvar, hipStream_t s) {
   constexpr int rows = 16;
-  dim3 grid(static_cast<unsigned>((nx + kWave - 1) / kWave),
+  // strips of 64 columns for 32-bit storage, of 62 for 16-bit (DPP halo)
+  const int64_t strip = dt == PDIV_F32 ? kWave : kWave - 2;
+  dim3 grid(static_cast<unsigned>((nx + strip - 1) / strip),
             static_cast<unsigned>((ny + rows * kWavesPerBlock - 1) / (rows * kWavesPerBlock)));
   const int iny = static_cast<int>(ny), inx = static_cast<int>(nx);
   switch (dt) {

@@ -28,18 +28,6 @@ constexpr int kStrip = 62;
 // needs more registers (5 or 3 waves per SIMD) and takes 0.144 or 0.222 ms.
 constexpr int kUnroll = 1;
 
-// Lane L receives lane L-1's value (wave_shr:1) or lane L+1's (wave_shl:1);
-// the lanes with no source keep their own (only halo lanes, never stored).
-// A source lane must be active: call these outside lane-dependent branches.
-__device__ __forceinline__ float from_left(float x) {
-  return __int_as_float(
-      __builtin_amdgcn_update_dpp(__float_as_int(x), __float_as_int(x), 0x138, 0xf, 0xf, false));
-}
-__device__ __forceinline__ float from_right(float x) {
-  return __int_as_float(
-      __builtin_amdgcn_update_dpp(__float_as_int(x), __float_as_int(x), 0x130, 0xf, 0xf, false));
-}
-
 template <typename Tin, typename Tout>
 __global__ __launch_bounds__(kBlock) void speed_gradient_moments_kernel(
     const Tin* __restrict__ u, const Tin* __restrict__ v, int m_members, int ny, int nx,
@@ -84,8 +72,8 @@ __global__ __launch_bounds__(kBlock) void speed_gradient_moments_kernel(
       const float own = s[r + 1];
       // both neighbours read with every lane active: a DPP read inside a
       // lane-dependent branch would find its partner lane switched off
-      const float left = from_left(own);
-      const float right = from_right(own);
+      const float left = dpp_from_left(own);
+      const float right = dpp_from_right(own);
       const float sl = x == 0 ? own : left;
       const float sr = x == nx - 1 ? own : right;
       const float gx = (sr - sl) * cxm;

@@ -96,6 +96,19 @@ struct RowWriter {
   }
 };
 
+// Lane L receives lane L-1's value (wave_shr:1) or lane L+1's (wave_shl:1);
+// a lane with no source keeps its own.  The source lane must be active: call
+// these outside lane-dependent branches (a DPP read inside one finds its
+// partner lane switched off and returns the lane's own value).
+__device__ __forceinline__ float dpp_from_left(float x) {
+  return __int_as_float(
+      __builtin_amdgcn_update_dpp(__float_as_int(x), __float_as_int(x), 0x138, 0xf, 0xf, false));
+}
+__device__ __forceinline__ float dpp_from_right(float x) {
+  return __int_as_float(
+      __builtin_amdgcn_update_dpp(__float_as_int(x), __float_as_int(x), 0x130, 0xf, 0xf, false));
+}
+
 // ---------------------------------------------------------------------------
 // Eq. 2 and Eq. 3 at one vertex (Section 3.1).  The caller supplies the two
 // U neighbours along x and the two V neighbours along y, already clamped at
