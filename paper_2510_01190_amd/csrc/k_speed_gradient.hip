@@ -4,13 +4,22 @@
 // analyses.  Fused: the members' speed and gradient never reach HBM; each
 // member value is read once (plus halos), the fit accumulates in registers.
 //
-// Tile: a wave holds 64 columns x0-1 .. x0+62 (lanes 1..62 produce outputs,
-// lanes 0 and 63 are the x halo) and a band of kBand output rows.  Per
-// member it loads the band's rows and the two halo rows (one load per lane
-// and component), takes the speed once per point, forms the x difference
-// from the neighbouring lanes through DPP and the y difference from the
-// rows in registers (Eq. 1's scheme: central inside, one-sided on the
-// boundary), and updates a float32 Welford fit of gx and gy per point.
+// Tile: 64 columns x0-1 .. x0+62 (lanes 1..62 produce outputs, lanes 0 and
+// 63 are the x halo) by a band of kBand output rows, one tile per block.
+// The block's four waves split the members into four contiguous runs; per
+// member a wave loads the band's rows and the two halo rows (one load per
+// lane and component), takes the speed once per point, forms the x
+// difference from the neighbouring lanes through DPP and the y difference
+// from the rows in registers (Eq. 1's scheme: central inside, one-sided on
+// the boundary), and updates a float32 Welford fit of gx and gy per point.
+// The four partial fits then meet in LDS and wave w merges those of output
+// rows w and w + 4 in run order (the pairwise update of Chan, Golub and
+// LeVeque), so each member value is still read once and a tile has four
+// waves in flight.  Measured at 721 x 1440 x 50, float32: one wave per
+// 4-row tile walking all members 0.120 ms; four waves per 4-row tile
+// 0.105 ms; per 8-row tile (two halo rows per eight output rows, not per
+// four) 0.099 ms; per 16-row tile 0.107 ms (254 registers); eight waves per
+// 8-row tile 0.101 ms.
 #include <hip/hip_runtime.h>
 
 #include "pdiv_device.hpp"
@@ -21,23 +30,41 @@ namespace {
 
 constexpr int kBlock = 256;
 constexpr int kWavesPerBlock = kBlock / 64;
-constexpr int kBand = 4;
+constexpr int kBand = 8;
 constexpr int kStrip = 62;
-// Members walked one at a time: at 721 x 1440 x 50 this runs 7 waves per
-// SIMD and takes 0.121 ms; issuing the loads of 2 or 4 members together
-// needs more registers (5 or 3 waves per SIMD) and takes 0.144 or 0.222 ms.
-constexpr int kUnroll = 1;
+static_assert(kBand % kWavesPerBlock == 0, "the merge gives each wave whole output rows");
+
+// first member of wave w's run
+__device__ __forceinline__ int member_run_start(int w, int m_members) {
+  return int(int64_t(w) * m_members / kWavesPerBlock);
+}
+
+// (mean, m2) over n_a values merged with (mean_b, m2_b) over n_b values;
+// n_a may be 0 (then mean and m2 are 0 and the result is exactly b's)
+__device__ __forceinline__ void merge_fit(float& mean, float& m2, int n_a, float mean_b,
+                                          float m2_b, int n_b) {
+  if (n_b == 0) return;
+  const float d = mean_b - mean;
+  const float f_b = static_cast<float>(n_b) / static_cast<float>(n_a + n_b);
+  mean = fmaf(d, f_b, mean);
+  m2 = (m2 + m2_b) + d * d * (static_cast<float>(n_a) * f_b);
+}
 
 template <typename Tin, typename Tout>
 __global__ __launch_bounds__(kBlock) void speed_gradient_moments_kernel(
     const Tin* __restrict__ u, const Tin* __restrict__ v, int m_members, int ny, int nx,
     int64_t stride, StencilCoef k, float inv_dof, Tout* __restrict__ mgx,
-    Tout* __restrict__ vgx, Tout* __restrict__ mgy, Tout* __restrict__ vgy, int n_strips,
-    int n_bands) {
-  const int wave = __builtin_amdgcn_readfirstlane(blockIdx.x * kWavesPerBlock + (threadIdx.x >> 6));
-  const int strip = wave % n_strips;
-  const int band = wave / n_strips;
-  if (band >= n_bands) return;  // wave-uniform: whole waves leave, DPP partners stay together
+    Tout* __restrict__ vgx, Tout* __restrict__ mgy, Tout* __restrict__ vgy, int n_strips) {
+  // partial fits: [wave][row of the band][mean_x, m2_x, mean_y, m2_y][lane]
+  __shared__ float part[kWavesPerBlock][kBand][4][64];
+  // Blocks are dealt round-robin to the 8 XCDs, each with its own L2; give
+  // each XCD a contiguous run of tiles, so that the halo rows two bands
+  // share are fetched into one L2.  The map is a bijection on [0, gridDim.x).
+  const int nb = gridDim.x, xcd = blockIdx.x % 8, q8 = nb / 8, r8 = nb % 8;
+  const int blk = xcd * q8 + min(xcd, r8) + blockIdx.x / 8;
+  const int strip = blk % n_strips;
+  const int band = blk / n_strips;
+  const int w = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
   const int lane = threadIdx.x & 63;
   const int x = strip * kStrip - 1 + lane;
   const int xc = x < 0 ? 0 : (x > nx - 1 ? nx - 1 : x);
@@ -63,9 +90,9 @@ __global__ __launch_bounds__(kBlock) void speed_gradient_moments_kernel(
 #pragma unroll
     for (int r = 0; r < kBand + 2; ++r) s[r] = sqrtf(fmaf(a[r], a[r], b[r] * b[r]));
   };
-  // one member's gradients folded into the running fit (Welford)
-  auto update = [&](int m, const float (&s)[kBand + 2]) {
-    const float inv = 1.0f / static_cast<float>(m + 1);
+  // the i-th member of the run folded into the running fit (Welford)
+  auto update = [&](int i, const float (&s)[kBand + 2]) {
+    const float inv = 1.0f / static_cast<float>(i + 1);
 #pragma unroll
     for (int r = 0; r < kBand; ++r) {
       const int y = y0 + r;
@@ -89,31 +116,42 @@ __global__ __launch_bounds__(kBlock) void speed_gradient_moments_kernel(
       m2_y[r] = fmaf(e, gy - mean_y[r], m2_y[r]);
     }
   };
-  // kUnroll members' loads are issued together, so their latencies overlap
-  int m = 0;
-  for (; m + kUnroll <= m_members; m += kUnroll) {
-    float s[kUnroll][kBand + 2];
-#pragma unroll
-    for (int q = 0; q < kUnroll; ++q) speeds(m + q, s[q]);
-#pragma unroll
-    for (int q = 0; q < kUnroll; ++q) update(m + q, s[q]);
-  }
-  for (; m < m_members; ++m) {
+  const int m_lo = member_run_start(w, m_members);
+  const int m_hi = member_run_start(w + 1, m_members);
+  for (int m = m_lo; m < m_hi; ++m) {
     float s[kBand + 2];
     speeds(m, s);
-    update(m, s);
+    update(m - m_lo, s);
   }
-  if (lane == 0 || lane == 63 || x >= nx) return;
 #pragma unroll
   for (int r = 0; r < kBand; ++r) {
+    part[w][r][0][lane] = mean_x[r];
+    part[w][r][1][lane] = m2_x[r];
+    part[w][r][2][lane] = mean_y[r];
+    part[w][r][3][lane] = m2_y[r];
+  }
+  __syncthreads();
+  if (lane == 0 || lane == 63 || x >= nx) return;
+  // wave w now owns output rows y0 + w, y0 + w + 4, ...: the runs' fits
+  // merged in run order
+#pragma unroll
+  for (int r = w; r < kBand; r += kWavesPerBlock) {
     const int y = y0 + r;
-    if (y < ny) {
-      const int64_t o = int64_t(y) * nx + x;
-      mgx[o] = from_f32<Tout>(mean_x[r]);
-      vgx[o] = from_f32<Tout>(m2_x[r] * inv_dof);
-      mgy[o] = from_f32<Tout>(mean_y[r]);
-      vgy[o] = from_f32<Tout>(m2_y[r] * inv_dof);
+    if (y >= ny) break;
+    float mx = 0.0f, qx = 0.0f, my = 0.0f, qy = 0.0f;
+    int n = 0;
+#pragma unroll
+    for (int p = 0; p < kWavesPerBlock; ++p) {
+      const int np = member_run_start(p + 1, m_members) - member_run_start(p, m_members);
+      merge_fit(mx, qx, n, part[p][r][0][lane], part[p][r][1][lane], np);
+      merge_fit(my, qy, n, part[p][r][2][lane], part[p][r][3][lane], np);
+      n += np;
     }
+    const int64_t o = int64_t(y) * nx + x;
+    mgx[o] = from_f32<Tout>(mx);
+    vgx[o] = from_f32<Tout>(qx * inv_dof);
+    mgy[o] = from_f32<Tout>(my);
+    vgy[o] = from_f32<Tout>(qy * inv_dof);
   }
 }
 
@@ -123,14 +161,13 @@ hipError_t launch_sg(const void* u, const void* v, int64_t m, int64_t ny, int64_
                      void* mgy, void* vgy, hipStream_t s) {
   const float inv_dof = static_cast<float>(1.0 / static_cast<double>(m - ddof));
   const int n_strips = int((nx + kStrip - 1) / kStrip);
-  const int n_bands = int((ny + kBand - 1) / kBand);
-  const int64_t blocks = (int64_t(n_strips) * n_bands + kWavesPerBlock - 1) / kWavesPerBlock;
-  if (blocks > 0x7fffffff / kWavesPerBlock) return hipErrorInvalidConfiguration;
+  const int64_t blocks = speed_gradient_blocks(ny, nx);  // one per tile
+  if (blocks * kBlock > int64_t(0xffffffff)) return hipErrorInvalidConfiguration;
   hipLaunchKernelGGL((speed_gradient_moments_kernel<Tin, Tout>), dim3(unsigned(blocks)),
                      dim3(kBlock), 0, s, static_cast<const Tin*>(u), static_cast<const Tin*>(v),
                      int(m), int(ny), int(nx), stride, k, inv_dof, static_cast<Tout*>(mgx),
                      static_cast<Tout*>(vgx), static_cast<Tout*>(mgy), static_cast<Tout*>(vgy),
-                     n_strips, n_bands);
+                     n_strips);
   return hipGetLastError();
 }
 
@@ -149,8 +186,7 @@ hipError_t launch_sg_out(const void* u, const void* v, int64_t m, int64_t ny, in
 }  // namespace
 
 int64_t speed_gradient_blocks(int64_t ny, int64_t nx) {
-  return (((nx + kStrip - 1) / kStrip) * ((ny + kBand - 1) / kBand) + kWavesPerBlock - 1) /
-         kWavesPerBlock;
+  return ((nx + kStrip - 1) / kStrip) * ((ny + kBand - 1) / kBand);
 }
 
 hipError_t launch_speed_gradient_moments(const void* u, const void* v, pdiv_dtype in_dt,

@@ -223,7 +223,7 @@ pdiv_status pdiv_speed_gradient_moments(const void* u_members, const void* v_mem
   if (member_stride == 0) member_stride = n;
   if (member_stride < n)
     return invalid("member_stride %lld < ny*nx %lld", (long long)member_stride, (long long)n);
-  if (speed_gradient_blocks(ny, nx) > (int64_t(1) << 29))
+  if (speed_gradient_blocks(ny, nx) >= (int64_t(1) << 24))  // 256 threads each, < 2^32 per launch
     return invalid("grid of %lld x %lld points is too large for one launch", (long long)ny,
                    (long long)nx);
   return device_status(

@@ -4,8 +4,9 @@ same stored members; then the path on the fitted gradient field.
 
 Tolerance, per output: each member's gradient is rounded in float32 (two
 speeds, a difference, a coefficient) with error at most
-eps = 3 u (s_lo + s_hi) c <= 3 u 2 max|F| max(c); the float32 Welford fit
-adds at most 2 M u max|g| to the mean and a relative 4 M u to the variance,
+eps = 3 u (s_lo + s_hi) c <= 3 u 2 max|F| max(c); the float32 fit (Welford
+over four runs of members, merged pairwise, whose rounding stays within that
+of one sequential pass) adds at most 2 M u max|g| to the mean and a relative 4 M u to the variance,
 and a perturbation eps of every member moves the variance by at most
 2 eps sqrt(var M / (M - ddof)) + 2 eps^2."""
 
