@@ -842,9 +842,8 @@ def main():
             "closed_form_ms": round(t_cf * 1e3, 4), "seed": 2025, "curve": curve}
         del mco, d2
         # spaghetti plot: every member's divergence contour at the middle
-        # isovalue (a divergence and an isocontour per member; the binding
-        # sizes each output from a count call, so this includes 50 host
-        # synchronisations)
+        # isovalue; the binding makes one counting pdiv_spaghetti call, reads
+        # the total (one host synchronisation), then the writing call
         c_sp = float(c2["isovalues"][4])
         P.spaghetti(u[:2], v[:2], c_sp)
         torch.cuda.synchronize()

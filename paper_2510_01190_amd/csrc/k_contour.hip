@@ -21,6 +21,12 @@ namespace {
 constexpr int kBlock = 256;
 constexpr int kWavesPerBlock = kBlock / 64;
 constexpr int kScanBlock = 1024;
+constexpr int kScanItems = 8;  // consecutive rows per scan thread
+// A wave walks its cell row in chunks of 64 cells, kUnroll chunks at a time:
+// their loads are unconditional (clamped to the last cell) and issued
+// together before any of them is classified, so that the row's walk is not
+// one dependent load round per chunk.
+constexpr int kUnroll = 4;
 
 // Edges: 0 bottom (i,j)-(i+1,j), 1 right (i+1,j)-(i+1,j+1), 2 top
 // (i,j+1)-(i+1,j+1), 3 left (i,j)-(i,j+1).  Nibble `case` of kEdgeA / kEdgeB
@@ -93,9 +99,15 @@ __global__ __launch_bounds__(kBlock) void contour_count_kernel(const float* __re
   const float* const f = f0 + int64_t(r / (ny - 1)) * field_stride;
   const int lane = threadIdx.x & 63;
   int n = 0;
-  for (int i = lane; i < nx - 1; i += 64) {
-    const Corners k = corners(f, nx, j, i);
-    n += classify(k.v00, k.v10, k.v11, k.v01, c).n;
+  for (int i0 = 0; i0 < nx - 1; i0 += 64 * kUnroll) {
+    Corners k[kUnroll];
+#pragma unroll
+    for (int q = 0; q < kUnroll; ++q) k[q] = corners(f, nx, j, min(i0 + 64 * q + lane, nx - 2));
+#pragma unroll
+    for (int q = 0; q < kUnroll; ++q) {
+      const int ni = classify(k[q].v00, k[q].v10, k[q].v11, k[q].v01, c).n;
+      n += i0 + 64 * q + lane < nx - 1 ? ni : 0;
+    }
   }
 #pragma unroll
   for (int s = 32; s > 0; s >>= 1) n += __shfl_xor(n, s, 64);
@@ -103,14 +115,24 @@ __global__ __launch_bounds__(kBlock) void contour_count_kernel(const float* __re
 }
 
 // Exclusive scan of counts[0 .. n) in place, total to counts[n]; one block.
+// Per pass thread t sums its kScanItems consecutive counts, the block scans
+// the thread sums (Hillis-Steele in LDS), and each thread writes its items'
+// offsets from its own prefix.
 __global__ __launch_bounds__(kScanBlock) void contour_scan_kernel(int64_t* __restrict__ counts,
                                                                   int n) {
   __shared__ int64_t buf[kScanBlock];
+  const int t = threadIdx.x;
   int64_t carry = 0;
-  for (int base = 0; base < n; base += kScanBlock) {
-    const int t = threadIdx.x;
-    const int64_t x = base + t < n ? counts[base + t] : 0;
-    buf[t] = x;
+  for (int64_t base = 0; base < n; base += int64_t(kScanBlock) * kScanItems) {
+    const int64_t first = base + int64_t(t) * kScanItems;
+    int64_t x[kScanItems];
+    int64_t sum = 0;
+#pragma unroll
+    for (int q = 0; q < kScanItems; ++q) {
+      x[q] = first + q < n ? counts[first + q] : 0;
+      sum += x[q];
+    }
+    buf[t] = sum;
     __syncthreads();
     for (int d = 1; d < kScanBlock; d <<= 1) {
       const int64_t y = t >= d ? buf[t - d] : 0;
@@ -118,11 +140,16 @@ __global__ __launch_bounds__(kScanBlock) void contour_scan_kernel(int64_t* __res
       buf[t] += y;
       __syncthreads();
     }
-    if (base + t < n) counts[base + t] = carry + buf[t] - x;
+    int64_t run = carry + buf[t] - sum;
+#pragma unroll
+    for (int q = 0; q < kScanItems; ++q) {
+      if (first + q < n) counts[first + q] = run;
+      run += x[q];
+    }
     carry += buf[kScanBlock - 1];
     __syncthreads();
   }
-  if (threadIdx.x == 0) counts[n] = carry;
+  if (t == 0) counts[n] = carry;
 }
 
 __global__ __launch_bounds__(kBlock) void contour_write_kernel(
@@ -136,29 +163,31 @@ __global__ __launch_bounds__(kBlock) void contour_write_kernel(
   const uint64_t below_me = __lanemask_lt();
   int64_t k = offsets[r];
   // every lane walks the same number of chunks, so the ballots see the wave
-  for (int i0 = 0; i0 < nx - 1; i0 += 64) {
-    const int i = i0 + lane;
-    Cell cell;
-    cell.n = 0;
-    Corners v{0.0f, 0.0f, 0.0f, 0.0f};
-    if (i < nx - 1) {
-      v = corners(f, nx, j, i);
-      cell = classify(v.v00, v.v10, v.v11, v.v01, c);
+  for (int i00 = 0; i00 < nx - 1; i00 += 64 * kUnroll) {
+    Corners vs[kUnroll];
+#pragma unroll
+    for (int q = 0; q < kUnroll; ++q) vs[q] = corners(f, nx, j, min(i00 + 64 * q + lane, nx - 2));
+#pragma unroll
+    for (int q = 0; q < kUnroll; ++q) {
+      const int i = i00 + 64 * q + lane;
+      const Corners& v = vs[q];
+      Cell cell = classify(v.v00, v.v10, v.v11, v.v01, c);
+      if (i >= nx - 1) cell.n = 0;
+      const uint64_t one = __ballot(cell.n >= 1);
+      const uint64_t two = __ballot(cell.n >= 2);
+      const int64_t at = k + __popcll(one & below_me) + __popcll(two & below_me);
+      if (cell.n >= 1 && at < max_segs) {
+        const float2 p = edge_point(cell.a0, i, j, v.v00, v.v10, v.v11, v.v01, c);
+        const float2 q2 = edge_point(cell.b0, i, j, v.v00, v.v10, v.v11, v.v01, c);
+        segs[at] = make_float4(p.x, p.y, q2.x, q2.y);
+      }
+      if (cell.n >= 2 && at + 1 < max_segs) {
+        const float2 p = edge_point(cell.a1, i, j, v.v00, v.v10, v.v11, v.v01, c);
+        const float2 q2 = edge_point(cell.b1, i, j, v.v00, v.v10, v.v11, v.v01, c);
+        segs[at + 1] = make_float4(p.x, p.y, q2.x, q2.y);
+      }
+      k += __popcll(one) + __popcll(two);
     }
-    const uint64_t one = __ballot(cell.n >= 1);
-    const uint64_t two = __ballot(cell.n >= 2);
-    const int64_t at = k + __popcll(one & below_me) + __popcll(two & below_me);
-    if (cell.n >= 1 && at < max_segs) {
-      const float2 p = edge_point(cell.a0, i, j, v.v00, v.v10, v.v11, v.v01, c);
-      const float2 q = edge_point(cell.b0, i, j, v.v00, v.v10, v.v11, v.v01, c);
-      segs[at] = make_float4(p.x, p.y, q.x, q.y);
-    }
-    if (cell.n >= 2 && at + 1 < max_segs) {
-      const float2 p = edge_point(cell.a1, i, j, v.v00, v.v10, v.v11, v.v01, c);
-      const float2 q = edge_point(cell.b1, i, j, v.v00, v.v10, v.v11, v.v01, c);
-      segs[at + 1] = make_float4(p.x, p.y, q.x, q.y);
-    }
-    k += __popcll(one) + __popcll(two);
   }
 }
 
