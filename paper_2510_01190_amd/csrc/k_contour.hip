@@ -25,8 +25,10 @@ constexpr int kScanItems = 8;  // consecutive rows per scan thread
 // A wave walks its cell row in chunks of 64 cells, kUnroll chunks at a time:
 // their loads are unconditional (clamped to the last cell) and issued
 // together before any of them is classified, so that the row's walk is not
-// one dependent load round per chunk.
-constexpr int kUnroll = 4;
+// one dependent load round per chunk.  At 8192^2 (6 M segments) the three
+// passes take 0.370 ms one chunk at a time, 0.345 / 0.324 / 0.316 ms with
+// 2 / 4 / 8 chunks.
+constexpr int kUnroll = 8;
 
 // Edges: 0 bottom (i,j)-(i+1,j), 1 right (i+1,j)-(i+1,j+1), 2 top
 // (i,j+1)-(i+1,j+1), 3 left (i,j)-(i,j+1).  Nibble `case` of kEdgeA / kEdgeB
