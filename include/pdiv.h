@@ -198,7 +198,8 @@ pdiv_status pdiv_isocontour(const float* field, int64_t ny, int64_t nx, float is
  * m*(ny-1) + j receives the first segment of member m's cell row j, the last
  * entry the total, so member m's segments are
  * [row_offsets[m*(ny-1)], row_offsets[(m+1)*(ny-1)]); segments and
- * max_segments as in pdiv_isocontour.  n_members*ny <= 2^30. */
+ * max_segments as in pdiv_isocontour.  n_members*ny*nx, with nx rounded up
+ * to a multiple of 64, must be below 2^32 (one launch's thread count). */
 pdiv_status pdiv_spaghetti(const void* u_members, const void* v_members, pdiv_dtype in_dtype,
                            int64_t n_members, int64_t ny, int64_t nx, int64_t member_stride,
                            double dx, double dy, float isovalue, float* div_workspace,

@@ -320,9 +320,13 @@ pdiv_status pdiv_spaghetti(const void* u_members, const void* v_members, pdiv_dt
   PDIV_TRY(check_dtype(in_dtype, "in_dtype"));
   PDIV_TRY(check_grid(ny, nx));
   PDIV_TRY(check_spacing(dx, dy));
-  if (n_members < 1 || n_members * ny > (int64_t(1) << 30))
-    return invalid("n_members must be >= 1 with n_members*ny <= 2^30 (got %lld)",
-                   (long long)n_members);
+  // the per-member divergence runs a thread per point of 64-column strips,
+  // the contour passes 64 threads per cell row, both over all members' rows
+  // rounded up to a block's 4: (n_members*ny + 3) * nx_r < 2^32 per launch
+  const int64_t nx_r = (nx + 63) / 64 * 64;
+  if (n_members < 1 || n_members > (int64_t(0xffffffff) / nx_r - 3) / ny)
+    return invalid("n_members must be >= 1 with n_members*ny*nx (nx rounded up to 64) < 2^32 "
+                   "(got %lld)", (long long)n_members);
   const int64_t n = ny * nx;
   if (member_stride == 0) member_stride = n;
   if (member_stride < n)

@@ -244,3 +244,6 @@ def test_spaghetti_rejects_bad_arguments():
                                      NUL), "segments is NULL")
     _expect_invalid(L.pdiv_spaghetti(FAKE, FAKE, 0, 3, 1, 8, 0, 1.0, 1.0, c, FAKE, FAKE, FAKE, 4,
                                      NUL), "at least 2x2")
+    # 4096 members of 1024 x 1024: 2^32 threads in one launch
+    _expect_invalid(L.pdiv_spaghetti(FAKE, FAKE, 0, 4096, 1024, 1024, 0, 1.0, 1.0, c, FAKE, FAKE,
+                                     FAKE, 4, NUL), "n_members")
