@@ -227,7 +227,10 @@ __global__ __launch_bounds__(kBlock) void members_divergence_kernel(
 hipError_t launch_isocontours(const float* fields, int64_t n_fields, int64_t field_stride,
                               int64_t ny, int64_t nx, float c, int64_t* row_offsets,
                               float* segments, int64_t max_segments, hipStream_t s) {
-  const int rows = int(n_fields * (ny - 1));
+  const int64_t rows64 = n_fields * (ny - 1);
+  if (rows64 > 0x7fffffff || !launch_fits((rows64 + kWavesPerBlock - 1) / kWavesPerBlock, kBlock))
+    return hipErrorInvalidConfiguration;
+  const int rows = int(rows64);
   const unsigned blocks = unsigned((rows + kWavesPerBlock - 1) / kWavesPerBlock);
   hipLaunchKernelGGL(contour_count_kernel, dim3(blocks), dim3(kBlock), 0, s, fields, int(ny),
                      int(nx), field_stride, rows, c, row_offsets);
@@ -249,8 +252,10 @@ hipError_t launch_members_divergence(const void* u, const void* v, pdiv_dtype dt
                                      int64_t ny, int64_t nx, int64_t stride,
                                      const StencilCoef& k, float* div, hipStream_t s) {
   const int n_xb = int((nx + 63) / 64);
+  const int64_t blocks64 = int64_t(n_xb) * ((m * ny + kWavesPerBlock - 1) / kWavesPerBlock);
+  if (m * ny > 0x7fffffff || !launch_fits(blocks64, kBlock)) return hipErrorInvalidConfiguration;
   const int rows = int(m * ny);
-  const unsigned blocks = unsigned(int64_t(n_xb) * ((rows + kWavesPerBlock - 1) / kWavesPerBlock));
+  const unsigned blocks = unsigned(blocks64);
 #define PDIV_MDIV(T)                                                                           \
   hipLaunchKernelGGL(members_divergence_kernel<T>, dim3(blocks), dim3(kBlock), 0, s,           \
                      static_cast<const T*>(u), static_cast<const T*>(v), int(ny), int(nx),     \

@@ -191,6 +191,8 @@ hipError_t launch_kc(const void* p0, const void* p1, const void* p2, const void*
   const int n_strips = (nx - 1 + cells - 1) / cells;
   const int n_bands = (ny - 1 + band_rows - 1) / band_rows;
   const int64_t waves = static_cast<int64_t>(n_strips) * n_bands;
+  if (!launch_fits((waves + kWavesPerBlock - 1) / kWavesPerBlock, kBlock))
+    return hipErrorInvalidConfiguration;
   const unsigned blocks = static_cast<unsigned>((waves + kWavesPerBlock - 1) / kWavesPerBlock);
   if (paired)
     hipLaunchKernelGGL((lcp_kernel_paired<KC, FUSED, T>), dim3(blocks), dim3(kBlock), 0, s,

@@ -315,7 +315,7 @@ hipError_t launch_lcp3d_kc(const Planes6& src, int nz, int ny, int nx, const Ste
   const int n_bands = (ny - 1 + kBandRows3 - 1) / kBandRows3;
   const int64_t waves = int64_t(n_groups) * n_strips * n_bands;
   const int64_t blocks = (waves + kWavesPerBlock - 1) / kWavesPerBlock;
-  if (blocks > 0x7fffffff) return hipErrorInvalidConfiguration;
+  if (!launch_fits(blocks, kBlock)) return hipErrorInvalidConfiguration;
   hipLaunchKernelGGL((lcp3d_kernel<KC, LZ, FUSED, T>), dim3(unsigned(blocks)), dim3(kBlock), 0, s,
                      src, nz, ny, nx, k, iso, out, plane, n_groups, n_strips, n_bands);
   return hipGetLastError();
@@ -342,7 +342,7 @@ hipError_t launch_divergence3d(const void* mu, const void* vu, const void* mv, c
   const int n_xb = int((nx + 63) / 64);
   const int n_yq = int((ny + kWavesPerBlock - 1) / kWavesPerBlock);
   const int64_t blocks = divergence3d_blocks(nz, ny, nx);
-  if (blocks > 0x7fffffff) return hipErrorInvalidConfiguration;
+  if (!launch_fits(blocks, kBlock)) return hipErrorInvalidConfiguration;
   const dim3 grid{unsigned(blocks)}, block{unsigned(kBlock)};
   const int z = int(nz), y = int(ny), x = int(nx);
 #define PDIV_DIV3(T)                                                                         \

@@ -247,6 +247,7 @@ hipError_t launch_mc_sample(const void* mu, const void* vu, const void* mv, cons
                             pdiv_dtype dt, int64_t ny, int64_t nx, int64_t sample,
                             uint64_t seed, float* us, float* vs, hipStream_t s) {
   const int64_t n = ny * nx;
+  if (!launch_fits((n + kBlock - 1) / kBlock, kBlock)) return hipErrorInvalidConfiguration;
   dim3 grid(static_cast<unsigned>((n + kBlock - 1) / kBlock));
   const uint32_t pair = static_cast<uint32_t>(sample >> 1);
   const int odd = static_cast<int>(sample & 1);

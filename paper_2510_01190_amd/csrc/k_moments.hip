@@ -122,12 +122,14 @@ hipError_t launch_typed(const void* u, const void* v, int64_t m, int64_t n, int6
   constexpr int kBlock = 256;
   if (vec4) {
     const int64_t threads = (n + 3) / 4;
+    if (!launch_fits((threads + kBlock - 1) / kBlock, kBlock)) return hipErrorInvalidConfiguration;
     dim3 grid(static_cast<unsigned>((threads + kBlock - 1) / kBlock));
     hipLaunchKernelGGL((moments_kernel<Tin, Tout, 4, 4>), grid, dim3(kBlock), 0, s,
                        static_cast<const Tin*>(u), static_cast<const Tin*>(v),
                        static_cast<int>(m), n, stride, inv_dof, static_cast<Tout*>(mu),
                        static_cast<Tout*>(vu), static_cast<Tout*>(mv), static_cast<Tout*>(vv));
   } else {
+    if (!launch_fits((n + kBlock - 1) / kBlock, kBlock)) return hipErrorInvalidConfiguration;
     dim3 grid(static_cast<unsigned>((n + kBlock - 1) / kBlock));
     hipLaunchKernelGGL((moments_kernel<Tin, Tout, 1, 8>), grid, dim3(kBlock), 0, s,
                        static_cast<const Tin*>(u), static_cast<const Tin*>(v),

@@ -162,7 +162,7 @@ hipError_t launch_sg(const void* u, const void* v, int64_t m, int64_t ny, int64_
   const float inv_dof = static_cast<float>(1.0 / static_cast<double>(m - ddof));
   const int n_strips = int((nx + kStrip - 1) / kStrip);
   const int64_t blocks = speed_gradient_blocks(ny, nx);  // one per tile
-  if (blocks * kBlock > int64_t(0xffffffff)) return hipErrorInvalidConfiguration;
+  if (!launch_fits(blocks, kBlock)) return hipErrorInvalidConfiguration;
   hipLaunchKernelGGL((speed_gradient_moments_kernel<Tin, Tout>), dim3(unsigned(blocks)),
                      dim3(kBlock), 0, s, static_cast<const Tin*>(u), static_cast<const Tin*>(v),
                      int(m), int(ny), int(nx), stride, k, inv_dof, static_cast<Tout*>(mgx),

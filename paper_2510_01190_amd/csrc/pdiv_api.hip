@@ -103,7 +103,8 @@ pdiv_status check_grid3(int64_t nz, int64_t ny, int64_t nx) {
   if (nx > kMaxNx || ny > kMaxNy || nz > kMaxNy)
     return invalid("grid too large (nz, ny > 2^21 or nx > 2^29)");
   if (double(nz) * double(ny) * double(nx) > double(int64_t(1) << 40) ||
-      divergence3d_blocks(nz, ny, nx) > 0x7fffffff || lcp3d_blocks(nz, ny, nx, 1) > (1 << 29))
+      !launch_fits(divergence3d_blocks(nz, ny, nx), 256) ||
+      !launch_fits(lcp3d_blocks(nz, ny, nx, 16), 256))
     return invalid("grid of %lld x %lld x %lld points is too large for one launch",
                    (long long)nz, (long long)ny, (long long)nx);
   return PDIV_OK;
@@ -223,7 +224,7 @@ pdiv_status pdiv_speed_gradient_moments(const void* u_members, const void* v_mem
   if (member_stride == 0) member_stride = n;
   if (member_stride < n)
     return invalid("member_stride %lld < ny*nx %lld", (long long)member_stride, (long long)n);
-  if (speed_gradient_blocks(ny, nx) >= (int64_t(1) << 24))  // 256 threads each, < 2^32 per launch
+  if (!launch_fits(speed_gradient_blocks(ny, nx), 256))
     return invalid("grid of %lld x %lld points is too large for one launch", (long long)ny,
                    (long long)nx);
   return device_status(

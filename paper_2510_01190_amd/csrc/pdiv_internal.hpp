@@ -22,6 +22,12 @@ pdiv_status device_status(hipError_t e, const char* what);
 // Isovalues of one launch, passed by value in the kernel arguments so that
 // every wave reads them from scalar registers.
 constexpr int kIsoChunk = 16;
+// A dispatch covers at most 2^32 - 1 work-items per grid dimension; a 1D
+// launch of `blocks` blocks of `threads` threads fits iff this holds.
+inline bool launch_fits(int64_t blocks, int threads) {
+  return blocks >= 0 && blocks <= int64_t(0xffffffff) / threads;
+}
+
 struct IsoChunk {
   float c[kIsoChunk];
 };
