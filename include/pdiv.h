@@ -132,21 +132,41 @@ pdiv_status pdiv_lcp(const float* div_mean, const float* div_var, int64_t ny, in
                      const float* isovalues_host, int32_t n_iso, float* lcp,
                      int64_t lcp_row_pitch, int64_t lcp_plane_stride, pdiv_stream stream);
 
-/* (d) Monte Carlo LCP, the paper's comparison (Sections 3.2 and 4): draw
- * n_samples samples of the uncertain vectors at every grid point, take the
- * divergence of each sample by Eq. 1 (one-sided at the boundary), and count
- * per cell and isovalue the samples whose four corner divergences are not all
- * on one side of c (>= counts as above); lcp = count / n_samples.
- * Sample s at point p = j*nx + i uses Philox4x32-10 keyed by seed (low word,
- * high word) at counter (p, s/2, 0, 0); output words (w0, w1) feed a
- * Box-Muller pair giving the U and V normals of even s, (w2, w3) those of odd
- * s.  U = mean_u + sqrt(var_u) * z, likewise V.
- * Requires ny*nx < 2^32 and 1 <= n_samples < 2^31.  Other arguments as in
- * pdiv_divergence_gaussian and pdiv_lcp. */
+/* Sampling modes of pdiv_mc_lcp. */
+enum {
+  PDIV_MC_VECTOR = 0, /* the paper's Monte Carlo: sample the vectors (Sections 3.2, 4)  */
+  PDIV_MC_VERTEX = 1  /* test mode: sample each vertex divergence on its own            */
+};
+
+/* (d) Monte Carlo LCP, the paper's comparison (Sections 3.2 and 4): count
+ * per cell and isovalue the samples whose four corner divergences are not
+ * all on one side of c (>= counts as above); lcp = count / n_samples.
+ *
+ * mode PDIV_MC_VECTOR (the paper's): draw n_samples samples of the uncertain
+ * vectors at every grid point and take the divergence of each sample by
+ * Eq. 1 (one-sided at the boundary).  Sample s at point p = j*nx + i uses
+ * Philox4x32-10 keyed by seed (low word, high word) at counter
+ * (p, s/2, 0, 0); output words (w0, w1) feed a Box-Muller pair giving the U
+ * and V normals of even s, (w2, w3) those of odd s.
+ * U = mean_u + sqrt(var_u) * z, likewise V.
+ *
+ * mode PDIV_MC_VERTEX: draw every vertex divergence on its own from
+ * N(mean, var) of Eq. 2-3 (as pdiv_divergence_gaussian computes them), so the
+ * four corners of a cell are independent -- the closed form's model, to
+ * which this mode converges on every cell, boundary cells included (the
+ * vector mode shares grid points between neighbouring one-sided
+ * differences there).  Sample s at vertex p uses counter (p, s/4, 1, 0);
+ * Box-Muller on (w0, w1) gives the normals of samples 4q and 4q+1, on
+ * (w2, w3) those of 4q+2 and 4q+3; value = mean + sqrt(var) * z.
+ *
+ * Requires ny*nx < 2^32 and 1 <= n_samples < 2^31; any other mode is
+ * PDIV_ERR_INVALID.  Other arguments as in pdiv_divergence_gaussian and
+ * pdiv_lcp; lcp is dense [n_iso][ny-1][nx-1]. */
 pdiv_status pdiv_mc_lcp(const void* mean_u, const void* var_u, const void* mean_v,
                         const void* var_v, pdiv_dtype in_dtype, int64_t ny, int64_t nx,
                         double dx, double dy, const float* isovalues_host, int32_t n_iso,
-                        int64_t n_samples, uint64_t seed, float* lcp, pdiv_stream stream);
+                        int64_t n_samples, uint64_t seed, uint32_t mode, float* lcp,
+                        pdiv_stream stream);
 
 /* (b)+(c) fused: Eq. 2-3 and the closed-form LCP in one pass over the moment
  * planes; the divergence Gaussians never leave the chip.  Gives bitwise the

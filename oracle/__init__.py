@@ -17,6 +17,7 @@ from .pdiv_oracle import (  # noqa: F401
     speed_gradient,
     speed_gradient_moments,
     divergence_gaussian,
+    divergence_gaussian_f32,
     vertex_probs,
     lcp,
     philox4x32_10,
@@ -29,6 +30,7 @@ from .pdiv_oracle import (  # noqa: F401
 )
 from .pdiv_oracle3d import (  # noqa: F401
     divergence_gaussian_3d,
+    divergence_gaussian_3d_f32,
     fd_divergence_3d,
     lcp_3d,
     crossed_3d,

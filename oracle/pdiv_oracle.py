@@ -18,6 +18,9 @@ Parity status per function:
                      identical members (zero variance)
   divergence_gaussian pinned (Fig. 2 worked example, numpy.gradient, closed forms,
                       brute-force sampling)
+  divergence_gaussian_f32  pinned to divergence_gaussian: equal on inputs where
+                      every float32 operation is exact, within float32
+                      rounding elsewhere
   lcp                pinned (marching-squares limit, i.i.d. closed form, symmetry,
                       brute-force sampling, mpmath tails)
   philox4x32_10      pinned (published known-answer vectors, rocRAND routine)
@@ -26,8 +29,10 @@ Parity status per function:
                      closed loops, every point shared by two segments; crossed
                      cells = the zero-variance LCP indicator; saddles)
   spaghetti          marching_squares of fd_divergence per member
-  mc_lcp             pinned statistically against lcp on interior cells; a single
-                     MC draw has no closed form to pin to.
+  mc_lcp             vector mode: pinned statistically against lcp on interior
+                     cells; vertex mode: against lcp on every cell, and exactly
+                     against the marching-squares indicator at zero variance.
+                     A single MC draw has no closed form to pin to.
 """
 
 from __future__ import annotations
@@ -272,6 +277,51 @@ def mc_sample_field(mean_u, var_u, mean_v, var_v, s: int, seed: int):
     return u, v
 
 
+def _vertex_normals(n_points: int, s: int, seed: int):
+    """Standard normal of sample s at vertices 0..n_points-1 for vertex-level
+    sampling: counter (vertex index p, s // 4, 1, 0) -- the third word 1 keeps
+    these streams apart from the vector-level ones -- with Box-Muller on
+    (w0, w1) giving samples 4q and 4q+1 and on (w2, w3) samples 4q+2, 4q+3."""
+    p = np.arange(n_points, dtype=np.uint64).astype(np.uint32)
+    q = np.full(n_points, s // 4, np.uint32)
+    one = np.ones(n_points, np.uint32)
+    zero = np.zeros(n_points, np.uint32)
+    w0, w1, w2, w3 = philox4x32_10(p, q, one, zero, seed & 0xFFFFFFFF, (seed >> 32) & 0xFFFFFFFF)
+    pair = box_muller(w0, w1) if (s % 4) < 2 else box_muller(w2, w3)
+    return pair[s % 2]
+
+
+def divergence_gaussian_f32(mean_u, var_u, mean_v, var_v, dx: float, dy: float):
+    """Eq. 2 and Eq. 3 with every operation rounded to float32, in the order
+    mean = (mu_r - mu_l) cm_x + (mv_r - mv_l) cm_y and
+    var = (var_r + var_l) cv_x + (var_r + var_l) cv_y, where cm = 1/(2h)
+    inside and 1/h on the boundary and cv = 1/(4h^2) or 1/h^2, each rounded
+    once from float64.  Returns float32 planes: the divergence Gaussians a
+    float32 implementation that rounds in this order holds, bit for bit --
+    the input for checking its later steps (the crossing decisions of the
+    Monte Carlo, the relative accuracy of tiny LCP values) in its own
+    precision."""
+    f = np.float32
+    mu_u, s2_u = np.asarray(mean_u, f), np.asarray(var_u, f)
+    mu_v, s2_v = np.asarray(mean_v, f), np.asarray(var_v, f)
+    ny, nx = mu_u.shape
+    i, j = np.arange(nx), np.arange(ny)
+    xl, xr = np.maximum(i - 1, 0), np.minimum(i + 1, nx - 1)
+    yl, yr = np.maximum(j - 1, 0), np.minimum(j + 1, ny - 1)
+    bx, by = (i == 0) | (i == nx - 1), (j == 0) | (j == ny - 1)
+    cxm = np.where(bx, f(1.0 / dx), f(1.0 / (2.0 * dx))).astype(f)[None, :]
+    cxv = np.where(bx, f(1.0 / (dx * dx)), f(1.0 / (4.0 * dx * dx))).astype(f)[None, :]
+    cym = np.where(by, f(1.0 / dy), f(1.0 / (2.0 * dy))).astype(f)[:, None]
+    cyv = np.where(by, f(1.0 / (dy * dy)), f(1.0 / (4.0 * dy * dy))).astype(f)[:, None]
+    mx = (mu_u[:, xr] - mu_u[:, xl]) * cxm
+    my = (mu_v[yr, :] - mu_v[yl, :]) * cym
+    vx = (s2_u[:, xr] + s2_u[:, xl]) * cxv
+    vy = (s2_v[yr, :] + s2_v[yl, :]) * cyv
+    mean = mx + my
+    var = vx + vy
+    return mean, var
+
+
 def _crossed(d, c):
     """Cells whose four corners are not all on one side of c (>= is above)."""
     up = d >= c
@@ -280,8 +330,15 @@ def _crossed(d, c):
 
 
 def mc_lcp(mean_u, var_u, mean_v, var_v, dx: float, dy: float, isovalues,
-           n_samples: int, seed: int, precision: str = "f64"):
-    """Vector-level MC LCP maps [K][ny-1][nx-1] (crossing counts / n_samples).
+           n_samples: int, seed: int, precision: str = "f64", mode: str = "vector"):
+    """MC LCP maps [K][ny-1][nx-1] (crossing counts / n_samples).
+
+    mode="vector" (the paper's sampling, Sections 3.2 and 4): each sample
+    draws U and V at every grid point and takes the divergence by Eq. 1.
+    mode="vertex": each sample draws every vertex divergence on its own from
+    N(mu, var) of Eq. 2-3, so the four corners of a cell are independent even
+    where the one-sided boundary differences share grid points -- the closed
+    form's model, to which this mode converges on every cell.
 
     precision="f64": every step in float64 (the definition).
     precision="f32": the same steps with the sample field, the divergence and
@@ -292,6 +349,28 @@ def mc_lcp(mean_u, var_u, mean_v, var_v, dx: float, dy: float, isovalues,
     mu_u = np.asarray(mean_u, np.float64)
     ny, nx = mu_u.shape
     counts = np.zeros((iso.size, ny - 1, nx - 1), np.int64)
+    if mode == "vertex":
+        if precision == "f64":
+            m, v = divergence_gaussian(mean_u, var_u, mean_v, var_v, dx, dy)
+            sd = np.sqrt(v)
+            for s in range(n_samples):
+                d = m + sd * _vertex_normals(ny * nx, s, seed).reshape(ny, nx)
+                for k, c in enumerate(iso):
+                    counts[k] += _crossed(d, c)
+        elif precision == "f32":
+            f = np.float32
+            m, v = divergence_gaussian_f32(mean_u, var_u, mean_v, var_v, dx, dy)
+            sd = np.sqrt(v)
+            for s in range(n_samples):
+                z = _vertex_normals(ny * nx, s, seed).reshape(ny, nx).astype(f)
+                d = m + f(sd * z)
+                for k, c in enumerate(iso.astype(f)):
+                    counts[k] += _crossed(d, c)
+        else:
+            raise ValueError(precision)
+        return counts / float(n_samples)
+    if mode != "vector":
+        raise ValueError(mode)
     if precision == "f64":
         for s in range(n_samples):
             u, v = mc_sample_field(mean_u, var_u, mean_v, var_v, s, seed)

@@ -22,6 +22,9 @@ Parity status per function:
                           variances at interior, face, edge and corner
                           vertices, linear fields, reduction to the 2D
                           oracle, brute-force sampling)
+  divergence_gaussian_3d_f32  pinned to divergence_gaussian_3d: equal where
+                          every float32 operation is exact, within float32
+                          rounding elsewhere
   lcp_3d                  pinned (marching-cubes limit, i.i.d. closed form,
                           symmetry, range, far isovalues, brute force)
   mc_lcp_3d               pinned statistically against lcp_3d on interior
@@ -75,6 +78,34 @@ def divergence_gaussian_3d(mean_u, var_u, mean_v, var_v, mean_w, var_w, dx: floa
         out_m = m if out_m is None else out_m + m
         out_v = v if out_v is None else out_v + v
     return out_m, out_v
+
+
+def divergence_gaussian_3d_f32(mean_u, var_u, mean_v, var_v, mean_w, var_w, dx: float,
+                               dy: float, dz: float):
+    """divergence_gaussian_3d with every operation rounded to float32 in the
+    order mean = (mx + my) + mz, var = (vx + vy) + vz, where per axis
+    m = (mu_r - mu_l) cm and v = (var_r + var_l) cv, cm = 1/(2h) inside and
+    1/h on the two boundary planes, cv = 1/(4h^2) or 1/h^2, each coefficient
+    rounded once from float64.  Float32 [nz][ny][nx] planes: the divergence
+    Gaussians, bit for bit, of a float32 implementation that rounds in this
+    order."""
+    f = np.float32
+    parts_m, parts_v = [], []
+    for mu, var, h, axis in ((mean_u, var_u, dx, 2), (mean_v, var_v, dy, 1),
+                             (mean_w, var_w, dz, 0)):
+        mu = np.asarray(mu, f)
+        var = np.asarray(var, f)
+        n = mu.shape[axis]
+        i = np.arange(n)
+        lo, hi = np.maximum(i - 1, 0), np.minimum(i + 1, n - 1)
+        bd = (i == 0) | (i == n - 1)
+        shape = [1, 1, 1]
+        shape[axis] = n
+        cm = np.where(bd, f(1.0 / h), f(1.0 / (2.0 * h))).astype(f).reshape(shape)
+        cv = np.where(bd, f(1.0 / (h * h)), f(1.0 / (4.0 * h * h))).astype(f).reshape(shape)
+        parts_m.append((np.take(mu, hi, axis) - np.take(mu, lo, axis)) * cm)
+        parts_v.append((np.take(var, hi, axis) + np.take(var, lo, axis)) * cv)
+    return (parts_m[0] + parts_m[1]) + parts_m[2], (parts_v[0] + parts_v[1]) + parts_v[2]
 
 
 def fd_divergence_3d(u, v, w, dx: float, dy: float, dz: float):

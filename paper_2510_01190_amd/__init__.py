@@ -79,7 +79,8 @@ _SIGS = {
     "pdiv_lcp_3d": [_p, _p, _i64, _i64, _i64, _fp, _i32, _p, _p],
     "pdiv_lcp_3d_from_moments": [_p, _p, _p, _p, _p, _p, _c.c_int, _i64, _i64, _i64, _f64, _f64,
                                  _f64, _fp, _i32, _p, _p],
-    "pdiv_mc_lcp": [_p, _p, _p, _p, _c.c_int, _i64, _i64, _f64, _f64, _fp, _i32, _i64, _u64, _p, _p],
+    "pdiv_mc_lcp": [_p, _p, _p, _p, _c.c_int, _i64, _i64, _f64, _f64, _fp, _i32, _i64, _u64,
+                    _c.c_uint32, _p, _p],
     "pdiv_lcp_from_moments": [_p, _p, _p, _p, _c.c_int, _i64, _i64, _f64, _f64, _fp, _i32, _p,
                               _i64, _i64, _p],
     "pdiv_mc_sample_field": [_p, _p, _p, _p, _c.c_int, _i64, _i64, _i64, _u64, _p, _p, _p],
@@ -379,17 +380,23 @@ def lcp_from_moments(mean_u, var_u, mean_v, var_v, isovalues, dx: float = 1.0,
     return out
 
 
+MC_MODES = {"vector": 0, "vertex": 1}
+
+
 def mc_lcp(mean_u, var_u, mean_v, var_v, isovalues, n_samples: int, seed: int,
-           dx: float = 1.0, dy: float = 1.0, out=None):
-    """Vector-level Monte Carlo LCP [K][ny-1][nx-1]."""
+           dx: float = 1.0, dy: float = 1.0, out=None, mode: str = "vector"):
+    """Monte Carlo LCP [K][ny-1][nx-1]: mode "vector" samples the vectors (the
+    paper's comparison), "vertex" each vertex divergence on its own."""
     torch = _torch()
+    if mode not in MC_MODES:
+        raise ValueError(f"mode must be one of {sorted(MC_MODES)}")
     ptrs, ny, nx, dt = _moment_ptrs(mean_u, var_u, mean_v, var_v)
     iso, ip = _iso_arr(isovalues)
     if out is None:
         out = torch.empty((iso.size, ny - 1, nx - 1), dtype=torch.float32, device=mean_u.device)
     po = _dev(out, "out", (iso.size, ny - 1, nx - 1), torch.float32)
     _check(lib().pdiv_mc_lcp(*ptrs, dt, ny, nx, dx, dy, ip, iso.size, n_samples,
-                             seed & 0xFFFFFFFFFFFFFFFF, po, _stream()))
+                             seed & 0xFFFFFFFFFFFFFFFF, MC_MODES[mode], po, _stream()))
     return out
 
 
@@ -460,22 +467,54 @@ class Batch:
             pass
 
 
+def _host_plane(a):
+    """A host plane as (contiguous array, dtype code): numpy float32 or
+    float16, or a torch CPU tensor of float32, float16 or bfloat16 (passed
+    as its raw 16-bit words)."""
+    if hasattr(a, "is_cuda"):  # torch tensor
+        if a.is_cuda:
+            raise ValueError("put_field takes host planes, not device tensors")
+        code = _dtype_code(a)
+        a = a.contiguous()
+        return (a.view(_torch().int16).numpy() if code == 2 else a.numpy()), code
+    a = np.ascontiguousarray(a)
+    codes = {np.dtype(np.float32): 0, np.dtype(np.float16): 1}
+    if a.dtype not in codes:
+        raise TypeError(f"unsupported host dtype {a.dtype}; use float32 or float16 "
+                        "(bfloat16 as a torch CPU tensor)")
+    return a, codes[a.dtype]
+
+
 class Server:
-    """Continuous-batching LCP server over device-resident fields."""
+    """Continuous-batching LCP server over device-resident fields.
+
+    The binding remembers each field's grid, so that submit_lcp can check the
+    output tensor: the C call takes no size for it and writes
+    n_iso*(ny-1)*(nx-1) floats."""
 
     def __init__(self, hbm_budget: int, n_streams: int = 2):
         h = _p()
         _check(lib().pdiv_server_create(hbm_budget, n_streams, _c.byref(h)))
         self._h = h
+        self._grid = {}
 
     def put_field(self, fid: int, mean_u, var_u, mean_v, var_v, dx=1.0, dy=1.0) -> int:
-        """Host numpy planes (float32/float16) -> ticket."""
-        arrs = [np.ascontiguousarray(a) for a in (mean_u, var_u, mean_v, var_v)]
-        code = {np.dtype(np.float32): 0, np.dtype(np.float16): 1}[arrs[0].dtype]
+        """Host planes [ny][nx] of one dtype and shape (numpy float32/float16,
+        or torch CPU float32/float16/bfloat16) -> ticket.  The planes are
+        copied before the call returns."""
+        planes = [_host_plane(a) for a in (mean_u, var_u, mean_v, var_v)]
+        arrs = [a for a, _ in planes]
+        code = planes[0][1]
+        if arrs[0].ndim != 2:
+            raise ValueError(f"mean_u must be a [ny][nx] plane, got shape {arrs[0].shape}")
+        for (a, c), name in zip(planes[1:], ("var_u", "mean_v", "var_v")):
+            if c != code or a.shape != arrs[0].shape:
+                raise ValueError(f"{name} must match mean_u's shape {arrs[0].shape} and dtype")
         ny, nx = arrs[0].shape
         t = _u64()
         _check(lib().pdiv_server_put_field(self._h, fid, *[_p(a.ctypes.data) for a in arrs],
                                            code, ny, nx, dx, dy, _c.byref(t)))
+        self._grid[fid] = (ny, nx)
         return t.value
 
     def reserve_staging(self, max_points: int, count: int, dtype=np.float32):
@@ -484,8 +523,22 @@ class Server:
         code = {np.dtype(np.float32): 0, np.dtype(np.float16): 1}[np.dtype(dtype)]
         _check(lib().pdiv_server_reserve_staging(self._h, max_points, code, count))
 
-    def submit_lcp(self, fid: int, isovalues, out) -> int:
+    def submit_lcp(self, fid: int, isovalues, out, sync: bool = True) -> int:
+        """Slider request: LCP maps of resident field fid at the isovalues into
+        out, a contiguous float32 device tensor [n_iso][ny-1][nx-1] that must
+        stay alive until the ticket completes.  The server writes it from its
+        own streams, so work still pending on out in torch's current stream
+        must finish first: with sync (the default) the current stream is
+        synchronised before the request is submitted; pass sync=False only
+        when no work on out can be pending."""
         iso, ip = _iso_arr(isovalues)
+        grid = self._grid.get(fid)
+        if grid is None:
+            raise PdivError(1, f"field id {fid} was never put on this server")
+        ny, nx = grid
+        _dev(out, "out", (iso.size, ny - 1, nx - 1), _torch().float32)
+        if sync:
+            _torch().cuda.current_stream().synchronize()
         t = _u64()
         _check(lib().pdiv_server_submit_lcp(self._h, fid, ip, iso.size, _p(out.data_ptr()),
                                             _c.byref(t)))

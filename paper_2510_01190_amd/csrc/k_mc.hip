@@ -11,6 +11,12 @@
 // registers.  Samples are regenerated from their counters, never stored, so
 // neighbouring tiles see identical values at shared points.  This path is
 // bound by integer multiplies and transcendentals, not by memory.
+//
+// Vertex-level sampling (PDIV_MC_VERTEX) draws each vertex divergence on its
+// own from the Gaussian of Eq. 2-3 instead, so the four corners of every cell
+// are independent -- the closed form's model, which it converges to on every
+// cell, boundary cells included (where the paper's vector-level sampling
+// shares grid points between the one-sided differences).
 #include "pdiv_device.hpp"
 #include "pdiv_internal.hpp"
 
@@ -173,6 +179,122 @@ __global__ __launch_bounds__(kBlock) void mc_kernel(const T* __restrict__ mu,
   }
 }
 
+// Vertex-level sampling.  Each thread holds the divergence Gaussians of its
+// vertices of the tile (Eq. 2-3 evaluated as in the closed-form path).  Per
+// group of four samples one Philox4x32-10 call per vertex, at counter
+// (vertex index, group, 1, 0), gives four normals by two Box-Muller pairs:
+// (w0, w1) for samples 4g and 4g+1, (w2, w3) for 4g+2 and 4g+3.
+template <int KC, typename T>
+__global__ __launch_bounds__(kBlock) void mc_vertex_kernel(const T* __restrict__ mu,
+                                                           const T* __restrict__ vu,
+                                                           const T* __restrict__ mv,
+                                                           const T* __restrict__ vv, int ny,
+                                                           int nx, StencilCoef k, IsoChunk iso,
+                                                           int n_store, int n_samples,
+                                                           uint32_t key0, uint32_t key1,
+                                                           float* __restrict__ out,
+                                                           int64_t plane) {
+  __shared__ float sD[4][NV];
+
+  const int tid = threadIdx.x;
+  const int x0 = blockIdx.x * TX;
+  const int y0 = blockIdx.y * TY;
+
+  float dm[VPT], ds[VPT];
+  uint32_t vid[VPT];
+  bool vin[VPT];
+#pragma unroll
+  for (int m = 0; m < VPT; ++m) {
+    const int v = tid + m * kBlock;
+    const int gx = x0 + v % VX;
+    const int gy = y0 + v / VX;
+    vin[m] = (v < NV) & (gx < nx) & (gy < ny);
+    dm[m] = ds[m] = 0.0f;
+    vid[m] = 0;
+    if (vin[m]) {
+      const int xl = gx > 0 ? gx - 1 : 0;
+      const int xr = gx < nx - 1 ? gx + 1 : nx - 1;
+      const int yl = gy > 0 ? gy - 1 : 0;
+      const int yr = gy < ny - 1 ? gy + 1 : ny - 1;
+      const bool bx = (gx == 0) | (gx == nx - 1);
+      const bool by = (gy == 0) | (gy == ny - 1);
+      const int64_t row = static_cast<int64_t>(gy) * nx;
+      const int64_t rl = static_cast<int64_t>(yl) * nx, rr = static_cast<int64_t>(yr) * nx;
+      const DivGauss g =
+          div_gauss(ld(mu, row + xl), ld(mu, row + xr), ld(vu, row + xl), ld(vu, row + xr),
+                    ld(mv, rl + gx), ld(mv, rr + gx), ld(vv, rl + gx), ld(vv, rr + gx),
+                    bx ? k.cxm_bd : k.cxm_in, bx ? k.cxv_bd : k.cxv_in,
+                    by ? k.cym_bd : k.cym_in, by ? k.cyv_bd : k.cyv_in);
+      dm[m] = g.mean;
+      ds[m] = __fsqrt_rn(g.var);
+      vid[m] = static_cast<uint32_t>(row + gx);
+    }
+  }
+
+  uint32_t cnt[CPT][KC];
+#pragma unroll
+  for (int m = 0; m < CPT; ++m)
+#pragma unroll
+    for (int q = 0; q < KC; ++q) cnt[m][q] = 0;
+
+  const int n_groups = (n_samples + 3) >> 2;
+  for (int gr = 0; gr < n_groups; ++gr) {
+#pragma unroll
+    for (int m = 0; m < VPT; ++m) {
+      if (vin[m]) {
+        const int v = tid + m * kBlock;
+        U4 c;
+        c.x = vid[m];
+        c.y = static_cast<uint32_t>(gr);
+        c.z = 1u;
+        c.w = 0u;
+        const U4 w = philox4x32_10(c, key0, key1);
+        const F2 z01 = box_muller(w.x, w.y);
+        const F2 z23 = box_muller(w.z, w.w);
+        sD[0][v] = draw(dm[m], ds[m], z01.x);
+        sD[1][v] = draw(dm[m], ds[m], z01.y);
+        sD[2][v] = draw(dm[m], ds[m], z23.x);
+        sD[3][v] = draw(dm[m], ds[m], z23.y);
+      }
+    }
+    __syncthreads();
+#pragma unroll
+    for (int m = 0; m < CPT; ++m) {
+      const int cidx = tid + m * kBlock;
+      const int cx = cidx % TX, cy = cidx / TX;
+      if (x0 + cx < nx - 1 && y0 + cy < ny - 1) {
+        const int v00 = cy * VX + cx;
+#pragma unroll
+        for (int s = 0; s < 4; ++s) {
+          if (4 * gr + s < n_samples) {
+            const float d0 = sD[s][v00], d1 = sD[s][v00 + 1];
+            const float d2 = sD[s][v00 + VX], d3 = sD[s][v00 + VX + 1];
+            const float lo = fminf(fminf(d0, d1), fminf(d2, d3));
+            const float hi = fmaxf(fmaxf(d0, d1), fmaxf(d2, d3));
+#pragma unroll
+            for (int q = 0; q < KC; ++q)
+              cnt[m][q] += static_cast<uint32_t>((lo < iso.c[q]) & (hi >= iso.c[q]));
+          }
+        }
+      }
+    }
+    __syncthreads();
+  }
+
+  const float fs = static_cast<float>(n_samples);
+#pragma unroll
+  for (int m = 0; m < CPT; ++m) {
+    const int cidx = tid + m * kBlock;
+    const int gx = x0 + cidx % TX, gy = y0 + cidx / TX;
+    if (gx < nx - 1 && gy < ny - 1) {
+      float* o = out + static_cast<int64_t>(gy) * (nx - 1) + gx;
+#pragma unroll
+      for (int q = 0; q < KC; ++q)
+        if (q < n_store) o[q * plane] = static_cast<float>(cnt[m][q]) / fs;
+    }
+  }
+}
+
 template <typename T>
 __global__ __launch_bounds__(kBlock) void mc_sample_kernel(const T* __restrict__ mu,
                                                            const T* __restrict__ vu,
@@ -198,47 +320,57 @@ __global__ __launch_bounds__(kBlock) void mc_sample_kernel(const T* __restrict__
 template <int KC, typename T>
 hipError_t launch_kc(const void* mu, const void* vu, const void* mv, const void* vv, int ny,
                      int nx, const StencilCoef& k, const IsoChunk& iso, int kc, int n_samples,
-                     uint64_t seed, float* out, hipStream_t s) {
-  dim3 grid(static_cast<unsigned>((nx - 1 + TX - 1) / TX),
-            static_cast<unsigned>((ny - 1 + TY - 1) / TY));
+                     uint64_t seed, bool vertex, float* out, hipStream_t s) {
+  dim3 grid(static_cast<unsigned>(mc_tiles_x(nx)), static_cast<unsigned>(mc_tiles_y(ny)));
   const int64_t plane = static_cast<int64_t>(ny - 1) * (nx - 1);
-  hipLaunchKernelGGL((mc_kernel<KC, T>), grid, dim3(kBlock), 0, s,
-                     static_cast<const T*>(mu), static_cast<const T*>(vu),
-                     static_cast<const T*>(mv), static_cast<const T*>(vv), ny, nx, k, iso, kc,
-                     n_samples, static_cast<uint32_t>(seed), static_cast<uint32_t>(seed >> 32),
-                     out, plane);
+  if (vertex)
+    hipLaunchKernelGGL((mc_vertex_kernel<KC, T>), grid, dim3(kBlock), 0, s,
+                       static_cast<const T*>(mu), static_cast<const T*>(vu),
+                       static_cast<const T*>(mv), static_cast<const T*>(vv), ny, nx, k, iso, kc,
+                       n_samples, static_cast<uint32_t>(seed),
+                       static_cast<uint32_t>(seed >> 32), out, plane);
+  else
+    hipLaunchKernelGGL((mc_kernel<KC, T>), grid, dim3(kBlock), 0, s,
+                       static_cast<const T*>(mu), static_cast<const T*>(vu),
+                       static_cast<const T*>(mv), static_cast<const T*>(vv), ny, nx, k, iso, kc,
+                       n_samples, static_cast<uint32_t>(seed),
+                       static_cast<uint32_t>(seed >> 32), out, plane);
   return hipGetLastError();
 }
 
 template <typename T>
 hipError_t launch_typed(const void* mu, const void* vu, const void* mv, const void* vv, int ny,
                         int nx, const StencilCoef& k, const IsoChunk& iso, int kc,
-                        int n_samples, uint64_t seed, float* out, hipStream_t s) {
+                        int n_samples, uint64_t seed, bool vertex, float* out, hipStream_t s) {
   // isovalue counts are bucketed to 1, 2, 4, 8, 16; the caller pads the
   // unused isovalue slots and only the first kc planes are stored
   const int kb = kc <= 1 ? 1 : kc <= 2 ? 2 : kc <= 4 ? 4 : kc <= 8 ? 8 : 16;
   switch (kb) {
-    case 1: return launch_kc<1, T>(mu, vu, mv, vv, ny, nx, k, iso, kc, n_samples, seed, out, s);
-    case 2: return launch_kc<2, T>(mu, vu, mv, vv, ny, nx, k, iso, kc, n_samples, seed, out, s);
-    case 4: return launch_kc<4, T>(mu, vu, mv, vv, ny, nx, k, iso, kc, n_samples, seed, out, s);
-    case 8: return launch_kc<8, T>(mu, vu, mv, vv, ny, nx, k, iso, kc, n_samples, seed, out, s);
-    case 16: return launch_kc<16, T>(mu, vu, mv, vv, ny, nx, k, iso, kc, n_samples, seed, out, s);
+    case 1: return launch_kc<1, T>(mu, vu, mv, vv, ny, nx, k, iso, kc, n_samples, seed, vertex, out, s);
+    case 2: return launch_kc<2, T>(mu, vu, mv, vv, ny, nx, k, iso, kc, n_samples, seed, vertex, out, s);
+    case 4: return launch_kc<4, T>(mu, vu, mv, vv, ny, nx, k, iso, kc, n_samples, seed, vertex, out, s);
+    case 8: return launch_kc<8, T>(mu, vu, mv, vv, ny, nx, k, iso, kc, n_samples, seed, vertex, out, s);
+    case 16: return launch_kc<16, T>(mu, vu, mv, vv, ny, nx, k, iso, kc, n_samples, seed, vertex, out, s);
   }
   return hipErrorInvalidValue;
 }
 
 }  // namespace
 
+int64_t mc_tiles_x(int64_t nx) { return (nx - 1 + TX - 1) / TX; }
+int64_t mc_tiles_y(int64_t ny) { return (ny - 1 + TY - 1) / TY; }
+
 hipError_t launch_mc(const void* mu, const void* vu, const void* mv, const void* vv,
                      pdiv_dtype dt, int64_t ny, int64_t nx, const StencilCoef& k,
                      const IsoChunk& iso, int kc, int64_t n_samples, uint64_t seed,
-                     float* lcp_k0, hipStream_t s) {
+                     uint32_t mode, float* lcp_k0, hipStream_t s) {
   const int iny = static_cast<int>(ny), inx = static_cast<int>(nx);
   const int ns = static_cast<int>(n_samples);
+  const bool vx = mode == PDIV_MC_VERTEX;
   switch (dt) {
-    case PDIV_F32: return launch_typed<float>(mu, vu, mv, vv, iny, inx, k, iso, kc, ns, seed, lcp_k0, s);
-    case PDIV_F16: return launch_typed<__half>(mu, vu, mv, vv, iny, inx, k, iso, kc, ns, seed, lcp_k0, s);
-    case PDIV_BF16: return launch_typed<bf16_t>(mu, vu, mv, vv, iny, inx, k, iso, kc, ns, seed, lcp_k0, s);
+    case PDIV_F32: return launch_typed<float>(mu, vu, mv, vv, iny, inx, k, iso, kc, ns, seed, vx, lcp_k0, s);
+    case PDIV_F16: return launch_typed<__half>(mu, vu, mv, vv, iny, inx, k, iso, kc, ns, seed, vx, lcp_k0, s);
+    case PDIV_BF16: return launch_typed<bf16_t>(mu, vu, mv, vv, iny, inx, k, iso, kc, ns, seed, vx, lcp_k0, s);
   }
   return hipErrorInvalidValue;
 }

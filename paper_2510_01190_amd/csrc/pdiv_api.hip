@@ -77,11 +77,16 @@ pdiv_status check_layout(int64_t row_pitch, int64_t plane_stride, int64_t ny, in
   if (pitch < cells || pitch > (int64_t(1) << 52))
     return invalid("lcp_row_pitch must be 0 or in [nx - 1, 2^52] (got %lld, nx=%lld)",
                    (long long)row_pitch, (long long)nx);
-  const int64_t plane = plane_stride == 0 ? rows * pitch : plane_stride;
+  // rows x pitch is bounded in double (exact up to 2^53, so the comparison is
+  // exact) before the int64 product is formed
+  if (double(rows) * double(pitch) > double(int64_t(1) << 52))
+    return invalid("LCP output layout is too large (rows x pitch > 2^52 floats)");
+  const int64_t map = rows * pitch;
+  const int64_t plane = plane_stride == 0 ? map : plane_stride;
   if (plane < 0 || plane > (int64_t(1) << 52))
     return invalid("lcp_plane_stride must be 0 or in [1, 2^52] (got %lld)",
                    (long long)plane_stride);
-  const bool apart = plane >= rows * pitch;
+  const bool apart = plane >= map;
   const bool interleaved = plane >= cells && pitch >= int64_t(n_iso) * plane;
   if (!apart && !interleaved)
     return invalid("lcp_plane_stride %lld with lcp_row_pitch %lld makes the %d maps of "
@@ -436,7 +441,8 @@ pdiv_status pdiv_lcp_3d_from_moments(const void* mean_u, const void* var_u, cons
 pdiv_status pdiv_mc_lcp(const void* mean_u, const void* var_u, const void* mean_v,
                         const void* var_v, pdiv_dtype in_dtype, int64_t ny, int64_t nx,
                         double dx, double dy, const float* isovalues_host, int32_t n_iso,
-                        int64_t n_samples, uint64_t seed, float* lcp, pdiv_stream stream) {
+                        int64_t n_samples, uint64_t seed, uint32_t mode, float* lcp,
+                        pdiv_stream stream) {
   g_last_error.clear();
   PDIV_NONNULL(mean_u);
   PDIV_NONNULL(var_u);
@@ -451,6 +457,11 @@ pdiv_status pdiv_mc_lcp(const void* mean_u, const void* var_u, const void* mean_
     return invalid("Monte Carlo needs ny*nx < 2^32 (point index is a 32-bit counter word)");
   if (n_samples < 1 || n_samples >= (int64_t(1) << 31))
     return invalid("n_samples must be in [1, 2^31) (got %lld)", (long long)n_samples);
+  if (mode != PDIV_MC_VECTOR && mode != PDIV_MC_VERTEX)
+    return invalid("mode must be PDIV_MC_VECTOR (0) or PDIV_MC_VERTEX (1) (got %u)", mode);
+  if (!launch_fits(mc_tiles_x(nx), 256) || !launch_fits(mc_tiles_y(ny), 256))
+    return invalid("grid of %lld x %lld points is too large for one Monte Carlo launch",
+                   (long long)ny, (long long)nx);
   const StencilCoef k = make_coef(dx, dy);
   const int64_t plane = (ny - 1) * (nx - 1);
   for (int32_t k0 = 0; k0 < n_iso; k0 += kIsoChunk) {
@@ -458,7 +469,7 @@ pdiv_status pdiv_mc_lcp(const void* mean_u, const void* var_u, const void* mean_
     IsoChunk c;
     for (int q = 0; q < kIsoChunk; ++q) c.c[q] = isovalues_host[k0 + (q < kc ? q : kc - 1)];
     hipError_t e = launch_mc(mean_u, var_u, mean_v, var_v, in_dtype, ny, nx, k, c, kc,
-                             n_samples, seed, lcp + k0 * plane,
+                             n_samples, seed, mode, lcp + k0 * plane,
                              static_cast<hipStream_t>(stream));
     if (e != hipSuccess) return device_status(e, "Monte Carlo launch");
   }

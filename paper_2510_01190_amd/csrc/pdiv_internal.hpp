@@ -77,10 +77,15 @@ hipError_t launch_lcp(bool fused, const void* p0, const void* p1, const void* p2
                       const StencilCoef& k, const IsoChunk& iso, int kc, float* lcp_k0,
                       int64_t pitch, int64_t plane, LcpShape shape, hipStream_t s);
 
+// Monte Carlo LCP, mode PDIV_MC_VECTOR (the paper's sampling of the vectors)
+// or PDIV_MC_VERTEX (each vertex divergence drawn on its own).  The launch is
+// mc_tiles_x(nx) x mc_tiles_y(ny) blocks of 256 threads.
+int64_t mc_tiles_x(int64_t nx);
+int64_t mc_tiles_y(int64_t ny);
 hipError_t launch_mc(const void* mu, const void* vu, const void* mv, const void* vv,
                      pdiv_dtype dt, int64_t ny, int64_t nx, const StencilCoef& k,
                      const IsoChunk& iso, int kc, int64_t n_samples, uint64_t seed,
-                     float* lcp_k0, hipStream_t s);
+                     uint32_t mode, float* lcp_k0, hipStream_t s);
 
 hipError_t launch_mc_sample(const void* mu, const void* vu, const void* mv, const void* vv,
                             pdiv_dtype dt, int64_t ny, int64_t nx, int64_t sample,

@@ -23,6 +23,7 @@ from .fields import (  # noqa: F401
     config_c1,
     config_c2,
     config_c3,
+    config_c3_low_spread,
     config_c4,
     batch_sizes,
     request_stream,

@@ -198,6 +198,19 @@ def config_c3(n: int = 8192):
     return f
 
 
+def config_c3_low_spread(n: int = 8192):
+    """The precision sweep's field (same seed, so the same features) with a
+    small spread, sigma ~ U[0.002, 0.02]: most cells then sit deep in the
+    LCP tails (near 0) or are crossed with near certainty (near 1), the cells
+    whose accuracy a cancellation-free evaluation must keep.  16 isovalues at
+    divergence quantiles linspace(0.01, 0.99, 16)."""
+    f = gen_moments(n, n, SEED_BASE + 3, sigma=(0.002, 0.02))
+    div = analytic_divergence(f["features"], n, n)
+    f.update(isovalues=quantile_isovalues(div, np.linspace(0.01, 0.99, 16)),
+             name=f"c3_low_spread_{n}x{n}_k16")
+    return f
+
+
 def batch_sizes(n_fields: int, lo: int, hi: int, seed: int):
     """(ny, nx) pairs with each side round(exp(U[ln lo, ln hi])) independently."""
     rng = np.random.default_rng(seed)

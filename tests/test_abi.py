@@ -72,6 +72,12 @@ def test_lcp_rejects_bad_arguments():
     _expect_invalid(L.pdiv_lcp(FAKE, FAKE, 8, 8, ip, 2, FAKE, 6, 0, NUL), "lcp_row_pitch")
     _expect_invalid(L.pdiv_lcp(FAKE, FAKE, 8, 8, ip, 2, FAKE, -1, 0, NUL), "lcp_row_pitch")
     _expect_invalid(L.pdiv_lcp(FAKE, FAKE, 8, 8, ip, 2, FAKE, 1 << 62, 0, NUL), "lcp_row_pitch")
+    # the largest pitch on the most rows: rows x pitch exceeds 2^52 floats and
+    # is rejected before any int64 product of the two is formed
+    _expect_invalid(L.pdiv_lcp(FAKE, FAKE, 1 << 21, 8, ip, 2, FAKE, 1 << 52, 0, NUL),
+                    "too large")
+    _expect_invalid(L.pdiv_lcp(FAKE, FAKE, 1 << 21, 8, ip, 2, FAKE, 1 << 40, 1 << 20, NUL),
+                    "too large")
     # maps that overlap: plane stride between a row and a map, or rows too short
     _expect_invalid(L.pdiv_lcp(FAKE, FAKE, 8, 8, ip, 2, FAKE, 7, 20, NUL), "overlap")
     _expect_invalid(L.pdiv_lcp(FAKE, FAKE, 8, 8, ip, 2, FAKE, 10, 7, NUL), "overlap")
@@ -109,12 +115,20 @@ def test_moments_rejects_bad_arguments():
 def test_mc_rejects_bad_arguments():
     L = P.lib()
     keep, ip = _iso([0.0])
-    _expect_invalid(L.pdiv_mc_lcp(FAKE, FAKE, FAKE, FAKE, 0, 8, 8, 1.0, 1.0, ip, 1, 0, 1, FAKE,
-                                  NUL), "n_samples")
-    _expect_invalid(L.pdiv_mc_lcp(FAKE, FAKE, FAKE, FAKE, 0, 8, 8, 1.0, 1.0, ip, 1, 1 << 31, 1,
+    _expect_invalid(L.pdiv_mc_lcp(FAKE, FAKE, FAKE, FAKE, 0, 8, 8, 1.0, 1.0, ip, 1, 0, 1, 0,
                                   FAKE, NUL), "n_samples")
+    _expect_invalid(L.pdiv_mc_lcp(FAKE, FAKE, FAKE, FAKE, 0, 8, 8, 1.0, 1.0, ip, 1, 1 << 31, 1,
+                                  0, FAKE, NUL), "n_samples")
     _expect_invalid(L.pdiv_mc_lcp(FAKE, FAKE, FAKE, FAKE, 0, 1 << 21, 1 << 11, 1.0, 1.0, ip, 1,
-                                  10, 1, FAKE, NUL), "2^32")
+                                  10, 1, 0, FAKE, NUL), "2^32")
+    for mode in (2, 7, 0xFFFFFFFF):
+        _expect_invalid(L.pdiv_mc_lcp(FAKE, FAKE, FAKE, FAKE, 0, 8, 8, 1.0, 1.0, ip, 1, 10, 1,
+                                      mode, FAKE, NUL), "mode")
+    # nx = 2^29 with ny = 7 keeps ny*nx below 2^32, but the launch would need
+    # 2^24 blocks of 256 threads, one work-item more than a dispatch holds
+    for mode in (0, 1):
+        _expect_invalid(L.pdiv_mc_lcp(FAKE, FAKE, FAKE, FAKE, 0, 7, 1 << 29, 1.0, 1.0, ip, 1,
+                                      10, 1, mode, FAKE, NUL), "too large")
     _expect_invalid(L.pdiv_mc_sample_field(FAKE, FAKE, FAKE, FAKE, 0, 8, 8, -1, 1, FAKE, FAKE,
                                            NUL), "sample")
 

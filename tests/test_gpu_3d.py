@@ -57,12 +57,29 @@ def test_divergence_3d_matches_oracle(shape, dt):
     np.testing.assert_allclose(host64(dv), rv, rtol=8 * U32, atol=0)
 
 
+def _oracle_div3(ts, h=(1.0, 1.0, 1.0)):
+    """The oracle's float32 3D divergence Gaussians of the stored volumes, as
+    numpy arrays and device tensors: the pdiv_lcp_3d input of both sides."""
+    m, v = O.divergence_gaussian_3d_f32(*[host64(t) for t in ts], *h)
+    return m, v, torch.from_numpy(m).cuda(), torch.from_numpy(v).cuda()
+
+
+@pytest.mark.parametrize("dt", ["f32", "f16", "bf16"])
+@pytest.mark.parametrize("shape", SHAPES)
+def test_divergence_3d_rounds_like_the_float32_oracle(shape, dt):
+    h = (0.75, 1.0, 2.5)
+    _, ts = _field(shape, seed=5 * sum(shape), dt=dt)
+    dm, dv = P.divergence_gaussian_3d(*ts, *h)
+    m, v, _, _ = _oracle_div3(ts, h)
+    assert np.array_equal(dm.cpu().numpy(), m) and np.array_equal(dv.cpu().numpy(), v)
+
+
 @pytest.mark.parametrize("k", [1, 3, 4, 8, 16, 17])
 @pytest.mark.parametrize("shape", SHAPES)
 def test_lcp_3d_matches_oracle(shape, k):
     _, ts = _field(shape, seed=7 * sum(shape) + k)
-    dm, dv = P.divergence_gaussian_3d(*ts)
-    m64, v64 = host64(dm), host64(dv)
+    m, v, dm, dv = _oracle_div3(ts)
+    m64, v64 = m.astype(np.float64), v.astype(np.float64)
     iso = np.quantile(m64, np.linspace(0.05, 0.95, k)).astype(np.float32)
     g = host64(P.lcp_3d(dm, dv, iso))
     r = O.lcp_3d(m64, v64, iso)
@@ -81,8 +98,9 @@ def test_fused_equals_two_step(shape, dt):
     h = (1.0, 0.5, 2.0)
     _, ts = _field(shape, seed=3 * sum(shape), dt=dt)
     dm, dv = P.divergence_gaussian_3d(*ts, *h)
+    m = _oracle_div3(ts, h)[0]
     for k in (1, 4, 8, 16, 17):
-        iso = np.quantile(host64(dm), np.linspace(0.05, 0.95, k)).astype(np.float32)
+        iso = np.quantile(m, np.linspace(0.05, 0.95, k)).astype(np.float32)
         two = P.lcp_3d(dm, dv, iso)
         fused = P.lcp_3d_from_moments(*ts, iso, *h)
         assert torch.equal(fused, two), (shape, dt, k)
@@ -104,11 +122,11 @@ def test_zero_variance_is_marching_cubes():
     shape = (6, 20, 70)
     f = synth.gen_moments_3d(*shape, 5)
     ts = [dev(f[k] if k.startswith("mean") else 0.0 * f[k]) for k in KEYS]
-    dm, dv = P.divergence_gaussian_3d(*ts)
-    assert float(dv.abs().max()) == 0.0
-    m64 = host64(dm)
+    m32, v32, dm, dv = _oracle_div3(ts)
+    assert float(np.abs(v32).max()) == 0.0
+    m64 = m32.astype(np.float64)
     iso = np.quantile(m64, [0.1, 0.5, 0.9]).astype(np.float32)
-    iso[1] = np.float32(m64[3, 10, 35])  # a tie at a vertex: >= counts as above
+    iso[1] = m32[3, 10, 35]  # a tie at a vertex: >= counts as above
     g = host64(P.lcp_3d(dm, dv, iso))
     for q, c in enumerate(iso):
         np.testing.assert_array_equal(g[q], O.crossed_3d(m64, float(c)).astype(np.float64))
@@ -117,7 +135,7 @@ def test_zero_variance_is_marching_cubes():
 def test_nan_reaches_exactly_its_cells():
     shape = (5, 9, 70)
     _, ts = _field(shape, seed=3)
-    dm, dv = P.divergence_gaussian_3d(*ts)
+    _, _, dm, dv = _oracle_div3(ts)
     dm[2, 4, 66] = float("nan")
     g = host64(P.lcp_3d(dm, dv, [0.0, 0.3]))
     bad = np.zeros(g.shape[1:], bool)
@@ -133,18 +151,24 @@ def test_bench_size_sampled_slabs():
     n = 512
     f = synth.gen_moments_3d(n, n, n, synth.SEED_BASE + 30, dtype=np.float32)
     ts = [torch.from_numpy(f[k]).cuda() for k in KEYS]
-    del f
+
+    def oracle_vertices(k0):
+        # vertex planes k0..k0+2 from the z slab around them (planes k0-1 ..
+        # k0+3): inside the slab they are differenced as in the whole volume
+        a, b = max(0, k0 - 1), min(n, k0 + 4)
+        m, v = O.divergence_gaussian_3d(*[f[k][a:b].astype(np.float64) for k in KEYS],
+                                        1.0, 1.0, 1.0)
+        return m[k0 - a:k0 - a + 3], v[k0 - a:k0 - a + 3]
+
+    iso = np.quantile(oracle_vertices(n // 2 - 2)[0], [0.2, 0.4, 0.6, 0.8]).astype(np.float32)
     dm, dv = P.divergence_gaussian_3d(*ts)
-    iso = np.quantile(host64(dm[::8, ::8, ::8]), [0.2, 0.4, 0.6, 0.8]).astype(np.float32)
     out = P.lcp_3d(dm, dv, iso)
     assert torch.equal(P.lcp_3d_from_moments(*ts, iso), out)
     assert not torch.isnan(out).any()
     assert float(out.min()) >= 0.0 and float(out.max()) <= 1.0
     worst = 0.0
     for k0 in (0, n // 2 - 2, n - 3):
-        m = host64(dm[k0:k0 + 3])
-        v = host64(dv[k0:k0 + 3])
-        r = O.lcp_3d(m, v, iso)
+        r = O.lcp_3d(*oracle_vertices(k0), iso)
         worst = max(worst, float(np.max(np.abs(host64(out[:, k0:k0 + 2]) - r))))
-    print(f"\n[512^3 K=4] max |LCP - oracle| on sampled slabs = {worst:.3e}")
+    print(f"\n[512^3 K=4] max |LCP - oracle(stored volumes)| on sampled slabs = {worst:.3e}")
     assert worst <= LCP_TOL

@@ -72,13 +72,11 @@ def test_offsets_and_a_short_buffer():
 
 def test_mean_field_contour_of_the_ensemble():
     """The mean-field isocontour of the fitted 721 x 1440 ensemble's
-    divergence at its isovalues, against the oracle on the same float32
-    divergence."""
+    divergence at its isovalues: the oracle's fit, stored as float32, and its
+    float32 divergence are the field both sides contour."""
     e = synth.config_c2()
-    u = torch.from_numpy(e["u_members"]).cuda()
-    v = torch.from_numpy(e["v_members"]).cuda()
-    dm, _ = P.divergence_gaussian(*P.moments(u, v))
-    d32 = dm.cpu().numpy()
+    mom32 = [m.astype(np.float32) for m in O.moments(e["u_members"], e["v_members"], 1)]
+    d32 = O.divergence_gaussian_f32(*mom32, 1.0, 1.0)[0]
     for c in e["isovalues"][[0, 4, 7]]:
         r = _compare(d32, c)
         assert len(r) > 100
@@ -91,13 +89,15 @@ def test_spaghetti_matches_per_member_contours():
     sp = P.spaghetti(u, v, 0.02)
     assert len(sp) == 6
     zero = torch.zeros((60, 90), device="cuda")
+    z64 = np.zeros((60, 90))
     for m in range(6):
         d, _ = P.divergence_gaussian(u[m].contiguous(), zero, v[m].contiguous(), zero)
-        d32 = d.cpu().numpy()
-        # the member's divergence is Eq. 1 in float32
-        ref_d = O.fd_divergence(e["u_members"][m].astype(np.float64),
-                                e["v_members"][m].astype(np.float64), 1.0, 1.0)
-        scale = max(np.abs(e["u_members"][m]).max(), np.abs(e["v_members"][m]).max())
+        # the member's divergence is Eq. 1 in float32, as the oracle rounds it
+        um, vm = e["u_members"][m].astype(np.float64), e["v_members"][m].astype(np.float64)
+        d32 = O.divergence_gaussian_f32(um, z64, vm, z64, 1.0, 1.0)[0]
+        assert np.array_equal(d.cpu().numpy(), d32)
+        ref_d = O.fd_divergence(um, vm, 1.0, 1.0)
+        scale = max(np.abs(um).max(), np.abs(vm).max())
         assert np.max(np.abs(d32 - ref_d)) <= 8 * U32 * scale
         r = O.marching_squares(d32.astype(np.float64), float(np.float32(0.02)))
         g = host64(sp[m])

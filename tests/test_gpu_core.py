@@ -2,7 +2,9 @@
 FP64 oracle, through the C ABI.  Oracle inputs are the values the GPU actually
 received (storage dtype upcast exactly), so these tests measure the kernels'
 float32 arithmetic; the end-to-end storage error is measured at full size in
-test_gpu_fullsize.py."""
+test_gpu_fullsize.py.  No oracle input comes from a kernel: the divergence
+Gaussians given to pdiv_lcp are the oracle's own float32 evaluation of
+Eq. 2-3 (which the divergence kernel must reproduce bit for bit)."""
 
 import mpmath
 import numpy as np
@@ -40,6 +42,13 @@ SHAPES = [(2, 2), (2, 3), (3, 2), (2, 200), (200, 2), (64, 64), (65, 127), (130,
 DIV_SHAPES = SHAPES + [(5, 62), (6, 63), (7, 124), (8, 125)]
 
 
+def _oracle_div(ts, dx=1.0, dy=1.0):
+    """The oracle's float32 divergence Gaussians of the stored moments, as
+    numpy planes and as device tensors (the pdiv_lcp input of both sides)."""
+    rm, rv = O.divergence_gaussian_f32(*stored64(ts), dx, dy)
+    return rm, rv, torch.from_numpy(rm).cuda(), torch.from_numpy(rv).cuda()
+
+
 @pytest.mark.parametrize("dt", ["f32", "f16", "bf16"])
 @pytest.mark.parametrize("shape", DIV_SHAPES)
 def test_divergence_gaussian_parity(shape, dt):
@@ -53,6 +62,10 @@ def test_divergence_gaussian_parity(shape, dt):
     gm, gv = host64(dm), host64(dv)
     assert np.max(np.abs(gm - rm)) <= _div_tol(mu_u, mu_v, dx, dy)
     assert np.max(np.abs(gv - rv) / rv) <= 6.0 * U32
+    # the kernel rounds in the order the float32 oracle states, bit for bit
+    r32m, r32v = O.divergence_gaussian_f32(mu_u, var_u, mu_v, var_v, dx, dy)
+    assert np.array_equal(gm, r32m.astype(np.float64))
+    assert np.array_equal(gv, r32v.astype(np.float64))
 
 
 @pytest.mark.parametrize("shape", SHAPES)
@@ -61,12 +74,12 @@ def test_lcp_parity(shape, k):
     ny, nx = shape
     f = _field(ny, nx, seed=7 + ny + nx)
     ts = moments_dev(f)
-    dm, dv = P.divergence_gaussian(*ts)
+    rm, rv, dm, dv = _oracle_div(ts)
     rng = np.random.default_rng(k)
     div = synth.analytic_divergence(f["features"], ny, nx)
     iso = synth.quantile_isovalues(div, rng.uniform(0.02, 0.98, k))
     L = P.lcp(dm, dv, iso)
-    ref = O.lcp(host64(dm), host64(dv), iso)
+    ref = O.lcp(rm, rv, iso)
     e = err_report(host64(L), ref)
     assert e["max_abs"] <= LCP_TOL, e
     # the fused kernel gives bitwise the same maps
@@ -89,7 +102,7 @@ def test_pitched_output_equals_dense_and_keeps_padding(shape):
     iso = np.array([-0.05, -0.02, -0.01, 0.0, 0.004, 0.01, 0.02, 0.03, 0.06], np.float32)
     K = iso.size
     dense = P.lcp_from_moments(*ts, iso)
-    dm, dv = P.divergence_gaussian(*ts)
+    rm, rv, dm, dv = _oracle_div(ts)
     for pitch in ((nx - 1 + 31) // 32 * 32, nx + 40):
         for fused in (True, False):
             buf = torch.full((K, ny - 1, pitch), -7.0, device="cuda")
@@ -116,7 +129,7 @@ def test_pitched_output_equals_dense_and_keeps_padding(shape):
         assert torch.equal(view, dense)
     assert torch.equal(P.lcp_from_moments(*ts, iso, out=P.empty_lcp(K, ny, nx,
                                                                    interleave_rows=True)), dense)
-    ref = O.lcp(host64(dm), host64(dv), iso)
+    ref = O.lcp(rm, rv, iso)
     assert err_report(host64(e), ref)["max_abs"] <= LCP_TOL
 
 
@@ -161,11 +174,11 @@ def test_relative_accuracy_near_zero_and_one():
     ny, nx = 300, 301
     f = _field(ny, nx, seed=12, sigma=(0.002, 0.02))
     ts = moments_dev(f)
-    dm, dv = P.divergence_gaussian(*ts)
+    m, v, dm, dv = _oracle_div(ts)
     div = synth.analytic_divergence(f["features"], ny, nx)
     iso = synth.quantile_isovalues(div, [0.01, 0.3, 0.5, 0.7, 0.99])
     L = host64(P.lcp(dm, dv, iso))
-    m, v = host64(dm), host64(dv)
+    m, v = m.astype(np.float64), v.astype(np.float64)
     ref = O.lcp(m, v, iso)
     # the FP64 oracle evaluates 1 - A - B literally (absolute error ~1e-16), so
     # it is a relative reference only down to ~1e-9
@@ -188,12 +201,11 @@ def test_relative_accuracy_near_zero_and_one():
         exact = float(1 - A - B)
         assert abs(L[k, j, i] - exact) <= 1e-4 * exact, (k, j, i, L[k, j, i], exact)
 
-    ramp = np.add.outer(np.zeros(40), (np.arange(120) - 60.3) * 0.5)
-    rm = torch.from_numpy(ramp.astype(np.float32)).cuda()
-    rv = torch.full_like(rm, 0.01)
+    ramp = np.add.outer(np.zeros(40), (np.arange(120) - 60.3) * 0.5).astype(np.float32)
+    ramp_v = np.full_like(ramp, 0.01)
     iso2 = np.array([0.1, 1.1, -2.4], np.float32)
-    L2 = host64(P.lcp(rm, rv, iso2))
-    ref2 = O.lcp(host64(rm), host64(rv), iso2)
+    L2 = host64(P.lcp(torch.from_numpy(ramp).cuda(), torch.from_numpy(ramp_v).cuda(), iso2))
+    ref2 = O.lcp(ramp.astype(np.float64), ramp_v.astype(np.float64), iso2)
     big = ref2 > 1 - 1e-3
     assert big.sum() >= 3 * 39
     assert np.max(np.abs(L2[big] - ref2[big])) <= 4 * U32
@@ -203,10 +215,11 @@ def test_zero_variance_is_exact_crossing_indicator():
     ny, nx = 70, 90
     f = _field(ny, nx, seed=13)
     ts = moments_dev(f)
-    dm, _ = P.divergence_gaussian(*ts)
+    m32, _, dm, _ = _oracle_div(ts)
     zero = torch.zeros_like(dm)
-    m = host64(dm)
-    iso = np.array([np.float32(m[5, 5]), np.float32(m[40, 17]), 0.0, 0.01], np.float32)
+    m = m32.astype(np.float64)
+    # isovalues equal to vertex means: ties, above by the >= rule
+    iso = np.array([m32[5, 5], m32[40, 17], 0.0, 0.01], np.float32)
     L = P.lcp(dm, zero, iso)
     ref = O.lcp(m, np.zeros_like(m), iso)
     assert np.array_equal(host64(L), ref)
@@ -216,12 +229,12 @@ def test_mixed_deterministic_corners_and_nan():
     ny, nx = 40, 41
     f = _field(ny, nx, seed=14)
     ts = moments_dev(f)
-    dm, dv = P.divergence_gaussian(*ts)
-    dv[::3, ::2] = 0.0  # deterministic corners mixed with random ones
-    dm[20, 20] = float("nan")
+    m, v, _, _ = _oracle_div(ts)
+    v[::3, ::2] = 0.0  # deterministic corners mixed with random ones
+    m[20, 20] = np.nan
     iso = np.array([0.0, 0.02], np.float32)
-    L = host64(P.lcp(dm, dv, iso))
-    ref = O.lcp(host64(dm), host64(dv), iso)
+    L = host64(P.lcp(torch.from_numpy(m).cuda(), torch.from_numpy(v).cuda(), iso))
+    ref = O.lcp(m.astype(np.float64), v.astype(np.float64), iso)
     nan_ref = np.isnan(ref)
     assert np.array_equal(np.isnan(L), nan_ref) and nan_ref.sum() == 2 * 4
     ok = ~nan_ref
@@ -231,9 +244,9 @@ def test_mixed_deterministic_corners_and_nan():
 def test_far_isovalues_vanish():
     f = _field(50, 60, seed=15)
     ts = moments_dev(f)
-    dm, dv = P.divergence_gaussian(*ts)
-    hi = float(dm.max() + 12 * dv.max().sqrt())
-    lo = float(dm.min() - 12 * dv.max().sqrt())
+    m, v, dm, dv = _oracle_div(ts)
+    hi = float(m.max() + 12 * np.sqrt(v.max()))
+    lo = float(m.min() - 12 * np.sqrt(v.max()))
     L = host64(P.lcp(dm, dv, [hi, lo]))
     assert L.max() <= 1e-30
 

@@ -103,3 +103,67 @@ def test_mc_sse_follows_sample_count(S):
     sse = float(np.sum(((E - L) ** 2)[inner]))
     print(f"\n[S={S}] SSE {sse:.4g}, expected {expected:.4g}, ratio {sse / expected:.4f}")
     assert abs(sse / expected - 1.0) < 0.05
+
+
+@pytest.mark.parametrize("shape,k,s,dt,d", [((37, 45), 3, 301, "f32", (1.0, 1.0)),
+                                            ((2, 2), 1, 64, "f32", (1.0, 1.0)),
+                                            ((2, 70), 2, 50, "f32", (0.5, 2.0)),
+                                            ((70, 2), 2, 51, "f16", (1.0, 1.0)),
+                                            ((66, 130), 17, 42, "bf16", (1.3, 0.7))])
+def test_vertex_mode_counts_match_oracle(shape, k, s, dt, d):
+    """Vertex-level sampling: the same Philox counters on both sides, the
+    crossing decision taken in float32 on both; counts agree up to samples
+    within a few ulps of the isovalue."""
+    ny, nx = shape
+    f = synth.gen_moments(ny, nx, seed=3 * ny + nx, sigma=(0.05, 0.5))
+    ts = moments_dev(f, dt)
+    rng = np.random.default_rng(k + 100)
+    iso = rng.uniform(-0.15, 0.15, k).astype(np.float32)
+    seed = 0xDEAD_BEEF_0000_0000 + k
+    g = host64(P.mc_lcp(*ts, iso, n_samples=s, seed=seed, dx=d[0], dy=d[1], mode="vertex"))
+    r = O.mc_lcp(*stored64(ts), d[0], d[1], iso, s, seed, precision="f32", mode="vertex")
+    flips = np.abs(np.rint(g * s) - np.rint(r * s))
+    assert flips.sum() <= 5 + 1e-5 * flips.size * s, flips.sum()
+
+
+def test_vertex_mode_converges_to_closed_form_on_every_cell():
+    """Vertex mode samples the closed form's own model, so it lands within
+    sampling error of the FP64 oracle's LCP on every cell, boundary cells
+    included (3 SE per cell up to a binomial allowance, chi-square aggregate),
+    and the boundary cells where the paper's vector-level MC leaves the
+    closed form are among them."""
+    from scipy import stats
+    c = synth.config_c1()
+    ts = moments_dev(c)
+    S = c["n_samples"]
+    iso = c["isovalues"]
+    E = host64(P.mc_lcp(*ts, iso, n_samples=S, seed=2026, mode="vertex"))
+    L = O.lcp(*O.divergence_gaussian(*stored64(ts), 1.0, 1.0), iso)
+    se = np.sqrt(np.maximum(L * (1 - L), 1.0 / S) / S)
+    z = np.abs(E - L) / se
+    assert np.sum(z > 3.0 + 1.0 / (S * se)) <= stats.binom.isf(1e-3, z.size, 0.0027)
+    assert np.mean(z ** 2) < 1.2
+    ny, nx = c["ny"], c["nx"]
+    edge = np.ones((ny - 1, nx - 1), bool)
+    edge[1:ny - 2, 1:nx - 2] = False
+    ze = z[:, edge]
+    assert np.mean(ze ** 2) < 1.3 and np.sum(ze > 4.5) == 0
+
+
+def test_vertex_mode_zero_variance_is_deterministic():
+    ny, nx = 40, 50
+    f = synth.gen_moments(ny, nx, seed=6)
+    f["var_u"] = np.zeros_like(f["var_u"])
+    f["var_v"] = np.zeros_like(f["var_v"])
+    ts = moments_dev(f)
+    iso = np.array([-0.05, 0.0, 0.05], np.float32)
+    g = host64(P.mc_lcp(*ts, iso, n_samples=7, seed=1, mode="vertex"))
+    r = O.mc_lcp(*stored64(ts), 1.0, 1.0, iso, 7, 1, precision="f32", mode="vertex")
+    assert np.array_equal(g, r)
+
+
+def test_unknown_mode_is_rejected():
+    f = synth.gen_moments(8, 8, seed=1)
+    ts = moments_dev(f)
+    with pytest.raises(ValueError):
+        P.mc_lcp(*ts, [0.0], n_samples=4, seed=1, mode="pixel")

@@ -92,10 +92,20 @@ def test_ensemble_full_size_and_the_path_on_it():
     v = torch.from_numpy(e["v_members"]).cuda()
     mom = P.speed_gradient_moments(u, v)
     got = [host64(t) for t in mom]
-    _check(got, O.speed_gradient_moments(U, V, 1.0, 1.0, 1), U, V, 50, 1)
-    dm, dv = O.divergence_gaussian(*got, 1.0, 1.0)
+    ref = O.speed_gradient_moments(U, V, 1.0, 1.0, 1)
+    _check(got, ref, U, V, 50, 1)
+    # the path on the gradient field: the oracle's fit, stored as float32, is
+    # the input of both sides, so no kernel output feeds the oracle
+    st32 = [r.astype(np.float32) for r in ref]
+    dm, dv = O.divergence_gaussian(*[a.astype(np.float64) for a in st32], 1.0, 1.0)
     iso = np.quantile(dm, [0.5, 0.9, 0.99]).astype(np.float32)
-    lcp = host64(P.lcp_from_moments(*mom, iso))
+    lcp = host64(P.lcp_from_moments(*[torch.from_numpy(a).cuda() for a in st32], iso))
     err = float(np.max(np.abs(lcp - O.lcp(dm, dv, iso))))
     print(f"\n[721x1440x50] max |LCP - oracle| on the gradient-of-speed field = {err:.3e}")
     assert err <= 1e-5
+    # the GPU pipeline end to end (its own float32 fit feeding the LCP) against
+    # the oracle of the float64 fit: reported, the fit's rounding included
+    e2e = host64(P.lcp_from_moments(*mom, iso))
+    ref_e2e = O.lcp(*O.divergence_gaussian(*ref, 1.0, 1.0), iso)
+    print(f"[721x1440x50] end to end max |LCP - oracle(float64 fit)| = "
+          f"{float(np.max(np.abs(e2e - ref_e2e))):.3e}")

@@ -148,3 +148,32 @@ def test_vector_monte_carlo_converges_on_interior_cells():
     z = (np.abs(E - L) / se)[:, inner]
     assert np.sum(z > 3.0 + 1.0 / (S * se[:, inner])) <= max(1, int(0.01 * z.size))
     assert np.mean(z ** 2) < 1.5
+
+
+def test_f32_divergence_3d_equals_f64_where_float32_is_exact():
+    rng = np.random.default_rng(31)
+    for shape, h in (((5, 6, 7), (0.5, 2.0, 1.0)), ((2, 2, 2), (1.0, 1.0, 1.0)),
+                     ((3, 2, 9), (4.0, 0.25, 0.5))):
+        planes = []
+        for _ in range(3):
+            planes += [rng.integers(-1000, 1000, shape).astype(np.float64),
+                       rng.integers(0, 1000, shape).astype(np.float64)]
+        m64, v64 = O.divergence_gaussian_3d(*planes, *h)
+        m32, v32 = O.divergence_gaussian_3d_f32(*planes, *h)
+        assert m32.dtype == np.float32
+        np.testing.assert_array_equal(m32.astype(np.float64), m64)
+        # the float64 definition squares sqrt(var) / h, which rounds twice
+        np.testing.assert_allclose(v32.astype(np.float64), v64, rtol=4e-16, atol=0)
+
+
+def test_f32_divergence_3d_is_within_rounding_of_f64():
+    rng = np.random.default_rng(32)
+    shape = (6, 7, 8)
+    planes = []
+    for _ in range(3):
+        planes += [rng.normal(0, 1, shape), rng.uniform(0.01, 1, shape)]
+    m64, v64 = O.divergence_gaussian_3d(*planes, 0.7, 1.1, 1.9)
+    m32, v32 = O.divergence_gaussian_3d_f32(*planes, 0.7, 1.1, 1.9)
+    u = 2.0 ** -24
+    assert np.max(np.abs(m32 - m64)) <= 12 * u * 3 * (1 / 0.7 + 1 / 1.1 + 1 / 1.9) * 4
+    assert np.max(np.abs(v32 - v64) / v64) <= 12 * u

@@ -156,3 +156,34 @@ def test_brute_force_sampling_every_vertex():
     ev = acc2 / n - em ** 2
     assert np.all(np.abs(em - m) < 4.5 * np.sqrt(v / n))
     assert np.all(np.abs(ev / v - 1.0) < 4.5 * np.sqrt(2.0 / n) + 1e-3)
+
+
+def test_f32_divergence_equals_f64_where_float32_is_exact():
+    """Integer means and variances with power-of-two spacings make every
+    float32 operation of Eq. 2-3 exact, so the float32 evaluation must equal
+    the float64 definition (bit for bit for the mean; the variance up to the
+    float64 definition's own rounding of sqrt(var) squared) -- a dropped term,
+    a wrong neighbour or a wrong boundary coefficient cannot survive this."""
+    rng = np.random.default_rng(21)
+    for ny, nx, dx, dy in ((7, 9, 0.5, 2.0), (2, 2, 1.0, 1.0), (2, 13, 4.0, 0.25), (11, 2, 1.0, 0.5)):
+        mu_u, mu_v = rng.integers(-1000, 1000, (2, ny, nx)).astype(np.float64)
+        var_u, var_v = rng.integers(0, 1000, (2, ny, nx)).astype(np.float64)
+        m64, v64 = O.divergence_gaussian(mu_u, var_u, mu_v, var_v, dx, dy)
+        m32, v32 = O.divergence_gaussian_f32(mu_u, var_u, mu_v, var_v, dx, dy)
+        assert m32.dtype == np.float32 and v32.dtype == np.float32
+        np.testing.assert_array_equal(m32.astype(np.float64), m64)
+        # the float64 definition squares sqrt(var) / h, which rounds twice
+        np.testing.assert_allclose(v32.astype(np.float64), v64, rtol=4e-16, atol=0)
+
+
+def test_f32_divergence_is_within_rounding_of_f64():
+    rng = np.random.default_rng(22)
+    ny, nx = 23, 31
+    mu_u, mu_v = rng.normal(0, 1, (2, ny, nx))
+    var_u, var_v = rng.uniform(0.01, 1, (2, ny, nx))
+    m64, v64 = O.divergence_gaussian(mu_u, var_u, mu_v, var_v, 0.3, 1.7)
+    m32, v32 = O.divergence_gaussian_f32(mu_u, var_u, mu_v, var_v, 0.3, 1.7)
+    u = 2.0 ** -24
+    scale = (np.abs(mu_u).max() / 0.3 + np.abs(mu_v).max() / 1.7) * 2
+    assert np.max(np.abs(m32 - m64)) <= 8 * u * scale
+    assert np.max(np.abs(v32 - v64) / v64) <= 8 * u

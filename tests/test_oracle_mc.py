@@ -175,3 +175,84 @@ def test_mc_sse_follows_binomial_expectation(S):
     sse = [float(np.sum(((O.mc_lcp(mu_u, var_u, mu_v, var_v, 1.0, 1.0, iso, S, seed) - L)
                          ** 2)[inner])) for seed in range(100, 140)]
     assert abs(np.mean(sse) / expected - 1.0) < 0.05
+
+
+def test_vertex_mode_matches_closed_form_on_every_cell():
+    """Vertex-level sampling draws each vertex divergence on its own from the
+    Gaussian of Eq. 2-3, which is exactly the closed form's independent-corner
+    model: it converges to lcp() on boundary cells too -- the very field on
+    which the vector-level MC misses the closed form at column 0."""
+    ny, nx = 6, 6
+    mu = np.zeros((ny, nx))
+    var_u = np.full((ny, nx), 1e-4); var_u[:, 0] = 100.0
+    var_v = np.full((ny, nx), 1e-4)
+    S = 4000
+    m, v = O.divergence_gaussian(mu, var_u, mu, var_v, 1.0, 1.0)
+    L = O.lcp(m, v, [0.0])
+    E = O.mc_lcp(mu, var_u, mu, var_v, 1.0, 1.0, [0.0], S, seed=5, mode="vertex")
+    se = np.sqrt(np.maximum(L * (1 - L), 1.0 / S) / S)
+    assert np.all(np.abs(E - L) < 4.5 * se)
+
+
+def test_vertex_mode_converges_on_a_random_field_all_cells():
+    rng = np.random.default_rng(13)
+    ny, nx = 9, 11
+    mu_u, mu_v = rng.normal(0, 0.5, (ny, nx)), rng.normal(0, 0.5, (ny, nx))
+    var_u, var_v = rng.uniform(0.05, 0.5, (ny, nx)) ** 2, rng.uniform(0.05, 0.5, (ny, nx)) ** 2
+    iso = [-0.2, 0.05]
+    S = 3000
+    m, v = O.divergence_gaussian(mu_u, var_u, mu_v, var_v, 0.8, 1.25)
+    L = O.lcp(m, v, iso)
+    E = O.mc_lcp(mu_u, var_u, mu_v, var_v, 0.8, 1.25, iso, S, seed=77, mode="vertex")
+    se = np.sqrt(np.maximum(L * (1 - L), 1.0 / S) / S)
+    z = np.abs(E - L) / se
+    # cells beyond 3 SE: at most the count a binomial(n, 0.0027) exceeds with
+    # probability 1e-3 (neighbouring cells share corners, which only widens
+    # the spread of the count, not its mean)
+    assert np.sum(z > 3.0 + 1.0 / (S * se)) <= stats.binom.isf(1e-3, z.size, 0.0027)
+    assert np.mean(z ** 2) < 1.5
+
+
+def test_vertex_mode_zero_variance_is_the_crossing_indicator():
+    rng = np.random.default_rng(14)
+    mu_u, mu_v = rng.normal(0, 1, (7, 9)), rng.normal(0, 1, (7, 9))
+    z = np.zeros_like(mu_u)
+    iso = [-0.5, 0.0, 0.3]
+    d = O.fd_divergence(mu_u, mu_v, 1.0, 1.0)
+    for prec in ("f64", "f32"):
+        E = O.mc_lcp(mu_u, z, mu_v, z, 1.0, 1.0, iso, 9, seed=1, precision=prec, mode="vertex")
+        for k, c in enumerate(iso):
+            up = d >= c
+            n_up = up[:-1, :-1].astype(int) + up[:-1, 1:] + up[1:, :-1] + up[1:, 1:]
+            np.testing.assert_array_equal(E[k], ((n_up % 4) != 0).astype(float))
+
+
+def test_vertex_mode_draws_are_standard_and_independent():
+    """The four normals of one vertex counter and the normals of neighbouring
+    vertices are independent standard normals (the draws of sample s at
+    vertex p are those of the divergence minus its mean, over its sd)."""
+    ny, nx = 40, 50
+    mu = np.zeros((ny, nx)); one = np.ones((ny, nx))
+    m, v = O.divergence_gaussian(mu, one, mu, one, 1.0, 1.0)
+    zs = []
+    for s in range(8):
+        # the crossing counts of a single sample reveal nothing; draw the
+        # normals through the definition instead: d = m + sd z
+        from oracle.pdiv_oracle import _vertex_normals
+        zs.append(_vertex_normals(ny * nx, s, 99))
+    zs = np.array(zs)
+    assert stats.kstest(zs.ravel(), "norm").pvalue > 1e-4
+    for a, b in ((0, 1), (0, 2), (1, 3), (2, 3), (3, 4)):
+        assert abs(np.corrcoef(zs[a], zs[b])[0, 1]) < 5 / np.sqrt(ny * nx)
+    assert abs(np.corrcoef(zs[0][:-1], zs[0][1:])[0, 1]) < 5 / np.sqrt(ny * nx)
+
+
+def test_vertex_mode_f32_and_f64_agree_up_to_rare_flips():
+    rng = np.random.default_rng(15)
+    ny, nx = 10, 11
+    mu_u, mu_v = rng.normal(0, 0.5, (ny, nx)), rng.normal(0, 0.5, (ny, nx))
+    var_u, var_v = rng.uniform(0.05, 0.5, (ny, nx)) ** 2, rng.uniform(0.05, 0.5, (ny, nx)) ** 2
+    S = 1000
+    a = O.mc_lcp(mu_u, var_u, mu_v, var_v, 1.0, 1.0, [0.0, 0.3], S, 3, "f64", mode="vertex")
+    b = O.mc_lcp(mu_u, var_u, mu_v, var_v, 1.0, 1.0, [0.0, 0.3], S, 3, "f32", mode="vertex")
+    assert np.sum(np.abs(a - b) * S) <= 5
