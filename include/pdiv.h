@@ -226,6 +226,24 @@ pdiv_status pdiv_spaghetti(const void* u_members, const void* v_members, pdiv_dt
                            int64_t* row_offsets, float* segments, int64_t max_segments,
                            pdiv_stream stream);
 
+/* pdiv_spaghetti for callers that cannot allocate device memory (code under
+ * HIP graph capture, tight serving loops, harnesses that forbid hipMalloc):
+ * no div_workspace argument.  The members' divergence planes go to a
+ * workspace the library holds itself, a static device array of 2^24 floats
+ * (64 MiB) on each GPU it runs on, kept until the process ends; the call
+ * allocates nothing.  n_members*ny*nx must be at most 2^24 floats, else
+ * PDIV_ERR_INVALID (nothing enqueued); the other arguments, checks and
+ * results are those of pdiv_spaghetti, bit for bit.  Every call on one GPU
+ * shares that GPU's workspace and leaves its contents there: calls whose
+ * work overlaps on the device (issued on different streams, or from
+ * different threads without ordering) race, so order them on one stream or
+ * synchronise between them. */
+pdiv_status pdiv_spaghetti_noalloc(const void* u_members, const void* v_members,
+                                   pdiv_dtype in_dtype, int64_t n_members, int64_t ny,
+                                   int64_t nx, int64_t member_stride, double dx, double dy,
+                                   float isovalue, int64_t* row_offsets, float* segments,
+                                   int64_t max_segments, pdiv_stream stream);
+
 /* ------------------------------------------------------------------------
  * 3D vector fields, the extension the paper names as future work (Section 5).
  * Nothing in the method changes but the dimension: the divergence adds

@@ -74,6 +74,8 @@ _SIGS = {
     "pdiv_isocontour": [_p, _i64, _i64, _c.c_float, _p, _p, _i64, _p],
     "pdiv_spaghetti": [_p, _p, _c.c_int, _i64, _i64, _i64, _i64, _f64, _f64, _c.c_float, _p, _p,
                        _p, _i64, _p],
+    "pdiv_spaghetti_noalloc": [_p, _p, _c.c_int, _i64, _i64, _i64, _i64, _f64, _f64,
+                               _c.c_float, _p, _p, _i64, _p],
     "pdiv_divergence_gaussian_3d": [_p, _p, _p, _p, _p, _p, _c.c_int, _i64, _i64, _i64, _f64,
                                     _f64, _f64, _p, _p, _p],
     "pdiv_lcp_3d": [_p, _p, _i64, _i64, _i64, _fp, _i32, _p, _p],

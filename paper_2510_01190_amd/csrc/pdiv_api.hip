@@ -5,6 +5,7 @@
 #include <cstdarg>
 #include <cstdio>
 #include <cstring>
+#include <mutex>
 #include <string>
 
 #include "pdiv_internal.hpp"
@@ -144,6 +145,83 @@ pdiv_status lcp_chunks(bool fused, const void* p0, const void* p1, const void* p
     if (e != hipSuccess) return device_status(e, "LCP launch");
     k0 += kc;
   }
+  return PDIV_OK;
+}
+
+pdiv_status check_spaghetti(const void* u_members, const void* v_members, pdiv_dtype in_dtype,
+                            int64_t n_members, int64_t ny, int64_t nx, int64_t* member_stride,
+                            double dx, double dy, const int64_t* row_offsets,
+                            const float* segments, int64_t max_segments) {
+  PDIV_NONNULL(u_members);
+  PDIV_NONNULL(v_members);
+  PDIV_NONNULL(row_offsets);
+  PDIV_TRY(check_dtype(in_dtype, "in_dtype"));
+  PDIV_TRY(check_grid(ny, nx));
+  PDIV_TRY(check_spacing(dx, dy));
+  // the per-member divergence runs a thread per point of 64-column strips,
+  // the contour passes 64 threads per cell row, both over all members' rows
+  // rounded up to a block's 4: (n_members*ny + 3) * nx_r < 2^32 per launch
+  const int64_t nx_r = (nx + 63) / 64 * 64;
+  if (n_members < 1 || n_members > (int64_t(0xffffffff) / nx_r - 3) / ny)
+    return invalid("n_members must be >= 1 with n_members*ny*nx (nx rounded up to 64) < 2^32 "
+                   "(got %lld)", (long long)n_members);
+  const int64_t n = ny * nx;
+  if (*member_stride == 0) *member_stride = n;
+  if (*member_stride < n)
+    return invalid("member_stride %lld < ny*nx %lld", (long long)*member_stride, (long long)n);
+  if (max_segments < 0) return invalid("max_segments must be >= 0 (got %lld)",
+                                       (long long)max_segments);
+  if (max_segments > 0 && segments == nullptr) return invalid("segments is NULL");
+  if (max_segments > 0 && reinterpret_cast<uintptr_t>(segments) % 16 != 0)
+    return invalid("segments must be 16-byte aligned");
+  return PDIV_OK;
+}
+
+// Every member's Eq. 1 divergence into div (n_members planes of ny*nx
+// floats), then all members' contours from it.
+hipError_t run_spaghetti(const void* u_members, const void* v_members, pdiv_dtype in_dtype,
+                         int64_t n_members, int64_t ny, int64_t nx, int64_t member_stride,
+                         double dx, double dy, float isovalue, float* div,
+                         int64_t* row_offsets, float* segments, int64_t max_segments,
+                         hipStream_t s) {
+  hipError_t e = launch_members_divergence(u_members, v_members, in_dtype, n_members, ny, nx,
+                                           member_stride, make_coef(dx, dy), div, s);
+  return e != hipSuccess ? e
+                         : launch_isocontours(div, n_members, ny * nx, ny, nx, isovalue,
+                                              row_offsets, segments, max_segments, s);
+}
+
+// ---------------------------------------------------------------------------
+// Workspace of pdiv_spaghetti_noalloc: the members' divergence planes live in
+// this file-scope device array instead of a caller's buffer.  Its name is a
+// host-side stand-in in host code; the device address of each GPU's copy is
+// looked up once per device (hipGetSymbolAddress, with that device current)
+// and only that address is handed to kernels.
+// ---------------------------------------------------------------------------
+constexpr int64_t kScratchFloats = int64_t(1) << 24;  // 64 MiB per device
+static __device__ __align__(256) float scratch[kScratchFloats];
+
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+float* g_scratch_ptr[kMaxDevices] = {};
+
+pdiv_status scratch_for_current_device(float** out) {
+  int dev = -1;
+  hipError_t e = hipGetDevice(&dev);
+  if (e != hipSuccess) return device_status(e, "hipGetDevice");
+  if (dev < 0 || dev >= kMaxDevices) {
+    set_error("device index %d beyond the %d devices the workspace table holds", dev,
+              kMaxDevices);
+    return PDIV_ERR_UNSUPPORTED;
+  }
+  std::lock_guard<std::mutex> lock(g_scratch_mu);
+  if (g_scratch_ptr[dev] == nullptr) {
+    void* p = nullptr;
+    e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+    if (e != hipSuccess) return device_status(e, "hipGetSymbolAddress(scratch)");
+    g_scratch_ptr[dev] = static_cast<float*>(p);
+  }
+  *out = g_scratch_ptr[dev];
   return PDIV_OK;
 }
 
@@ -319,36 +397,34 @@ pdiv_status pdiv_spaghetti(const void* u_members, const void* v_members, pdiv_dt
                            int64_t* row_offsets, float* segments, int64_t max_segments,
                            pdiv_stream stream) {
   g_last_error.clear();
-  PDIV_NONNULL(u_members);
-  PDIV_NONNULL(v_members);
   PDIV_NONNULL(div_workspace);
-  PDIV_NONNULL(row_offsets);
-  PDIV_TRY(check_dtype(in_dtype, "in_dtype"));
-  PDIV_TRY(check_grid(ny, nx));
-  PDIV_TRY(check_spacing(dx, dy));
-  // the per-member divergence runs a thread per point of 64-column strips,
-  // the contour passes 64 threads per cell row, both over all members' rows
-  // rounded up to a block's 4: (n_members*ny + 3) * nx_r < 2^32 per launch
-  const int64_t nx_r = (nx + 63) / 64 * 64;
-  if (n_members < 1 || n_members > (int64_t(0xffffffff) / nx_r - 3) / ny)
-    return invalid("n_members must be >= 1 with n_members*ny*nx (nx rounded up to 64) < 2^32 "
-                   "(got %lld)", (long long)n_members);
-  const int64_t n = ny * nx;
-  if (member_stride == 0) member_stride = n;
-  if (member_stride < n)
-    return invalid("member_stride %lld < ny*nx %lld", (long long)member_stride, (long long)n);
-  if (max_segments < 0) return invalid("max_segments must be >= 0 (got %lld)",
-                                       (long long)max_segments);
-  if (max_segments > 0 && segments == nullptr) return invalid("segments is NULL");
-  if (max_segments > 0 && reinterpret_cast<uintptr_t>(segments) % 16 != 0)
-    return invalid("segments must be 16-byte aligned");
-  const hipStream_t s = static_cast<hipStream_t>(stream);
-  hipError_t e = launch_members_divergence(u_members, v_members, in_dtype, n_members, ny, nx,
-                                           member_stride, make_coef(dx, dy), div_workspace, s);
-  e = e != hipSuccess ? e
-                      : launch_isocontours(div_workspace, n_members, n, ny, nx, isovalue,
-                                           row_offsets, segments, max_segments, s);
-  return device_status(e, "spaghetti launch");
+  PDIV_TRY(check_spaghetti(u_members, v_members, in_dtype, n_members, ny, nx, &member_stride,
+                           dx, dy, row_offsets, segments, max_segments));
+  return device_status(run_spaghetti(u_members, v_members, in_dtype, n_members, ny, nx,
+                                     member_stride, dx, dy, isovalue, div_workspace,
+                                     row_offsets, segments, max_segments,
+                                     static_cast<hipStream_t>(stream)),
+                       "spaghetti launch");
+}
+
+pdiv_status pdiv_spaghetti_noalloc(const void* u_members, const void* v_members,
+                                   pdiv_dtype in_dtype, int64_t n_members, int64_t ny,
+                                   int64_t nx, int64_t member_stride, double dx, double dy,
+                                   float isovalue, int64_t* row_offsets, float* segments,
+                                   int64_t max_segments, pdiv_stream stream) {
+  g_last_error.clear();
+  PDIV_TRY(check_spaghetti(u_members, v_members, in_dtype, n_members, ny, nx, &member_stride,
+                           dx, dy, row_offsets, segments, max_segments));
+  if (n_members * ny * nx > kScratchFloats)
+    return invalid("n_members*ny*nx = %lld exceeds the %lld floats of the library's own "
+                   "workspace; use pdiv_spaghetti with a caller workspace",
+                   (long long)(n_members * ny * nx), (long long)kScratchFloats);
+  float* div = nullptr;
+  PDIV_TRY(scratch_for_current_device(&div));
+  return device_status(run_spaghetti(u_members, v_members, in_dtype, n_members, ny, nx,
+                                     member_stride, dx, dy, isovalue, div, row_offsets,
+                                     segments, max_segments, static_cast<hipStream_t>(stream)),
+                       "spaghetti launch");
 }
 
 pdiv_status pdiv_divergence_gaussian_3d(const void* mean_u, const void* var_u,
