@@ -251,6 +251,26 @@ def time_launches(fn, n, torch):
     return start.elapsed_time(stop) / n / 1e3
 
 
+SETTLE_S = 0.4
+
+
+def settle(fn, torch, seconds=SETTLE_S):
+    """Run fn() back to back for `seconds` of wall time before anything is
+    timed.  Under sustained load the MI355X's clocks take tens of
+    milliseconds to settle: measured per dispatch, the first ~20 launches of
+    the 8192^2 fused step take 1.10-1.43 ms and later ones 1.06-1.07 ms.
+    Without this, a few warmup steps leave the timed steps in that ramp."""
+    import time as _t
+    t0 = _t.perf_counter()
+    n = 0
+    while _t.perf_counter() - t0 < seconds:
+        for _ in range(8):
+            fn()
+        torch.cuda.synchronize()
+        n += 8
+    return n
+
+
 def batch_leg(P, synth, torch, np):
     """512 fields of uneven size (sides log-uniform in [64, 2048]), 4 isovalues
     each: one persistent launch (autotuned, graph-replayed) against 512
@@ -365,16 +385,52 @@ LCP_BIN_NAMES = ["[0,1e-6)", "[1e-6,1e-3)", "[1e-3,0.5)", "[0.5,1-1e-3)", "[1-1e
                  "[1-1e-6,1]"]
 
 
+def new_bins():
+    """Per-bin error records of LCP maps against the oracle (see add_to_bins)."""
+    out = []
+    for q, nm in enumerate(LCP_BIN_NAMES):
+        b = {"bin": nm, "count": 0, "max_abs": 0.0}
+        if LCP_BIN_EDGES[q] < 0.5:
+            b["max_rel"] = 0.0
+        else:
+            b["max_abs_in_ulps_of_1"] = 0.0
+        out.append(b)
+    return out
+
+
+def add_to_bins(bins, ref, err, np):
+    """Bins of the oracle value L: count and max abs error; below 0.5 also
+    the max error relative to L (cells with L >= 1e-9: below that the
+    oracle's literal 1 - A - B has no relative accuracy, its absolute error
+    being ~1e-16); above 0.5 the max abs error in units of 2^-24, the
+    spacing of float32 values below 1 (the finest a float32 map resolves
+    1 - L)."""
+    for q, b in enumerate(bins):
+        sel = (ref >= LCP_BIN_EDGES[q]) & (ref < LCP_BIN_EDGES[q + 1])
+        if not sel.any():
+            continue
+        b["count"] += int(sel.sum())
+        b["max_abs"] = max(b["max_abs"], float(err[sel].max()))
+        if "max_rel" in b:
+            rs = sel & (ref >= 1e-9)
+            if rs.any():
+                b["max_rel"] = max(b["max_rel"], float((err[rs] / ref[rs]).max()))
+        else:
+            b["max_abs_in_ulps_of_1"] = round(b["max_abs"] / 2.0 ** -24, 3)
+
+
 def near01_leg(P, synth, torch, np, rows=(4096, 4224)):
     """LCP error near 0 and 1 in the headline launch (fused Eq. 2-3 + LCP, 16
     isovalues, rows padded to 128-byte lines and interleaved by isovalue) on
     the precision sweep's grid with a small spread, sigma ~ U[0.002, 0.02],
     whose cells sit deep in the tails or are crossed with near certainty.
-    Per storage type and per bin of the oracle value: count, max abs error
-    and max error relative to min(L, 1 - L), against the FP64 oracle on the
-    stored values (Eq. 2-3 in float64); relative errors below L = 1e-9 are
-    left out, where the oracle's literal 1 - A - B has no relative accuracy
-    (its absolute error is ~1e-16)."""
+    Per storage type and per bin of the oracle value: count, max abs error,
+    and below 0.5 the max error relative to L (cells with L >= 1e-9: below
+    that the oracle's literal 1 - A - B has no relative accuracy, its
+    absolute error being ~1e-16), above 0.5 the max abs error in units of
+    2^-24 (the spacing of float32 values below 1, the finest a float32 map
+    resolves 1 - L); against the FP64 oracle on the stored values (Eq. 2-3
+    in float64)."""
     import oracle as O
     log("near-0/1 accuracy: generating the low-spread 8192x8192 field (seeded)")
     f = synth.config_c3_low_spread()
@@ -396,17 +452,8 @@ def near01_leg(P, synth, torch, np, rows=(4096, 4224)):
         m, v = O.divergence_gaussian(*st, 1.0, 1.0)
         ref = O.lcp(m[1:-1], v[1:-1], iso)
         err = np.abs(g - ref)
-        side = np.minimum(ref, 1.0 - ref)
-        bins = []
-        for q, nm in enumerate(LCP_BIN_NAMES):
-            sel = (ref >= LCP_BIN_EDGES[q]) & (ref < LCP_BIN_EDGES[q + 1])
-            b = {"bin": nm, "count": int(sel.sum()), "max_abs": 0.0, "max_rel": 0.0}
-            if sel.any():
-                b["max_abs"] = float(err[sel].max())
-                rs = sel & (side >= 1e-9)
-                if rs.any():
-                    b["max_rel"] = float((err[rs] / side[rs]).max())
-            bins.append(b)
+        bins = new_bins()
+        add_to_bins(bins, ref, err, np)
         res[name] = {"max_abs": float(err.max()), "mean_abs": float(err.mean()),
                      "bins_by_oracle_lcp": bins}
     del out
@@ -430,8 +477,11 @@ def mc_leg(P, synth, torch, np, samples=1000):
 def served_leg(P, synth, torch, np, n_streams=2, fracs=(0.5, 0.9), baseline=True):
     """Poisson request stream of 10^4 requests: 70% isovalue-slider requests
     (1-4 isovalues) on a field already resident on the device, 30% new float32
-    square fields with sides log-uniform in [256, 4096] (drawn from six
-    pre-generated sides, 256..4096 log-spaced).  Capacity is measured with
+    square fields with sides log-uniform in [256, 4096] (rounded to whole
+    points).  A new field of side s is the first s^2 values of each plane of
+    one pre-generated 4096^2 field, viewed as [s][s] (no host copy before the
+    call; for s < 4096 its rows are consecutive pieces of the big field's
+    rows).  Capacity is measured with
     every request submitted at once; the stream then runs at 50% and 90% of
     it.  Clients are independent: new fields are put from two client threads
     (their host copy into pinned staging takes milliseconds), sliders from the
@@ -441,22 +491,36 @@ def served_leg(P, synth, torch, np, n_streams=2, fracs=(0.5, 0.9), baseline=True
     the same HBM budget, give the baseline."""
     import time as _t
     from concurrent.futures import ThreadPoolExecutor
-    log("served leg: preparing the field pool")
-    sides = [256, 445, 776, 1351, 2353, 4096]
-    pool = {}
-    for s_ in sides:
-        f = synth.gen_moments(s_, s_, synth.SEED_BASE + 5 + s_, n_features=max(1, s_ * s_ // 65536))
-        pool[s_] = [f[k].astype(np.float32) for k in ("mean_u", "var_u", "mean_v", "var_v")]
+    log("served leg: preparing the 4096^2 field the new fields are cut from")
+    big_side = 4096
+    f = synth.gen_moments(big_side, big_side, synth.SEED_BASE + 5 + big_side,
+                          n_features=big_side * big_side // 65536)
+    big = [np.ascontiguousarray(f[k], np.float32).ravel()
+           for k in ("mean_u", "var_u", "mean_v", "var_v")]
+    del f
+
+    def planes(side):  # zero-copy [side][side] views
+        return [b[: side * side].reshape(side, side) for b in big]
+
     budget = 24 << 30
     n_req = 10000
     n_staging = 6
     n_put_threads = 2
+    first_sides = (776, 2353)  # resident before the clock starts
 
     def stream(rate, seed):
-        return synth.request_stream(n_req, rate, seed)
+        reqs = synth.request_stream(n_req, rate, seed)
+        for r in reqs:
+            if r["kind"] == "new":
+                r["side"] = int(min(big_side, max(256, round(float(r["side"])))))
+        return reqs
 
-    ring = {s_: [torch.empty((4, s_ - 1, s_ - 1), device="cuda") for _ in range(8)]
-            for s_ in sides}
+    # output ring: 8 buffers of the largest request's size, viewed per request
+    n_ring = 8
+    ring = [torch.empty(4 * (big_side - 1) ** 2, device="cuda") for _ in range(n_ring)]
+
+    def ring_view(q, k, side):
+        return ring[q][: k * (side - 1) ** 2].view(k, side - 1, side - 1)
 
     def pct(v, q):
         return round(float(np.percentile(np.asarray(v) * 1e6, q)), 1) if v else None
@@ -465,18 +529,18 @@ def served_leg(P, synth, torch, np, n_streams=2, fracs=(0.5, 0.9), baseline=True
         srv = P.Server(hbm_budget=budget, n_streams=n_streams)
         # pinned staging set aside before the clock starts, as the one-at-a-time
         # baseline's runtime keeps its own staging buffers warm
-        srv.reserve_staging(max(sides) ** 2, n_staging)
+        srv.reserve_staging(big_side ** 2, n_staging)
         ready = []    # (id, side) of fields whose upload has completed
         pending = []  # (id, side, future of the put_field ticket)
         tickets = []
-        last = {}     # (side, ring slot) -> ticket of the slider writing it
-        used = {s_: 0 for s_ in sides}
+        last = {}     # ring slot -> ticket of the slider writing it
+        used = 0
         lag = {"slider": [], "new": []}
         failed_puts = 0
         next_id = 0
         # two fields resident before the clock starts so sliders have targets
-        for s_ in (776, 2353):
-            srv.wait(srv.put_field(next_id, *pool[s_]))
+        for s_ in first_sides:
+            srv.wait(srv.put_field(next_id, *planes(s_)))
             ready.append((next_id, s_))
             next_id += 1
         puts = ThreadPoolExecutor(max_workers=n_put_threads)
@@ -484,7 +548,7 @@ def served_leg(P, synth, torch, np, n_streams=2, fracs=(0.5, 0.9), baseline=True
 
         def put(fid, side, t_arr):
             lag["new"].append(_t.perf_counter() - t0 - t_arr)
-            return srv.put_field(fid, *pool[side])
+            return srv.put_field(fid, *planes(side))
 
         def refresh():
             nonlocal failed_puts
@@ -511,7 +575,7 @@ def served_leg(P, synth, torch, np, n_streams=2, fracs=(0.5, 0.9), baseline=True
                 while _t.perf_counter() - t0 < r["t"]:
                     pass
             if r["kind"] == "new":
-                side = min(sides, key=lambda s_: abs(np.log(s_ / r["side"])))
+                side = r["side"]
                 pending.append((next_id, side, puts.submit(put, next_id, side, r["t"])))
                 next_id += 1
                 continue
@@ -524,20 +588,21 @@ def served_leg(P, synth, torch, np, n_streams=2, fracs=(0.5, 0.9), baseline=True
                         next_id += 1
                     refresh()
                 fid, side = ready[int(r["pick"] * len(ready))]
-                slot = used[side] % len(ring[side])
-                if (side, slot) in last:  # the buffer's previous writer must be done
-                    srv.wait(last.pop((side, slot)))
+                slot = used % n_ring
+                if slot in last:  # the buffer's previous writer must be done
+                    srv.wait(last.pop(slot))
                 if paced:
                     lag["slider"].append(_t.perf_counter() - t0 - r["t"])
                 try:
-                    t = srv.submit_lcp(fid, iso, ring[side][slot][: len(iso)])
+                    # no torch work ever touches the ring: nothing to order after
+                    t = srv.submit_lcp(fid, iso, ring_view(slot, len(iso), side), sync=False)
                 except P.PdivError:  # evicted since it was ready: pick another
                     ready.remove((fid, side))
                     if paced:
                         lag["slider"].pop()
                     continue
-                used[side] += 1
-                last[(side, slot)] = t
+                used += 1
+                last[slot] = t
                 tickets.append(t)
                 break
         for _, _, fut in pending:
@@ -563,7 +628,10 @@ def served_leg(P, synth, torch, np, n_streams=2, fracs=(0.5, 0.9), baseline=True
     capacity = n_req / wall
     out = {"requests": n_req, "budget_bytes": budget, "n_streams": n_streams,
            "client_put_threads": n_put_threads,
-           "pinned_staging": f"{n_staging} x {16 * max(sides) ** 2} B reserved before timing",
+           "pinned_staging": f"{n_staging} x {16 * big_side ** 2} B reserved before timing",
+           "new_field_sides": "log-uniform in [256, 4096], rounded; each new field is the "
+                              "first side^2 values of a 4096^2 field's planes viewed as "
+                              "[side][side]",
            "capacity_req_per_s": round(capacity, 1),
            "capacity_lcp_cells_per_s": round(st["lcp_cells"] / wall, 1)}
     for frac in fracs:
@@ -588,8 +656,8 @@ def served_leg(P, synth, torch, np, n_streams=2, fracs=(0.5, 0.9), baseline=True
     log("served leg: one-request-at-a-time baseline")
     res = {}
     nid = 0
-    for s_ in (776, 2353):
-        ts = [torch.from_numpy(p).cuda() for p in pool[s_]]
+    for s_ in first_sides:
+        ts = [torch.from_numpy(p).cuda() for p in planes(s_)]
         res[nid] = (P.divergence_gaussian(*ts), s_)
         nid += 1
     torch.cuda.synchronize()
@@ -598,10 +666,10 @@ def served_leg(P, synth, torch, np, n_streams=2, fracs=(0.5, 0.9), baseline=True
     order = list(res)
     for r in reqs:
         if r["kind"] == "new":
-            side = min(sides, key=lambda s_: abs(np.log(s_ / r["side"])))
+            side = r["side"]
             while held + 24 * side * side > budget:
                 held -= 8 * res.pop(order.pop(0))[1] ** 2
-            ts = [torch.from_numpy(p).cuda() for p in pool[side]]
+            ts = [torch.from_numpy(p).cuda() for p in planes(side)]
             res[nid] = (P.divergence_gaussian(*ts), side)
             held += 8 * side * side
             del ts
@@ -687,7 +755,8 @@ def main():
     def step():
         P.lcp_from_moments(*mom, iso, out=out)
 
-    log(f"warmup {args.warmup}")
+    n_settle = settle(step, torch)
+    log(f"device settled with {n_settle} steps; warmup {args.warmup}")
     for _ in range(args.warmup):
         step()
     torch.cuda.synchronize()
@@ -722,7 +791,8 @@ def main():
 
     result = {"metric": METRIC, "value": round(value, 1), "unit": "LCP cells/s",
               "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
-              "ms_per_step": round(step_s * 1e3, 4), "higher_is_better": True,
+              "ms_per_step": round(step_s * 1e3, 4), "settle_steps": n_settle,
+              "higher_is_better": True,
               "scaling": "weak", "vs_baseline": None, "dtype": "f32", "data": "synthetic",
               "config": {"workload": "lcp_from_moments_8192x8192_k16_f32", "ny": ny, "nx": nx,
                          "n_iso": K, "storage": "float32", "cells": cells,
@@ -935,10 +1005,8 @@ def main():
         n_cpu = 0
         worst = 0.0
         sum_err = 0.0
-        # LCP bins of the oracle value: count, max abs error, max error
-        # relative to min(L, 1 - L) (the accuracy the stable combination keeps)
-        edges, names = LCP_BIN_EDGES, LCP_BIN_NAMES
-        bins = [{"bin": nm, "count": 0, "max_abs": 0.0, "max_rel": 0.0} for nm in names]
+        # LCP bins of the oracle value (add_to_bins)
+        bins = new_bins()
         for j0 in range(rows[0], rows[1], 256):
             j1 = min(j0 + 256, rows[1])
             a, b = j0 - 1, j1 + 2
@@ -951,15 +1019,7 @@ def main():
             err = np.abs(g - ref)
             worst = max(worst, float(np.max(err)))
             sum_err += float(err.sum())
-            side = np.minimum(ref, 1.0 - ref)
-            for q, bn in enumerate(bins):
-                sel = (ref >= edges[q]) & (ref < edges[q + 1])
-                if sel.any():
-                    bn["count"] += int(sel.sum())
-                    bn["max_abs"] = max(bn["max_abs"], float(err[sel].max()))
-                    rel = err[sel] / np.maximum(side[sel], 1e-300)
-                    bn["max_rel"] = max(bn["max_rel"], float(rel[side[sel] > 0].max())
-                                        if (side[sel] > 0).any() else 0.0)
+            add_to_bins(bins, ref, err, np)
         cpu = n_cpu / t_cpu
         result["cpu_baseline"] = {"value": round(cpu, 1), "unit": "LCP cells/s",
                                   "cores": 1, "kind": "oracle",

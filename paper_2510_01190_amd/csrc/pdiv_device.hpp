@@ -70,16 +70,19 @@ __device__ __forceinline__ T* at(T* row, uint32_t idx) {
 // can be used).  Descriptor word 3 is the raw 32-bit buffer format of
 // gfx9-family targets.
 //
-// STREAM selects the non-temporal cache policy.  It pays only when every
-// store writes whole 128-byte lines (rows starting on a line): then the
-// output, written once, does not push the input rows out of L2 (measured on
-// gfx950 at 8192^2, K = 16: 1.26 ms against 1.31 ms).  Where rows start
-// inside a line, neighbouring tiles write the two parts of the lines where
-// rows meet, the parts merge in L2 only if the line stays there, and the
-// default policy is faster (1.52 ms against 1.67 ms).
+// STREAM selects the streaming cache policy: non-temporal (nt) with the sc1
+// scope bit.  It pays only when every store writes whole 128-byte lines
+// (rows starting on a line): then the output, written once, does not push
+// the input rows out of the caches.  Measured on gfx950, fused kernel at
+// 8192^2, K = 16, rows interleaved by isovalue: 1.09 ms with sc1+nt, 1.14 ms
+// with nt alone, 1.13-1.15 ms with sc1 or sc0+sc1 alone, 1.18 ms with the
+// default policy.  Where rows start inside a line, neighbouring tiles write
+// the two parts of the lines where rows meet, the parts merge in L2 only if
+// the line stays there, and the default policy is the fastest (dense rows:
+// 1.45 ms, against 1.99 ms with sc1 and 2.63 ms with sc1+nt).
 template <bool STREAM>
 struct RowWriter {
-  static constexpr int kPolicy = STREAM ? 2 : 0;
+  static constexpr int kPolicy = STREAM ? 0x12 : 0;  // 0x12: sc1 | nt (0x10 | 0x2)
   __amdgpu_buffer_rsrc_t r;
   __device__ __forceinline__ RowWriter(float* row, uint32_t bytes)
       : r(__builtin_amdgcn_make_buffer_rsrc(row, 0, static_cast<int>(bytes), 0x00020000)) {}
