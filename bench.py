@@ -205,13 +205,12 @@ def cpu_legs(stored, iso, rows, mc_rows=34, mc_samples=100, mc_target=1000):
 PROFILE_MC = os.path.join(ROOT, "profiles", "mc_8192x8192_k16_s1000_valu.txt")
 MC_SRC = [os.path.join(ROOT, "paper_2510_01190_amd", "csrc", f)
           for f in ("k_mc.hip", "pdiv_device.hpp")]
-VALU_ISSUE_PEAK = 256 * 2.4e9  # wave64 VALU instructions/s: 1 per CU per cycle
 
 
 def read_mc_valu():
-    """Vector-ALU instructions per point-sample of the Monte Carlo kernel
-    from the committed counter summary, or None if absent or taken on other
-    kernel source."""
+    """(VALU busy fraction, VALU wave instructions per point-sample) of the
+    Monte Carlo kernel from the committed counter summary, or None if absent
+    or taken on other kernel source."""
     if not os.path.exists(PROFILE_MC):
         return None
     vals = {}
@@ -222,7 +221,7 @@ def read_mc_valu():
     if vals.get("kernel_source_sha256_16") != source_hash(MC_SRC):
         return None
     try:
-        return float(vals["valu_wave_instructions_per_point_sample"])
+        return float(vals["valu_busy"]), float(vals["valu_wave_instructions_per_point_sample"])
     except (KeyError, ValueError):
         return None
 
@@ -814,13 +813,14 @@ def main():
                         "ms": round(t * 1e3, 3),
                         "point_samples_per_s": round(ny * nx * S / t, 1),
                         "closed_form_speedup": round(t / kern_s, 1)}
-        ipps = read_mc_valu()
-        if ipps is not None:
-            ach = ipps * ny * nx * S / t
+        valu = read_mc_valu()
+        if valu is not None:
+            busy, ipps = valu
             result["mc"]["roofline"] = {
-                "bound": "alu", "achieved": round(ach, 1), "peak": VALU_ISSUE_PEAK,
-                "unit": "wave64 VALU instructions/s", "frac": round(ach / VALU_ISSUE_PEAK, 4),
-                "valu_instructions_per_point_sample": ipps}
+                "bound": "alu", "achieved": busy, "peak": 1.0,
+                "unit": "fraction of the launch's cycles with the vector ALUs executing "
+                        "(rocprofv3 VALUBusy, counters in profiles/mc_8192x8192_k16_s1000_valu.txt)",
+                "frac": busy, "valu_wave_instructions_per_point_sample": ipps}
         d = (mc_out - out).double()
         result["mc"]["sse_vs_closed_form_per_map"] = round(float((d * d).sum()) / K, 3)
         del mc_out, d
