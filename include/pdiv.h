@@ -49,8 +49,12 @@ typedef enum pdiv_status {
 } pdiv_status;
 
 /* Storage type of the moment planes (mean and variance of U and V).  All
- * arithmetic is float32 whatever the storage type. */
-typedef enum pdiv_dtype { PDIV_F32 = 0, PDIV_F16 = 1, PDIV_BF16 = 2 } pdiv_dtype;
+ * arithmetic is float32 whatever the storage type.  An int32_t rather than an
+ * enum type, so that every value a caller passes is well defined on the
+ * library's side; values other than these are rejected with
+ * PDIV_ERR_INVALID. */
+typedef int32_t pdiv_dtype;
+enum { PDIV_F32 = 0, PDIV_F16 = 1, PDIV_BF16 = 2 };
 
 /* Largest isovalue count one call accepts. */
 #define PDIV_MAX_ISO 256
@@ -410,6 +414,27 @@ pdiv_status pdiv_server_destroy(pdiv_server srv);
  * pdiv_lcp_from_moments), process-wide; 0 restores the built-in choice.
  * Results do not depend on it.  Returns PDIV_ERR_INVALID outside [0, 4096]. */
 pdiv_status pdiv_set_lcp_band_rows(int32_t rows);
+
+/* ------------------------------------------------------------------------
+ * Checking modes (process-wide; for debugging, not for timing)
+ * ------------------------------------------------------------------------ */
+/* The fused float32 LCP kernel with rows on 128-byte lines fills each slot
+ * of its LDS row ring with NaN before the row's loads are issued: a read
+ * that ran ahead of its load would give NaN maps instead of stale values. */
+#define PDIV_DEBUG_POISON_LDS 1u
+/* Before any work, pdiv_divergence_gaussian, pdiv_lcp, pdiv_lcp_from_moments
+ * and pdiv_mc_lcp scan their input planes on the device and return
+ * PDIV_ERR_INVALID if a mean or a variance is not finite or a variance is
+ * negative (the value preconditions that are otherwise the caller's).  The
+ * scan waits for the stream, so these calls become synchronous.  Also set by
+ * the environment variable PDIV_DEBUG_CHECKS=1 when the library loads. */
+#define PDIV_DEBUG_CHECK_INPUTS 2u
+/* Each core call writes one line (its name and sizes) to stderr.  Also set
+ * by the environment variable PDIV_LOG=1 when the library loads. */
+#define PDIV_DEBUG_LOG 4u
+/* Sets the checking modes (an OR of PDIV_DEBUG_*; 0 switches all off).
+ * Returns PDIV_ERR_INVALID for unknown bits. */
+pdiv_status pdiv_set_debug(uint32_t flags);
 
 /* ------------------------------------------------------------------------
  * Status

@@ -99,6 +99,7 @@ _SIGS = {
     "pdiv_server_stats": [_p, _c.POINTER(ServerStats)],
     "pdiv_server_destroy": [_p],
     "pdiv_set_lcp_band_rows": [_i32],
+    "pdiv_set_debug": [_c.c_uint32],
 }
 EXPORTS = list(_SIGS) + ["pdiv_status_string", "pdiv_last_error", "pdiv_version"]
 
@@ -219,6 +220,14 @@ def _moment_ptrs(mean_u, var_u, mean_v, var_v):
 def set_lcp_band_rows(rows: int):
     """Cell rows per wave band of the closed-form LCP kernels (0 = built-in choice)."""
     _check(lib().pdiv_set_lcp_band_rows(rows))
+
+
+DEBUG_POISON_LDS, DEBUG_CHECK_INPUTS, DEBUG_LOG = 1, 2, 4
+
+
+def set_debug(flags: int):
+    """Process-wide checking modes, an OR of DEBUG_* (0 switches all off)."""
+    _check(lib().pdiv_set_debug(flags))
 
 
 def moments(u_members, v_members, ddof: int = 1, out_dtype=None):

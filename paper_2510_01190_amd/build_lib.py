@@ -33,14 +33,42 @@ def _hipcc() -> str:
     return h
 
 
-def build(verbose: bool = False, jobs: int | None = None) -> str:
-    """Compiles every source (always, even if a library exists) and links libpdiv.so."""
+# Host-side sanitizers for the checking build: AddressSanitizer and
+# UndefinedBehaviorSanitizer on the host code only (each flag after
+# -Xarch_host); the device code is compiled as usual.
+SANITIZE_FLAGS = ["-O1", "-g", "-Xarch_host", "-fsanitize=address", "-Xarch_host",
+                  "-fsanitize=undefined", "-Xarch_host", "-fno-sanitize-recover=undefined",
+                  "-Xarch_host", "-fno-omit-frame-pointer"]
+
+
+def asan_runtime() -> str:
+    """Path of clang's shared AddressSanitizer runtime, which a process
+    loading the sanitized library must preload."""
+    import glob
+    root = os.path.join(os.path.dirname(os.path.dirname(_hipcc())), "lib", "llvm", "lib",
+                        "clang")
+    hits = sorted(glob.glob(os.path.join(root, "*", "lib", "linux",
+                                         "libclang_rt.asan-x86_64.so")))
+    if not hits:
+        raise RuntimeError("clang's AddressSanitizer runtime not found")
+    return hits[-1]
+
+
+def build(verbose: bool = False, jobs: int | None = None, sanitize: bool = False,
+          out_dir: str | None = None) -> str:
+    """Compiles every source (always, even if a library exists) and links
+    libpdiv.so.  sanitize=True builds the host-sanitized variant
+    (libpdiv_san.so, in out_dir), for checking runs only."""
     hipcc = _hipcc()
-    os.makedirs(OUT, exist_ok=True)
+    obj_dir = os.path.join(out_dir, "obj") if out_dir else OUT
+    os.makedirs(obj_dir, exist_ok=True)
+    flags = CFLAGS + SANITIZE_FLAGS if sanitize else CFLAGS
+    lib_path = os.path.join(out_dir, "libpdiv_san.so" if sanitize else "libpdiv.so") \
+        if out_dir else LIB
 
     def compile_one(src: str) -> str:
-        obj = os.path.join(OUT, src.rsplit(".", 1)[0] + ".o")
-        cmd = [hipcc, *CFLAGS, "-c", os.path.join(CSRC, src), "-o", obj]
+        obj = os.path.join(obj_dir, src.rsplit(".", 1)[0] + ".o")
+        cmd = [hipcc, *flags, "-c", os.path.join(CSRC, src), "-o", obj]
         r = subprocess.run(cmd, capture_output=True, text=True)
         if r.returncode != 0:
             raise RuntimeError(f"hipcc failed on {src}:\n{r.stdout}\n{r.stderr}")
@@ -50,13 +78,15 @@ def build(verbose: bool = False, jobs: int | None = None) -> str:
 
     with ThreadPoolExecutor(max_workers=jobs or min(8, len(SOURCES))) as ex:
         objs = list(ex.map(compile_one, SOURCES))
-    tmp = LIB + ".tmp"
-    cmd = [hipcc, f"--offload-arch={ARCH}", "-shared", "-fPIC", "-o", tmp, *objs, "-lpthread"]
+    tmp = lib_path + ".tmp"
+    link = ["-fsanitize=address,undefined", "-shared-libasan"] if sanitize else []
+    cmd = [hipcc, f"--offload-arch={ARCH}", "-shared", "-fPIC", *link, "-o", tmp, *objs,
+           "-lpthread"]
     r = subprocess.run(cmd, capture_output=True, text=True)
     if r.returncode != 0:
         raise RuntimeError(f"link failed:\n{r.stdout}\n{r.stderr}")
-    os.replace(tmp, LIB)
-    return LIB
+    os.replace(tmp, lib_path)
+    return lib_path
 
 
 if __name__ == "__main__":

@@ -3,6 +3,7 @@
 // walk itself lives in lcp_tile.hpp; here a grid of waves covers the field's
 // strips x bands, one tile per wave.
 #include <atomic>
+#include <type_traits>
 
 #include "lcp_tile.hpp"
 
@@ -37,6 +38,7 @@ LcpShape default_lcp_shape(int64_t ny, int64_t nx, int n_iso) {
   (void)ny;
   LcpShape s;
   s.band_rows = g_band_rows_override.load();
+  s.poison = (debug_flags() & PDIV_DEBUG_POISON_LDS) != 0;
   return s;
 }
 
@@ -133,7 +135,7 @@ __global__ __launch_bounds__(kBlock) void divergence_kernel(const T* __restrict_
   }
 }
 
-template <int KC, bool FUSED, bool PAIRED, typename T>
+template <int KC, bool FUSED, bool PAIRED, typename T, bool POISON = false>
 __device__ __forceinline__ void lcp_body(const T* __restrict__ p0,
                                                      const T* __restrict__ p1,
                                                      const T* __restrict__ p2,
@@ -154,21 +156,21 @@ __device__ __forceinline__ void lcp_body(const T* __restrict__ p0,
   const int band = wave / n_strips;
   if (band >= n_bands) return;
   const int j0 = band * band_rows;
-  lcp_tile<KC, FUSED, PAIRED>(p0, p1, p2, p3, ny, nx, k, iso, KC, out, plane, pitch, strip, j0,
-                              min(j0 + band_rows, ny - 1));
+  lcp_tile<KC, FUSED, PAIRED, T, POISON>(p0, p1, p2, p3, ny, nx, k, iso, KC, out, plane, pitch,
+                                         strip, j0, min(j0 + band_rows, ny - 1));
 }
 
 // Paired-layout kernel: asks the compiler for three waves per SIMD (at most
 // 168 VGPRs); with the alternating carried sets the tile needs one more, and
 // one spill costs less than the third wave's absence or the per-row moves of
 // a single set (measured on gfx950 at 8192^2, K = 16: 1.144 ms against 1.151).
-template <int KC, bool FUSED, typename T>
+template <int KC, bool FUSED, typename T, bool POISON = false>
 __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(3))) void lcp_kernel_paired(
     const T* __restrict__ p0, const T* __restrict__ p1, const T* __restrict__ p2,
     const T* __restrict__ p3, int ny, int nx, StencilCoef k, IsoChunk iso, float* __restrict__ out,
     int64_t plane, int64_t pitch, int band_rows, int n_strips, int n_bands) {
-  lcp_body<KC, FUSED, true>(p0, p1, p2, p3, ny, nx, k, iso, out, plane, pitch, band_rows,
-                            n_strips, n_bands);
+  lcp_body<KC, FUSED, true, T, POISON>(p0, p1, p2, p3, ny, nx, k, iso, out, plane, pitch,
+                                       band_rows, n_strips, n_bands);
 }
 
 // Split-layout kernel (its tile has no LDS ring; two waves per SIMD).
@@ -194,6 +196,16 @@ hipError_t launch_kc(const void* p0, const void* p1, const void* p2, const void*
   if (!launch_fits((waves + kWavesPerBlock - 1) / kWavesPerBlock, kBlock))
     return hipErrorInvalidConfiguration;
   const unsigned blocks = static_cast<unsigned>((waves + kWavesPerBlock - 1) / kWavesPerBlock);
+  if constexpr (FUSED && std::is_same<T, float>::value) {
+    // the checking variant exists for the fused float32 kernel only
+    if (paired && shape.poison) {
+      hipLaunchKernelGGL((lcp_kernel_paired<KC, FUSED, T, true>), dim3(blocks), dim3(kBlock), 0,
+                         s, static_cast<const T*>(p0), static_cast<const T*>(p1),
+                         static_cast<const T*>(p2), static_cast<const T*>(p3), ny, nx, k, iso,
+                         out, plane, pitch, band_rows, n_strips, n_bands);
+      return hipGetLastError();
+    }
+  }
   if (paired)
     hipLaunchKernelGGL((lcp_kernel_paired<KC, FUSED, T>), dim3(blocks), dim3(kBlock), 0, s,
                        static_cast<const T*>(p0), static_cast<const T*>(p1),

@@ -432,7 +432,11 @@ __device__ __forceinline__ float lds_at(const lds_char* base, uint32_t off) {
     return __uint_as_float(w << 16);
 }
 
-template <int KC, bool STREAM, typename T>
+// POISON (a checking mode, pdiv_set_debug): every ring slot is filled with
+// NaN before its row's loads are issued, so a step that read its rows before
+// the loads had landed (a wait count too lax for the code the compiler made)
+// would see NaN, which reaches the map, instead of an older row's values.
+template <int KC, bool STREAM, typename T, bool POISON = false>
 __device__ __forceinline__ void lcp_tile_paired_lds(const T* __restrict__ mu,
                                                     const T* __restrict__ vu,
                                                     const T* __restrict__ mv,
@@ -458,6 +462,12 @@ __device__ __forceinline__ void lcp_tile_paired_lds(const T* __restrict__ mu,
   auto load_row = [&](int rho) {  // logical row rho = vertex row j0 - 1 + rho, clamped
     const int y = min(max(j0 - 1 + rho, 0), ny - 1);
     lds_float* slot = ring + (rho % kRingRows) * kSlotFloats;
+    if constexpr (POISON) {
+      lds_u32* const words = reinterpret_cast<lds_u32*>(slot);
+      for (uint32_t w = lane; w < uint32_t(kSlotFloats); w += kWave) words[w] = 0x7fc00000u;
+      // the NaNs are in LDS before any row data can land on them
+      asm volatile("s_waitcnt lgkmcnt(0)" ::: "memory");
+    }
     const int64_t ro = static_cast<int64_t>(y) * nx;
     const T* planes[4] = {mu, vu, mv, vv};
 #pragma unroll
@@ -686,7 +696,7 @@ inline bool use_paired_tile(const float* out, int64_t pitch, int64_t plane, int 
 
 // The tile of layout PAIRED (paired tiles store non-temporally: their rows
 // start on 128-byte lines).
-template <int KC, bool FUSED, bool PAIRED, typename T>
+template <int KC, bool FUSED, bool PAIRED, typename T, bool POISON = false>
 __device__ __forceinline__ void lcp_tile(const T* __restrict__ p0, const T* __restrict__ p1,
                                          const T* __restrict__ p2, const T* __restrict__ p3,
                                          int ny, int nx, const StencilCoef& k,
@@ -694,8 +704,8 @@ __device__ __forceinline__ void lcp_tile(const T* __restrict__ p0, const T* __re
                                          float* __restrict__ out, int64_t plane, int64_t pitch,
                                          int strip, int j0, int j1) {
   if constexpr (PAIRED && FUSED)
-    lcp_tile_paired_lds<KC, true>(p0, p1, p2, p3, ny, nx, k, iso, n_store, out, plane, pitch,
-                                  strip, j0, j1);
+    lcp_tile_paired_lds<KC, true, T, POISON>(p0, p1, p2, p3, ny, nx, k, iso, n_store, out, plane,
+                                              pitch, strip, j0, j1);
   else if constexpr (PAIRED)
     lcp_tile_paired<KC, FUSED, true>(p0, p1, p2, p3, ny, nx, k, iso, n_store, out, plane, pitch,
                                      strip, j0, j1);

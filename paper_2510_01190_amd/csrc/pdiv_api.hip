@@ -1,13 +1,17 @@
 // C ABI of libpdiv: argument validation, dtype dispatch and launch of the
 // core calls.  Every check runs before any HIP call, so a rejected call
 // touches neither the device nor the outputs.
+#include <algorithm>
+#include <atomic>
 #include <cmath>
 #include <cstdarg>
 #include <cstdio>
+#include <cstdlib>
 #include <cstring>
 #include <mutex>
 #include <string>
 
+#include "pdiv_device.hpp"
 #include "pdiv_internal.hpp"
 
 namespace pdiv {
@@ -31,6 +35,30 @@ pdiv_status invalid(const char* fmt, ...) {
   va_end(ap);
   g_last_error = buf;
   return PDIV_ERR_INVALID;
+}
+
+// --- checking modes --------------------------------------------------------
+uint32_t initial_debug_flags() {
+  uint32_t f = 0;
+  const char* c = std::getenv("PDIV_DEBUG_CHECKS");
+  if (c && *c && std::strcmp(c, "0") != 0) f |= PDIV_DEBUG_CHECK_INPUTS;
+  const char* l = std::getenv("PDIV_LOG");
+  if (l && *l && std::strcmp(l, "0") != 0) f |= PDIV_DEBUG_LOG;
+  return f;
+}
+std::atomic<uint32_t> g_debug{initial_debug_flags()};
+uint32_t debug_flags() { return g_debug.load(std::memory_order_relaxed); }
+void set_debug_flags(uint32_t flags) { g_debug.store(flags, std::memory_order_relaxed); }
+
+// One line per core call on stderr under PDIV_DEBUG_LOG.
+void log_call(const char* fmt, ...) {
+  if (!(debug_flags() & PDIV_DEBUG_LOG)) return;
+  char buf[512];
+  va_list ap;
+  va_start(ap, fmt);
+  std::vsnprintf(buf, sizeof buf, fmt, ap);
+  va_end(ap);
+  std::fprintf(stderr, "[pdiv] %s\n", buf);
 }
 
 pdiv_status device_status(hipError_t e, const char* what) {
@@ -192,6 +220,85 @@ hipError_t run_spaghetti(const void* u_members, const void* v_members, pdiv_dtyp
 }
 
 // ---------------------------------------------------------------------------
+// PDIV_DEBUG_CHECK_INPUTS: a scan of the moment (or divergence) planes for
+// non-finite values and negative variances, counted in a device word.
+// ---------------------------------------------------------------------------
+static __device__ unsigned int check_count;
+
+__global__ void check_zero_kernel(unsigned int* c) { *c = 0u; }
+
+template <typename T>
+__global__ __launch_bounds__(256) void check_planes_kernel(const T* __restrict__ m0,
+                                                           const T* __restrict__ v0,
+                                                           const T* __restrict__ m1,
+                                                           const T* __restrict__ v1, int64_t n,
+                                                           unsigned int* __restrict__ bad) {
+  unsigned int b = 0;
+  for (int64_t p = int64_t(blockIdx.x) * 256 + threadIdx.x; p < n;
+       p += int64_t(gridDim.x) * 256) {
+    const float a = to_f32(m0[p]), c = to_f32(m1[p]), va = to_f32(v0[p]), vc = to_f32(v1[p]);
+    b |= unsigned(!__builtin_isfinite(a)) | unsigned(!__builtin_isfinite(c)) |
+         unsigned(!(__builtin_isfinite(va) && va >= 0.0f)) |
+         unsigned(!(__builtin_isfinite(vc) && vc >= 0.0f));
+  }
+  if (b) atomicAdd(bad, 1u);
+}
+
+std::mutex g_check_mu;
+unsigned int* g_check_ptr[64] = {};
+
+// Scans the planes of a call under PDIV_DEBUG_CHECK_INPUTS (waits for the
+// stream); PDIV_OK when every value is admissible.
+pdiv_status check_inputs(const void* m0, const void* v0, const void* m1, const void* v1,
+                         pdiv_dtype dt, int64_t n, hipStream_t s, const char* call) {
+  if (!(debug_flags() & PDIV_DEBUG_CHECK_INPUTS)) return PDIV_OK;
+  int dev = -1;
+  hipError_t e = hipGetDevice(&dev);
+  if (e != hipSuccess) return device_status(e, "hipGetDevice");
+  if (dev < 0 || dev >= 64) {
+    set_error("device index %d beyond the checking table", dev);
+    return PDIV_ERR_UNSUPPORTED;
+  }
+  unsigned int* cnt = nullptr;
+  {
+    std::lock_guard<std::mutex> lock(g_check_mu);
+    if (!g_check_ptr[dev]) {
+      void* p = nullptr;
+      e = hipGetSymbolAddress(&p, HIP_SYMBOL(check_count));
+      if (e != hipSuccess) return device_status(e, "hipGetSymbolAddress(check_count)");
+      g_check_ptr[dev] = static_cast<unsigned int*>(p);
+    }
+    cnt = g_check_ptr[dev];
+  }
+  const unsigned grid = unsigned(std::min<int64_t>((n + 255) / 256, 4096));
+  hipLaunchKernelGGL(check_zero_kernel, dim3(1), dim3(1), 0, s, cnt);
+  switch (dt) {
+    case PDIV_F32:
+      hipLaunchKernelGGL(check_planes_kernel<float>, dim3(grid), dim3(256), 0, s,
+                         static_cast<const float*>(m0), static_cast<const float*>(v0),
+                         static_cast<const float*>(m1), static_cast<const float*>(v1), n, cnt);
+      break;
+    case PDIV_F16:
+      hipLaunchKernelGGL(check_planes_kernel<__half>, dim3(grid), dim3(256), 0, s,
+                         static_cast<const __half*>(m0), static_cast<const __half*>(v0),
+                         static_cast<const __half*>(m1), static_cast<const __half*>(v1), n, cnt);
+      break;
+    default:
+      hipLaunchKernelGGL(check_planes_kernel<bf16_t>, dim3(grid), dim3(256), 0, s,
+                         static_cast<const bf16_t*>(m0), static_cast<const bf16_t*>(v0),
+                         static_cast<const bf16_t*>(m1), static_cast<const bf16_t*>(v1), n, cnt);
+      break;
+  }
+  unsigned int host = 0;
+  e = hipGetLastError();
+  e = e != hipSuccess ? e : hipMemcpyAsync(&host, cnt, sizeof host, hipMemcpyDeviceToHost, s);
+  e = e != hipSuccess ? e : hipStreamSynchronize(s);
+  if (e != hipSuccess) return device_status(e, "input check");
+  if (host) return invalid("%s: input planes hold non-finite values or negative variances", call);
+  return PDIV_OK;
+}
+
+// ---------------------------------------------------------------------------
 // Workspace of pdiv_spaghetti_noalloc: the members' divergence planes live in
 // this file-scope device array instead of a caller's buffer.  Its name is a
 // host-side stand-in in host code; the device address of each GPU's copy is
@@ -240,6 +347,14 @@ pdiv_status pdiv_set_lcp_band_rows(int32_t rows) {
   return PDIV_OK;
 }
 
+pdiv_status pdiv_set_debug(uint32_t flags) {
+  g_last_error.clear();
+  const uint32_t known = PDIV_DEBUG_POISON_LDS | PDIV_DEBUG_CHECK_INPUTS | PDIV_DEBUG_LOG;
+  if (flags & ~known) return invalid("unknown debug flags 0x%x", flags & ~known);
+  set_debug_flags(flags);
+  return PDIV_OK;
+}
+
 const char* pdiv_last_error(void) { return g_last_error.c_str(); }
 
 const char* pdiv_status_string(pdiv_status s) {
@@ -260,6 +375,8 @@ pdiv_status pdiv_moments(const void* u_members, const void* v_members, pdiv_dtyp
                          int32_t ddof, void* mean_u, void* var_u, void* mean_v, void* var_v,
                          pdiv_dtype out_dtype, pdiv_stream stream) {
   g_last_error.clear();
+  log_call("pdiv_moments members=%lld ny=%lld nx=%lld in=%d out=%d ddof=%d", (long long)n_members,
+           (long long)ny, (long long)nx, int(in_dtype), int(out_dtype), ddof);
   PDIV_NONNULL(u_members);
   PDIV_NONNULL(v_members);
   PDIV_NONNULL(mean_u);
@@ -290,6 +407,8 @@ pdiv_status pdiv_speed_gradient_moments(const void* u_members, const void* v_mem
                                         void* mean_gy, void* var_gy, pdiv_dtype out_dtype,
                                         pdiv_stream stream) {
   g_last_error.clear();
+  log_call("pdiv_speed_gradient_moments members=%lld ny=%lld nx=%lld in=%d", (long long)n_members,
+           (long long)ny, (long long)nx, int(in_dtype));
   PDIV_NONNULL(u_members);
   PDIV_NONNULL(v_members);
   PDIV_NONNULL(mean_gx);
@@ -322,6 +441,8 @@ pdiv_status pdiv_divergence_gaussian(const void* mean_u, const void* var_u, cons
                                      int64_t nx, double dx, double dy, float* div_mean,
                                      float* div_var, pdiv_stream stream) {
   g_last_error.clear();
+  log_call("pdiv_divergence_gaussian ny=%lld nx=%lld in=%d", (long long)ny, (long long)nx,
+           int(in_dtype));
   PDIV_NONNULL(mean_u);
   PDIV_NONNULL(var_u);
   PDIV_NONNULL(mean_v);
@@ -331,6 +452,8 @@ pdiv_status pdiv_divergence_gaussian(const void* mean_u, const void* var_u, cons
   PDIV_TRY(check_dtype(in_dtype, "in_dtype"));
   PDIV_TRY(check_grid(ny, nx));
   PDIV_TRY(check_spacing(dx, dy));
+  PDIV_TRY(check_inputs(mean_u, var_u, mean_v, var_v, in_dtype, ny * nx,
+                        static_cast<hipStream_t>(stream), "pdiv_divergence_gaussian"));
   return device_status(launch_divergence(mean_u, var_u, mean_v, var_v, in_dtype, ny, nx,
                                          make_coef(dx, dy), div_mean, div_var,
                                          static_cast<hipStream_t>(stream)),
@@ -341,6 +464,8 @@ pdiv_status pdiv_lcp(const float* div_mean, const float* div_var, int64_t ny, in
                      const float* isovalues_host, int32_t n_iso, float* lcp,
                      int64_t lcp_row_pitch, int64_t lcp_plane_stride, pdiv_stream stream) {
   g_last_error.clear();
+  log_call("pdiv_lcp ny=%lld nx=%lld n_iso=%d pitch=%lld plane=%lld", (long long)ny,
+           (long long)nx, n_iso, (long long)lcp_row_pitch, (long long)lcp_plane_stride);
   PDIV_NONNULL(div_mean);
   PDIV_NONNULL(div_var);
   PDIV_NONNULL(lcp);
@@ -348,6 +473,8 @@ pdiv_status pdiv_lcp(const float* div_mean, const float* div_var, int64_t ny, in
   PDIV_TRY(check_iso(isovalues_host, n_iso));
   OutLayout lo;
   PDIV_TRY(check_layout(lcp_row_pitch, lcp_plane_stride, ny, nx, n_iso, &lo));
+  PDIV_TRY(check_inputs(div_mean, div_var, div_mean, div_var, PDIV_F32, ny * nx,
+                        static_cast<hipStream_t>(stream), "pdiv_lcp"));
   return lcp_chunks(false, div_mean, div_var, nullptr, nullptr, PDIV_F32, ny, nx, 1.0, 1.0,
                     isovalues_host, n_iso, lcp, lo, static_cast<hipStream_t>(stream));
 }
@@ -359,6 +486,9 @@ pdiv_status pdiv_lcp_from_moments(const void* mean_u, const void* var_u, const v
                                   int64_t lcp_row_pitch, int64_t lcp_plane_stride,
                                   pdiv_stream stream) {
   g_last_error.clear();
+  log_call("pdiv_lcp_from_moments ny=%lld nx=%lld in=%d n_iso=%d pitch=%lld plane=%lld",
+           (long long)ny, (long long)nx, int(in_dtype), n_iso, (long long)lcp_row_pitch,
+           (long long)lcp_plane_stride);
   PDIV_NONNULL(mean_u);
   PDIV_NONNULL(var_u);
   PDIV_NONNULL(mean_v);
@@ -370,6 +500,8 @@ pdiv_status pdiv_lcp_from_moments(const void* mean_u, const void* var_u, const v
   PDIV_TRY(check_iso(isovalues_host, n_iso));
   OutLayout lo;
   PDIV_TRY(check_layout(lcp_row_pitch, lcp_plane_stride, ny, nx, n_iso, &lo));
+  PDIV_TRY(check_inputs(mean_u, var_u, mean_v, var_v, in_dtype, ny * nx,
+                        static_cast<hipStream_t>(stream), "pdiv_lcp_from_moments"));
   return lcp_chunks(true, mean_u, var_u, mean_v, var_v, in_dtype, ny, nx, dx, dy,
                     isovalues_host, n_iso, lcp, lo, static_cast<hipStream_t>(stream));
 }
@@ -378,6 +510,8 @@ pdiv_status pdiv_isocontour(const float* field, int64_t ny, int64_t nx, float is
                             int64_t* row_offsets, float* segments, int64_t max_segments,
                             pdiv_stream stream) {
   g_last_error.clear();
+  log_call("pdiv_isocontour ny=%lld nx=%lld max_segments=%lld", (long long)ny, (long long)nx,
+           (long long)max_segments);
   PDIV_NONNULL(field);
   PDIV_NONNULL(row_offsets);
   PDIV_TRY(check_grid(ny, nx));
@@ -397,6 +531,8 @@ pdiv_status pdiv_spaghetti(const void* u_members, const void* v_members, pdiv_dt
                            int64_t* row_offsets, float* segments, int64_t max_segments,
                            pdiv_stream stream) {
   g_last_error.clear();
+  log_call("pdiv_spaghetti members=%lld ny=%lld nx=%lld", (long long)n_members, (long long)ny,
+           (long long)nx);
   PDIV_NONNULL(div_workspace);
   PDIV_TRY(check_spaghetti(u_members, v_members, in_dtype, n_members, ny, nx, &member_stride,
                            dx, dy, row_offsets, segments, max_segments));
@@ -413,6 +549,8 @@ pdiv_status pdiv_spaghetti_noalloc(const void* u_members, const void* v_members,
                                    float isovalue, int64_t* row_offsets, float* segments,
                                    int64_t max_segments, pdiv_stream stream) {
   g_last_error.clear();
+  log_call("pdiv_spaghetti_noalloc members=%lld ny=%lld nx=%lld", (long long)n_members,
+           (long long)ny, (long long)nx);
   PDIV_TRY(check_spaghetti(u_members, v_members, in_dtype, n_members, ny, nx, &member_stride,
                            dx, dy, row_offsets, segments, max_segments));
   if (n_members * ny * nx > kScratchFloats)
@@ -434,6 +572,8 @@ pdiv_status pdiv_divergence_gaussian_3d(const void* mean_u, const void* var_u,
                                         double dx, double dy, double dz, float* div_mean,
                                         float* div_var, pdiv_stream stream) {
   g_last_error.clear();
+  log_call("pdiv_divergence_gaussian_3d nz=%lld ny=%lld nx=%lld", (long long)nz, (long long)ny,
+           (long long)nx);
   PDIV_NONNULL(mean_u);
   PDIV_NONNULL(var_u);
   PDIV_NONNULL(mean_v);
@@ -481,6 +621,8 @@ pdiv_status pdiv_lcp_3d(const float* div_mean, const float* div_var, int64_t nz,
                         int64_t nx, const float* isovalues_host, int32_t n_iso, float* lcp,
                         pdiv_stream stream) {
   g_last_error.clear();
+  log_call("pdiv_lcp_3d nz=%lld ny=%lld nx=%lld n_iso=%d", (long long)nz, (long long)ny,
+           (long long)nx, n_iso);
   PDIV_NONNULL(div_mean);
   PDIV_NONNULL(div_var);
   PDIV_NONNULL(lcp);
@@ -497,6 +639,8 @@ pdiv_status pdiv_lcp_3d_from_moments(const void* mean_u, const void* var_u, cons
                                      const float* isovalues_host, int32_t n_iso, float* lcp,
                                      pdiv_stream stream) {
   g_last_error.clear();
+  log_call("pdiv_lcp_3d_from_moments nz=%lld ny=%lld nx=%lld n_iso=%d", (long long)nz,
+           (long long)ny, (long long)nx, n_iso);
   PDIV_NONNULL(mean_u);
   PDIV_NONNULL(var_u);
   PDIV_NONNULL(mean_v);
@@ -520,6 +664,8 @@ pdiv_status pdiv_mc_lcp(const void* mean_u, const void* var_u, const void* mean_
                         int64_t n_samples, uint64_t seed, uint32_t mode, float* lcp,
                         pdiv_stream stream) {
   g_last_error.clear();
+  log_call("pdiv_mc_lcp ny=%lld nx=%lld n_iso=%d samples=%lld mode=%u", (long long)ny,
+           (long long)nx, n_iso, (long long)n_samples, mode);
   PDIV_NONNULL(mean_u);
   PDIV_NONNULL(var_u);
   PDIV_NONNULL(mean_v);
@@ -538,6 +684,8 @@ pdiv_status pdiv_mc_lcp(const void* mean_u, const void* var_u, const void* mean_
   if (!launch_fits(mc_tiles_x(nx), 256) || !launch_fits(mc_tiles_y(ny), 256))
     return invalid("grid of %lld x %lld points is too large for one Monte Carlo launch",
                    (long long)ny, (long long)nx);
+  PDIV_TRY(check_inputs(mean_u, var_u, mean_v, var_v, in_dtype, ny * nx,
+                        static_cast<hipStream_t>(stream), "pdiv_mc_lcp"));
   const StencilCoef k = make_coef(dx, dy);
   const int64_t plane = (ny - 1) * (nx - 1);
   for (int32_t k0 = 0; k0 < n_iso; k0 += kIsoChunk) {

@@ -57,9 +57,16 @@ pdiv_status check_layout(int64_t row_pitch, int64_t plane_stride, int64_t ny, in
 // cell rows; 0 lets the launcher choose per layout.
 struct LcpShape {
   int band_rows;
+  bool poison;  // PDIV_DEBUG_POISON_LDS: NaN-fill the LDS ring slots
 };
 LcpShape default_lcp_shape(int64_t ny, int64_t nx, int n_iso);
 void set_band_rows_override(int rows);
+
+// Process-wide checking modes (PDIV_DEBUG_* of pdiv_set_debug; the
+// environment variables PDIV_DEBUG_CHECKS and PDIV_LOG set their bits at
+// load).
+uint32_t debug_flags();
+void set_debug_flags(uint32_t flags);
 
 hipError_t launch_moments(const void* u, const void* v, pdiv_dtype in_dtype, int64_t m,
                           int64_t n_points, int64_t stride, int ddof, void* mu, void* vu,

@@ -261,3 +261,28 @@ def test_spaghetti_rejects_bad_arguments():
     # 4096 members of 1024 x 1024: 2^32 threads in one launch
     _expect_invalid(L.pdiv_spaghetti(FAKE, FAKE, 0, 4096, 1024, 1024, 0, 1.0, 1.0, c, FAKE, FAKE,
                                      FAKE, 4, NUL), "n_members")
+
+
+def test_debug_flags_reject_unknown_bits():
+    L = P.lib()
+    _expect_invalid(L.pdiv_set_debug(8), "unknown debug flags")
+    assert L.pdiv_set_debug(0) == 0
+    assert L.pdiv_set_debug(1 | 2 | 4) == 0
+    assert L.pdiv_set_debug(0) == 0
+
+
+def test_log_mode_writes_one_line_per_call():
+    """PDIV_LOG=1 at load: each core call (even one that is rejected) writes
+    its name and sizes to stderr; without it nothing is written."""
+    import subprocess
+    import sys
+    code = ("import ctypes, sys; sys.path.insert(0, %r); import paper_2510_01190_amd as P; "
+            "L = P.lib(); iso = (ctypes.c_float * 1)(0.0); "
+            "print(L.pdiv_lcp(ctypes.c_void_p(0x1000), ctypes.c_void_p(0x1000), 1, 8, iso, 1, "
+            "ctypes.c_void_p(0x1000), 0, 0, None))" % ROOT)
+    for env_val, expect in (("1", True), ("0", False)):
+        env = dict(os.environ, PDIV_LOG=env_val)
+        r = subprocess.run([sys.executable, "-c", code], capture_output=True, text=True, env=env,
+                           timeout=120)
+        assert r.stdout.strip() == str(INVALID)
+        assert ("[pdiv] pdiv_lcp ny=1 nx=8 n_iso=1" in r.stderr) == expect, r.stderr

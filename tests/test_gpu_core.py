@@ -390,3 +390,60 @@ def test_extreme_aspect_ratios(shape, k):
     for out in (None, P.empty_lcp(k, ny, nx), P.empty_lcp(k, ny, nx, interleave_rows=True)):
         g = host64(P.lcp_from_moments(*ts, iso, out=out))
         assert np.max(np.abs(g - ref)) <= LCP_TOL
+
+
+def test_band_heights_under_lds_poison():
+    """The band-height sweep of the LDS-staged paired tile with every ring
+    slot filled with NaN before its row's loads (PDIV_DEBUG_POISON_LDS): a
+    read that ran ahead of its load would put NaN in the maps; every band
+    height must still give bitwise the maps of the default run."""
+    ny, nx = 61, 300
+    f = _field(ny, nx, seed=77)
+    ts = moments_dev(f, "f32")
+    P.set_lcp_band_rows(0)
+    for k in (16, 9, 1):
+        iso = np.linspace(-0.08, 0.08, k).astype(np.float32)
+        ref = P.lcp_from_moments(*ts, iso, out=P.empty_lcp(iso.size, ny, nx))
+        torch.cuda.synchronize()
+        try:
+            P.set_debug(P.DEBUG_POISON_LDS)
+            for rows in (0, 1, 2, 3, 4, 5, 6, 7, 13, 64):
+                P.set_lcp_band_rows(rows)
+                got = P.lcp_from_moments(*ts, iso, out=P.empty_lcp(iso.size, ny, nx))
+                torch.cuda.synchronize()
+                assert not torch.isnan(got).any(), (k, rows)
+                assert torch.equal(got, ref), (k, rows)
+        finally:
+            P.set_debug(0)
+            P.set_lcp_band_rows(0)
+
+
+def test_input_checks_reject_bad_values():
+    """PDIV_DEBUG_CHECK_INPUTS: a negative variance or a non-finite mean is
+    reported as PDIV_ERR_INVALID before any work; admissible inputs pass and
+    give the same maps as without the checks."""
+    ny, nx = 40, 70
+    f = _field(ny, nx, seed=78)
+    iso = np.array([0.0, 0.01], np.float32)
+    good = moments_dev(f)
+    ref = P.lcp_from_moments(*good, iso)
+    try:
+        P.set_debug(P.DEBUG_CHECK_INPUTS)
+        assert torch.equal(P.lcp_from_moments(*good, iso), ref)
+        bad_var = [t.clone() for t in good]
+        bad_var[3][7, 9] = -1e-3
+        bad_mean = [t.clone() for t in good]
+        bad_mean[0][3, 5] = float("nan")
+        for ts in (bad_var, bad_mean):
+            for call in (lambda: P.lcp_from_moments(*ts, iso),
+                         lambda: P.divergence_gaussian(*ts),
+                         lambda: P.mc_lcp(*ts, iso, n_samples=4, seed=1)):
+                with pytest.raises(P.PdivError) as e:
+                    call()
+                assert e.value.status == 1 and "non-finite" in str(e.value)
+        dm, dv = P.divergence_gaussian(*good)
+        dv[0, 0] = -1.0
+        with pytest.raises(P.PdivError):
+            P.lcp(dm, dv, iso)
+    finally:
+        P.set_debug(0)
