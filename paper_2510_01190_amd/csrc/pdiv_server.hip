@@ -31,13 +31,14 @@
 #include <vector>
 
 #include "batch_internal.hpp"
+#include "server_core.hpp"
 
 using Clock = std::chrono::steady_clock;
 using namespace pdiv;
 
 namespace {
 
-constexpr int kMaxBatch = 512;   // slider requests per launch
+constexpr int kMaxBatch = serve::kMaxBatch;
 constexpr int kBandRows = 16;    // tile height of server launches
 constexpr int kMaxStreams = 8;
 // Pinned staging buffers come in power-of-two size classes from 1 MiB up and
@@ -78,43 +79,10 @@ void staged_copy(char* dst, const void* const* src, int n_parts, size_t part) {
 
 size_t dtype_bytes(pdiv_dtype d) { return d == PDIV_F32 ? 4 : 2; }
 
-struct ServerField {
-  uint64_t id = 0;
-  int ny = 0, nx = 0;
-  double dx = 1, dy = 1;
-  float* dmean = nullptr;
-  float* dvar = nullptr;
-  size_t bytes = 0;
-  bool ready = false;
-  bool failed = false;  // its upload or divergence launch failed
-  uint64_t last_use = 0;
-  int refs = 0;  // requests (queued or in flight) that name this field
-};
-
 struct PinnedBuf {
   void* p = nullptr;
   size_t bytes = 0;
   bool busy = false;
-};
-
-enum class Kind { kNew, kSlider };
-
-struct Request {
-  uint64_t ticket = 0;
-  Kind kind = Kind::kSlider;
-  uint64_t fid = 0;
-  // new field
-  PinnedBuf* host = nullptr;
-  pdiv_dtype dtype = PDIV_F32;
-  int ny = 0, nx = 0;
-  double dx = 1, dy = 1;
-  // slider
-  float iso[kIsoChunk] = {};
-  int n_iso = 0;
-  float* out = nullptr;
-  Clock::time_point t_submit;
-  pdiv_status status = PDIV_OK;
-  bool done = false;
 };
 
 struct Slot {  // descriptor table + isovalues of one slider launch
@@ -122,17 +90,11 @@ struct Slot {  // descriptor table + isovalues of one slider launch
   float* dev_iso = nullptr;
   BatchField* host_fields = nullptr;  // pinned
   float* host_iso = nullptr;          // pinned
-  bool busy = false;
 };
 
-struct Launch {
+struct Pending {  // device side of one in-flight handle
   hipEvent_t ev = nullptr;
-  std::vector<Request*> reqs;
-  int slot = -1;
   void* staging = nullptr;  // device staging of a new field
-  size_t staging_bytes = 0;
-  PinnedBuf* host = nullptr;
-  double cells = 0;
 };
 
 int fault_after() {  // PDIV_FAULT=server_launch:<n>: the n-th slider launch fails (n >= 1)
@@ -141,18 +103,17 @@ int fault_after() {  // PDIV_FAULT=server_launch:<n>: the n-th slider launch fai
   return std::atoi(f + 14);
 }
 
-double pct(std::vector<double> v, double p) {
-  if (v.empty()) return 0.0;
-  std::sort(v.begin(), v.end());
-  const double r = p * (v.size() - 1);
-  const size_t a = size_t(std::floor(r)), b = std::min(v.size() - 1, a + 1);
-  return v[a] + (v[b] - v[a]) * (r - a);
+double seconds_now() {
+  return std::chrono::duration<double>(Clock::now().time_since_epoch()).count();
 }
+
+static_assert(serve::kMaxIso == kIsoChunk, "slider requests carry one isovalue chunk");
 
 }  // namespace
 
-struct pdiv_server_s {
-  size_t budget = 0;
+// The policy (admission, eviction, merging, accounting) lives in serve::Core;
+// this object is its device executor, the pinned staging pool and the worker.
+struct pdiv_server_s : serve::Executor {
   int n_streams = 1;
   int device = 0;
   // private stream-ordered pool for resident fields and upload staging; it
@@ -169,27 +130,16 @@ struct pdiv_server_s {
   bool stop = false;
   std::thread worker;
 
-  std::unordered_map<uint64_t, std::unique_ptr<ServerField>> fields;
-  std::deque<Request*> queue;
-  std::unordered_map<uint64_t, std::unique_ptr<Request>> tickets;
-  std::vector<Launch> inflight;
+  std::unique_ptr<serve::Core> core;
+  std::unordered_map<uint64_t, std::unique_ptr<serve::Request>> tickets;
+  std::unordered_map<uint64_t, Pending> pending;
+  uint64_t next_handle = 1;
   std::vector<std::unique_ptr<PinnedBuf>> pinned;
   size_t pinned_total = 0, pinned_cap = kDefaultPinnedCap;
   uint64_t next_ticket = 1;
-  uint64_t clock = 0;
   int next_stream = 0;
-  int launches_issued = 0;
+  int slider_starts = 0;
   int fault_at = 0;
-
-  size_t resident = 0, peak = 0;
-  uint64_t done = 0, failed = 0, launches = 0;
-  double cells = 0;
-  std::vector<double> lat_new, lat_slider;
-
-  void account(int64_t delta) {
-    resident = size_t(int64_t(resident) + delta);
-    peak = std::max(peak, resident);
-  }
 
   // --- pinned host staging (reused, released at destroy) -------------------
   PinnedBuf* alloc_pinned(size_t cls) {
@@ -244,223 +194,126 @@ struct pdiv_server_s {
     }
   }
 
-  void finish(Request* r, pdiv_status st) {
-    r->status = st;
-    r->done = true;
-    const double us =
-        std::chrono::duration<double, std::micro>(Clock::now() - r->t_submit).count();
-    if (st == PDIV_OK) {
-      ++done;
-      (r->kind == Kind::kNew ? lat_new : lat_slider).push_back(us);
-    } else {
-      ++failed;
+  // --- serve::Executor (called by the core with mu held) --------------------
+  uint64_t record(hipError_t e, hipStream_t s, void* staging) {
+    Pending P;
+    P.staging = staging;
+    e = e != hipSuccess ? e : hipEventCreateWithFlags(&P.ev, hipEventDisableTiming);
+    e = e != hipSuccess ? e : hipEventRecord(P.ev, s);
+    if (e != hipSuccess) {
+      (void)hipGetLastError();
+      if (P.ev) (void)hipEventDestroy(P.ev);
+      if (staging) (void)hipFreeAsync(staging, upload);
+      return 0;
     }
-    auto it = fields.find(r->fid);
-    if (it != fields.end()) {
-      it->second->refs--;
-      if (r->kind == Kind::kNew && st != PDIV_OK) it->second->failed = true;
-    }
+    const uint64_t h = next_handle++;
+    pending[h] = P;
+    return h;
   }
 
-  // --- worker steps (called with mu held) -----------------------------------
-  void poll_completions() {
-    for (size_t i = 0; i < inflight.size();) {
-      Launch& L = inflight[i];
-      const hipError_t q = hipEventQuery(L.ev);
-      if (q == hipErrorNotReady) {
-        ++i;
-        continue;
-      }
-      const pdiv_status st = (q == hipSuccess) ? PDIV_OK : PDIV_ERR_DEVICE;
-      for (Request* r : L.reqs) {
-        if (r->kind == Kind::kNew) {
-          auto it = fields.find(r->fid);
-          if (it != fields.end()) it->second->ready = (st == PDIV_OK);
-        }
-        finish(r, st);
-      }
-      if (st == PDIV_OK) cells += L.cells;
-      if (L.slot >= 0) slots[L.slot].busy = false;
-      if (L.staging) {
-        (void)hipFreeAsync(L.staging, upload);
-        account(-int64_t(L.staging_bytes));
-      }
-      if (L.host) L.host->busy = false;
-      (void)hipEventDestroy(L.ev);
-      inflight.erase(inflight.begin() + i);
+  uint64_t start_upload(serve::Request* r, serve::Field* f, size_t staging_bytes) override {
+    const size_t n = size_t(r->ny) * size_t(r->nx);
+    void* staging = nullptr;
+    hipError_t e = hipMallocFromPoolAsync(&f->dev[0], 4 * n, pool, upload);
+    e = e != hipSuccess ? e : hipMallocFromPoolAsync(&f->dev[1], 4 * n, pool, upload);
+    e = e != hipSuccess ? e : hipMallocFromPoolAsync(&staging, staging_bytes, pool, upload);
+    e = e != hipSuccess ? e
+                        : hipMemcpyAsync(staging, static_cast<PinnedBuf*>(r->host)->p,
+                                         staging_bytes, hipMemcpyHostToDevice, upload);
+    const size_t pb = r->dtype_bytes * n;
+    char* s = static_cast<char*>(staging);
+    if (e == hipSuccess)
+      e = launch_divergence(s, s + pb, s + 2 * pb, s + 3 * pb, pdiv_dtype(r->dtype), r->ny,
+                            r->nx, make_coef(r->dx, r->dy), static_cast<float*>(f->dev[0]),
+                            static_cast<float*>(f->dev[1]), upload);
+    if (e != hipSuccess && staging) {
+      (void)hipGetLastError();
+      (void)hipFreeAsync(staging, upload);
+      staging = nullptr;
     }
+    return record(e, upload, staging);
   }
 
-  bool evict_for(size_t need) {
-    while (resident + need > budget) {
-      ServerField* victim = nullptr;
-      for (auto& kv : fields) {
-        ServerField* f = kv.second.get();
-        if ((f->ready || f->failed) && f->refs == 0 &&
-            (!victim || f->last_use < victim->last_use))
-          victim = f;
-      }
-      if (!victim) return false;
-      if (victim->dmean) (void)hipFreeAsync(victim->dmean, upload);
-      if (victim->dvar) (void)hipFreeAsync(victim->dvar, upload);
-      account(-int64_t(victim->bytes));
-      fields.erase(victim->id);
+  uint64_t start_sliders(const std::vector<serve::Request*>& take,
+                         const std::vector<serve::Field*>& fs, int slot) override {
+    Slot& S = slots[size_t(slot)];
+    int kc = 1;
+    std::vector<BatchField> fv(take.size());
+    for (size_t i = 0; i < take.size(); ++i) {
+      const serve::Request* r = take[i];
+      const serve::Field* f = fs[i];
+      BatchField& x = fv[i];
+      x = BatchField{};
+      x.p0 = f->dev[0];
+      x.p1 = f->dev[1];
+      x.p2 = x.p3 = nullptr;
+      x.lcp = r->out;
+      x.iso = S.dev_iso + i * kIsoChunk;
+      x.ny = f->ny;
+      x.nx = f->nx;
+      x.n_iso = r->n_iso;
+      x.pitch = f->nx - 1;
+      x.plane = int64_t(f->ny - 1) * x.pitch;
+      x.coef = make_coef(f->dx, f->dy);
+      std::memcpy(S.host_iso + i * kIsoChunk, r->iso, sizeof(float) * kIsoChunk);
+      kc = std::max(kc, iso_bucket(r->n_iso));
     }
-    return true;
+    const bool paired = kc >= 8 && all_rows_on_lines(fv);
+    const int64_t n_tiles = fill_tiles(fv, kBandRows, paired);
+    std::memcpy(S.host_fields, fv.data(), sizeof(BatchField) * fv.size());
+    hipStream_t s = streams[size_t(next_stream)];
+    next_stream = (next_stream + 1) % n_streams;
+    const void* kernel = batch_kernel_ptr(false, PDIV_F32, kc, paired);
+    const int grid =
+        int(std::max<int64_t>(1, std::min<int64_t>(resident_blocks(kernel), (n_tiles + 3) / 4)));
+    if (fault_at > 0 && ++slider_starts == fault_at)
+      return 0;  // forced from the host: nothing is enqueued
+    hipError_t e = hipMemcpyAsync(S.dev_fields, S.host_fields, sizeof(BatchField) * fv.size(),
+                                  hipMemcpyHostToDevice, s);
+    e = e != hipSuccess ? e
+                        : hipMemcpyAsync(S.dev_iso, S.host_iso,
+                                         sizeof(float) * kIsoChunk * fv.size(),
+                                         hipMemcpyHostToDevice, s);
+    e = e != hipSuccess
+            ? e
+            : launch_batch(kernel, S.dev_fields, int(fv.size()), n_tiles, kBandRows, grid, s);
+    return record(e, s, nullptr);
   }
 
-  void admit_new() {
-    for (auto it = queue.begin(); it != queue.end();) {
-      Request* r = *it;
-      if (r->kind != Kind::kNew) {
-        ++it;
-        continue;
-      }
-      const size_t n = size_t(r->ny) * r->nx;
-      const size_t res = 8 * n, stg = 4 * dtype_bytes(r->dtype) * n;
-      if (resident + res + stg > budget && !evict_for(res + stg)) break;  // keep FIFO order
-      ServerField* f = fields[r->fid].get();
-      Launch L;
-      hipError_t e =
-          hipMallocFromPoolAsync(reinterpret_cast<void**>(&f->dmean), 4 * n, pool, upload);
-      e = e != hipSuccess
-              ? e
-              : hipMallocFromPoolAsync(reinterpret_cast<void**>(&f->dvar), 4 * n, pool, upload);
-      e = e != hipSuccess ? e : hipMallocFromPoolAsync(&L.staging, stg, pool, upload);
-      e = e != hipSuccess ? e
-                          : hipMemcpyAsync(L.staging, r->host->p, stg, hipMemcpyHostToDevice, upload);
-      const size_t pb = dtype_bytes(r->dtype) * n;
-      char* s = static_cast<char*>(L.staging);
-      if (e == hipSuccess)
-        e = launch_divergence(s, s + pb, s + 2 * pb, s + 3 * pb, r->dtype, r->ny, r->nx,
-                              make_coef(r->dx, r->dy), f->dmean, f->dvar, upload);
-      e = e != hipSuccess ? e : hipEventCreateWithFlags(&L.ev, hipEventDisableTiming);
-      e = e != hipSuccess ? e : hipEventRecord(L.ev, upload);
-      it = queue.erase(it);
-      f->bytes = res;
-      account(int64_t(res + stg));
-      if (e != hipSuccess) {
-        (void)hipGetLastError();
-        r->host->busy = false;
-        account(-int64_t(stg));
-        finish(r, PDIV_ERR_DEVICE);
-        continue;
-      }
-      L.staging_bytes = stg;
-      L.host = r->host;
-      L.reqs.push_back(r);
-      inflight.push_back(L);
-    }
+  int poll(uint64_t h) override {
+    const hipError_t q = hipEventQuery(pending[h].ev);
+    if (q == hipErrorNotReady) return 0;
+    return q == hipSuccess ? 1 : -1;
   }
 
-  void launch_sliders() {
-    while (true) {
-      int slot = -1;
-      for (size_t i = 0; i < slots.size(); ++i)
-        if (!slots[i].busy) {
-          slot = int(i);
-          break;
-        }
-      if (slot < 0) return;
-      std::vector<Request*> take;
-      for (auto it = queue.begin(); it != queue.end() && int(take.size()) < kMaxBatch;) {
-        Request* r = *it;
-        if (r->kind == Kind::kSlider) {
-          auto f = fields.find(r->fid);
-          if (f != fields.end() && f->second->failed) {  // its field never arrived
-            it = queue.erase(it);
-            finish(r, PDIV_ERR_DEVICE);
-            continue;
-          }
-          if (f != fields.end() && f->second->ready) {
-            take.push_back(r);
-            it = queue.erase(it);
-            continue;
-          }
-        }
-        ++it;
-      }
-      if (take.empty()) return;
-      Slot& S = slots[slot];
-      int kc = 1;
-      double cells_here = 0;
-      std::vector<BatchField> fv(take.size());
-      for (size_t i = 0; i < take.size(); ++i) {
-        Request* r = take[i];
-        ServerField* f = fields[r->fid].get();
-        f->last_use = ++clock;
-        BatchField& x = fv[i];
-        x = BatchField{};
-        x.p0 = f->dmean;
-        x.p1 = f->dvar;
-        x.p2 = x.p3 = nullptr;
-        x.lcp = r->out;
-        x.iso = S.dev_iso + i * kIsoChunk;
-        x.ny = f->ny;
-        x.nx = f->nx;
-        x.n_iso = r->n_iso;
-        x.pitch = f->nx - 1;
-        x.plane = int64_t(f->ny - 1) * x.pitch;
-        x.coef = make_coef(f->dx, f->dy);
-        std::memcpy(S.host_iso + i * kIsoChunk, r->iso, sizeof(float) * kIsoChunk);
-        kc = std::max(kc, iso_bucket(r->n_iso));
-        cells_here += double(x.plane) * r->n_iso;
-      }
-      const bool paired = kc >= 8 && all_rows_on_lines(fv);
-      const int64_t n_tiles = fill_tiles(fv, kBandRows, paired);
-      std::memcpy(S.host_fields, fv.data(), sizeof(BatchField) * fv.size());
-      hipStream_t s = streams[next_stream];
-      next_stream = (next_stream + 1) % n_streams;
-      const void* kernel = batch_kernel_ptr(false, PDIV_F32, kc, paired);
-      const int grid =
-          int(std::max<int64_t>(1, std::min<int64_t>(resident_blocks(kernel), (n_tiles + 3) / 4)));
-      Launch L;
-      L.slot = slot;
-      L.reqs = take;
-      L.cells = cells_here;
-      ++launches_issued;
-      hipError_t e = hipSuccess;
-      if (fault_at > 0 && launches_issued == fault_at) {
-        e = hipErrorLaunchFailure;  // forced from the host: nothing is enqueued
-      } else {
-        e = hipMemcpyAsync(S.dev_fields, S.host_fields, sizeof(BatchField) * fv.size(),
-                           hipMemcpyHostToDevice, s);
-        e = e != hipSuccess ? e
-                            : hipMemcpyAsync(S.dev_iso, S.host_iso,
-                                             sizeof(float) * kIsoChunk * fv.size(),
-                                             hipMemcpyHostToDevice, s);
-        e = e != hipSuccess ? e
-                            : launch_batch(kernel, S.dev_fields, int(fv.size()), n_tiles,
-                                           kBandRows, grid, s);
-        e = e != hipSuccess ? e : hipEventCreateWithFlags(&L.ev, hipEventDisableTiming);
-        e = e != hipSuccess ? e : hipEventRecord(L.ev, s);
-      }
-      if (e != hipSuccess) {
-        (void)hipGetLastError();
-        if (L.ev) (void)hipEventDestroy(L.ev);
-        for (Request* r : take) finish(r, PDIV_ERR_DEVICE);
-        continue;
-      }
-      ++launches;
-      S.busy = true;
-      inflight.push_back(L);
-    }
+  void release(uint64_t h) override {
+    auto it = pending.find(h);
+    if (it->second.staging) (void)hipFreeAsync(it->second.staging, upload);
+    (void)hipEventDestroy(it->second.ev);
+    pending.erase(it);
   }
+
+  void free_field(serve::Field* f) override {
+    for (void*& p : f->dev)
+      if (p) {
+        (void)hipFreeAsync(p, upload);
+        p = nullptr;
+      }
+  }
+
+  void return_host(void* host) override { static_cast<PinnedBuf*>(host)->busy = false; }
 
   void run() {
     (void)hipSetDevice(device);
     std::unique_lock<std::mutex> lk(mu);
     while (true) {
-      poll_completions();
-      admit_new();
-      launch_sliders();
+      core->step(*this);
       cv_done.notify_all();
-      if (stop && queue.empty() && inflight.empty()) break;
-      if (inflight.empty()) {
-        if (stop && !queue.empty()) {
+      if (stop && core->idle()) break;
+      if (core->nothing_in_flight()) {
+        if (stop) {
           // nothing in flight and nothing admissible: fail what is left
-          for (Request* r : queue) finish(r, PDIV_ERR_BUSY);
-          queue.clear();
+          core->fail_queued(serve::kBusy);
           continue;
         }
         cv_work.wait(lk);
@@ -488,7 +341,6 @@ pdiv_status pdiv_server_create(size_t hbm_budget, int32_t n_streams, pdiv_server
     return invalid("hbm_budget too small (need more than %zu bytes)",
                    size_t(n_slots) * slot_bytes + (size_t(1) << 20));
   auto srv = std::make_unique<pdiv_server_s>();
-  srv->budget = hbm_budget;
   srv->n_streams = n_streams;
   srv->fault_at = fault_after();
   hipError_t e = hipGetDevice(&srv->device);
@@ -522,7 +374,7 @@ pdiv_status pdiv_server_create(size_t hbm_budget, int32_t n_streams, pdiv_server
                                         hipHostMallocDefault);
   }
   srv->slot_bytes = size_t(n_slots) * slot_bytes;
-  srv->account(int64_t(srv->slot_bytes));
+  srv->core = std::make_unique<serve::Core>(hbm_budget, n_slots, srv->slot_bytes, seconds_now);
   pdiv_server raw = srv.release();
   if (e != hipSuccess) {
     device_status(e, "server create");
@@ -549,51 +401,47 @@ pdiv_status pdiv_server_put_field(pdiv_server srv, uint64_t id, const void* mean
   if (!(std::isfinite(dx) && dx > 0) || !(std::isfinite(dy) && dy > 0))
     return invalid("dx and dy must be finite and > 0");
   const size_t n = size_t(ny) * size_t(nx), pb = dtype_bytes(dtype) * n;
-  if (8 * n + 4 * pb + srv->slot_bytes > srv->budget) {
-    set_error("field of %zu points can never fit the %zu-byte budget", n, srv->budget);
+  if (8 * n + 4 * pb + srv->slot_bytes > srv->core->budget()) {
+    set_error("field of %zu points can never fit the %zu-byte budget", n, srv->core->budget());
     return PDIV_ERR_BUSY;
   }
-  std::unique_ptr<Request> r(new Request());
+  auto r = std::make_unique<serve::Request>();
   // latency counts from the call: waiting for staging and the host copy are
   // part of serving a new field
-  r->t_submit = Clock::now();
-  {
-    std::unique_lock<std::mutex> lk(srv->mu);
-    if (srv->stop) return invalid("server is shutting down");
-    if (srv->fields.count(id)) return invalid("field id %llu is in use", (unsigned long long)id);
-    r->host = srv->get_pinned(4 * pb, lk);
-    if (!r->host) {
-      set_error("cannot allocate %zu bytes of pinned staging", 4 * pb);
-      return PDIV_ERR_NOMEM;
-    }
-    if (srv->fields.count(id)) {  // taken while this call waited for staging
-      r->host->busy = false;
-      return invalid("field id %llu is in use", (unsigned long long)id);
-    }
-    auto f = std::make_unique<ServerField>();
-    f->id = id;
-    f->ny = int(ny);
-    f->nx = int(nx);
-    f->dx = dx;
-    f->dy = dy;
-    f->refs = 1;
-    f->last_use = ++srv->clock;
-    srv->fields[id] = std::move(f);
-  }
-  const void* const planes[4] = {mean_u_host, var_u_host, mean_v_host, var_v_host};
-  staged_copy(static_cast<char*>(r->host->p), planes, 4, pb);
-  r->kind = Kind::kNew;
+  r->t_submit = seconds_now();
   r->fid = id;
   r->dtype = dtype;
+  r->dtype_bytes = dtype_bytes(dtype);
   r->ny = int(ny);
   r->nx = int(nx);
   r->dx = dx;
   r->dy = dy;
+  PinnedBuf* host = nullptr;
+  {
+    std::unique_lock<std::mutex> lk(srv->mu);
+    if (srv->stop) return invalid("server is shutting down");
+    if (srv->core->has_field(id))
+      return invalid("field id %llu is in use", (unsigned long long)id);
+    host = srv->get_pinned(4 * pb, lk);
+    if (!host) {
+      set_error("cannot allocate %zu bytes of pinned staging", 4 * pb);
+      return PDIV_ERR_NOMEM;
+    }
+    if (srv->core->has_field(id)) {  // taken while this call waited for staging
+      host->busy = false;
+      return invalid("field id %llu is in use", (unsigned long long)id);
+    }
+    // registered now (not yet queued) so that the id stays taken during the copy
+    srv->core->reserve_field(r.get());
+  }
+  const void* const planes[4] = {mean_u_host, var_u_host, mean_v_host, var_v_host};
+  staged_copy(static_cast<char*>(host->p), planes, 4, pb);
+  r->host = host;
   {
     std::lock_guard<std::mutex> g(srv->mu);
     r->ticket = srv->next_ticket++;
     *ticket = r->ticket;
-    srv->queue.push_back(r.get());
+    srv->core->add_new(r.get());
     srv->tickets[r->ticket] = std::move(r);
   }
   srv->cv_work.notify_one();
@@ -640,23 +488,19 @@ pdiv_status pdiv_server_submit_lcp(pdiv_server srv, uint64_t id, const float* is
   g_last_error.clear();
   if (!srv || !isovalues_host || !out || !ticket) return invalid("NULL argument");
   if (n_iso < 1 || n_iso > kIsoChunk) return invalid("n_iso must be in [1, %d]", kIsoChunk);
-  std::unique_ptr<Request> r(new Request());
-  r->kind = Kind::kSlider;
+  auto r = std::make_unique<serve::Request>();
   r->fid = id;
   r->n_iso = n_iso;
   for (int q = 0; q < kIsoChunk; ++q) r->iso[q] = isovalues_host[q < n_iso ? q : n_iso - 1];
   r->out = out;
-  r->t_submit = Clock::now();
+  r->t_submit = seconds_now();
   {
     std::lock_guard<std::mutex> g(srv->mu);
     if (srv->stop) return invalid("server is shutting down");
-    auto f = srv->fields.find(id);
-    if (f == srv->fields.end())
+    if (!srv->core->add_slider(r.get()))
       return invalid("field id %llu is not resident", (unsigned long long)id);
-    f->second->refs++;
     r->ticket = srv->next_ticket++;
     *ticket = r->ticket;
-    srv->queue.push_back(r.get());
     srv->tickets[r->ticket] = std::move(r);
   }
   srv->cv_work.notify_one();
@@ -670,14 +514,14 @@ pdiv_status pdiv_server_wait(pdiv_server srv, uint64_t ticket, int64_t timeout_u
   std::unique_lock<std::mutex> lk(srv->mu);
   auto it = srv->tickets.find(ticket);
   if (it == srv->tickets.end()) return invalid("unknown ticket %llu", (unsigned long long)ticket);
-  Request* r = it->second.get();
+  serve::Request* r = it->second.get();
   if (timeout_us < 0) {
     srv->cv_done.wait(lk, [&] { return r->done; });
   } else if (!srv->cv_done.wait_for(lk, std::chrono::microseconds(timeout_us),
                                     [&] { return r->done; })) {
     return PDIV_ERR_TIMEOUT;
   }
-  *result = r->status;
+  *result = pdiv_status(r->status);
   srv->tickets.erase(it);
   return PDIV_OK;
 }
@@ -686,20 +530,19 @@ pdiv_status pdiv_server_stats(pdiv_server srv, pdiv_server_stats_t* out) {
   g_last_error.clear();
   if (!srv || !out) return invalid("NULL argument");
   std::lock_guard<std::mutex> g(srv->mu);
-  std::vector<double> all = srv->lat_new;
-  all.insert(all.end(), srv->lat_slider.begin(), srv->lat_slider.end());
-  out->done = srv->done;
-  out->failed = srv->failed;
-  out->launches = srv->launches;
-  out->p50_us = pct(all, 0.50);
-  out->p99_us = pct(all, 0.99);
-  out->p50_new_us = pct(srv->lat_new, 0.50);
-  out->p99_new_us = pct(srv->lat_new, 0.99);
-  out->p50_slider_us = pct(srv->lat_slider, 0.50);
-  out->p99_slider_us = pct(srv->lat_slider, 0.99);
-  out->lcp_cells = srv->cells;
-  out->resident_bytes = srv->resident;
-  out->peak_bytes = srv->peak;
+  const serve::Core::Stats s = srv->core->stats();
+  out->done = s.done;
+  out->failed = s.failed;
+  out->launches = s.launches;
+  out->p50_us = s.p50_us;
+  out->p99_us = s.p99_us;
+  out->p50_new_us = s.p50_new_us;
+  out->p99_new_us = s.p99_new_us;
+  out->p50_slider_us = s.p50_slider_us;
+  out->p99_slider_us = s.p99_slider_us;
+  out->lcp_cells = s.cells;
+  out->resident_bytes = s.resident;
+  out->peak_bytes = s.peak;
   return PDIV_OK;
 }
 
@@ -712,10 +555,7 @@ pdiv_status pdiv_server_destroy(pdiv_server srv) {
   }
   srv->cv_work.notify_all();
   if (srv->worker.joinable()) srv->worker.join();
-  for (auto& kv : srv->fields) {
-    if (kv.second->dmean) (void)hipFreeAsync(kv.second->dmean, srv->upload);
-    if (kv.second->dvar) (void)hipFreeAsync(kv.second->dvar, srv->upload);
-  }
+  if (srv->core) srv->core->free_all(*srv);
   if (srv->upload) (void)hipStreamSynchronize(srv->upload);
   for (auto& S : srv->slots) {
     if (S.dev_fields) (void)hipFree(S.dev_fields);
