@@ -346,35 +346,42 @@ def volume_leg(P, synth, torch, np, n=512):
                              "achieved_GBs": round(b / t / 1e9, 1),
                              "frac_hbm": round(b / t / 1e9 / HBM_PEAK_GBS, 4)}}
     sub = slabs[n // 2 - 2][0]
+
+    def timed(fn, b, k):
+        fn()
+        t = time_launches(fn, 10, torch)
+        return {"ms": round(t * 1e3, 4), "cells_per_s": round(k * cells / t, 1),
+                "algorithmic_bytes": b, "achieved_GBs": round(b / t / 1e9, 1),
+                "frac_hbm": round(b / t / 1e9 / HBM_PEAK_GBS, 4)}
+
     for k in (1, 4, 16):
         iso = np.quantile(sub, np.linspace(0.2, 0.8, k) if k > 1 else [0.5]).astype(np.float32)
-        o = torch.empty((k, n - 1, n - 1, n - 1), device="cuda")
-        P.lcp_3d(dm, dv, iso, out=o)
-        t = time_launches(lambda: P.lcp_3d(dm, dv, iso, out=o), 10, torch)
-        b = 8 * pts + 4 * k * cells
-        leg = {"ms": round(t * 1e3, 4), "cells_per_s": round(k * cells / t, 1),
-               "algorithmic_bytes": b, "achieved_GBs": round(b / t / 1e9, 1),
-               "frac_hbm": round(b / t / 1e9 / HBM_PEAK_GBS, 4)}
-        if k == 4:
-            worst = 0.0
-            for k0, (m, v) in slabs.items():
-                tc = time.perf_counter()
-                r = O.lcp_3d(m, v, iso)
-                tc = time.perf_counter() - tc
-                worst = max(worst, float(np.max(np.abs(
-                    o[:, k0:k0 + 2].double().cpu().numpy() - r))))
-            leg["max_abs_err_vs_fp64_oracle_sampled_layers"] = worst
-            leg["cpu_oracle_cells_per_s_1core"] = round(r.size / tc, 1)
-            out["two_step_k4_ms"] = round(out["divergence_3d"]["ms"] + leg["ms"], 4)
-        out[f"lcp_3d_k{k}"] = leg
-        # the two steps fused: the divergence volumes never reach HBM
-        P.lcp_3d_from_moments(*ts, iso, out=o)
-        t = time_launches(lambda: P.lcp_3d_from_moments(*ts, iso, out=o), 10, torch)
-        b = 6 * 4 * pts + 4 * k * cells
-        out[f"fused_3d_k{k}"] = {"ms": round(t * 1e3, 4), "cells_per_s": round(k * cells / t, 1),
-                                 "algorithmic_bytes": b, "achieved_GBs": round(b / t / 1e9, 1),
-                                 "frac_hbm": round(b / t / 1e9 / HBM_PEAK_GBS, 4)}
-        del o
+        b2 = 8 * pts + 4 * k * cells    # two-step LCP: divergence volumes in, maps out
+        bf = 6 * 4 * pts + 4 * k * cells  # fused: the six moment volumes in
+        # rows padded to 512 floats (whole-line stores: the 64-cell tile with
+        # the seam step), then dense [K][511][511][511] rows (63-cell tile)
+        for name, make in (("", lambda: P.empty_lcp_3d(k, n, n, n)),
+                           ("_dense", lambda: torch.empty((k, n - 1, n - 1, n - 1),
+                                                          device="cuda"))):
+            o = make()
+            leg = timed(lambda: P.lcp_3d(dm, dv, iso, out=o), b2, k)
+            if k == 4:
+                worst = 0.0
+                for k0, (m, v) in slabs.items():
+                    tc = time.perf_counter()
+                    r = O.lcp_3d(m, v, iso)
+                    tc = time.perf_counter() - tc
+                    worst = max(worst, float(np.max(np.abs(
+                        o[:, k0:k0 + 2].double().cpu().numpy() - r))))
+                leg["max_abs_err_vs_fp64_oracle_sampled_layers"] = worst
+                leg["cpu_oracle_cells_per_s_1core"] = round(r.size / tc, 1)
+                if not name:
+                    out["two_step_k4_ms"] = round(out["divergence_3d"]["ms"] + leg["ms"], 4)
+            out[f"lcp_3d_k{k}{name}"] = leg
+            # the two steps fused: the divergence volumes never reach HBM
+            out[f"fused_3d_k{k}{name}"] = timed(lambda: P.lcp_3d_from_moments(*ts, iso, out=o),
+                                                bf, k)
+            del o
     del dm, dv, ts
     return out
 

@@ -278,12 +278,21 @@ pdiv_status pdiv_divergence_gaussian_3d(const void* mean_u, const void* var_u,
  * crossing indicator).  Evaluated in float32 with one Gaussian tail per
  * corner and isovalue and the cancellation-free pairwise combination.
  * div_mean, div_var: [nz][ny][nx] float32 (device); isovalues_host: n_iso
- * floats in host memory, 1 <= n_iso <= PDIV_MAX_ISO; lcp: dense
- * [n_iso][nz-1][ny-1][nx-1] float32 (device), cell (i, j, k) having corners
- * (i+a, j+b, k+c), a, b, c in {0, 1}. */
+ * floats in host memory, 1 <= n_iso <= PDIV_MAX_ISO; lcp: n_iso maps of
+ * float32 cells (device), cell (q, k, j, i) -- corners (i+a, j+b, k+c), a, b,
+ * c in {0, 1} -- at lcp[q*plane_stride + (k*(ny-1) + j)*row_pitch + i].
+ * lcp_row_pitch: floats between rows (0: nx-1, dense; larger values pad the
+ * rows, and padding is never written); lcp_plane_stride: floats between maps
+ * (0: (nz-1)*(ny-1)*row_pitch; smaller values are PDIV_ERR_INVALID).  Rows
+ * that all start on 128-byte lines (lcp 128-byte aligned, row pitch and
+ * plane stride multiples of 32) are written as whole lines, the fastest
+ * layout on gfx950; every layout gives bitwise the same values.  A walk
+ * reads up to 7 z slices from one 32-bit-addressed base, so 7*ny*nx*4 bytes
+ * (2 bytes per element for 16-bit moments in the fused call) must stay
+ * below 2^31; larger slices are PDIV_ERR_INVALID. */
 pdiv_status pdiv_lcp_3d(const float* div_mean, const float* div_var, int64_t nz, int64_t ny,
                         int64_t nx, const float* isovalues_host, int32_t n_iso, float* lcp,
-                        pdiv_stream stream);
+                        int64_t lcp_row_pitch, int64_t lcp_plane_stride, pdiv_stream stream);
 
 /* The two 3D steps fused: Eq. 2-3 with the z term and the 8-corner LCP in
  * one pass over the six moment volumes (the divergence Gaussians never leave
@@ -294,6 +303,7 @@ pdiv_status pdiv_lcp_3d_from_moments(const void* mean_u, const void* var_u, cons
                                      pdiv_dtype in_dtype, int64_t nz, int64_t ny, int64_t nx,
                                      double dx, double dy, double dz,
                                      const float* isovalues_host, int32_t n_iso, float* lcp,
+                                     int64_t lcp_row_pitch, int64_t lcp_plane_stride,
                                      pdiv_stream stream);
 
 /* ------------------------------------------------------------------------

@@ -78,9 +78,9 @@ _SIGS = {
                                _c.c_float, _p, _p, _i64, _p],
     "pdiv_divergence_gaussian_3d": [_p, _p, _p, _p, _p, _p, _c.c_int, _i64, _i64, _i64, _f64,
                                     _f64, _f64, _p, _p, _p],
-    "pdiv_lcp_3d": [_p, _p, _i64, _i64, _i64, _fp, _i32, _p, _p],
+    "pdiv_lcp_3d": [_p, _p, _i64, _i64, _i64, _fp, _i32, _p, _i64, _i64, _p],
     "pdiv_lcp_3d_from_moments": [_p, _p, _p, _p, _p, _p, _c.c_int, _i64, _i64, _i64, _f64, _f64,
-                                 _f64, _fp, _i32, _p, _p],
+                                 _f64, _fp, _i32, _p, _i64, _i64, _p],
     "pdiv_mc_lcp": [_p, _p, _p, _p, _c.c_int, _i64, _i64, _f64, _f64, _fp, _i32, _i64, _u64,
                     _c.c_uint32, _p, _p],
     "pdiv_lcp_from_moments": [_p, _p, _p, _p, _c.c_int, _i64, _i64, _f64, _f64, _fp, _i32, _p,
@@ -202,6 +202,44 @@ def empty_lcp(k: int, ny: int, nx: int, pitch: int = None, interleave_rows: bool
         return buf.permute(1, 0, 2)[:, :, : nx - 1]
     buf = torch.empty((k, ny - 1, pitch), dtype=torch.float32, device=device)
     return buf[:, :, : nx - 1]
+
+
+def _lcp3_out(t, k, nz, ny, nx):
+    """Pointer, row pitch and map stride (floats) of a 3D LCP output: a
+    [k][nz-1][ny-1][nx-1] float32 device tensor whose cells are contiguous
+    within a row and whose layers are (ny-1) rows apart -- dense, or a view
+    such as empty_lcp_3d returns."""
+    if not t.is_cuda:
+        raise ValueError("out must be a device tensor")
+    if t.dtype != _torch().float32:
+        raise ValueError(f"out has dtype {t.dtype}, expected torch.float32")
+    shape = (k, nz - 1, ny - 1, nx - 1)
+    if tuple(t.shape) != shape:
+        raise ValueError(f"out has shape {tuple(t.shape)}, expected {shape}")
+    s0, s1, s2, s3 = t.stride()
+    if s3 != 1 and nx > 2:
+        raise ValueError("out: the cells of a row must be contiguous")
+    pitch = s2 if ny > 2 else (s1 if nz > 2 else max(s2, nx - 1))
+    if pitch < nx - 1:
+        raise ValueError("out: rows overlap")
+    if nz > 2 and s1 != (ny - 1) * pitch:
+        raise ValueError("out: layers must follow each other, (ny-1) rows apart")
+    plane = s0 if k > 1 else 0
+    return _p(t.data_ptr()), pitch, plane
+
+
+def empty_lcp_3d(k: int, nz: int, ny: int, nx: int, pitch: int = None, device="cuda"):
+    """Uninitialised 3D LCP output [k][nz-1][ny-1][nx-1] whose rows are
+    `pitch` floats long (default: nx-1 rounded up to a multiple of 32 floats,
+    so that every row starts on a 128-byte line, the layout the kernels write
+    fastest); padding floats are never written."""
+    torch = _torch()
+    if pitch is None:
+        pitch = (nx - 1 + 31) // 32 * 32
+    if pitch < nx - 1:
+        raise ValueError("pitch must be >= nx - 1")
+    buf = torch.empty((k, nz - 1, ny - 1, pitch), dtype=torch.float32, device=device)
+    return buf[..., : nx - 1]
 
 
 def _iso_arr(isovalues):
@@ -343,8 +381,9 @@ def divergence_gaussian_3d(mean_u, var_u, mean_v, var_v, mean_w, var_w, dx: floa
 
 def lcp_3d_from_moments(mean_u, var_u, mean_v, var_v, mean_w, var_w, isovalues,
                         dx: float = 1.0, dy: float = 1.0, dz: float = 1.0, out=None):
-    """Fused 3D Eq. 2-3 + 8-corner LCP [K][nz-1][ny-1][nx-1] (dense) from the
-    six [nz][ny][nx] moment volumes."""
+    """Fused 3D Eq. 2-3 + 8-corner LCP [K][nz-1][ny-1][nx-1] from the six
+    [nz][ny][nx] moment volumes; `out` may be dense or a row-padded view
+    (empty_lcp_3d)."""
     torch = _torch()
     nz, ny, nx = mean_u.shape
     dt = mean_u.dtype
@@ -352,27 +391,28 @@ def lcp_3d_from_moments(mean_u, var_u, mean_v, var_v, mean_w, var_w, isovalues,
             ((mean_u, "mean_u"), (var_u, "var_u"), (mean_v, "mean_v"), (var_v, "var_v"),
              (mean_w, "mean_w"), (var_w, "var_w"))]
     iso, ip = _iso_arr(isovalues)
-    shape = (iso.size, nz - 1, ny - 1, nx - 1)
     if out is None:
-        out = torch.empty(shape, dtype=torch.float32, device=mean_u.device)
-    po = _dev(out, "out", shape, torch.float32)
+        out = torch.empty((iso.size, nz - 1, ny - 1, nx - 1), dtype=torch.float32,
+                          device=mean_u.device)
+    po, pitch, plane = _lcp3_out(out, iso.size, nz, ny, nx)
     _check(lib().pdiv_lcp_3d_from_moments(*ptrs, _dtype_code(mean_u), nz, ny, nx, dx, dy, dz, ip,
-                                          iso.size, po, _stream()))
+                                          iso.size, po, pitch, plane, _stream()))
     return out
 
 
 def lcp_3d(div_mean, div_var, isovalues, out=None):
-    """8-corner LCP [K][nz-1][ny-1][nx-1] (dense) from 3D divergence Gaussians."""
+    """8-corner LCP [K][nz-1][ny-1][nx-1] from 3D divergence Gaussians; `out`
+    may be dense or a row-padded view (empty_lcp_3d)."""
     torch = _torch()
     nz, ny, nx = div_mean.shape
     pm = _dev(div_mean, "div_mean", (nz, ny, nx), torch.float32)
     pv = _dev(div_var, "div_var", (nz, ny, nx), torch.float32)
     iso, ip = _iso_arr(isovalues)
-    shape = (iso.size, nz - 1, ny - 1, nx - 1)
     if out is None:
-        out = torch.empty(shape, dtype=torch.float32, device=div_mean.device)
-    po = _dev(out, "out", shape, torch.float32)
-    _check(lib().pdiv_lcp_3d(pm, pv, nz, ny, nx, ip, iso.size, po, _stream()))
+        out = torch.empty((iso.size, nz - 1, ny - 1, nx - 1), dtype=torch.float32,
+                          device=div_mean.device)
+    po, pitch, plane = _lcp3_out(out, iso.size, nz, ny, nx)
+    _check(lib().pdiv_lcp_3d(pm, pv, nz, ny, nx, ip, iso.size, po, pitch, plane, _stream()))
     return out
 
 

@@ -89,22 +89,24 @@ struct RowReader {
       : r(__builtin_amdgcn_make_buffer_rsrc(const_cast<T*>(row), 0,
                                             static_cast<int>(uint32_t(nx) * sizeof(T)),
                                             0x00020000)) {}
-  __device__ __forceinline__ float get(uint32_t byte_off) const;
+  // byte_off: per lane; so: a wave-uniform byte offset added to it
+  __device__ __forceinline__ float get(uint32_t byte_off, uint32_t so = 0) const;
 };
 template <>
-__device__ __forceinline__ float RowReader<float>::get(uint32_t o) const {
-  return __uint_as_float(__builtin_amdgcn_raw_buffer_load_b32(r, static_cast<int>(o), 0, 0));
-}
-template <>
-__device__ __forceinline__ float RowReader<__half>::get(uint32_t o) const {
-  return __half2float(__ushort_as_half(
-      __builtin_amdgcn_raw_buffer_load_b16(r, static_cast<int>(o), 0, 0)));
-}
-template <>
-__device__ __forceinline__ float RowReader<bf16_t>::get(uint32_t o) const {
+__device__ __forceinline__ float RowReader<float>::get(uint32_t o, uint32_t so) const {
   return __uint_as_float(
-      static_cast<uint32_t>(__builtin_amdgcn_raw_buffer_load_b16(r, static_cast<int>(o), 0, 0))
-      << 16);
+      __builtin_amdgcn_raw_buffer_load_b32(r, static_cast<int>(o), static_cast<int>(so), 0));
+}
+template <>
+__device__ __forceinline__ float RowReader<__half>::get(uint32_t o, uint32_t so) const {
+  return __half2float(__ushort_as_half(
+      __builtin_amdgcn_raw_buffer_load_b16(r, static_cast<int>(o), static_cast<int>(so), 0)));
+}
+template <>
+__device__ __forceinline__ float RowReader<bf16_t>::get(uint32_t o, uint32_t so) const {
+  return __uint_as_float(static_cast<uint32_t>(__builtin_amdgcn_raw_buffer_load_b16(
+                             r, static_cast<int>(o), static_cast<int>(so), 0))
+                         << 16);
 }
 
 template <typename T>

@@ -594,21 +594,50 @@ pdiv_status pdiv_divergence_gaussian_3d(const void* mean_u, const void* var_u,
 
 namespace {
 
-// Isovalue chunks of 16, 8, 4, 2, 1 for the 3D LCP launches; planes is null
-// for the two-step form (dm, dv given), else the six moment volumes.
+// Output layout of the 3D maps: rows of `pitch` floats (0: nx-1, dense),
+// layers (ny-1) pitch apart, maps `plane` floats apart (0: the layers of one
+// map back to back).  Maps may not overlap.
+pdiv_status check_layout3(int64_t row_pitch, int64_t plane_stride, int64_t nz, int64_t ny,
+                          int64_t nx, int32_t n_iso, OutLayout* out) {
+  const int64_t cells = nx - 1;
+  const int64_t pitch = row_pitch == 0 ? cells : row_pitch;
+  if (pitch < cells || pitch > (int64_t(1) << 52))
+    return invalid("lcp_row_pitch must be 0 or in [nx - 1, 2^52] (got %lld, nx=%lld)",
+                   (long long)row_pitch, (long long)nx);
+  const double map_d = double(nz - 1) * double(ny - 1) * double(pitch);
+  if (map_d > double(int64_t(1) << 52))
+    return invalid("LCP output layout is too large (layers x rows x pitch > 2^52 floats)");
+  const int64_t map = (nz - 1) * (ny - 1) * pitch;
+  const int64_t plane = plane_stride == 0 ? map : plane_stride;
+  if (plane < map || plane > (int64_t(1) << 52))
+    return invalid("lcp_plane_stride must be 0 or in [(nz-1)(ny-1) row pitch, 2^52] (got %lld)",
+                   (long long)plane_stride);
+  if ((double(n_iso - 1) * double(plane) + map_d) * 4.0 >= double(int64_t(1) << 56))
+    return invalid("LCP output layout is too large");
+  out->pitch = pitch;
+  out->plane = plane;
+  return PDIV_OK;
+}
+
+// Isovalue chunks for the 3D LCP launches: 8, 4, 2, 1 for the two-step form
+// (a wave carries four cell layers at up to 8 isovalues; at 16 it could
+// carry only two, and the tails of the extra shared z levels cost more than
+// reading the divergence volumes twice), 16, 8, 4, 2, 1 fused (the six
+// moment volumes are read once).  planes is null for the two-step form (dm,
+// dv given), else the six moment volumes.
 pdiv_status lcp3d_chunks(const float* dm, const float* dv, const void* const* planes,
                          pdiv_dtype dt, int64_t nz, int64_t ny, int64_t nx,
                          const StencilCoef3& k, const float* iso_host, int32_t n_iso,
-                         float* lcp, hipStream_t s) {
-  const int64_t plane = (nz - 1) * (ny - 1) * (nx - 1);
+                         float* lcp, const OutLayout& lo, hipStream_t s) {
   for (int32_t k0 = 0; k0 < n_iso;) {
     const int left = n_iso - k0;
-    const int kc = left >= 16 ? 16 : left >= 8 ? 8 : left >= 4 ? 4 : left >= 2 ? 2 : 1;
+    const int kc = (left >= 16 && planes) ? 16 : left >= 8 ? 8 : left >= 4 ? 4 : left >= 2 ? 2 : 1;
     IsoChunk c;
     for (int q = 0; q < kIsoChunk; ++q) c.c[q] = iso_host[k0 + (q < kc ? q : kc - 1)];
+    float* const out = lcp + k0 * lo.plane;
     const hipError_t e =
-        planes ? launch_lcp3d_fused(planes, dt, nz, ny, nx, k, c, kc, lcp + k0 * plane, plane, s)
-               : launch_lcp3d(dm, dv, nz, ny, nx, c, kc, lcp + k0 * plane, plane, s);
+        planes ? launch_lcp3d_fused(planes, dt, nz, ny, nx, k, c, kc, out, lo.pitch, lo.plane, s)
+               : launch_lcp3d(dm, dv, nz, ny, nx, c, kc, out, lo.pitch, lo.plane, s);
     if (e != hipSuccess) return device_status(e, "3D LCP launch");
     k0 += kc;
   }
@@ -619,7 +648,7 @@ pdiv_status lcp3d_chunks(const float* dm, const float* dv, const void* const* pl
 
 pdiv_status pdiv_lcp_3d(const float* div_mean, const float* div_var, int64_t nz, int64_t ny,
                         int64_t nx, const float* isovalues_host, int32_t n_iso, float* lcp,
-                        pdiv_stream stream) {
+                        int64_t lcp_row_pitch, int64_t lcp_plane_stride, pdiv_stream stream) {
   g_last_error.clear();
   log_call("pdiv_lcp_3d nz=%lld ny=%lld nx=%lld n_iso=%d", (long long)nz, (long long)ny,
            (long long)nx, n_iso);
@@ -628,8 +657,13 @@ pdiv_status pdiv_lcp_3d(const float* div_mean, const float* div_var, int64_t nz,
   PDIV_NONNULL(lcp);
   PDIV_TRY(check_grid3(nz, ny, nx));
   PDIV_TRY(check_iso(isovalues_host, n_iso));
+  if (!lcp3d_slice_fits(ny, nx, 4))
+    return invalid("3D LCP slices are limited to 7 ny nx x 4 bytes < 2^31 (ny=%lld, nx=%lld)",
+                   (long long)ny, (long long)nx);
+  OutLayout lo;
+  PDIV_TRY(check_layout3(lcp_row_pitch, lcp_plane_stride, nz, ny, nx, n_iso, &lo));
   return lcp3d_chunks(div_mean, div_var, nullptr, PDIV_F32, nz, ny, nx, StencilCoef3{},
-                      isovalues_host, n_iso, lcp, static_cast<hipStream_t>(stream));
+                      isovalues_host, n_iso, lcp, lo, static_cast<hipStream_t>(stream));
 }
 
 pdiv_status pdiv_lcp_3d_from_moments(const void* mean_u, const void* var_u, const void* mean_v,
@@ -637,6 +671,7 @@ pdiv_status pdiv_lcp_3d_from_moments(const void* mean_u, const void* var_u, cons
                                      pdiv_dtype in_dtype, int64_t nz, int64_t ny, int64_t nx,
                                      double dx, double dy, double dz,
                                      const float* isovalues_host, int32_t n_iso, float* lcp,
+                                     int64_t lcp_row_pitch, int64_t lcp_plane_stride,
                                      pdiv_stream stream) {
   g_last_error.clear();
   log_call("pdiv_lcp_3d_from_moments nz=%lld ny=%lld nx=%lld n_iso=%d", (long long)nz,
@@ -653,9 +688,14 @@ pdiv_status pdiv_lcp_3d_from_moments(const void* mean_u, const void* var_u, cons
   PDIV_TRY(check_spacing(dx, dy));
   if (!(std::isfinite(dz) && dz > 0.0)) return invalid("dz must be finite and > 0 (got %g)", dz);
   PDIV_TRY(check_iso(isovalues_host, n_iso));
+  if (!lcp3d_slice_fits(ny, nx, in_dtype == PDIV_F32 ? 4 : 2))
+    return invalid("3D LCP slices are limited to 7 ny nx x element bytes < 2^31 (ny=%lld, "
+                   "nx=%lld)", (long long)ny, (long long)nx);
+  OutLayout lo;
+  PDIV_TRY(check_layout3(lcp_row_pitch, lcp_plane_stride, nz, ny, nx, n_iso, &lo));
   const void* const planes[6] = {mean_u, var_u, mean_v, var_v, mean_w, var_w};
   return lcp3d_chunks(nullptr, nullptr, planes, in_dtype, nz, ny, nx, make_coef3(dx, dy, dz),
-                      isovalues_host, n_iso, lcp, static_cast<hipStream_t>(stream));
+                      isovalues_host, n_iso, lcp, lo, static_cast<hipStream_t>(stream));
 }
 
 pdiv_status pdiv_mc_lcp(const void* mean_u, const void* var_u, const void* mean_v,

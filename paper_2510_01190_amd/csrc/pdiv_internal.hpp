@@ -134,6 +134,9 @@ StencilCoef3 make_coef3(double dx, double dy, double dz);
 // Blocks of the 3D launches (the API rejects grids whose launch would not fit).
 int64_t divergence3d_blocks(int64_t nz, int64_t ny, int64_t nx);
 int64_t lcp3d_blocks(int64_t nz, int64_t ny, int64_t nx, int kc);
+// The 3D LCP walks reach up to 7 z levels of a plane from one buffer base
+// (32-bit offsets): 7 ny nx elem_bytes < 2^31.
+bool lcp3d_slice_fits(int64_t ny, int64_t nx, size_t elem_bytes);
 
 hipError_t launch_divergence3d(const void* mu, const void* vu, const void* mv, const void* vv,
                                const void* mw, const void* vw, pdiv_dtype dt, int64_t nz,
@@ -141,14 +144,15 @@ hipError_t launch_divergence3d(const void* mu, const void* vu, const void* mv, c
                                float* dvar, hipStream_t s);
 
 // 8-corner LCP for isovalues [k0, k0+kc) (kc in {1, 2, 4, 8, 16}) from 3D
-// divergence Gaussians; maps [kc][nz-1][ny-1][nx-1], `plane` floats apart.
+// divergence Gaussians; maps [kc][nz-1][ny-1][nx-1], rows `pitch` floats
+// apart, layers (ny-1) pitch, maps `plane` floats apart.
 hipError_t launch_lcp3d(const float* dm, const float* dv, int64_t nz, int64_t ny, int64_t nx,
-                        const IsoChunk& iso, int kc, float* out_k0, int64_t plane,
-                        hipStream_t s);
+                        const IsoChunk& iso, int kc, float* out_k0, int64_t pitch,
+                        int64_t plane, hipStream_t s);
 // The same from the six moment volumes (mean_u, var_u, mean_v, var_v,
 // mean_w, var_w) of type dt, Eq. 2-3 evaluated on the spot.
 hipError_t launch_lcp3d_fused(const void* const* planes, pdiv_dtype dt, int64_t nz, int64_t ny,
                               int64_t nx, const StencilCoef3& k, const IsoChunk& iso, int kc,
-                              float* out_k0, int64_t plane, hipStream_t s);
+                              float* out_k0, int64_t pitch, int64_t plane, hipStream_t s);
 
 }  // namespace pdiv

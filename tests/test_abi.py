@@ -195,21 +195,29 @@ def test_3d_calls_reject_bad_arguments():
                                                   NUL), "dtype")
     _expect_invalid(L.pdiv_divergence_gaussian_3d(*six, 0, 1 << 14, 1 << 14, 1 << 14, 1.0, 1.0,
                                                   1.0, FAKE, FAKE, NUL), "too large")
-    _expect_invalid(L.pdiv_lcp_3d(FAKE, FAKE, 4, 8, 1, ip, 1, FAKE, NUL), "at least 2x2x2")
-    _expect_invalid(L.pdiv_lcp_3d(FAKE, FAKE, 4, 8, 8, ip, 0, FAKE, NUL), "n_iso")
-    _expect_invalid(L.pdiv_lcp_3d(FAKE, FAKE, 4, 8, 8, ip, 257, FAKE, NUL), "n_iso")
-    _expect_invalid(L.pdiv_lcp_3d(FAKE, FAKE, 4, 8, 8, ip, 1, NUL, NUL), "lcp")
-    _expect_invalid(L.pdiv_lcp_3d(FAKE, FAKE, 4, 1 << 22, 8, ip, 1, FAKE, NUL), "too large")
+    _expect_invalid(L.pdiv_lcp_3d(FAKE, FAKE, 4, 8, 1, ip, 1, FAKE, 0, 0, NUL), "at least 2x2x2")
+    _expect_invalid(L.pdiv_lcp_3d(FAKE, FAKE, 4, 8, 8, ip, 0, FAKE, 0, 0, NUL), "n_iso")
+    _expect_invalid(L.pdiv_lcp_3d(FAKE, FAKE, 4, 8, 8, ip, 257, FAKE, 0, 0, NUL), "n_iso")
+    _expect_invalid(L.pdiv_lcp_3d(FAKE, FAKE, 4, 8, 8, ip, 1, NUL, 0, 0, NUL), "lcp")
+    _expect_invalid(L.pdiv_lcp_3d(FAKE, FAKE, 4, 1 << 22, 8, ip, 1, FAKE, 0, 0, NUL), "too large")
+    _expect_invalid(L.pdiv_lcp_3d(FAKE, FAKE, 4, 9000, 9000, ip, 1, FAKE, 0, 0, NUL), "limited")
+    _expect_invalid(L.pdiv_lcp_3d_from_moments(*six, 1, 4, 13000, 13000, 1.0, 1.0, 1.0, ip, 1,
+                                               FAKE, 0, 0, NUL), "limited")
+    _expect_invalid(L.pdiv_lcp_3d(FAKE, FAKE, 4, 8, 8, ip, 1, FAKE, 6, 0, NUL), "lcp_row_pitch")
+    _expect_invalid(L.pdiv_lcp_3d(FAKE, FAKE, 4, 8, 8, ip, 2, FAKE, 32, 32 * 7 * 3 - 1, NUL),
+                    "lcp_plane_stride")
+    _expect_invalid(L.pdiv_lcp_3d(FAKE, FAKE, 4, 8, 8, ip, 2, FAKE, 1 << 50, 0, NUL),
+                    "too large")
     _expect_invalid(L.pdiv_lcp_3d_from_moments(*six, 0, 4, 8, 8, 1.0, 1.0, -2.0, ip, 1, FAKE,
-                                               NUL), "dz")
+                                               0, 0, NUL), "dz")
     _expect_invalid(L.pdiv_lcp_3d_from_moments(*six, 0, 4, 8, 8, 1.0, 1.0, 1.0, ip, 0, FAKE,
-                                               NUL), "n_iso")
+                                               0, 0, NUL), "n_iso")
     _expect_invalid(L.pdiv_lcp_3d_from_moments(*six, 3, 4, 8, 8, 1.0, 1.0, 1.0, ip, 1, FAKE,
-                                               NUL), "dtype")
+                                               0, 0, NUL), "dtype")
     _expect_invalid(L.pdiv_lcp_3d_from_moments(*six, 0, 2, 1, 8, 1.0, 1.0, 1.0, ip, 1, FAKE,
-                                               NUL), "at least 2x2x2")
+                                               0, 0, NUL), "at least 2x2x2")
     _expect_invalid(L.pdiv_lcp_3d_from_moments(*six, 0, 4, 8, 8, 1.0, 1.0, 1.0, ip, 1, NUL,
-                                               NUL), "lcp")
+                                               0, 0, NUL), "lcp")
 
 
 def test_speed_gradient_rejects_bad_arguments():

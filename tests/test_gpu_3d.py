@@ -16,11 +16,32 @@ pytestmark = pytest.mark.gpu
 KEYS = ("mean_u", "var_u", "mean_v", "var_v", "mean_w", "var_w")
 LCP_TOL = 1e-5
 
-# (nz, ny, nx): one cell wide; strips of 63 cells exact and ragged; two bands
-# of 64 rows; layer counts that are and are not multiples of the layers a
-# wave carries (4 or 2)
+# (nz, ny, nx): one cell wide; strips of 63 (dense rows) and 64 cells
+# (line-aligned rows) exact and ragged; two bands of 64 rows; layer counts
+# that are and are not multiples of the layers a wave carries (4 or 2)
 SHAPES = [(2, 2, 2), (3, 5, 70), (9, 33, 130), (17, 40, 64), (5, 3, 127), (4, 130, 65),
-          (6, 7, 2), (2, 66, 190)]
+          (6, 7, 2), (2, 66, 190), (3, 4, 129)]
+SENTINEL = -7.0  # padding floats of an output must keep this
+
+
+def _padded(k, shape, pitch=None, gap=0):
+    """A [k][nz-1][ny-1][nx-1] view with rows padded to `pitch` floats
+    (default: the next multiple of 32) and `gap` extra floats between maps,
+    filled with SENTINEL; returns (view, backing buffer)."""
+    nz, ny, nx = shape
+    pitch = pitch or (nx - 1 + 31) // 32 * 32
+    map_ = (nz - 1) * (ny - 1) * pitch
+    buf = torch.full((k * (map_ + gap),), SENTINEL, dtype=torch.float32, device="cuda")
+    view = buf.as_strided((k, nz - 1, ny - 1, nx - 1),
+                          (map_ + gap, (ny - 1) * pitch, pitch, 1))
+    return view, buf
+
+
+def _padding_untouched(view, buf):
+    mask = torch.ones_like(buf, dtype=torch.bool)
+    idx = torch.arange(buf.numel(), device=buf.device).as_strided(view.shape, view.stride())
+    mask[idx.reshape(-1)] = False
+    return bool(torch.all(buf[mask] == SENTINEL))
 
 
 def _field(shape, seed, dt="f32", sigma=(0.05, 0.5)):
@@ -106,6 +127,53 @@ def test_fused_equals_two_step(shape, dt):
         assert torch.equal(fused, two), (shape, dt, k)
 
 
+@pytest.mark.parametrize("shape", SHAPES)
+def test_line_aligned_layout_is_bitwise_the_dense_maps(shape):
+    """Rows padded to whole 128-byte lines take the 64-cell tile with the
+    seam step; the maps are bitwise those of the dense layout (63-cell
+    tile), which the oracle test above checks, and the padding is never
+    written.  Pitches of 32 (line-aligned) and of nx - 1 + 5 (not aligned),
+    with and without a gap between maps."""
+    _, ts = _field(shape, seed=11 * sum(shape))
+    m, _, dm, dv = _oracle_div3(ts)
+    nz, ny, nx = shape
+    for k in (1, 2, 3, 4, 8, 16, 17):
+        iso = np.quantile(m, np.linspace(0.05, 0.95, k)).astype(np.float32)
+        dense = P.lcp_3d(dm, dv, iso)
+        for pitch, gap in ((None, 0), (None, 64), ((nx - 1 + 31) // 32 * 32 + 32, 32),
+                           (nx - 1 + 5, 3)):
+            view, buf = _padded(k, shape, pitch, gap)
+            P.lcp_3d(dm, dv, iso, out=view)
+            assert torch.equal(view, dense), (shape, k, pitch, gap)
+            assert _padding_untouched(view, buf), (shape, k, pitch, gap)
+
+
+@pytest.mark.parametrize("dt", ["f32", "f16", "bf16"])
+@pytest.mark.parametrize("shape", SHAPES)
+def test_fused_line_aligned_layout_equals_two_step(shape, dt):
+    h = (0.5, 1.0, 1.5)
+    _, ts = _field(shape, seed=13 * sum(shape), dt=dt)
+    dm, dv = P.divergence_gaussian_3d(*ts, *h)
+    m = _oracle_div3(ts, h)[0]
+    for k in (1, 4, 8, 16):
+        iso = np.quantile(m, np.linspace(0.05, 0.95, k)).astype(np.float32)
+        two = P.lcp_3d(dm, dv, iso)
+        view, buf = _padded(k, shape)
+        P.lcp_3d_from_moments(*ts, iso, *h, out=view)
+        assert torch.equal(view, two), (shape, dt, k)
+        assert _padding_untouched(view, buf)
+
+
+def test_empty_lcp_3d_pads_rows_to_lines():
+    shape = (4, 9, 100)
+    _, ts = _field(shape, seed=17)
+    _, _, dm, dv = _oracle_div3(ts)
+    out = P.empty_lcp_3d(3, *shape)
+    assert out.stride() == (3 * 8 * 128, 8 * 128, 128, 1) and out.data_ptr() % 128 == 0
+    iso = [-0.1, 0.0, 0.1]
+    assert torch.equal(P.lcp_3d(dm, dv, iso, out=out), P.lcp_3d(dm, dv, iso))
+
+
 def test_lcp_3d_end_to_end_float32():
     """From the float64 field through float32 storage and arithmetic."""
     shape = (9, 33, 130)
@@ -164,6 +232,11 @@ def test_bench_size_sampled_slabs():
     dm, dv = P.divergence_gaussian_3d(*ts)
     out = P.lcp_3d(dm, dv, iso)
     assert torch.equal(P.lcp_3d_from_moments(*ts, iso), out)
+    # the benchmark's layouts: rows padded to 512 floats, two-step and fused
+    padded = P.empty_lcp_3d(4, n, n, n)
+    assert torch.equal(P.lcp_3d(dm, dv, iso, out=padded), out)
+    assert torch.equal(P.lcp_3d_from_moments(*ts, iso, out=padded), out)
+    del padded
     assert not torch.isnan(out).any()
     assert float(out.min()) >= 0.0 and float(out.max()) <= 1.0
     worst = 0.0
