@@ -694,6 +694,61 @@ def served_leg(P, synth, torch, np, n_streams=2, fracs=(0.5, 0.9), baseline=True
     return out
 
 
+def contour_timing(P, torch, dm, c):
+    """pdiv_isocontour (count, row scan, write) on the divergence-mean plane
+    dm at isovalue c, timed over 10 launches into a buffer sized by a first
+    call."""
+    ny, nx = dm.shape
+    offs = torch.empty(ny, dtype=torch.int64, device="cuda")
+    n_seg = int(P.isocontour(dm, c).shape[0])
+    segs = torch.empty((max(n_seg, 1), 4), device="cuda")
+
+    def contour():
+        P.lib().pdiv_isocontour(P._p(dm.data_ptr()), ny, nx, ctypes.c_float(c),
+                                P._p(offs.data_ptr()), P._p(segs.data_ptr()), n_seg,
+                                P._stream())
+
+    contour()
+    t = time_launches(contour, 10, torch)
+    b = 2 * 4 * ny * nx + 16 * n_seg + 16 * ny
+    return {"ms": round(t * 1e3, 4), "segments": n_seg, "achieved_GBs": round(b / t / 1e9, 1),
+            "frac_hbm": round(b / t / 1e9 / HBM_PEAK_GBS, 4),
+            "note": "count pass, row scan and write pass; bytes = field read twice + segments"}
+
+
+def c3_resident(synth, torch):
+    """The 8192x8192 field's four float32 moment planes on the device, its
+    isovalues and sizes."""
+    c3 = synth.config_c3()
+    mom = [torch.from_numpy(c3[k]).float().cuda() for k in ("mean_u", "var_u", "mean_v", "var_v")]
+    return mom, c3["isovalues"], c3["ny"], c3["nx"]
+
+
+def isocontour_leg(P, synth, torch, np):
+    """The mean-field isocontour of the 8192x8192 field's divergence at its
+    middle isovalue alone (for profiling the three contour kernels)."""
+    mom, iso, ny, nx = c3_resident(synth, torch)
+    dm = torch.empty((ny, nx), device="cuda")
+    dv = torch.empty_like(dm)
+    P.lib().pdiv_divergence_gaussian(*[P._p(t.data_ptr()) for t in mom], 0, ny, nx, 1.0, 1.0,
+                                     P._p(dm.data_ptr()), P._p(dv.data_ptr()), P._stream())
+    return contour_timing(P, torch, dm, float(iso[iso.size // 2]))
+
+
+def dense_leg(P, synth, torch, np):
+    """The fused kernel into dense [K][ny-1][nx-1] maps alone (for profiling
+    that output layout)."""
+    mom, iso, ny, nx = c3_resident(synth, torch)
+    K = int(iso.size)
+    cells = (ny - 1) * (nx - 1)
+    dense = torch.empty((K, ny - 1, nx - 1), device="cuda")
+    P.lcp_from_moments(*mom, iso, out=dense)
+    t = time_launches(lambda: P.lcp_from_moments(*mom, iso, out=dense), 10, torch)
+    b = 4 * 4 * ny * nx + 4 * K * cells
+    return {"ms": round(t * 1e3, 4), "cells_per_s": round(cells * K / t, 1),
+            "achieved_GBs": round(b / t / 1e9, 1), "frac_hbm": round(b / t / 1e9 / HBM_PEAK_GBS, 4)}
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -705,7 +760,8 @@ def main():
     ap.add_argument("--no-cpu-legs", action="store_true",
                     help="only the single-thread oracle in the CPU baseline")
     ap.add_argument("--mc-samples", type=int, default=1000)
-    ap.add_argument("--only-leg", choices=["volume_3d", "batch", "served", "mc", "near01"],
+    ap.add_argument("--only-leg", choices=["volume_3d", "batch", "served", "mc", "near01", "isocontour",
+                             "dense"],
                     help="run one leg alone and print its JSON (for profiling)")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="only run a plain 1 GiB device copy (HBM counter calibration)")
@@ -738,7 +794,8 @@ def main():
     P.lib()  # fail loudly if the library is missing
     if args.only_leg:
         fn = {"volume_3d": volume_leg, "batch": batch_leg, "served": served_leg,
-              "mc": mc_leg, "near01": near01_leg}[args.only_leg]
+              "mc": mc_leg, "near01": near01_leg, "isocontour": isocontour_leg,
+              "dense": dense_leg}[args.only_leg]
         print(json.dumps(fn(P, synth, torch, np)), flush=True)
         return
 
@@ -882,23 +939,9 @@ def main():
         assert torch.equal(out, out2), "two-step path differs from the fused path"
         # the mean-field isocontour (marching squares) of the divergence at
         # the middle isovalue: count, scan and write, one call
-        c_mid = float(iso[K // 2])
-        offs = torch.empty(ny, dtype=torch.int64, device="cuda")
-        n_seg = int(P.isocontour(dm, c_mid).shape[0])
-        segs = torch.empty((max(n_seg, 1), 4), device="cuda")
-
-        def contour():
-            P.lib().pdiv_isocontour(P._p(dm.data_ptr()), ny, nx, ctypes.c_float(c_mid),
-                                    P._p(offs.data_ptr()), P._p(segs.data_ptr()), n_seg,
-                                    P._stream())
-
-        contour()
-        t = time_launches(contour, 10, torch)
-        b = 2 * 4 * ny * nx + 16 * n_seg + 16 * ny
-        legs["isocontour_8192x8192_mean_field"] = {
-            "ms": round(t * 1e3, 4), "segments": n_seg, "achieved_GBs": round(b / t / 1e9, 1),
-            "note": "count pass, row scan and write pass; bytes = field read twice + segments"}
-        del out2, dm, dv, offs, segs
+        legs["isocontour_8192x8192_mean_field"] = contour_timing(P, torch, dm,
+                                                                 float(iso[K // 2]))
+        del out2, dm, dv
         for name, dt, bpe in (("f16", torch.float16, 2), ("bf16", torch.bfloat16, 2)):
             m16 = [torch.from_numpy(c3[k]).to(dt).cuda() for k in
                    ("mean_u", "var_u", "mean_v", "var_v")]
