@@ -135,7 +135,8 @@ __global__ __launch_bounds__(kBlock) void divergence_kernel(const T* __restrict_
   }
 }
 
-template <int KC, bool FUSED, bool PAIRED, typename T, bool POISON = false>
+template <int KC, bool FUSED, bool PAIRED, typename T, bool POISON = false,
+          bool STREAM = PAIRED>
 __device__ __forceinline__ void lcp_body(const T* __restrict__ p0,
                                                      const T* __restrict__ p1,
                                                      const T* __restrict__ p2,
@@ -156,21 +157,22 @@ __device__ __forceinline__ void lcp_body(const T* __restrict__ p0,
   const int band = wave / n_strips;
   if (band >= n_bands) return;
   const int j0 = band * band_rows;
-  lcp_tile<KC, FUSED, PAIRED, T, POISON>(p0, p1, p2, p3, ny, nx, k, iso, KC, out, plane, pitch,
-                                         strip, j0, min(j0 + band_rows, ny - 1));
+  lcp_tile<KC, FUSED, PAIRED, T, POISON, STREAM>(p0, p1, p2, p3, ny, nx, k, iso, KC, out, plane,
+                                                 pitch, strip, j0, min(j0 + band_rows, ny - 1));
 }
 
 // Paired-layout kernel: asks the compiler for three waves per SIMD (at most
 // 168 VGPRs); with the alternating carried sets the tile needs one more, and
 // one spill costs less than the third wave's absence or the per-row moves of
 // a single set (measured on gfx950 at 8192^2, K = 16: 1.144 ms against 1.151).
-template <int KC, bool FUSED, typename T, bool POISON = false>
+// STREAM = false: the fused kernel on rows that start inside a line.
+template <int KC, bool FUSED, typename T, bool POISON = false, bool STREAM = true>
 __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(3))) void lcp_kernel_paired(
     const T* __restrict__ p0, const T* __restrict__ p1, const T* __restrict__ p2,
     const T* __restrict__ p3, int ny, int nx, StencilCoef k, IsoChunk iso, float* __restrict__ out,
     int64_t plane, int64_t pitch, int band_rows, int n_strips, int n_bands) {
-  lcp_body<KC, FUSED, true, T, POISON>(p0, p1, p2, p3, ny, nx, k, iso, out, plane, pitch,
-                                       band_rows, n_strips, n_bands);
+  lcp_body<KC, FUSED, true, T, POISON, STREAM>(p0, p1, p2, p3, ny, nx, k, iso, out, plane, pitch,
+                                               band_rows, n_strips, n_bands);
 }
 
 // Split-layout kernel (its tile has no LDS ring; two waves per SIMD).
@@ -187,7 +189,11 @@ template <int KC, bool FUSED, typename T>
 hipError_t launch_kc(const void* p0, const void* p1, const void* p2, const void* p3, int ny,
                      int nx, const StencilCoef& k, const IsoChunk& iso, float* out,
                      int64_t pitch, int64_t plane, LcpShape shape, hipStream_t s) {
-  const bool paired = use_paired_tile(out, pitch, plane, KC, int64_t(ny - 1) * (nx - 1));
+  const int64_t n_cells = int64_t(ny - 1) * (nx - 1);
+  const bool lines = use_paired_tile(out, pitch, plane, KC, n_cells);
+  // the fused kernel takes the paired tile on other rows too (default policy)
+  const bool unaligned = FUSED && !lines && use_paired_unaligned(KC, n_cells);
+  const bool paired = lines || unaligned;
   const int cells = cells_per_wave(paired);
   const int band_rows = band_rows_for(shape, ny, paired);
   const int n_strips = (nx - 1 + cells - 1) / cells;
@@ -199,8 +205,24 @@ hipError_t launch_kc(const void* p0, const void* p1, const void* p2, const void*
   if constexpr (FUSED && std::is_same<T, float>::value) {
     // the checking variant exists for the fused float32 kernel only
     if (paired && shape.poison) {
-      hipLaunchKernelGGL((lcp_kernel_paired<KC, FUSED, T, true>), dim3(blocks), dim3(kBlock), 0,
-                         s, static_cast<const T*>(p0), static_cast<const T*>(p1),
+      if (unaligned)
+        hipLaunchKernelGGL((lcp_kernel_paired<KC, FUSED, T, true, false>), dim3(blocks),
+                           dim3(kBlock), 0, s, static_cast<const T*>(p0),
+                           static_cast<const T*>(p1), static_cast<const T*>(p2),
+                           static_cast<const T*>(p3), ny, nx, k, iso, out, plane, pitch,
+                           band_rows, n_strips, n_bands);
+      else
+        hipLaunchKernelGGL((lcp_kernel_paired<KC, FUSED, T, true>), dim3(blocks), dim3(kBlock),
+                           0, s, static_cast<const T*>(p0), static_cast<const T*>(p1),
+                           static_cast<const T*>(p2), static_cast<const T*>(p3), ny, nx, k, iso,
+                           out, plane, pitch, band_rows, n_strips, n_bands);
+      return hipGetLastError();
+    }
+  }
+  if constexpr (FUSED) {
+    if (unaligned) {
+      hipLaunchKernelGGL((lcp_kernel_paired<KC, FUSED, T, false, false>), dim3(blocks),
+                         dim3(kBlock), 0, s, static_cast<const T*>(p0), static_cast<const T*>(p1),
                          static_cast<const T*>(p2), static_cast<const T*>(p3), ny, nx, k, iso,
                          out, plane, pitch, band_rows, n_strips, n_bands);
       return hipGetLastError();

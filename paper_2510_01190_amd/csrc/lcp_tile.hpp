@@ -22,6 +22,16 @@
 // over with one readlane/writelane per isovalue (about 7% more vector ALU
 // work at 16 isovalues).  On gfx950 such stores sustain about 5.4 TB/s.
 //
+// The fused kernel also takes the paired tile for rows that start inside a
+// line (dense [K][ny-1][nx-1] maps, odd pitches), with the default store
+// policy: a strip's 8-byte stores then fill the lines in its middle and leave
+// the two lines it shares with the neighbouring strips to be completed in L2
+// by the neighbour (XCD-contiguous strips share an L2).  It runs the same
+// arithmetic with the LDS-staged rows and three waves per SIMD; at 8192^2
+// into dense maps it takes 0.485 / 0.794 / 1.443 ms at 4 / 8 / 16 isovalues
+// against 0.47 / 0.66 / 1.13 ms into line-aligned rows (with the streaming
+// policy 0.578 / 0.974 / 1.760 ms; the split tile 1.51 ms at 16).
+//
 // Split (lcp_tile_split), for any other output: a wave owns 127 vertex
 // columns, the 126 cells [x0, x0+126), x0 = 126 strip.  Lane L holds columns
 // A = x0+L and B = x0+63+L (lane 63's A repeats lane 0's B), forms cells
@@ -682,7 +692,9 @@ __device__ __forceinline__ void lcp_tile_split(const T* __restrict__ p0, const T
 
 // Layout choice: the paired tile when every output row starts on a 128-byte
 // line (base aligned, row pitch and plane stride multiples of 32 floats) and
-// either there are at least 8 isovalues or the map has at least 2^22 cells.
+// either there are at least 8 isovalues or the map has at least 2^22 cells
+// (use_paired_tile); under the same size rule the fused kernel also takes it
+// for other rows (use_paired_unaligned), with the default store policy.
 // On large maps its whole-line stores outweigh the seam step at any
 // isovalue count (8192^2, rows interleaved, paired against split: 0.269 /
 // 0.293 ms at 1 isovalue, 0.318 / 0.360 ms at 2, 0.430 / 0.497 ms at 4;
@@ -695,22 +707,27 @@ inline bool use_paired_tile(const float* out, int64_t pitch, int64_t plane, int 
   return (reinterpret_cast<uintptr_t>(out) % 128 == 0) && (pitch % 32 == 0) &&
          (plane % 32 == 0) && (kc >= 8 || cells >= (int64_t(1) << 22));
 }
+inline bool use_paired_unaligned(int kc, int64_t cells) {
+  return kc >= 8 || cells >= (int64_t(1) << 22);
+}
 
-// The tile of layout PAIRED (paired tiles store non-temporally: their rows
-// start on 128-byte lines).
-template <int KC, bool FUSED, bool PAIRED, typename T, bool POISON = false>
+// The tile of layout PAIRED.  STREAM: non-temporal stores (for rows that
+// start on 128-byte lines; the unaligned paired tile of the fused kernel
+// stores with the default policy).
+template <int KC, bool FUSED, bool PAIRED, typename T, bool POISON = false, bool STREAM = PAIRED>
 __device__ __forceinline__ void lcp_tile(const T* __restrict__ p0, const T* __restrict__ p1,
                                          const T* __restrict__ p2, const T* __restrict__ p3,
                                          int ny, int nx, const StencilCoef& k,
                                          const IsoChunk& iso, int n_store,
                                          float* __restrict__ out, int64_t plane, int64_t pitch,
                                          int strip, int j0, int j1) {
+  static_assert(PAIRED || !STREAM, "the split tile stores with the default policy");
   if constexpr (PAIRED && FUSED)
-    lcp_tile_paired_lds<KC, true, T, POISON>(p0, p1, p2, p3, ny, nx, k, iso, n_store, out, plane,
-                                              pitch, strip, j0, j1);
+    lcp_tile_paired_lds<KC, STREAM, T, POISON>(p0, p1, p2, p3, ny, nx, k, iso, n_store, out,
+                                                plane, pitch, strip, j0, j1);
   else if constexpr (PAIRED)
-    lcp_tile_paired<KC, FUSED, true>(p0, p1, p2, p3, ny, nx, k, iso, n_store, out, plane, pitch,
-                                     strip, j0, j1);
+    lcp_tile_paired<KC, FUSED, STREAM>(p0, p1, p2, p3, ny, nx, k, iso, n_store, out, plane, pitch,
+                                       strip, j0, j1);
   else
     lcp_tile_split<KC, FUSED>(p0, p1, p2, p3, ny, nx, k, iso, n_store, out, plane, pitch, strip,
                               j0, j1);

@@ -93,9 +93,10 @@ def test_pitched_output_equals_dense_and_keeps_padding(shape):
     """Rows padded to a longer pitch hold bitwise the dense maps; the padding
     floats are never written (fused and two-step paths).  Nine isovalues run
     as a chunk of 8, which takes the paired tile when the rows start on
-    128-byte lines, and a chunk of 1 (split tile on these small maps): the
-    dense maps come from the split tile only, so this also checks that the
-    two layouts agree bit for bit, seam column included."""
+    128-byte lines (streaming stores) and for the fused kernel otherwise too
+    (default stores), the split tile for the two-step path on other rows, and
+    a chunk of 1 (split tile on these small maps), so this also checks that
+    the layouts agree bit for bit, seam column included."""
     ny, nx = shape
     f = _field(ny, nx, seed=5 + nx)
     ts = moments_dev(f)
@@ -350,10 +351,12 @@ def test_pipeline_fit_divergence_lcp():
 
 @pytest.mark.parametrize("dt", ["f32", "f16", "bf16"])
 def test_band_height_does_not_change_the_maps(dt):
-    """Every band height gives bitwise the maps of the default choice, for the
-    split tile (dense rows) and the LDS-staged paired tile (rows on 128-byte
-    lines, chunks of 8 isovalues): bands of 1..7 rows exercise the walk's
-    peeled first rows, its odd last row and the ring's reuse."""
+    """Every band height gives bitwise the maps of the default choice, for
+    dense rows (the LDS-staged paired tile with default stores for the chunk
+    of 8 isovalues, the split tile for the chunk of 1) and rows on 128-byte
+    lines (the paired tile with streaming stores): bands of 1..7 rows
+    exercise the walk's peeled first rows, its odd last row and the ring's
+    reuse."""
     ny, nx = 61, 300
     f = _field(ny, nx, seed=77)
     ts = moments_dev(f, dt)
@@ -416,6 +419,81 @@ def test_band_heights_under_lds_poison():
         finally:
             P.set_debug(0)
             P.set_lcp_band_rows(0)
+
+
+# Shapes for the fused kernel's paired tile on rows that start inside a
+# 128-byte line: 1, 2, 5, 6 and 9 strips of 128 cells, one and several bands,
+# widths whose last strip holds one cell or a full strip.
+DENSE_SHAPES = [(40, 130), (61, 300), (99, 701), (70, 642), (33, 1153), (130, 257), (5, 129)]
+
+
+@pytest.mark.parametrize("shape", DENSE_SHAPES)
+@pytest.mark.parametrize("k", [8, 16])
+def test_paired_tile_on_unaligned_rows(shape, k):
+    """The fused kernel on outputs whose rows start anywhere within a line
+    (8-byte stores at any 4-byte offset): planar dense maps, dense maps one
+    float into their buffer, planar rows of an odd pitch and maps interleaved
+    by rows at an odd pitch -- bitwise the maps of the line-aligned tile,
+    nothing written outside the cells, and within 1e-5 of the oracle."""
+    ny, nx = shape
+    f = _field(ny, nx, seed=13 * nx + ny)
+    ts = moments_dev(f)
+    iso = np.linspace(-0.06, 0.06, k).astype(np.float32)
+    ref = P.lcp_from_moments(*ts, iso, out=P.empty_lcp(k, ny, nx))
+    torch.cuda.synchronize()
+    cells = (ny - 1) * (nx - 1)
+    outs = []
+    flat = torch.full((k * cells + 64,), -7.0, device="cuda")
+    outs.append((flat, flat[1:1 + k * cells].view(k, ny - 1, nx - 1)))
+    outs.append((flat, flat[:k * cells].view(k, ny - 1, nx - 1)))
+    for pitch in (nx + 2, nx + 40):
+        buf = torch.full((k, ny - 1, pitch), -7.0, device="cuda")
+        outs.append((buf, buf[:, :, 3:3 + nx - 1]))
+        ibuf = torch.full((ny - 1, k, pitch), -7.0, device="cuda")
+        outs.append((ibuf, ibuf.permute(1, 0, 2)[:, :, 1:nx]))
+    for buf, view in outs:
+        buf.fill_(-7.0)
+        P.lcp_from_moments(*ts, iso, out=view)
+        torch.cuda.synchronize()
+        assert torch.equal(view, ref)
+        # every float outside the view keeps the fill
+        n_out = int((buf != -7.0).sum())
+        assert n_out == k * cells, (n_out, k * cells)
+    rm, rv, _, _ = _oracle_div(ts)
+    assert err_report(host64(ref), O.lcp(rm, rv, iso))["max_abs"] <= LCP_TOL
+
+
+def test_unaligned_paired_tile_large_map_and_poison():
+    """A map of more than 2^22 cells takes the paired tile on dense rows at
+    any isovalue count (here 1 and 4); with the LDS ring poisoned (NaN before
+    every row load) and short bands the maps stay bitwise those of the
+    line-aligned tile."""
+    ny, nx = 2050, 2100
+    f = _field(ny, nx, seed=99)
+    ts = moments_dev(f)
+    for k in (1, 4):
+        iso = np.linspace(-0.05, 0.05, k).astype(np.float32)
+        ref = P.lcp_from_moments(*ts, iso, out=P.empty_lcp(k, ny, nx))
+        torch.cuda.synchronize()
+        dense = P.lcp_from_moments(*ts, iso)
+        assert torch.equal(dense, ref)
+        try:
+            P.set_debug(P.DEBUG_POISON_LDS)
+            for rows in (0, 1, 3, 7):
+                P.set_lcp_band_rows(rows)
+                got = P.lcp_from_moments(*ts, iso)
+                torch.cuda.synchronize()
+                assert not torch.isnan(got).any(), (k, rows)
+                assert torch.equal(got, ref), (k, rows)
+        finally:
+            P.set_debug(0)
+            P.set_lcp_band_rows(0)
+    # cell rows a..b-1 against the oracle: their vertex rows a..b take Eq. 2-3
+    # from rows a-1..b+1, all interior
+    a, b = 1000, 1040
+    rm, rv = O.divergence_gaussian(*[m[a - 1:b + 2] for m in stored64(ts)], 1.0, 1.0)
+    want = O.lcp(rm[1:-1], rv[1:-1], iso)
+    assert err_report(host64(dense[:, a:b, :]), want)["max_abs"] <= LCP_TOL
 
 
 def test_input_checks_reject_bad_values():
