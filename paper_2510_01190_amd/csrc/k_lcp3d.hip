@@ -296,6 +296,15 @@ __device__ __forceinline__ void load_levels(Row3<L, true>& r, const Rows3<true, 
 // the spot from the six moment volumes (the divergence never reaches HBM),
 // with the operands and order of divergence3d_kernel, so the maps are
 // bitwise the two-step result.
+// With 8 corners the float32 combination can land an ulp outside [0, 1]
+// where the probability is 0 or 1; the exact value is inside, so clamping
+// only removes error.  The IEEE 754-2019 maximum and minimum (v_maximum3_f32,
+// v_minimum3_f32 on gfx950) return NaN for a NaN operand, so a NaN LCP stays
+// NaN, in two instructions.
+__device__ __forceinline__ float clamp01(float v) {
+  return __builtin_elementwise_minimum(__builtin_elementwise_maximum(v, 0.0f), 1.0f);
+}
+
 template <int KC, int LZ, bool FUSED, bool LINES, typename T>
 __global__ __launch_bounds__(kBlock) void lcp3d_kernel(Planes6 src, int nz, int ny, int nx,
                                                        StencilCoef3 k, IsoChunk iso,
@@ -445,8 +454,7 @@ __global__ __launch_bounds__(kBlock) void lcp3d_kernel(Planes6 src, int nz, int 
       const AB a1 = corner_probs(sc[1], c_seam);
       seam = cell_lcp_dpp(join_pairs(make_pair(sprev[0], a0), make_pair(sprev[1], a1)),
                           a0.below);
-      seam = seam < 0.0f ? 0.0f : seam;
-      seam = seam > 1.0f ? 1.0f : seam;
+      seam = clamp01(seam);
       snext[0] = a0;
       snext[1] = a1;
     }
@@ -465,11 +473,7 @@ __global__ __launch_bounds__(kBlock) void lcp3d_kernel(Planes6 src, int nz, int 
 #pragma unroll
       for (int l = 0; l < LZ; ++l) {
         float v = cell_lcp_dpp(join_pairs(yp[l], yp[l + 1]), below[l]);
-        // with 8 corners the float32 combination can land an ulp outside
-        // [0, 1] where the probability is 0 or 1; the exact value is inside,
-        // so clamping only removes error (NaN fails both tests and stays)
-        v = v < 0.0f ? 0.0f : v;
-        v = v > 1.0f ? 1.0f : v;
+        v = clamp01(v);
         if constexpr (LINES)
           v = to_lane63(v, __builtin_amdgcn_readlane(__float_as_int(seam), 2 * (q * LZ + l)));
         RowWriter<LINES>(row_out + int64_t(q) * plane + int64_t(l) * layer, layer_bytes[l])
