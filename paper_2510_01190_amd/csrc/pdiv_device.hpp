@@ -280,7 +280,11 @@ __device__ __forceinline__ U4 philox4x32_10(U4 c, uint32_t k0, uint32_t k1) {
 
 // Box-Muller (1958): u1 = (wa + 1) 2^-32 in (0, 1], u2 = wb 2^-32 in [0, 1);
 // r = sqrt(-2 ln u1); (r cos 2 pi u2, r sin 2 pi u2).  The hardware sine and
-// cosine take their argument in revolutions, so u2 is passed as is.
+// cosine take their argument in revolutions, so u2 is passed as is.  r is
+// sqrt(-2 ln 2 log2 u1) with the hardware base-2 logarithm and square root:
+// u1 >= 2^-32 and -2 ln u1 <= 44.4 are normal (or zero), so neither needs
+// the library functions' rescaling of tiny arguments, which cost 14 more
+// instructions per pair of normals.
 struct F2 {
   float x, y;
 };
@@ -289,7 +293,8 @@ __device__ __forceinline__ F2 box_muller(uint32_t wa, uint32_t wb) {
   constexpr float two_m32 = 2.3283064365386963e-10f;  // 2^-32
   float u1 = fmaf(static_cast<float>(wa), two_m32, two_m32);
   float u2 = static_cast<float>(wb) * two_m32;
-  float r = __fsqrt_rn(-2.0f * __logf(u1));
+  constexpr float kMinus2Ln2 = -1.38629436112f;  // -2 ln 2
+  const float r = __builtin_amdgcn_sqrtf(kMinus2Ln2 * __builtin_amdgcn_logf(u1));
   F2 z;
   z.x = r * __builtin_amdgcn_cosf(u2);
   z.y = r * __builtin_amdgcn_sinf(u2);
