@@ -123,7 +123,9 @@ pdiv_status pdiv_divergence_gaussian(const void* mean_u, const void* var_u, cons
  * free combination, so cells near 0 and near 1 keep their relative accuracy.
  * div_mean, div_var: [ny][nx] float32; isovalues_host: n_iso floats in host
  * memory, 1 <= n_iso <= PDIV_MAX_ISO; lcp: n_iso maps of ny-1 rows of nx-1
- * float32 cells, cell (q, j, i) at lcp[q*plane_stride + j*row_pitch + i].
+ * float32 cells (device memory, 4-byte aligned like any float array; a
+ * misaligned pointer is rejected), cell (q, j, i) at
+ * lcp[q*plane_stride + j*row_pitch + i].
  * lcp_row_pitch: floats between rows (0: nx-1, dense; larger values pad the
  * rows, and padding is never written).  lcp_plane_stride: floats between maps
  * (0: (ny-1)*row_pitch); maps may also be interleaved by rows (plane stride
@@ -131,7 +133,9 @@ pdiv_status pdiv_divergence_gaussian(const void* mean_u, const void* var_u, cons
  * buffer); layouts whose maps overlap are rejected.  When the row pitch and
  * plane stride are multiples of 32 floats and lcp is 128-byte aligned, every
  * store writes whole cache lines, which the kernel needs for its full write
- * bandwidth; rows interleaved by isovalue write faster still on gfx950. */
+ * bandwidth (on other rows the lines that neighbouring strips share are
+ * completed in L2: 8192^2 dense maps at 16 isovalues take about 1.36x the
+ * time); rows interleaved by isovalue write faster still on gfx950. */
 pdiv_status pdiv_lcp(const float* div_mean, const float* div_var, int64_t ny, int64_t nx,
                      const float* isovalues_host, int32_t n_iso, float* lcp,
                      int64_t lcp_row_pitch, int64_t lcp_plane_stride, pdiv_stream stream);

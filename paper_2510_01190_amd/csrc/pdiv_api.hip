@@ -155,6 +155,15 @@ pdiv_status check_grid3(int64_t nz, int64_t ny, int64_t nx) {
     if ((p) == nullptr) return invalid("%s is NULL", #p); \
   } while (0)
 
+// A float output: non-null and 4-byte aligned (the kernels store whole
+// floats, two at a time on the paired tiles).
+#define PDIV_FLOATS(p)                                                          \
+  do {                                                                          \
+    PDIV_NONNULL(p);                                                            \
+    if (reinterpret_cast<uintptr_t>(p) % 4 != 0)                                \
+      return invalid("%s must be 4-byte aligned (a float array)", #p);          \
+  } while (0)
+
 pdiv_status lcp_chunks(bool fused, const void* p0, const void* p1, const void* p2,
                        const void* p3, pdiv_dtype dt, int64_t ny, int64_t nx, double dx,
                        double dy, const float* iso_host, int32_t n_iso, float* lcp,
@@ -468,7 +477,7 @@ pdiv_status pdiv_lcp(const float* div_mean, const float* div_var, int64_t ny, in
            (long long)nx, n_iso, (long long)lcp_row_pitch, (long long)lcp_plane_stride);
   PDIV_NONNULL(div_mean);
   PDIV_NONNULL(div_var);
-  PDIV_NONNULL(lcp);
+  PDIV_FLOATS(lcp);
   PDIV_TRY(check_grid(ny, nx));
   PDIV_TRY(check_iso(isovalues_host, n_iso));
   OutLayout lo;
@@ -493,7 +502,7 @@ pdiv_status pdiv_lcp_from_moments(const void* mean_u, const void* var_u, const v
   PDIV_NONNULL(var_u);
   PDIV_NONNULL(mean_v);
   PDIV_NONNULL(var_v);
-  PDIV_NONNULL(lcp);
+  PDIV_FLOATS(lcp);
   PDIV_TRY(check_dtype(in_dtype, "in_dtype"));
   PDIV_TRY(check_grid(ny, nx));
   PDIV_TRY(check_spacing(dx, dy));
@@ -654,7 +663,7 @@ pdiv_status pdiv_lcp_3d(const float* div_mean, const float* div_var, int64_t nz,
            (long long)nx, n_iso);
   PDIV_NONNULL(div_mean);
   PDIV_NONNULL(div_var);
-  PDIV_NONNULL(lcp);
+  PDIV_FLOATS(lcp);
   PDIV_TRY(check_grid3(nz, ny, nx));
   PDIV_TRY(check_iso(isovalues_host, n_iso));
   if (!lcp3d_slice_fits(ny, nx, 4))
@@ -682,7 +691,7 @@ pdiv_status pdiv_lcp_3d_from_moments(const void* mean_u, const void* var_u, cons
   PDIV_NONNULL(var_v);
   PDIV_NONNULL(mean_w);
   PDIV_NONNULL(var_w);
-  PDIV_NONNULL(lcp);
+  PDIV_FLOATS(lcp);
   PDIV_TRY(check_dtype(in_dtype, "in_dtype"));
   PDIV_TRY(check_grid3(nz, ny, nx));
   PDIV_TRY(check_spacing(dx, dy));
@@ -710,7 +719,7 @@ pdiv_status pdiv_mc_lcp(const void* mean_u, const void* var_u, const void* mean_
   PDIV_NONNULL(var_u);
   PDIV_NONNULL(mean_v);
   PDIV_NONNULL(var_v);
-  PDIV_NONNULL(lcp);
+  PDIV_FLOATS(lcp);
   PDIV_TRY(check_dtype(in_dtype, "in_dtype"));
   PDIV_TRY(check_grid(ny, nx));
   PDIV_TRY(check_spacing(dx, dy));

@@ -65,6 +65,10 @@ def test_lcp_rejects_bad_arguments():
     _expect_invalid(L.pdiv_lcp(FAKE, FAKE, 8, 1, ip, 2, FAKE, 0, 0, NUL), "at least 2x2")
     _expect_invalid(L.pdiv_lcp(NUL, FAKE, 8, 8, ip, 2, FAKE, 0, 0, NUL), "div_mean is NULL")
     _expect_invalid(L.pdiv_lcp(FAKE, FAKE, 8, 8, ip, 2, NUL, 0, 0, NUL), "lcp is NULL")
+    _expect_invalid(L.pdiv_lcp(FAKE, FAKE, 8, 8, ip, 2, ctypes.c_void_p(0x1002), 0, 0, NUL),
+                    "4-byte aligned")
+    _expect_invalid(L.pdiv_lcp_from_moments(FAKE, FAKE, FAKE, FAKE, 0, 8, 8, 1.0, 1.0, ip, 2,
+                                            ctypes.c_void_p(0x1001), 0, 0, NUL), "4-byte aligned")
     _expect_invalid(L.pdiv_lcp(FAKE, FAKE, 8, 8, ip, 0, FAKE, 0, 0, NUL), "n_iso")
     _expect_invalid(L.pdiv_lcp(FAKE, FAKE, 8, 8, ip, 257, FAKE, 0, 0, NUL), "n_iso")
     _expect_invalid(L.pdiv_lcp(FAKE, FAKE, 8, 8, None, 2, FAKE, 0, 0, NUL), "isovalues_host")
