@@ -9,6 +9,7 @@ import pytest
 from scipy import stats
 
 import oracle as O
+from oracle import pdiv_oracle
 
 HERE = os.path.dirname(os.path.abspath(__file__))
 
@@ -28,22 +29,64 @@ def test_philox_known_answers(ctr, key, want):
     assert tuple(int(g[0]) for g in got) == want
 
 
-def test_philox_matches_rocrand_routine(tmp_path):
+@pytest.fixture(scope="module")
+def rocrand_philox(tmp_path_factory):
+    """rocRAND's Philox4x32-10 routine (compiled from its source header on the
+    host): an array [n][6] of (counter words, key words) -> [n][4] words."""
     hipcc = shutil.which("hipcc")
     if hipcc is None:
         pytest.skip("hipcc not available")
-    exe = str(tmp_path / "philox_check")
+    exe = str(tmp_path_factory.mktemp("philox") / "philox_check")
     subprocess.run([hipcc, "-x", "hip", "--offload-arch=gfx950", "-O1",
                     os.path.join(HERE, "philox_rocrand_check.cpp"), "-o", exe],
                    check=True, capture_output=True)
+
+    def run(tup):
+        inp = "\n".join(" ".join(f"{int(x):x}" for x in row) for row in tup) + "\n"
+        out = subprocess.run([exe], input=inp, capture_output=True, text=True, check=True).stdout
+        return np.array([[int(w, 16) for w in line.split()] for line in out.strip().splitlines()],
+                        np.uint32)
+    return run
+
+
+def test_philox_matches_rocrand_routine(rocrand_philox):
     rng = np.random.default_rng(9)
     tup = rng.integers(0, 2 ** 32, (64, 6), dtype=np.uint64).astype(np.uint32)
-    inp = "\n".join(" ".join(f"{int(x):x}" for x in row) for row in tup) + "\n"
-    out = subprocess.run([exe], input=inp, capture_output=True, text=True, check=True).stdout
-    lib = np.array([[int(w, 16) for w in line.split()] for line in out.strip().splitlines()])
+    lib = rocrand_philox(tup)
     for r in range(64):
         got = O.philox4x32_10(*[tup[r:r + 1, c] for c in range(4)], int(tup[r, 4]), int(tup[r, 5]))
         assert [int(g[0]) for g in got] == list(lib[r])
+
+
+def test_sample_streams_follow_the_documented_counter_layout(rocrand_philox):
+    """The counter layout stated for pdiv_mc_lcp, checked against rocRAND's
+    Philox: vector sampling draws sample s at point p = j*nx + i from counter
+    (p, s/2, 0, 0) with key (seed low word, high word), the U and V normals
+    of even s from Box-Muller on output words (w0, w1) and of odd s on
+    (w2, w3); vertex sampling draws from counter (p, s/4, 1, 0), samples 4q
+    and 4q+1 from (w0, w1), 4q+2 and 4q+3 from (w2, w3)."""
+    ny, nx = 5, 7
+    seed = 0x0123_4567_89AB_CDEF
+    k_lo, k_hi = seed & 0xFFFFFFFF, seed >> 32
+    rng = np.random.default_rng(4)
+    mu_u, mu_v = rng.normal(0, 1, (ny, nx)), rng.normal(0, 1, (ny, nx))
+    var_u, var_v = rng.uniform(0.1, 1, (ny, nx)), rng.uniform(0.1, 1, (ny, nx))
+    pts = [0, 1, nx, ny * nx - 1, 17]
+    for s in (0, 1, 2, 7, 1000):
+        u, v = O.mc_sample_field(mu_u, var_u, mu_v, var_v, s, seed)
+        w = rocrand_philox(np.array([[p, s // 2, 0, 0, k_lo, k_hi] for p in pts], np.uint64)
+                           .astype(np.uint32))
+        zu, zv = O.box_muller(w[:, 2 * (s % 2)], w[:, 2 * (s % 2) + 1])
+        for n, p in enumerate(pts):
+            j, i = divmod(p, nx)
+            assert u[j, i] == mu_u[j, i] + np.sqrt(var_u[j, i]) * zu[n]
+            assert v[j, i] == mu_v[j, i] + np.sqrt(var_v[j, i]) * zv[n]
+    for s in (0, 1, 2, 3, 4, 9, 403):
+        z = pdiv_oracle._vertex_normals(ny * nx, s, seed)
+        w = rocrand_philox(np.array([[p, s // 4, 1, 0, k_lo, k_hi] for p in pts], np.uint64)
+                           .astype(np.uint32))
+        pair = O.box_muller(w[:, 0], w[:, 1]) if s % 4 < 2 else O.box_muller(w[:, 2], w[:, 3])
+        assert np.array_equal(z[pts], pair[s % 2])
 
 
 def test_box_muller_closed_forms():
