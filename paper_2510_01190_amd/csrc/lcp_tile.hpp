@@ -8,7 +8,7 @@
 // right through DPP.  The next row's input loads are issued before the
 // current row is computed, and stores are masked by their buffer record range
 // (checked per dword), not by branches.  Two strip layouts, the same
-// arithmetic (so the same bits):
+// arithmetic (so the same bits), and two store policies for the paired one:
 //
 // Paired (lcp_tile_paired), for outputs whose rows start on 128-byte lines: a
 // wave owns the 128 cells [x0, x0+128), x0 = 128 strip, i.e. vertex columns
@@ -32,15 +32,14 @@
 // against 0.47 / 0.66 / 1.13 ms into line-aligned rows (with the streaming
 // policy 0.578 / 0.974 / 1.760 ms; the split tile 1.51 ms at 16).
 //
-// Split (lcp_tile_split), for any other output: a wave owns 127 vertex
-// columns, the 126 cells [x0, x0+126), x0 = 126 strip.  Lane L holds columns
-// A = x0+L and B = x0+63+L (lane 63's A repeats lane 0's B), forms cells
-// (A, A+1) and (B, B+1) with the right pair from lane L+1, and lanes 0..62
-// write 63 consecutive cells per store.  No seam step; rows that start
-// inside a line cap the store rate near 4.4 TB/s for either layout, so the
-// cheaper tile wins there, and on small maps with few isovalues, where a
-// launch's fixed cost dominates and is lower for this tile (use_paired_tile
-// below).
+// Split (lcp_tile_split), for the other outputs (the two-step path on rows
+// that start inside a line, and small maps with few isovalues, where a
+// launch's fixed cost dominates and is lower for this tile: use_paired_tile
+// below): a wave owns 127 vertex columns, the 126 cells [x0, x0+126),
+// x0 = 126 strip.  Lane L holds columns A = x0+L and B = x0+63+L (lane 63's
+// A repeats lane 0's B), forms cells (A, A+1) and (B, B+1) with the right
+// pair from lane L+1, and lanes 0..62 write 63 consecutive cells per store.
+// No seam step.
 #pragma once
 
 #include "pdiv_device.hpp"
