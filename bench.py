@@ -236,9 +236,13 @@ def guarded(name, fn, *args, **kw):
         return {"error": f"{type(e).__name__}: {e}"}
 
 
-def time_launches(fn, n, torch):
+def time_launches(fn, n, torch, settle_s=0.15):
     """Average device time of fn() over n back-to-back launches, HIP events on
-    the current stream (the stream every launch is enqueued on)."""
+    the current stream (the stream every launch is enqueued on), after fn()
+    has run back to back for settle_s seconds (see settle), so that each leg,
+    like the headline step, is timed at settled clocks."""
+    if settle_s > 0:
+        settle(fn, torch, settle_s)
     start = torch.cuda.Event(enable_timing=True)
     stop = torch.cuda.Event(enable_timing=True)
     torch.cuda.synchronize()
@@ -475,7 +479,8 @@ def mc_leg(P, synth, torch, np, samples=1000):
     iso = c3["isovalues"]
     out = torch.empty((iso.size, c3["ny"] - 1, c3["nx"] - 1), device="cuda")
     P.mc_lcp(*mom, iso, n_samples=2, seed=1, out=out)
-    t = time_launches(lambda: P.mc_lcp(*mom, iso, n_samples=samples, seed=2025, out=out), 1, torch)
+    t = time_launches(lambda: P.mc_lcp(*mom, iso, n_samples=samples, seed=2025, out=out), 1, torch,
+                      settle_s=0)
     return {"ms": round(t * 1e3, 3), "samples": samples,
             "point_samples_per_s": round(c3["ny"] * c3["nx"] * samples / t, 1)}
 
@@ -872,7 +877,8 @@ def main():
         mc_out = torch.empty((K, ny - 1, nx - 1), device="cuda")
         P.mc_lcp(*mom, iso, n_samples=2, seed=1, out=mc_out)
         torch.cuda.synchronize()
-        t = time_launches(lambda: P.mc_lcp(*mom, iso, n_samples=S, seed=2025, out=mc_out), 1, torch)
+        t = time_launches(lambda: P.mc_lcp(*mom, iso, n_samples=S, seed=2025, out=mc_out), 1,
+                          torch, settle_s=0)
         result["mc"] = {"value": round(cells * K / t, 1), "unit": "LCP cells/s", "samples": S,
                         "ms": round(t * 1e3, 3),
                         "point_samples_per_s": round(ny * nx * S / t, 1),
