@@ -24,6 +24,7 @@ from .pdiv_oracle import (  # noqa: F401
     box_muller,
     mc_sample_field,
     mc_lcp,
+    mc_lcp_rows,
     mc_lcp_vertex,
     marching_squares,
     spaghetti,

@@ -258,20 +258,22 @@ def box_muller(wa, wb):
     return r * np.cos(2.0 * np.pi * u2), r * np.sin(2.0 * np.pi * u2)
 
 
-def _normals(n_points: int, s: int, seed: int):
-    """Standard normals (zu, zv) of sample s at points 0..n_points-1."""
-    p = np.arange(n_points, dtype=np.uint64).astype(np.uint32)
+def _normals(n_points: int, s: int, seed: int, first: int = 0):
+    """Standard normals (zu, zv) of sample s at points first .. first+n_points-1."""
+    p = (np.arange(n_points, dtype=np.uint64) + np.uint64(first)).astype(np.uint32)
     q = np.full(n_points, s // 2, np.uint32)
     zero = np.zeros(n_points, np.uint32)
     w0, w1, w2, w3 = philox4x32_10(p, q, zero, zero, seed & 0xFFFFFFFF, (seed >> 32) & 0xFFFFFFFF)
     return box_muller(w0, w1) if s % 2 == 0 else box_muller(w2, w3)
 
 
-def mc_sample_field(mean_u, var_u, mean_v, var_v, s: int, seed: int):
-    """Sample s of the uncertain field: U = mu_u + sigma_u zu, V = mu_v + sigma_v zv (float64)."""
+def mc_sample_field(mean_u, var_u, mean_v, var_v, s: int, seed: int, first_point: int = 0):
+    """Sample s of the uncertain field: U = mu_u + sigma_u zu, V = mu_v + sigma_v zv (float64).
+    first_point: the index of the planes' first point in a larger grid (the
+    rows of a band of that grid), so that each point draws its own samples."""
     mu_u = np.asarray(mean_u, np.float64)
     ny, nx = mu_u.shape
-    zu, zv = _normals(ny * nx, s, seed)
+    zu, zv = _normals(ny * nx, s, seed, first_point)
     u = mu_u + np.sqrt(np.asarray(var_u, np.float64)) * zu.reshape(ny, nx)
     v = np.asarray(mean_v, np.float64) + np.sqrt(np.asarray(var_v, np.float64)) * zv.reshape(ny, nx)
     return u, v
@@ -330,7 +332,8 @@ def _crossed(d, c):
 
 
 def mc_lcp(mean_u, var_u, mean_v, var_v, dx: float, dy: float, isovalues,
-           n_samples: int, seed: int, precision: str = "f64", mode: str = "vector"):
+           n_samples: int, seed: int, precision: str = "f64", mode: str = "vector",
+           first_point: int = 0):
     """MC LCP maps [K][ny-1][nx-1] (crossing counts / n_samples).
 
     mode="vector" (the paper's sampling, Sections 3.2 and 4): each sample
@@ -344,7 +347,10 @@ def mc_lcp(mean_u, var_u, mean_v, var_v, dx: float, dy: float, isovalues,
     precision="f32": the same steps with the sample field, the divergence and
     the crossing test rounded to float32 -- the precision in which a float32
     implementation takes the crossing decision.  The normals themselves are
-    computed in float64 and rounded once."""
+    computed in float64 and rounded once.
+
+    first_point (vector mode): the index of the planes' first point in a
+    larger grid whose samples these are (see mc_lcp_rows)."""
     iso = np.atleast_1d(np.asarray(isovalues, np.float64))
     mu_u = np.asarray(mean_u, np.float64)
     ny, nx = mu_u.shape
@@ -373,7 +379,7 @@ def mc_lcp(mean_u, var_u, mean_v, var_v, dx: float, dy: float, isovalues,
         raise ValueError(mode)
     if precision == "f64":
         for s in range(n_samples):
-            u, v = mc_sample_field(mean_u, var_u, mean_v, var_v, s, seed)
+            u, v = mc_sample_field(mean_u, var_u, mean_v, var_v, s, seed, first_point)
             d = fd_divergence(u, v, dx, dy)
             for k, c in enumerate(iso):
                 counts[k] += _crossed(d, c)
@@ -387,7 +393,7 @@ def mc_lcp(mean_u, var_u, mean_v, var_v, dx: float, dy: float, isovalues,
         cx_in, cx_bd = f(1.0 / (2.0 * dx)), f(1.0 / dx)
         cy_in, cy_bd = f(1.0 / (2.0 * dy)), f(1.0 / dy)
         for s in range(n_samples):
-            zu, zv = _normals(ny * nx, s, seed)
+            zu, zv = _normals(ny * nx, s, seed, first_point)
             u = mu_u32 + sd_u32 * zu.reshape(ny, nx).astype(f)
             v = mu_v32 + sd_v32 * zv.reshape(ny, nx).astype(f)
             ddx = np.empty((ny, nx), f)
@@ -404,6 +410,21 @@ def mc_lcp(mean_u, var_u, mean_v, var_v, dx: float, dy: float, isovalues,
     else:
         raise ValueError(precision)
     return counts / float(n_samples)
+
+
+def mc_lcp_rows(mean_u, var_u, mean_v, var_v, dx: float, dy: float, isovalues,
+                n_samples: int, seed: int, j0: int, j1: int, precision: str = "f64"):
+    """mc_lcp (vector sampling) on cell rows [j0, j1) of the grid alone: the
+    same samples, since every point keeps its Philox counter (its index in
+    the whole grid), drawn on point rows j0-1 .. j1+1 (clamped to the grid),
+    the rows Eq. 1 reads for vertex rows j0 .. j1.  Equal to
+    mc_lcp(...)[:, j0:j1]."""
+    ny, nx = np.shape(mean_u)
+    a, b = max(0, j0 - 1), min(ny, j1 + 2)
+    band = [np.asarray(x)[a:b] for x in (mean_u, var_u, mean_v, var_v)]
+    lcp_band = mc_lcp(*band, dx, dy, isovalues, n_samples, seed, precision,
+                      first_point=a * nx)
+    return lcp_band[:, j0 - a:j1 - a]
 
 
 def mc_lcp_vertex(div_mean, div_var, isovalues, n_samples: int, seed: int):

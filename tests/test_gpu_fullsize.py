@@ -5,7 +5,9 @@ times, on sampled rows the oracle computes band by band.
 1e-5 of the FP64 oracle on the stored values and on the original float64
 field; float16 / bfloat16 errors are measured and stated.  721x1440 with 50
 members (the ensemble pipeline): fit -> fused LCP against the oracle run on
-the same members."""
+the same members.  The Monte Carlo comparison at 8192x8192, 16 isovalues and
+1000 samples: crossing counts on sampled rows against the oracle's float32 MC,
+drawn from the same Philox counters."""
 
 import numpy as np
 import pytest
@@ -66,6 +68,35 @@ def test_c3_sampled_rows(c3, dt):
     assert worst_k <= LCP_TOL
     if dt == "f32":
         assert worst_e <= LCP_TOL
+    del out, ts
+    torch.cuda.empty_cache()
+
+
+MC_ROWS = [(0, 2), (4095, 4097), (8189, 8191)]
+
+
+def test_c3_mc_sampled_rows(c3):
+    """The Monte Carlo comparison at its benchmark launch (the whole 8192x8192
+    field, 16 isovalues, 1000 samples, seed 2025) against the oracle's
+    float32-precision MC on bottom, middle and top cell rows: each point keeps
+    its Philox counter, so the oracle's band draws the kernel's samples."""
+    ny, nx = c3["ny"], c3["nx"]
+    iso = c3["isovalues"]
+    S, seed = 1000, 2025
+    ts = [torch.from_numpy(c3[k]).float().cuda() for k in ("mean_u", "var_u", "mean_v", "var_v")]
+    out = torch.empty((iso.size, ny - 1, nx - 1), device="cuda")
+    P.mc_lcp(*ts, iso, n_samples=S, seed=seed, out=out)
+    torch.cuda.synchronize()
+    stored = [host64(t) for t in ts]
+    total, n = 0, 0
+    for j0, j1 in MC_ROWS:
+        g = host64(out[:, j0:j1, :])
+        r = O.mc_lcp_rows(*stored, 1.0, 1.0, iso, S, seed, j0, j1, precision="f32")
+        flips = np.abs(np.rint(g * S) - np.rint(r * S))
+        total += int(flips.sum())
+        n += flips.size
+    print(f"\n[c3 mc S={S}] {total} crossing-count flips over {n} cells x {S} samples")
+    assert total <= 5 + 1e-5 * n * S
     del out, ts
     torch.cuda.empty_cache()
 

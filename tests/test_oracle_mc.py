@@ -198,6 +198,23 @@ def test_mc_f32_and_f64_agree_up_to_rare_flips():
     assert np.sum(np.abs(a - b) * S) <= 5
 
 
+@pytest.mark.parametrize("prec", ["f64", "f32"])
+def test_mc_on_a_band_of_rows_is_the_whole_grid_sliced(prec):
+    """Each point keeps its Philox counter (its index in the whole grid), so
+    the MC on a band of cell rows -- bottom, top, interior, one-row and
+    whole-grid bands -- reproduces those rows of the whole-grid run exactly."""
+    rng = np.random.default_rng(12)
+    ny, nx = 9, 11
+    mu_u, mu_v = rng.normal(0, 0.5, (ny, nx)), rng.normal(0, 0.5, (ny, nx))
+    var_u, var_v = rng.uniform(0.05, 0.5, (ny, nx)) ** 2, rng.uniform(0.05, 0.5, (ny, nx)) ** 2
+    iso, S = [-0.2, 0.0, 0.4], 24
+    full = O.mc_lcp(mu_u, var_u, mu_v, var_v, 0.5, 2.0, iso, S, seed=7, precision=prec)
+    for j0, j1 in [(0, 1), (0, 3), (3, 5), (4, 5), (6, 8), (7, 8), (0, 8)]:
+        band = O.mc_lcp_rows(mu_u, var_u, mu_v, var_v, 0.5, 2.0, iso, S, seed=7,
+                             j0=j0, j1=j1, precision=prec)
+        np.testing.assert_array_equal(band, full[:, j0:j1])
+
+
 @pytest.mark.parametrize("S", [8, 64])
 def test_mc_sse_follows_binomial_expectation(S):
     """The error curve of Sec. 4 (Fig. 4): on an interior cell each sample's
