@@ -27,6 +27,7 @@ from .pdiv_oracle import (  # noqa: F401
     mc_lcp_rows,
     mc_lcp_vertex,
     marching_squares,
+    marching_squares_row_counts,
     spaghetti,
 )
 from .pdiv_oracle3d import (  # noqa: F401

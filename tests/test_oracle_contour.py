@@ -57,6 +57,26 @@ def test_crossed_cells_are_the_zero_variance_lcp():
         np.testing.assert_array_equal(n_per_cell > 0, ind == 1.0)
 
 
+def test_row_counts_are_the_segments_of_each_row():
+    """marching_squares_row_counts, from the case numbers alone, equals the
+    number of segments marching_squares emits for each one-row band, on
+    fields with ties at the isovalue and saddles, and its crossed cells are
+    those of the zero-variance LCP."""
+    rng = np.random.default_rng(5)
+    fields = [np.round(rng.normal(0, 1, (9, 23)), 1),
+              np.tile(np.array([[1.0, 0.0], [0.0, 1.0]]), (5, 6)),
+              rng.normal(0, 1, (2, 40))]
+    for f in fields:
+        for c in (0.0, 0.3, 0.5, -1.1):
+            n = O.marching_squares_row_counts(f, c)
+            assert n.shape == (f.shape[0] - 1,)
+            for j in range(f.shape[0] - 1):
+                assert n[j] == len(O.marching_squares(f[j:j + 2], c))
+            assert n.sum() == len(O.marching_squares(f, c))
+            crossed = O.lcp(f, np.zeros_like(f), [c])[0] == 1.0
+            assert np.all(n >= crossed.sum(axis=1)) and np.all(n <= 2 * crossed.sum(axis=1))
+
+
 def test_saddles_follow_the_centre():
     f = np.array([[1.0, 0.0], [0.0, 1.0]])  # (0,0) and (1,1) above: case 5
     s = O.marching_squares(f, 0.5)  # centre 0.5 >= 0.5: the above corners join
