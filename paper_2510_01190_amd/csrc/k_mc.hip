@@ -10,7 +10,21 @@
 // 32x32 cells against every isovalue, accumulating integer counts in
 // registers.  Samples are regenerated from their counters, never stored, so
 // neighbouring tiles see identical values at shared points.  This path is
-// bound by integer multiplies and transcendentals, not by memory.
+// bound by vector ALU work (integer multiplies, transcendentals, compares),
+// not by memory.
+//
+// Crossing test at 16 isovalues (ranked): with the isovalues in ascending
+// order, a vertex's rank r(d) = #{q : c_q <= d} says that it is above exactly
+// the isovalues q < r(d) (>= counts as above), so a cell is crossed exactly
+// at the isovalues rmin <= q < rmax, rmin and rmax the smallest and largest
+// rank of its corners.  Each vertex's rank comes from a branch-free binary
+// search (four LDS lookups in a breadth-first table, one compare with the
+// largest isovalue); each cell's crossed set is the bit mask [rmin, rmax);
+// the masks of two cells share a 32-bit word and are counted in bit-sliced
+// counters (bit plane b holds bit b of every count): a 4-plane counter takes
+// each pair of samples with a handful of logic operations and is added into
+// a 16-plane counter every 7 pairs.  About a third of the instructions of
+// 16 compares and a carry-add per isovalue and cell, the same counts.
 //
 // Vertex-level sampling (PDIV_MC_VERTEX) draws each vertex divergence on its
 // own from the Gaussian of Eq. 2-3 instead, so the four corners of every cell
@@ -47,19 +61,112 @@ __device__ __forceinline__ float fd_div(float ul, float ur, float vl, float vr, 
   return (ur - ul) * cxm + (vr - vl) * cym;
 }
 
-template <int KC, typename T>
+// The isovalues of a 16-isovalue chunk in ascending order: tree[1..15] holds
+// the 15 smallest in breadth-first order of a complete binary search tree
+// (node i's children are 2i and 2i+1; an in-order walk visits them sorted),
+// tree[0] the largest; perm[q] is the output plane of the q-th smallest.
+struct RankTable {
+  float tree[16];
+  int perm[16];
+};
+
+// #{q : c_q <= d} over the 16 sorted isovalues (0..16); NaN ranks 0, below
+// every isovalue, as every >= comparison with it is false.  The walk keeps
+// the node's byte offset a = 4i in the table (children at 2a and 2a + 4), so
+// each level is one LDS read, a compare, a select and a shift-add.
+__device__ __forceinline__ uint32_t rank16(float d, const float* tree, float top) {
+  const char* base = reinterpret_cast<const char*>(tree);
+  uint32_t a = 4u;
+#pragma unroll
+  for (int k = 0; k < 4; ++k) {
+    const float t = *reinterpret_cast<const float*>(base + a);
+    a = 2u * a + (d >= t ? 4u : 0u);
+  }
+  return (a >> 2) - 16u + (d >= top ? 1u : 0u);
+}
+
+// Crossing counts of 32 (cell, isovalue) slots in bit-sliced form: bit j of
+// s[b] / t[b] is bit b of slot j's count.  add2 adds the 0/1 masks of two
+// samples to the 4-plane counter s (at most 15: flush after 7 pairs);
+// flush adds s into the 16-plane counter t (counts up to 65535) and clears s.
+struct Sliced {
+  uint32_t s[4];
+  uint32_t t[16];
+};
+
+__device__ __forceinline__ void sliced_clear(Sliced& c) {
+#pragma unroll
+  for (int b = 0; b < 4; ++b) c.s[b] = 0u;
+#pragma unroll
+  for (int b = 0; b < 16; ++b) c.t[b] = 0u;
+}
+
+__device__ __forceinline__ void sliced_add2(Sliced& c, uint32_t w0, uint32_t w1) {
+  const uint32_t x = w0 ^ w1, y = w0 & w1;  // the pair's sum: y x, two bits
+  const uint32_t c0 = c.s[0] & x;
+  c.s[0] ^= x;
+  const uint32_t t1 = c.s[1] ^ y;
+  const uint32_t c1 = (c.s[1] & y) | (t1 & c0);
+  c.s[1] = t1 ^ c0;
+  const uint32_t c2 = c.s[2] & c1;
+  c.s[2] ^= c1;
+  c.s[3] ^= c2;
+}
+
+__device__ __forceinline__ void sliced_flush(Sliced& c) {
+  uint32_t carry = c.t[0] & c.s[0];
+  c.t[0] ^= c.s[0];
+#pragma unroll
+  for (int b = 1; b < 4; ++b) {
+    const uint32_t u = c.t[b] ^ c.s[b];
+    const uint32_t nc = (c.t[b] & c.s[b]) | (u & carry);
+    c.t[b] = u ^ carry;
+    carry = nc;
+  }
+#pragma unroll
+  for (int b = 4; b < 16; ++b) {
+    const uint32_t nc = c.t[b] & carry;
+    c.t[b] ^= carry;
+    carry = nc;
+  }
+#pragma unroll
+  for (int b = 0; b < 4; ++b) c.s[b] = 0u;
+}
+
+__device__ __forceinline__ uint32_t sliced_count(const Sliced& c, int j) {
+  uint32_t n = 0;
+#pragma unroll
+  for (int b = 0; b < 16; ++b) n |= ((c.t[b] >> j) & 1u) << b;
+  return n;
+}
+
+// Crossed isovalues of a cell from its corners' ranks: the bits rmin..rmax-1.
+__device__ __forceinline__ uint32_t crossed_mask(uint32_t r0, uint32_t r1, uint32_t r2,
+                                                 uint32_t r3) {
+  const uint32_t lo = min(min(r0, r1), min(r2, r3));
+  const uint32_t hi = max(max(r0, r1), max(r2, r3));
+  return ((1u << (hi - lo)) - 1u) << lo;
+}
+
+// RANK (16 isovalues, at most 65535 samples): the ranked crossing test; the
+// divergence slots hold each vertex's rank instead of its value.
+template <int KC, bool RANK, typename T>
 __global__ __launch_bounds__(kBlock) void mc_kernel(const T* __restrict__ mu,
                                                     const T* __restrict__ vu,
                                                     const T* __restrict__ mv,
                                                     const T* __restrict__ vv, int ny, int nx,
-                                                    StencilCoef k, IsoChunk iso, int n_store,
-                                                    int n_samples, uint32_t key0, uint32_t key1,
-                                                    float* __restrict__ out, int64_t plane) {
+                                                    StencilCoef k, IsoChunk iso, RankTable rt,
+                                                    int n_store, int n_samples, uint32_t key0,
+                                                    uint32_t key1, float* __restrict__ out,
+                                                    int64_t plane) {
+  static_assert(!RANK || KC == 16, "the ranked test is for 16-isovalue chunks");
   __shared__ float sU[2][NP];
   __shared__ float sV[2][NP];
   __shared__ float sD[2][NV];
+  __shared__ float sTree[16];
 
   const int tid = threadIdx.x;
+  if (RANK && tid < 16) sTree[tid] = rt.tree[tid];  // read after the first barrier
   const int x0 = blockIdx.x * TX;
   const int y0 = blockIdx.y * TY;
 
@@ -84,11 +191,15 @@ __global__ __launch_bounds__(kBlock) void mc_kernel(const T* __restrict__ mu,
     }
   }
 
-  uint32_t cnt[CPT][KC];
+  constexpr int kCnt = RANK ? 1 : CPT;  // direct counters (unused when ranked)
+  uint32_t cnt[kCnt][KC];
 #pragma unroll
-  for (int m = 0; m < CPT; ++m)
+  for (int m = 0; m < kCnt; ++m)
 #pragma unroll
     for (int q = 0; q < KC; ++q) cnt[m][q] = 0;
+  Sliced sl[RANK ? CPT / 2 : 1];  // ranked: cells 2w and 2w+1 share word w
+#pragma unroll
+  for (int w = 0; w < (RANK ? CPT / 2 : 1); ++w) sliced_clear(sl[w]);
 
   const int n_pairs = (n_samples + 1) >> 1;
   for (int pr = 0; pr < n_pairs; ++pr) {
@@ -135,29 +246,62 @@ __global__ __launch_bounds__(kBlock) void mc_kernel(const T* __restrict__ mu,
           const int jl = (yl - (y0 - 1)) * PX + px;
           const int jr = (yr - (y0 - 1)) * PX + px;
 #pragma unroll
-          for (int s = 0; s < 2; ++s)
-            sD[s][v] = fd_div(sU[s][il], sU[s][ir], sV[s][jl], sV[s][jr], cxm, cym);
+          for (int s = 0; s < 2; ++s) {
+            const float d = fd_div(sU[s][il], sU[s][ir], sV[s][jl], sV[s][jr], cxm, cym);
+            sD[s][v] = RANK ? __uint_as_float(rank16(d, sTree, rt.tree[0])) : d;
+          }
         }
       }
     }
     __syncthreads();
     // 3. crossing test per cell: not all four corners on one side (>= is above)
+    if constexpr (RANK) {
+      uint32_t word[2][CPT / 2];
 #pragma unroll
-    for (int m = 0; m < CPT; ++m) {
-      const int cidx = tid + m * kBlock;
-      const int cx = cidx % TX, cy = cidx / TX;
-      if (x0 + cx < nx - 1 && y0 + cy < ny - 1) {
-        const int v00 = cy * VX + cx;
+      for (int s = 0; s < 2; ++s)
 #pragma unroll
-        for (int s = 0; s < 2; ++s) {
-          if (2 * pr + s < n_samples) {
-            const float d0 = sD[s][v00], d1 = sD[s][v00 + 1];
-            const float d2 = sD[s][v00 + VX], d3 = sD[s][v00 + VX + 1];
-            const float lo = fminf(fminf(d0, d1), fminf(d2, d3));
-            const float hi = fmaxf(fmaxf(d0, d1), fmaxf(d2, d3));
+        for (int w = 0; w < CPT / 2; ++w) word[s][w] = 0u;
 #pragma unroll
-            for (int q = 0; q < KC; ++q)
-              cnt[m][q] += static_cast<uint32_t>((lo < iso.c[q]) & (hi >= iso.c[q]));
+      for (int m = 0; m < CPT; ++m) {
+        const int cidx = tid + m * kBlock;
+        const int cx = cidx % TX, cy = cidx / TX;
+        if (x0 + cx < nx - 1 && y0 + cy < ny - 1) {
+          const int v00 = cy * VX + cx;
+#pragma unroll
+          for (int s = 0; s < 2; ++s) {
+            if (2 * pr + s < n_samples) {
+              const uint32_t mk = crossed_mask(
+                  __float_as_uint(sD[s][v00]), __float_as_uint(sD[s][v00 + 1]),
+                  __float_as_uint(sD[s][v00 + VX]), __float_as_uint(sD[s][v00 + VX + 1]));
+              word[s][m >> 1] |= mk << (16 * (m & 1));
+            }
+          }
+        }
+      }
+#pragma unroll
+      for (int w = 0; w < CPT / 2; ++w) sliced_add2(sl[w], word[0][w], word[1][w]);
+      if (pr % 7 == 6) {
+#pragma unroll
+        for (int w = 0; w < CPT / 2; ++w) sliced_flush(sl[w]);
+      }
+    } else {
+#pragma unroll
+      for (int m = 0; m < CPT; ++m) {
+        const int cidx = tid + m * kBlock;
+        const int cx = cidx % TX, cy = cidx / TX;
+        if (x0 + cx < nx - 1 && y0 + cy < ny - 1) {
+          const int v00 = cy * VX + cx;
+#pragma unroll
+          for (int s = 0; s < 2; ++s) {
+            if (2 * pr + s < n_samples) {
+              const float d0 = sD[s][v00], d1 = sD[s][v00 + 1];
+              const float d2 = sD[s][v00 + VX], d3 = sD[s][v00 + VX + 1];
+              const float lo = fminf(fminf(d0, d1), fminf(d2, d3));
+              const float hi = fmaxf(fmaxf(d0, d1), fmaxf(d2, d3));
+#pragma unroll
+              for (int q = 0; q < KC; ++q)
+                cnt[m][q] += static_cast<uint32_t>((lo < iso.c[q]) & (hi >= iso.c[q]));
+            }
           }
         }
       }
@@ -166,6 +310,10 @@ __global__ __launch_bounds__(kBlock) void mc_kernel(const T* __restrict__ mu,
   }
 
   const float fs = static_cast<float>(n_samples);
+  if constexpr (RANK) {
+#pragma unroll
+    for (int w = 0; w < CPT / 2; ++w) sliced_flush(sl[w]);
+  }
 #pragma unroll
   for (int m = 0; m < CPT; ++m) {
     const int cidx = tid + m * kBlock;
@@ -173,8 +321,15 @@ __global__ __launch_bounds__(kBlock) void mc_kernel(const T* __restrict__ mu,
     if (gx < nx - 1 && gy < ny - 1) {
       float* o = out + static_cast<int64_t>(gy) * (nx - 1) + gx;
 #pragma unroll
-      for (int q = 0; q < KC; ++q)
-        if (q < n_store) o[q * plane] = static_cast<float>(cnt[m][q]) / fs;
+      for (int q = 0; q < KC; ++q) {
+        if (q < n_store) {
+          if constexpr (RANK)
+            o[rt.perm[q] * plane] =
+                static_cast<float>(sliced_count(sl[m >> 1], q + 16 * (m & 1))) / fs;
+          else
+            o[q * plane] = static_cast<float>(cnt[m][q]) / fs;
+        }
+      }
     }
   }
 }
@@ -317,12 +472,60 @@ __global__ __launch_bounds__(kBlock) void mc_sample_kernel(const T* __restrict__
   vs[p] = draw(ld(mv, p), __fsqrt_rn(ld(vv, p)), z.y);
 }
 
+// The ranked test's table for a chunk of kc <= 16 isovalues, or false when the
+// chunk holds a NaN (which no ordering places).  Slots past kc hold +inf: a
+// vertex ranks above them only at +inf, and their counts are not stored.
+bool rank_table(const IsoChunk& iso, int kc, RankTable* rt) {
+  int idx[16];
+  for (int q = 0; q < 16; ++q) {
+    if (q < kc && iso.c[q] != iso.c[q]) return false;
+    idx[q] = q;
+  }
+  // stable insertion sort of the kc real isovalues
+  for (int a = 1; a < kc; ++a) {
+    const int v = idx[a];
+    int b = a;
+    for (; b > 0 && iso.c[idx[b - 1]] > iso.c[v]; --b) idx[b] = idx[b - 1];
+    idx[b] = v;
+  }
+  float sorted[16];
+  for (int q = 0; q < 16; ++q) {
+    sorted[q] = q < kc ? iso.c[idx[q]] : __builtin_inff();
+    rt->perm[q] = q < kc ? idx[q] : 0;
+  }
+  // breadth-first placement of sorted[0..14]: an in-order walk of nodes 1..15
+  int next = 0;
+  int stack[8], top = 0, node = 1;
+  while (top > 0 || node <= 15) {
+    while (node <= 15) {
+      stack[top++] = node;
+      node *= 2;
+    }
+    node = stack[--top];
+    rt->tree[node] = sorted[next++];
+    node = 2 * node + 1;
+  }
+  rt->tree[0] = sorted[15];
+  return true;
+}
+
 template <int KC, typename T>
 hipError_t launch_kc(const void* mu, const void* vu, const void* mv, const void* vv, int ny,
                      int nx, const StencilCoef& k, const IsoChunk& iso, int kc, int n_samples,
                      uint64_t seed, bool vertex, float* out, hipStream_t s) {
   dim3 grid(static_cast<unsigned>(mc_tiles_x(nx)), static_cast<unsigned>(mc_tiles_y(ny)));
   const int64_t plane = static_cast<int64_t>(ny - 1) * (nx - 1);
+  RankTable rt{};
+  if constexpr (KC == 16) {
+    if (!vertex && n_samples <= 65535 && rank_table(iso, kc, &rt)) {
+      hipLaunchKernelGGL((mc_kernel<16, true, T>), grid, dim3(kBlock), 0, s,
+                         static_cast<const T*>(mu), static_cast<const T*>(vu),
+                         static_cast<const T*>(mv), static_cast<const T*>(vv), ny, nx, k, iso,
+                         rt, kc, n_samples, static_cast<uint32_t>(seed),
+                         static_cast<uint32_t>(seed >> 32), out, plane);
+      return hipGetLastError();
+    }
+  }
   if (vertex)
     hipLaunchKernelGGL((mc_vertex_kernel<KC, T>), grid, dim3(kBlock), 0, s,
                        static_cast<const T*>(mu), static_cast<const T*>(vu),
@@ -330,10 +533,10 @@ hipError_t launch_kc(const void* mu, const void* vu, const void* mv, const void*
                        n_samples, static_cast<uint32_t>(seed),
                        static_cast<uint32_t>(seed >> 32), out, plane);
   else
-    hipLaunchKernelGGL((mc_kernel<KC, T>), grid, dim3(kBlock), 0, s,
+    hipLaunchKernelGGL((mc_kernel<KC, false, T>), grid, dim3(kBlock), 0, s,
                        static_cast<const T*>(mu), static_cast<const T*>(vu),
-                       static_cast<const T*>(mv), static_cast<const T*>(vv), ny, nx, k, iso, kc,
-                       n_samples, static_cast<uint32_t>(seed),
+                       static_cast<const T*>(mv), static_cast<const T*>(vv), ny, nx, k, iso, rt,
+                       kc, n_samples, static_cast<uint32_t>(seed),
                        static_cast<uint32_t>(seed >> 32), out, plane);
   return hipGetLastError();
 }

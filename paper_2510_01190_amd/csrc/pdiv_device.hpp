@@ -259,6 +259,16 @@ struct U4 {
   uint32_t x, y, z, w;
 };
 
+// a ^ b ^ k with k wave-uniform, in one instruction: gfx950's three-input
+// bitwise operation with truth table 0x96 (odd parity).  Left to itself the
+// compiler issues two two-input xors here.
+__device__ __forceinline__ uint32_t xor3_uniform(uint32_t a, uint32_t b, uint32_t k) {
+  uint32_t r;
+  asm("v_bitop3_b32 %0, %1, %2, %3 bitop3:0x96" : "=v"(r) : "v"(a), "v"(b), "s"(k));
+  return r;
+}
+
+// The keys k0, k1 are wave-uniform (kernel arguments).
 __device__ __forceinline__ U4 philox4x32_10(U4 c, uint32_t k0, uint32_t k1) {
   constexpr uint32_t M0 = 0xD2511F53u, M1 = 0xCD9E8D57u;
   constexpr uint32_t W0 = 0x9E3779B9u, W1 = 0xBB67AE85u;
@@ -267,9 +277,9 @@ __device__ __forceinline__ U4 philox4x32_10(U4 c, uint32_t k0, uint32_t k1) {
     uint64_t p0 = static_cast<uint64_t>(M0) * c.x;
     uint64_t p1 = static_cast<uint64_t>(M1) * c.z;
     U4 n;
-    n.x = static_cast<uint32_t>(p1 >> 32) ^ c.y ^ k0;
+    n.x = xor3_uniform(static_cast<uint32_t>(p1 >> 32), c.y, k0);
     n.y = static_cast<uint32_t>(p1);
-    n.z = static_cast<uint32_t>(p0 >> 32) ^ c.w ^ k1;
+    n.z = xor3_uniform(static_cast<uint32_t>(p0 >> 32), c.w, k1);
     n.w = static_cast<uint32_t>(p0);
     c = n;
     k0 += W0;

@@ -9,6 +9,7 @@ corner divergence lies within a few float32 ulps of the isovalue."""
 
 import numpy as np
 import pytest
+import torch
 
 import oracle as O
 import paper_2510_01190_amd as P
@@ -81,6 +82,73 @@ def test_mc_zero_variance_is_deterministic():
     g = host64(P.mc_lcp(*ts, iso, n_samples=10, seed=1))
     r = O.mc_lcp(*stored64(ts), 1.0, 1.0, iso, 10, 1, precision="f32")
     assert np.array_equal(g, r)
+
+
+def _iso16_cases():
+    rng = np.random.default_rng(21)
+    base = rng.uniform(-0.15, 0.15, 16).astype(np.float32)
+    ties = base.copy()
+    ties[[3, 7, 11]] = ties[0]          # equal isovalues, out of order
+    ties[[5, 9]] = np.float32(0.0)
+    yield "unsorted16", base
+    yield "ties16", ties
+    yield "thirteen", base[:13][::-1].copy()   # 16-slot chunk with 3 empty slots
+    yield "nine", base[:9]
+    yield "seventeen", np.append(base, np.float32(0.01))
+
+
+@pytest.mark.parametrize("shape,s", [((37, 45), 301), ((2, 2), 29), ((66, 130), 16),
+                                     ((3, 70), 1)])
+@pytest.mark.parametrize("name,iso", list(_iso16_cases()), ids=[c[0] for c in _iso16_cases()])
+def test_ranked_crossing_matches_oracle(shape, s, name, iso):
+    """Chunks of 9-16 isovalues take the ranked crossing test (vertex ranks
+    against the sorted isovalues, bit-sliced counters): counts equal the
+    oracle's float32-decision MC up to near-isovalue flips, with ties between
+    isovalues, unsorted isovalues, empty slots and odd sample counts."""
+    ny, nx = shape
+    f = synth.gen_moments(ny, nx, seed=7 * ny + nx, sigma=(0.05, 0.5))
+    ts = moments_dev(f)
+    seed = 0x5EED_0000_0000_0001 + s
+    g = host64(P.mc_lcp(*ts, iso, n_samples=s, seed=seed))
+    r = O.mc_lcp(*stored64(ts), 1.0, 1.0, iso, s, seed, precision="f32")
+    flips = np.abs(np.rint(g * s) - np.rint(r * s))
+    assert flips.sum() <= 5 + 1e-5 * flips.size * s, flips.sum()
+
+
+def test_ranked_and_direct_crossing_counts_are_identical():
+    """A chunk holding a NaN isovalue takes the direct test (16 compares per
+    cell); with the same samples the other 15 planes must equal the ranked
+    test's bitwise, and the NaN plane is 0 (no corner is >= NaN)."""
+    ny, nx = 130, 97
+    f = synth.gen_moments(ny, nx, seed=88, sigma=(0.05, 0.5))
+    ts = moments_dev(f)
+    iso = np.random.default_rng(3).uniform(-0.12, 0.12, 16).astype(np.float32)
+    a = P.mc_lcp(*ts, iso, n_samples=333, seed=99)
+    iso_nan = iso.copy()
+    iso_nan[6] = np.nan
+    b = P.mc_lcp(*ts, iso_nan, n_samples=333, seed=99)
+    keep = [q for q in range(16) if q != 6]
+    assert torch.equal(a[keep], b[keep])
+    assert float(b[6].abs().max()) == 0.0
+
+
+@pytest.mark.parametrize("s", [65535, 65536])
+def test_counter_capacity_at_the_ranked_limit(s):
+    """Zero variance: every sample crosses the same cells, so their count is
+    the sample count.  65535 samples fill the ranked test's 16-bit counters
+    exactly; 65536 take the direct test.  Both give exactly 1 there."""
+    ny, nx = 5, 6
+    f = synth.gen_moments(ny, nx, seed=2)
+    f["var_u"] = np.zeros_like(f["var_u"])
+    f["var_v"] = np.zeros_like(f["var_v"])
+    ts = moments_dev(f)
+    mu = stored64(ts)
+    d = O.fd_divergence(mu[0], mu[2], 1.0, 1.0)
+    iso = np.quantile(d, np.linspace(0.05, 0.95, 16)).astype(np.float32)
+    g = host64(P.mc_lcp(*ts, iso, n_samples=s, seed=5))
+    r = O.mc_lcp(*mu, 1.0, 1.0, iso, 2, 5, precision="f32")  # deterministic: 0 or 1
+    assert np.array_equal(g, r)
+    assert g.max() == 1.0
 
 
 @pytest.mark.parametrize("S", [10, 100, 1000])
