@@ -13,18 +13,19 @@
 // bound by vector ALU work (integer multiplies, transcendentals, compares),
 // not by memory.
 //
-// Crossing test at 16 isovalues (ranked): with the isovalues in ascending
+// Crossing test at 8 or 16 isovalues (ranked): with the isovalues in ascending
 // order, a vertex's rank r(d) = #{q : c_q <= d} says that it is above exactly
 // the isovalues q < r(d) (>= counts as above), so a cell is crossed exactly
 // at the isovalues rmin <= q < rmax, rmin and rmax the smallest and largest
 // rank of its corners.  Each vertex's rank comes from a branch-free binary
-// search (four LDS lookups in a breadth-first table, one compare with the
+// search (log2 K LDS lookups in a breadth-first table, one compare with the
 // largest isovalue); each cell's crossed set is the bit mask [rmin, rmax);
-// the masks of two cells share a 32-bit word and are counted in bit-sliced
+// the masks of 32/K cells share a 32-bit word and are counted in bit-sliced
 // counters (bit plane b holds bit b of every count): a 4-plane counter takes
 // each pair of samples with a handful of logic operations and is added into
-// a 16-plane counter every 7 pairs.  About a third of the instructions of
-// 16 compares and a carry-add per isovalue and cell, the same counts.
+// a 16-plane counter every 7 pairs.  At 16 isovalues about a third of the
+// instructions of 16 compares and a carry-add per isovalue and cell, for the
+// same counts.
 //
 // Vertex-level sampling (PDIV_MC_VERTEX) draws each vertex divergence on its
 // own from the Gaussian of Eq. 2-3 instead, so the four corners of every cell
@@ -61,28 +62,30 @@ __device__ __forceinline__ float fd_div(float ul, float ur, float vl, float vr, 
   return (ur - ul) * cxm + (vr - vl) * cym;
 }
 
-// The isovalues of a 16-isovalue chunk in ascending order: tree[1..15] holds
-// the 15 smallest in breadth-first order of a complete binary search tree
-// (node i's children are 2i and 2i+1; an in-order walk visits them sorted),
-// tree[0] the largest; perm[q] is the output plane of the q-th smallest.
+// The isovalues of a chunk of K = 8 or 16 slots in ascending order:
+// tree[1..K-1] holds the K-1 smallest in breadth-first order of a complete
+// binary search tree (node i's children are 2i and 2i+1; an in-order walk
+// visits them sorted), tree[0] the largest; perm[q] is the output plane of
+// the q-th smallest.
 struct RankTable {
   float tree[16];
   int perm[16];
 };
 
-// #{q : c_q <= d} over the 16 sorted isovalues (0..16); NaN ranks 0, below
+// #{q : c_q <= d} over the K sorted isovalues (0..K); NaN ranks 0, below
 // every isovalue, as every >= comparison with it is false.  The walk keeps
 // the node's byte offset a = 4i in the table (children at 2a and 2a + 4), so
 // each level is one LDS read, a compare, a select and a shift-add.
-__device__ __forceinline__ uint32_t rank16(float d, const float* tree, float top) {
+template <int K>
+__device__ __forceinline__ uint32_t rank_of(float d, const float* tree, float top) {
   const char* base = reinterpret_cast<const char*>(tree);
   uint32_t a = 4u;
 #pragma unroll
-  for (int k = 0; k < 4; ++k) {
+  for (int k = 1; k < K; k *= 2) {
     const float t = *reinterpret_cast<const float*>(base + a);
     a = 2u * a + (d >= t ? 4u : 0u);
   }
-  return (a >> 2) - 16u + (d >= top ? 1u : 0u);
+  return (a >> 2) - uint32_t(K) + (d >= top ? 1u : 0u);
 }
 
 // Crossing counts of 32 (cell, isovalue) slots in bit-sliced form: bit j of
@@ -148,8 +151,8 @@ __device__ __forceinline__ uint32_t crossed_mask(uint32_t r0, uint32_t r1, uint3
   return ((1u << (hi - lo)) - 1u) << lo;
 }
 
-// RANK (16 isovalues, at most 65535 samples): the ranked crossing test; the
-// divergence slots hold each vertex's rank instead of its value.
+// RANK (8 or 16 isovalue slots, at most 65535 samples): the ranked crossing
+// test; the divergence slots hold each vertex's rank instead of its value.
 template <int KC, bool RANK, typename T>
 __global__ __launch_bounds__(kBlock) void mc_kernel(const T* __restrict__ mu,
                                                     const T* __restrict__ vu,
@@ -159,14 +162,16 @@ __global__ __launch_bounds__(kBlock) void mc_kernel(const T* __restrict__ mu,
                                                     int n_store, int n_samples, uint32_t key0,
                                                     uint32_t key1, float* __restrict__ out,
                                                     int64_t plane) {
-  static_assert(!RANK || KC == 16, "the ranked test is for 16-isovalue chunks");
+  static_assert(!RANK || KC == 8 || KC == 16, "the ranked test takes 8 or 16 slots");
+  constexpr int kPer = 32 / KC;             // ranked: cells per counter word
+  constexpr int kWords = RANK ? CPT / kPer : 1;
   __shared__ float sU[2][NP];
   __shared__ float sV[2][NP];
   __shared__ float sD[2][NV];
   __shared__ float sTree[16];
 
   const int tid = threadIdx.x;
-  if (RANK && tid < 16) sTree[tid] = rt.tree[tid];  // read after the first barrier
+  if (RANK && tid < KC) sTree[tid] = rt.tree[tid];  // read after the first barrier
   const int x0 = blockIdx.x * TX;
   const int y0 = blockIdx.y * TY;
 
@@ -197,9 +202,9 @@ __global__ __launch_bounds__(kBlock) void mc_kernel(const T* __restrict__ mu,
   for (int m = 0; m < kCnt; ++m)
 #pragma unroll
     for (int q = 0; q < KC; ++q) cnt[m][q] = 0;
-  Sliced sl[RANK ? CPT / 2 : 1];  // ranked: cells 2w and 2w+1 share word w
+  Sliced sl[kWords];  // ranked: cell m in word m / kPer at bit (m % kPer) KC
 #pragma unroll
-  for (int w = 0; w < (RANK ? CPT / 2 : 1); ++w) sliced_clear(sl[w]);
+  for (int w = 0; w < kWords; ++w) sliced_clear(sl[w]);
 
   const int n_pairs = (n_samples + 1) >> 1;
   for (int pr = 0; pr < n_pairs; ++pr) {
@@ -248,7 +253,7 @@ __global__ __launch_bounds__(kBlock) void mc_kernel(const T* __restrict__ mu,
 #pragma unroll
           for (int s = 0; s < 2; ++s) {
             const float d = fd_div(sU[s][il], sU[s][ir], sV[s][jl], sV[s][jr], cxm, cym);
-            sD[s][v] = RANK ? __uint_as_float(rank16(d, sTree, rt.tree[0])) : d;
+            sD[s][v] = RANK ? __uint_as_float(rank_of<KC>(d, sTree, rt.tree[0])) : d;
           }
         }
       }
@@ -256,11 +261,11 @@ __global__ __launch_bounds__(kBlock) void mc_kernel(const T* __restrict__ mu,
     __syncthreads();
     // 3. crossing test per cell: not all four corners on one side (>= is above)
     if constexpr (RANK) {
-      uint32_t word[2][CPT / 2];
+      uint32_t word[2][kWords];
 #pragma unroll
       for (int s = 0; s < 2; ++s)
 #pragma unroll
-        for (int w = 0; w < CPT / 2; ++w) word[s][w] = 0u;
+        for (int w = 0; w < kWords; ++w) word[s][w] = 0u;
 #pragma unroll
       for (int m = 0; m < CPT; ++m) {
         const int cidx = tid + m * kBlock;
@@ -273,16 +278,16 @@ __global__ __launch_bounds__(kBlock) void mc_kernel(const T* __restrict__ mu,
               const uint32_t mk = crossed_mask(
                   __float_as_uint(sD[s][v00]), __float_as_uint(sD[s][v00 + 1]),
                   __float_as_uint(sD[s][v00 + VX]), __float_as_uint(sD[s][v00 + VX + 1]));
-              word[s][m >> 1] |= mk << (16 * (m & 1));
+              word[s][m / kPer] |= mk << (KC * (m % kPer));
             }
           }
         }
       }
 #pragma unroll
-      for (int w = 0; w < CPT / 2; ++w) sliced_add2(sl[w], word[0][w], word[1][w]);
+      for (int w = 0; w < kWords; ++w) sliced_add2(sl[w], word[0][w], word[1][w]);
       if (pr % 7 == 6) {
 #pragma unroll
-        for (int w = 0; w < CPT / 2; ++w) sliced_flush(sl[w]);
+        for (int w = 0; w < kWords; ++w) sliced_flush(sl[w]);
       }
     } else {
 #pragma unroll
@@ -312,7 +317,7 @@ __global__ __launch_bounds__(kBlock) void mc_kernel(const T* __restrict__ mu,
   const float fs = static_cast<float>(n_samples);
   if constexpr (RANK) {
 #pragma unroll
-    for (int w = 0; w < CPT / 2; ++w) sliced_flush(sl[w]);
+    for (int w = 0; w < kWords; ++w) sliced_flush(sl[w]);
   }
 #pragma unroll
   for (int m = 0; m < CPT; ++m) {
@@ -325,7 +330,7 @@ __global__ __launch_bounds__(kBlock) void mc_kernel(const T* __restrict__ mu,
         if (q < n_store) {
           if constexpr (RANK)
             o[rt.perm[q] * plane] =
-                static_cast<float>(sliced_count(sl[m >> 1], q + 16 * (m & 1))) / fs;
+                static_cast<float>(sliced_count(sl[m / kPer], q + KC * (m % kPer))) / fs;
           else
             o[q * plane] = static_cast<float>(cnt[m][q]) / fs;
         }
@@ -472,10 +477,11 @@ __global__ __launch_bounds__(kBlock) void mc_sample_kernel(const T* __restrict__
   vs[p] = draw(ld(mv, p), __fsqrt_rn(ld(vv, p)), z.y);
 }
 
-// The ranked test's table for a chunk of kc <= 16 isovalues, or false when the
-// chunk holds a NaN (which no ordering places).  Slots past kc hold +inf: a
-// vertex ranks above them only at +inf, and their counts are not stored.
-bool rank_table(const IsoChunk& iso, int kc, RankTable* rt) {
+// The ranked test's table for a chunk of kc <= slots isovalues (slots = 8 or
+// 16), or false when the chunk holds a NaN (which no ordering places).  Slots
+// past kc hold +inf: a vertex ranks above them only at +inf, and their counts
+// are not stored.
+bool rank_table(const IsoChunk& iso, int kc, int slots, RankTable* rt) {
   int idx[16];
   for (int q = 0; q < 16; ++q) {
     if (q < kc && iso.c[q] != iso.c[q]) return false;
@@ -492,12 +498,14 @@ bool rank_table(const IsoChunk& iso, int kc, RankTable* rt) {
   for (int q = 0; q < 16; ++q) {
     sorted[q] = q < kc ? iso.c[idx[q]] : __builtin_inff();
     rt->perm[q] = q < kc ? idx[q] : 0;
+    rt->tree[q] = __builtin_inff();
   }
-  // breadth-first placement of sorted[0..14]: an in-order walk of nodes 1..15
+  // breadth-first placement of sorted[0..slots-2]: an in-order walk of the
+  // nodes 1..slots-1
   int next = 0;
   int stack[8], top = 0, node = 1;
-  while (top > 0 || node <= 15) {
-    while (node <= 15) {
+  while (top > 0 || node < slots) {
+    while (node < slots) {
       stack[top++] = node;
       node *= 2;
     }
@@ -505,7 +513,7 @@ bool rank_table(const IsoChunk& iso, int kc, RankTable* rt) {
     rt->tree[node] = sorted[next++];
     node = 2 * node + 1;
   }
-  rt->tree[0] = sorted[15];
+  rt->tree[0] = sorted[slots - 1];
   return true;
 }
 
@@ -516,9 +524,9 @@ hipError_t launch_kc(const void* mu, const void* vu, const void* mv, const void*
   dim3 grid(static_cast<unsigned>(mc_tiles_x(nx)), static_cast<unsigned>(mc_tiles_y(ny)));
   const int64_t plane = static_cast<int64_t>(ny - 1) * (nx - 1);
   RankTable rt{};
-  if constexpr (KC == 16) {
-    if (!vertex && n_samples <= 65535 && rank_table(iso, kc, &rt)) {
-      hipLaunchKernelGGL((mc_kernel<16, true, T>), grid, dim3(kBlock), 0, s,
+  if constexpr (KC == 8 || KC == 16) {
+    if (!vertex && n_samples <= 65535 && rank_table(iso, kc, KC, &rt)) {
+      hipLaunchKernelGGL((mc_kernel<KC, true, T>), grid, dim3(kBlock), 0, s,
                          static_cast<const T*>(mu), static_cast<const T*>(vu),
                          static_cast<const T*>(mv), static_cast<const T*>(vv), ny, nx, k, iso,
                          rt, kc, n_samples, static_cast<uint32_t>(seed),

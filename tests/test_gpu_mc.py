@@ -95,14 +95,17 @@ def _iso16_cases():
     yield "thirteen", base[:13][::-1].copy()   # 16-slot chunk with 3 empty slots
     yield "nine", base[:9]
     yield "seventeen", np.append(base, np.float32(0.01))
+    yield "eight", base[8:]
+    yield "five_ties", np.array([0.02, -0.05, 0.02, 0.0, -0.05], np.float32)  # 8 slots
 
 
 @pytest.mark.parametrize("shape,s", [((37, 45), 301), ((2, 2), 29), ((66, 130), 16),
                                      ((3, 70), 1)])
 @pytest.mark.parametrize("name,iso", list(_iso16_cases()), ids=[c[0] for c in _iso16_cases()])
 def test_ranked_crossing_matches_oracle(shape, s, name, iso):
-    """Chunks of 9-16 isovalues take the ranked crossing test (vertex ranks
-    against the sorted isovalues, bit-sliced counters): counts equal the
+    """Chunks of 5-16 isovalues (8 or 16 slots) take the ranked crossing test
+    (vertex ranks against the sorted isovalues, bit-sliced counters): counts
+    equal the
     oracle's float32-decision MC up to near-isovalue flips, with ties between
     isovalues, unsorted isovalues, empty slots and odd sample counts."""
     ny, nx = shape
@@ -115,25 +118,27 @@ def test_ranked_crossing_matches_oracle(shape, s, name, iso):
     assert flips.sum() <= 5 + 1e-5 * flips.size * s, flips.sum()
 
 
-def test_ranked_and_direct_crossing_counts_are_identical():
-    """A chunk holding a NaN isovalue takes the direct test (16 compares per
-    cell); with the same samples the other 15 planes must equal the ranked
-    test's bitwise, and the NaN plane is 0 (no corner is >= NaN)."""
+@pytest.mark.parametrize("k", [16, 8])
+def test_ranked_and_direct_crossing_counts_are_identical(k):
+    """A chunk holding a NaN isovalue takes the direct test (one compare pair
+    per isovalue and cell); with the same samples the other planes must equal
+    the ranked test's bitwise, and the NaN plane is 0 (no corner is >= NaN)."""
     ny, nx = 130, 97
     f = synth.gen_moments(ny, nx, seed=88, sigma=(0.05, 0.5))
     ts = moments_dev(f)
-    iso = np.random.default_rng(3).uniform(-0.12, 0.12, 16).astype(np.float32)
+    iso = np.random.default_rng(3).uniform(-0.12, 0.12, k).astype(np.float32)
     a = P.mc_lcp(*ts, iso, n_samples=333, seed=99)
     iso_nan = iso.copy()
     iso_nan[6] = np.nan
     b = P.mc_lcp(*ts, iso_nan, n_samples=333, seed=99)
-    keep = [q for q in range(16) if q != 6]
+    keep = [q for q in range(k) if q != 6]
     assert torch.equal(a[keep], b[keep])
     assert float(b[6].abs().max()) == 0.0
 
 
+@pytest.mark.parametrize("k", [16, 8])
 @pytest.mark.parametrize("s", [65535, 65536])
-def test_counter_capacity_at_the_ranked_limit(s):
+def test_counter_capacity_at_the_ranked_limit(s, k):
     """Zero variance: every sample crosses the same cells, so their count is
     the sample count.  65535 samples fill the ranked test's 16-bit counters
     exactly; 65536 take the direct test.  Both give exactly 1 there."""
@@ -144,7 +149,7 @@ def test_counter_capacity_at_the_ranked_limit(s):
     ts = moments_dev(f)
     mu = stored64(ts)
     d = O.fd_divergence(mu[0], mu[2], 1.0, 1.0)
-    iso = np.quantile(d, np.linspace(0.05, 0.95, 16)).astype(np.float32)
+    iso = np.quantile(d, np.linspace(0.05, 0.95, k)).astype(np.float32)
     g = host64(P.mc_lcp(*ts, iso, n_samples=s, seed=5))
     r = O.mc_lcp(*mu, 1.0, 1.0, iso, 2, 5, precision="f32")  # deterministic: 0 or 1
     assert np.array_equal(g, r)
