@@ -208,9 +208,10 @@ MC_SRC = [os.path.join(ROOT, "paper_2510_01190_amd", "csrc", f)
 
 
 def read_mc_valu():
-    """(VALU busy fraction, VALU wave instructions per point-sample) of the
-    Monte Carlo kernel from the committed counter summary, or None if absent
-    or taken on other kernel source."""
+    """(fraction of the class-weighted vector-ALU issue bound, VALU wave
+    instructions per point-sample) of the Monte Carlo kernel from the
+    committed counter summary, or None if absent or taken on other kernel
+    source."""
     if not os.path.exists(PROFILE_MC):
         return None
     vals = {}
@@ -221,7 +222,8 @@ def read_mc_valu():
     if vals.get("kernel_source_sha256_16") != source_hash(MC_SRC):
         return None
     try:
-        return float(vals["valu_busy"]), float(vals["valu_wave_instructions_per_point_sample"])
+        return (float(vals["alu_bound_frac"]),
+                float(vals["valu_wave_instructions_per_point_sample"]))
     except (KeyError, ValueError):
         return None
 
@@ -885,12 +887,13 @@ def main():
                         "closed_form_speedup": round(t / kern_s, 1)}
         valu = read_mc_valu()
         if valu is not None:
-            busy, ipps = valu
+            frac, ipps = valu
             result["mc"]["roofline"] = {
-                "bound": "alu", "achieved": busy, "peak": 1.0,
-                "unit": "fraction of the launch's cycles with the vector ALUs executing "
-                        "(rocprofv3 VALUBusy, counters in profiles/mc_8192x8192_k16_s1000_valu.txt)",
-                "frac": busy, "valu_wave_instructions_per_point_sample": ipps}
+                "bound": "alu", "achieved": frac, "peak": 1.0,
+                "unit": "fraction of the vector-ALU issue bound: the launch's VALU instruction "
+                        "counts per class times each class's measured cycles per instruction "
+                        "per SIMD, over the launch's cycles (profiles/mc_8192x8192_k16_s1000_valu.txt)",
+                "frac": frac, "valu_wave_instructions_per_point_sample": ipps}
         d = (mc_out - out).double()
         result["mc"]["sse_vs_closed_form_per_map"] = round(float((d * d).sum()) / K, 3)
         del mc_out, d

@@ -1,7 +1,9 @@
 """Builds libpdiv.so (gfx950) in-tree with hipcc.
 
-Every source under csrc/ is compiled for gfx950 with packed-FP32 code
-generation switched off, then linked into paper_2510_01190_amd/libpdiv.so.
+Every library source under csrc/ is compiled for gfx950 with packed-FP32
+code generation switched off, then linked into paper_2510_01190_amd/libpdiv.so.
+csrc/probe_valu_costs.hip, a standalone measuring program (not linked into
+the library), is built next to it as paper_2510_01190_amd/probe_valu_costs.
 Run as `python -m paper_2510_01190_amd.build_lib` or through build().
 """
 
@@ -16,6 +18,8 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
 OUT = os.path.join(HERE, "_build")
 LIB = os.path.join(HERE, "libpdiv.so")
+PROBE_SRC = "probe_valu_costs.hip"
+PROBE = os.path.join(HERE, "probe_valu_costs")
 
 SOURCES = ["pdiv_api.hip", "k_moments.hip", "k_lcp.hip", "k_lcp3d.hip", "k_speed_gradient.hip",
            "k_contour.hip", "k_mc.hip", "pdiv_batch.hip", "pdiv_server.hip"]
@@ -86,7 +90,22 @@ def build(verbose: bool = False, jobs: int | None = None, sanitize: bool = False
     if r.returncode != 0:
         raise RuntimeError(f"link failed:\n{r.stdout}\n{r.stderr}")
     os.replace(tmp, lib_path)
+    if not sanitize and not out_dir:
+        build_probe(hipcc)
     return lib_path
+
+
+def build_probe(hipcc: str | None = None) -> str:
+    """Compiles the vector-ALU issue-cost probe (an executable)."""
+    hipcc = hipcc or _hipcc()
+    tmp = PROBE + ".tmp"
+    cmd = [hipcc, *[f for f in CFLAGS if f not in ("-fPIC", "-munsafe-fp-atomics")],
+           os.path.join(CSRC, PROBE_SRC), "-o", tmp]
+    r = subprocess.run(cmd, capture_output=True, text=True)
+    if r.returncode != 0:
+        raise RuntimeError(f"hipcc failed on {PROBE_SRC}:\n{r.stdout}\n{r.stderr}")
+    os.replace(tmp, PROBE)
+    return PROBE
 
 
 if __name__ == "__main__":
