@@ -134,7 +134,7 @@ pdiv_status pdiv_divergence_gaussian(const void* mean_u, const void* var_u, cons
  * plane stride are multiples of 32 floats and lcp is 128-byte aligned, every
  * store writes whole cache lines, which the kernel needs for its full write
  * bandwidth (on other rows the lines that neighbouring strips share are
- * completed in L2: 8192^2 dense maps at 16 isovalues take about 1.36x the
+ * completed in L2: 8192^2 dense maps at 16 isovalues take about 1.27x the
  * time); rows interleaved by isovalue write faster still on gfx950. */
 pdiv_status pdiv_lcp(const float* div_mean, const float* div_var, int64_t ny, int64_t nx,
                      const float* isovalues_host, int32_t n_iso, float* lcp,

@@ -185,6 +185,23 @@ __global__ __launch_bounds__(kBlock) void lcp_kernel_split(
                              n_strips, n_bands);
 }
 
+// Dynamic LDS that leaves room for only two 4-wave blocks of `kernel` per CU
+// (160 KiB of LDS: 3 x 54 KiB does not fit), i.e. two waves per SIMD instead
+// of the three its registers allow.  The fused kernel's stores into rows that
+// start inside a 128-byte line, and its launches at up to 4 isovalues, run
+// faster with fewer waves writing at once (8192^2 at 16 isovalues into dense
+// maps: 1.35 against 1.45 ms; at 8: 0.73 against 0.80 ms; line-aligned rows
+// at 4 isovalues: 0.403 against 0.418 ms; line-aligned at 16: unchanged).
+// Zero if the attributes cannot be read (the launch then runs at the usual
+// occupancy).
+template <typename Kernel>
+size_t two_waves_per_simd_lds(Kernel kernel) {
+  hipFuncAttributes a{};
+  if (hipFuncGetAttributes(&a, reinterpret_cast<const void*>(kernel)) != hipSuccess) return 0;
+  constexpr size_t kPerBlock = 54 * 1024;
+  return a.sharedSizeBytes < kPerBlock ? kPerBlock - a.sharedSizeBytes : 0;
+}
+
 template <int KC, bool FUSED, typename T>
 hipError_t launch_kc(const void* p0, const void* p1, const void* p2, const void* p3, int ny,
                      int nx, const StencilCoef& k, const IsoChunk& iso, float* out,
@@ -221,18 +238,27 @@ hipError_t launch_kc(const void* p0, const void* p1, const void* p2, const void*
   }
   if constexpr (FUSED) {
     if (unaligned) {
+      static const size_t lds =
+          two_waves_per_simd_lds(lcp_kernel_paired<KC, FUSED, T, false, false>);
       hipLaunchKernelGGL((lcp_kernel_paired<KC, FUSED, T, false, false>), dim3(blocks),
-                         dim3(kBlock), 0, s, static_cast<const T*>(p0), static_cast<const T*>(p1),
-                         static_cast<const T*>(p2), static_cast<const T*>(p3), ny, nx, k, iso,
-                         out, plane, pitch, band_rows, n_strips, n_bands);
+                         dim3(kBlock), lds, s, static_cast<const T*>(p0),
+                         static_cast<const T*>(p1), static_cast<const T*>(p2),
+                         static_cast<const T*>(p3), ny, nx, k, iso, out, plane, pitch, band_rows,
+                         n_strips, n_bands);
       return hipGetLastError();
     }
   }
-  if (paired)
-    hipLaunchKernelGGL((lcp_kernel_paired<KC, FUSED, T>), dim3(blocks), dim3(kBlock), 0, s,
+  if (paired) {
+    size_t lds = 0;
+    if constexpr (FUSED && KC <= 4) {
+      static const size_t two = two_waves_per_simd_lds(lcp_kernel_paired<KC, FUSED, T>);
+      lds = two;
+    }
+    hipLaunchKernelGGL((lcp_kernel_paired<KC, FUSED, T>), dim3(blocks), dim3(kBlock), lds, s,
                        static_cast<const T*>(p0), static_cast<const T*>(p1),
                        static_cast<const T*>(p2), static_cast<const T*>(p3), ny, nx, k, iso, out,
                        plane, pitch, band_rows, n_strips, n_bands);
+  }
   else
     hipLaunchKernelGGL((lcp_kernel_split<KC, FUSED, T>), dim3(blocks), dim3(kBlock), 0, s,
                        static_cast<const T*>(p0), static_cast<const T*>(p1),

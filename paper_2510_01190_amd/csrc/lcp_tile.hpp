@@ -27,10 +27,13 @@
 // policy: a strip's 8-byte stores then fill the lines in its middle and leave
 // the two lines it shares with the neighbouring strips to be completed in L2
 // by the neighbour (XCD-contiguous strips share an L2).  It runs the same
-// arithmetic with the LDS-staged rows and three waves per SIMD; at 8192^2
-// into dense maps it takes 0.485 / 0.794 / 1.443 ms at 4 / 8 / 16 isovalues
-// against 0.47 / 0.66 / 1.13 ms into line-aligned rows (with the streaming
-// policy 0.578 / 0.974 / 1.760 ms; the split tile 1.51 ms at 16).
+// arithmetic with the LDS-staged rows, launched at two waves per SIMD (the
+// launcher reserves LDS: fewer waves writing at once complete more shared
+// lines in L2); at 8192^2 into dense maps it takes 0.46 / 0.73 / 1.35 ms at
+// 4 / 8 / 16 isovalues (0.50 / 0.80 / 1.455 ms at three waves per SIMD)
+// against 0.40 / 0.66 / 1.07 ms into line-aligned rows (with the streaming
+// policy 0.578 / 0.974 / 1.760 ms at three waves; the split tile 1.51 ms at
+// 16).
 //
 // Split (lcp_tile_split), for the other outputs (the two-step path on rows
 // that start inside a line, and small maps with few isovalues, where a
