@@ -385,7 +385,12 @@ typedef struct pdiv_server_stats_t {
  * hardware queue with the upload stream, or they wait behind its host-to-device
  * copies (milliseconds per large field): keep n_streams + 2 (the upload stream
  * and the application's own stream) within the device's hardware queues per
- * process (4 by default on ROCm; GPU_MAX_HW_QUEUES). */
+ * process (4 by default on ROCm; GPU_MAX_HW_QUEUES).  For tests of the
+ * failure paths, the environment variable PDIV_FAULT=<point>:<n>[,...] read
+ * here makes the n-th start of <point> (server_launch: a merged slider
+ * launch; server_upload: a new field's upload) fail on the host before
+ * anything is enqueued; the requests it carries finish with
+ * PDIV_ERR_DEVICE. */
 pdiv_status pdiv_server_create(size_t hbm_budget, int32_t n_streams, pdiv_server* out);
 /* New field from host moment planes (pageable or pinned host memory, dtype as
  * given, [ny][nx] each): uploaded, reduced to its divergence Gaussians

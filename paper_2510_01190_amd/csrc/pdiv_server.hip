@@ -97,10 +97,22 @@ struct Pending {  // device side of one in-flight handle
   void* staging = nullptr;  // device staging of a new field
 };
 
-int fault_after() {  // PDIV_FAULT=server_launch:<n>: the n-th slider launch fails (n >= 1)
+// Forced failures for tests of the failure paths, read when a server is
+// created: PDIV_FAULT=<point>:<n>[,<point>:<n>] makes the n-th start (n >= 1)
+// of <point> fail on the host before anything is enqueued.  Points:
+// server_launch (a merged slider launch), server_upload (a new field's
+// upload).  0 when <point> is not named.
+int fault_after(const char* point) {
   const char* f = std::getenv("PDIV_FAULT");
-  if (!f || std::strncmp(f, "server_launch:", 14) != 0) return 0;
-  return std::atoi(f + 14);
+  if (!f) return 0;
+  const size_t len = std::strlen(point);
+  for (const char* p = f; *p;) {
+    if (std::strncmp(p, point, len) == 0 && p[len] == ':') return std::atoi(p + len + 1);
+    const char* c = std::strchr(p, ',');
+    if (!c) break;
+    p = c + 1;
+  }
+  return 0;
 }
 
 double seconds_now() {
@@ -139,7 +151,9 @@ struct pdiv_server_s : serve::Executor {
   uint64_t next_ticket = 1;
   int next_stream = 0;
   int slider_starts = 0;
-  int fault_at = 0;
+  int fault_at = 0;         // PDIV_FAULT server_launch
+  int upload_starts = 0;
+  int fault_upload_at = 0;  // PDIV_FAULT server_upload
 
   // --- pinned host staging (reused, released at destroy) -------------------
   PinnedBuf* alloc_pinned(size_t cls) {
@@ -212,6 +226,8 @@ struct pdiv_server_s : serve::Executor {
   }
 
   uint64_t start_upload(serve::Request* r, serve::Field* f, size_t staging_bytes) override {
+    if (fault_upload_at > 0 && ++upload_starts == fault_upload_at)
+      return 0;  // forced from the host: nothing is allocated or enqueued
     const size_t n = size_t(r->ny) * size_t(r->nx);
     void* staging = nullptr;
     hipError_t e = hipMallocFromPoolAsync(&f->dev[0], 4 * n, pool, upload);
@@ -342,7 +358,8 @@ pdiv_status pdiv_server_create(size_t hbm_budget, int32_t n_streams, pdiv_server
                    size_t(n_slots) * slot_bytes + (size_t(1) << 20));
   auto srv = std::make_unique<pdiv_server_s>();
   srv->n_streams = n_streams;
-  srv->fault_at = fault_after();
+  srv->fault_at = fault_after("server_launch");
+  srv->fault_upload_at = fault_after("server_upload");
   hipError_t e = hipGetDevice(&srv->device);
   hipMemPoolProps props{};
   props.allocType = hipMemAllocationTypePinned;

@@ -209,6 +209,29 @@ def test_forced_launch_failure_stays_with_its_requests(monkeypatch):
     srv.close()
 
 
+def test_forced_upload_failure_stays_with_its_field(monkeypatch):
+    # the second new field's upload is refused on the host before anything is
+    # allocated or enqueued: that put_field and the sliders on its field fail,
+    # the other fields and their sliders are served and correct
+    monkeypatch.setenv("PDIV_FAULT", "server_launch:0,server_upload:2")
+    srv = P.Server(hbm_budget=1 << 30, n_streams=2)
+    monkeypatch.delenv("PDIV_FAULT")
+    planes = [_field(90, 110, 30 + i) for i in range(3)]
+    puts = [srv.put_field(i, *planes[i]) for i in range(3)]
+    assert [srv.wait(t) for t in puts] == [OK, DEVICE, OK]
+    iso = np.array([-0.01, 0.02], np.float32)
+    outs = [torch.empty((2, 89, 109), device="cuda") for _ in range(3)]
+    status = [srv.wait(srv.submit_lcp(i, iso, outs[i])) for i in range(3)]
+    assert status == [OK, DEVICE, OK]
+    torch.cuda.synchronize()
+    orc = _Oracle()
+    for i in (0, 2):
+        _check_oracle(outs[i], orc(i, planes[i], iso))
+    st = srv.stats()
+    assert st["failed"] == 2 and st["peak_bytes"] <= 1 << 30
+    srv.close()
+
+
 def test_reserved_staging_pool_is_reused_under_back_pressure():
     # Two staging buffers for eight 1024x1024 fields submitted back to back:
     # put_field must wait for uploads to hand buffers back (the copies run on
