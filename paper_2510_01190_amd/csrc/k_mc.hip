@@ -343,8 +343,9 @@ __global__ __launch_bounds__(kBlock) void mc_kernel(const T* __restrict__ mu,
 // vertices of the tile (Eq. 2-3 evaluated as in the closed-form path).  Per
 // group of four samples one Philox4x32-10 call per vertex, at counter
 // (vertex index, group, 1, 0), gives four normals by two Box-Muller pairs:
-// (w0, w1) for samples 4g and 4g+1, (w2, w3) for 4g+2 and 4g+3.
-template <int KC, typename T>
+// (w0, w1) for samples 4g and 4g+1, (w2, w3) for 4g+2 and 4g+3.  RANK: the
+// ranked crossing test of mc_kernel (the slots hold each vertex's rank).
+template <int KC, bool RANK, typename T>
 __global__ __launch_bounds__(kBlock) void mc_vertex_kernel(const T* __restrict__ mu,
                                                            const T* __restrict__ vu,
                                                            const T* __restrict__ mv,
@@ -352,9 +353,14 @@ __global__ __launch_bounds__(kBlock) void mc_vertex_kernel(const T* __restrict__
                                                            int nx, StencilCoef k, IsoChunk iso,
                                                            int n_store, int n_samples,
                                                            uint32_t key0, uint32_t key1,
+                                                           RankTable rt,
                                                            float* __restrict__ out,
                                                            int64_t plane) {
+  static_assert(!RANK || KC == 8 || KC == 16, "the ranked test takes 8 or 16 slots");
+  constexpr int kPer = 32 / KC;
+  constexpr int kWords = RANK ? CPT / kPer : 1;
   __shared__ float sD[4][NV];
+  __shared__ float sTree[16];
 
   const int tid = threadIdx.x;
   const int x0 = blockIdx.x * TX;
@@ -391,11 +397,19 @@ __global__ __launch_bounds__(kBlock) void mc_vertex_kernel(const T* __restrict__
     }
   }
 
-  uint32_t cnt[CPT][KC];
+  constexpr int kCnt = RANK ? 1 : CPT;
+  uint32_t cnt[kCnt][KC];
 #pragma unroll
-  for (int m = 0; m < CPT; ++m)
+  for (int m = 0; m < kCnt; ++m)
 #pragma unroll
     for (int q = 0; q < KC; ++q) cnt[m][q] = 0;
+  Sliced sl[kWords];
+#pragma unroll
+  for (int w = 0; w < kWords; ++w) sliced_clear(sl[w]);
+  if constexpr (RANK) {
+    if (tid < KC) sTree[tid] = rt.tree[tid];
+    __syncthreads();
+  }
 
   const int n_groups = (n_samples + 3) >> 2;
   for (int gr = 0; gr < n_groups; ++gr) {
@@ -411,29 +425,66 @@ __global__ __launch_bounds__(kBlock) void mc_vertex_kernel(const T* __restrict__
         const U4 w = philox4x32_10(c, key0, key1);
         const F2 z01 = box_muller(w.x, w.y);
         const F2 z23 = box_muller(w.z, w.w);
-        sD[0][v] = draw(dm[m], ds[m], z01.x);
-        sD[1][v] = draw(dm[m], ds[m], z01.y);
-        sD[2][v] = draw(dm[m], ds[m], z23.x);
-        sD[3][v] = draw(dm[m], ds[m], z23.y);
+        const float d[4] = {draw(dm[m], ds[m], z01.x), draw(dm[m], ds[m], z01.y),
+                            draw(dm[m], ds[m], z23.x), draw(dm[m], ds[m], z23.y)};
+#pragma unroll
+        for (int s = 0; s < 4; ++s)
+          sD[s][v] = RANK ? __uint_as_float(rank_of<KC>(d[s], sTree, rt.tree[0])) : d[s];
       }
     }
     __syncthreads();
+    if constexpr (RANK) {
+      uint32_t word[4][kWords];
 #pragma unroll
-    for (int m = 0; m < CPT; ++m) {
-      const int cidx = tid + m * kBlock;
-      const int cx = cidx % TX, cy = cidx / TX;
-      if (x0 + cx < nx - 1 && y0 + cy < ny - 1) {
-        const int v00 = cy * VX + cx;
+      for (int s = 0; s < 4; ++s)
 #pragma unroll
-        for (int s = 0; s < 4; ++s) {
-          if (4 * gr + s < n_samples) {
-            const float d0 = sD[s][v00], d1 = sD[s][v00 + 1];
-            const float d2 = sD[s][v00 + VX], d3 = sD[s][v00 + VX + 1];
-            const float lo = fminf(fminf(d0, d1), fminf(d2, d3));
-            const float hi = fmaxf(fmaxf(d0, d1), fmaxf(d2, d3));
+        for (int w = 0; w < kWords; ++w) word[s][w] = 0u;
 #pragma unroll
-            for (int q = 0; q < KC; ++q)
-              cnt[m][q] += static_cast<uint32_t>((lo < iso.c[q]) & (hi >= iso.c[q]));
+      for (int m = 0; m < CPT; ++m) {
+        const int cidx = tid + m * kBlock;
+        const int cx = cidx % TX, cy = cidx / TX;
+        if (x0 + cx < nx - 1 && y0 + cy < ny - 1) {
+          const int v00 = cy * VX + cx;
+#pragma unroll
+          for (int s = 0; s < 4; ++s) {
+            if (4 * gr + s < n_samples) {
+              const uint32_t mk = crossed_mask(
+                  __float_as_uint(sD[s][v00]), __float_as_uint(sD[s][v00 + 1]),
+                  __float_as_uint(sD[s][v00 + VX]), __float_as_uint(sD[s][v00 + VX + 1]));
+              word[s][m / kPer] |= mk << (KC * (m % kPer));
+            }
+          }
+        }
+      }
+      // two sample pairs per group: the 4-plane counter takes at most 7
+      // pairs, so it is flushed after every third group (6 pairs)
+#pragma unroll
+      for (int w = 0; w < kWords; ++w) {
+        sliced_add2(sl[w], word[0][w], word[1][w]);
+        sliced_add2(sl[w], word[2][w], word[3][w]);
+      }
+      if (gr % 3 == 2) {
+#pragma unroll
+        for (int w = 0; w < kWords; ++w) sliced_flush(sl[w]);
+      }
+    } else {
+#pragma unroll
+      for (int m = 0; m < CPT; ++m) {
+        const int cidx = tid + m * kBlock;
+        const int cx = cidx % TX, cy = cidx / TX;
+        if (x0 + cx < nx - 1 && y0 + cy < ny - 1) {
+          const int v00 = cy * VX + cx;
+#pragma unroll
+          for (int s = 0; s < 4; ++s) {
+            if (4 * gr + s < n_samples) {
+              const float d0 = sD[s][v00], d1 = sD[s][v00 + 1];
+              const float d2 = sD[s][v00 + VX], d3 = sD[s][v00 + VX + 1];
+              const float lo = fminf(fminf(d0, d1), fminf(d2, d3));
+              const float hi = fmaxf(fmaxf(d0, d1), fmaxf(d2, d3));
+#pragma unroll
+              for (int q = 0; q < KC; ++q)
+                cnt[m][q] += static_cast<uint32_t>((lo < iso.c[q]) & (hi >= iso.c[q]));
+            }
           }
         }
       }
@@ -442,6 +493,10 @@ __global__ __launch_bounds__(kBlock) void mc_vertex_kernel(const T* __restrict__
   }
 
   const float fs = static_cast<float>(n_samples);
+  if constexpr (RANK) {
+#pragma unroll
+    for (int w = 0; w < kWords; ++w) sliced_flush(sl[w]);
+  }
 #pragma unroll
   for (int m = 0; m < CPT; ++m) {
     const int cidx = tid + m * kBlock;
@@ -449,8 +504,15 @@ __global__ __launch_bounds__(kBlock) void mc_vertex_kernel(const T* __restrict__
     if (gx < nx - 1 && gy < ny - 1) {
       float* o = out + static_cast<int64_t>(gy) * (nx - 1) + gx;
 #pragma unroll
-      for (int q = 0; q < KC; ++q)
-        if (q < n_store) o[q * plane] = static_cast<float>(cnt[m][q]) / fs;
+      for (int q = 0; q < KC; ++q) {
+        if (q < n_store) {
+          if constexpr (RANK)
+            o[rt.perm[q] * plane] =
+                static_cast<float>(sliced_count(sl[m / kPer], q + KC * (m % kPer))) / fs;
+          else
+            o[q * plane] = static_cast<float>(cnt[m][q]) / fs;
+        }
+      }
     }
   }
 }
@@ -525,21 +587,28 @@ hipError_t launch_kc(const void* mu, const void* vu, const void* mv, const void*
   const int64_t plane = static_cast<int64_t>(ny - 1) * (nx - 1);
   RankTable rt{};
   if constexpr (KC == 8 || KC == 16) {
-    if (!vertex && n_samples <= 65535 && rank_table(iso, kc, KC, &rt)) {
-      hipLaunchKernelGGL((mc_kernel<KC, true, T>), grid, dim3(kBlock), 0, s,
-                         static_cast<const T*>(mu), static_cast<const T*>(vu),
-                         static_cast<const T*>(mv), static_cast<const T*>(vv), ny, nx, k, iso,
-                         rt, kc, n_samples, static_cast<uint32_t>(seed),
-                         static_cast<uint32_t>(seed >> 32), out, plane);
+    if (n_samples <= 65535 && rank_table(iso, kc, KC, &rt)) {
+      if (vertex)
+        hipLaunchKernelGGL((mc_vertex_kernel<KC, true, T>), grid, dim3(kBlock), 0, s,
+                           static_cast<const T*>(mu), static_cast<const T*>(vu),
+                           static_cast<const T*>(mv), static_cast<const T*>(vv), ny, nx, k, iso,
+                           kc, n_samples, static_cast<uint32_t>(seed),
+                           static_cast<uint32_t>(seed >> 32), rt, out, plane);
+      else
+        hipLaunchKernelGGL((mc_kernel<KC, true, T>), grid, dim3(kBlock), 0, s,
+                           static_cast<const T*>(mu), static_cast<const T*>(vu),
+                           static_cast<const T*>(mv), static_cast<const T*>(vv), ny, nx, k, iso,
+                           rt, kc, n_samples, static_cast<uint32_t>(seed),
+                           static_cast<uint32_t>(seed >> 32), out, plane);
       return hipGetLastError();
     }
   }
   if (vertex)
-    hipLaunchKernelGGL((mc_vertex_kernel<KC, T>), grid, dim3(kBlock), 0, s,
+    hipLaunchKernelGGL((mc_vertex_kernel<KC, false, T>), grid, dim3(kBlock), 0, s,
                        static_cast<const T*>(mu), static_cast<const T*>(vu),
                        static_cast<const T*>(mv), static_cast<const T*>(vv), ny, nx, k, iso, kc,
                        n_samples, static_cast<uint32_t>(seed),
-                       static_cast<uint32_t>(seed >> 32), out, plane);
+                       static_cast<uint32_t>(seed >> 32), rt, out, plane);
   else
     hipLaunchKernelGGL((mc_kernel<KC, false, T>), grid, dim3(kBlock), 0, s,
                        static_cast<const T*>(mu), static_cast<const T*>(vu),

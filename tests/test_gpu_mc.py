@@ -118,8 +118,9 @@ def test_ranked_crossing_matches_oracle(shape, s, name, iso):
     assert flips.sum() <= 5 + 1e-5 * flips.size * s, flips.sum()
 
 
+@pytest.mark.parametrize("mode", ["vector", "vertex"])
 @pytest.mark.parametrize("k", [16, 8])
-def test_ranked_and_direct_crossing_counts_are_identical(k):
+def test_ranked_and_direct_crossing_counts_are_identical(k, mode):
     """A chunk holding a NaN isovalue takes the direct test (one compare pair
     per isovalue and cell); with the same samples the other planes must equal
     the ranked test's bitwise, and the NaN plane is 0 (no corner is >= NaN)."""
@@ -127,10 +128,10 @@ def test_ranked_and_direct_crossing_counts_are_identical(k):
     f = synth.gen_moments(ny, nx, seed=88, sigma=(0.05, 0.5))
     ts = moments_dev(f)
     iso = np.random.default_rng(3).uniform(-0.12, 0.12, k).astype(np.float32)
-    a = P.mc_lcp(*ts, iso, n_samples=333, seed=99)
+    a = P.mc_lcp(*ts, iso, n_samples=333, seed=99, mode=mode)
     iso_nan = iso.copy()
     iso_nan[6] = np.nan
-    b = P.mc_lcp(*ts, iso_nan, n_samples=333, seed=99)
+    b = P.mc_lcp(*ts, iso_nan, n_samples=333, seed=99, mode=mode)
     keep = [q for q in range(k) if q != 6]
     assert torch.equal(a[keep], b[keep])
     assert float(b[6].abs().max()) == 0.0
