@@ -481,8 +481,12 @@ __global__ __launch_bounds__(kBlock) void lcp3d_kernel(Planes6 src, int nz, int 
       }
     }
   };
-  if constexpr (KC <= 4 && !FUSED) {
-    // few isovalues: two sets, alternated (no copies, registers to spare)
+  if constexpr (KC == 4 && !FUSED) {
+    // 4 isovalues: two sets, alternated (no copies, registers to spare; 0.782
+    // against 0.790 ms with one set at 512^3); at 1 and 2 one set's lower
+    // register count (63 / 79 VGPRs: 8 / 6 waves per SIMD) pays for its
+    // copies on a random field (0.364 against 0.381 ms at 1 isovalue, 0.495
+    // against 0.502 at 2) and is neutral on the smooth benchmark field
     AB prev2[LZ + 1][KC];
     AB sprev2[2];
     int j = j0 + 1;
