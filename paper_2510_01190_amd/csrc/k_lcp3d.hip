@@ -43,7 +43,17 @@ constexpr int kWavesPerBlock = kBlock / 64;
 // longer chunks mean fewer waves.  At 512^3 float32: 8, 12, 16, 32, 64
 // slices take 0.877, 0.852, 0.901, 0.962, 0.976 ms.
 constexpr int kZChunk = 12;
-constexpr int kBandRows3 = 32;
+// Vertex rows per band: 32, except 16 for the two-step kernel on rows that
+// do not start on lines, where the shorter walks (twice the waves, the first
+// row of each band peeled) measured faster (512^3 dense maps: 0.396 / 0.911 /
+// 3.152 ms at 1 / 4 / 16 isovalues against 0.408 / 0.958 / 3.377 ms with
+// 32); line-aligned rows are unchanged by it and the fused kernel on dense
+// rows gains nothing (0.985 / 1.482 / 3.955 against 0.980 / 1.496 / 3.879).
+template <bool FUSED, bool LINES>
+constexpr int band_rows3() {
+  return (LINES || FUSED) ? 32 : 16;
+}
+constexpr int kMinBandRows3 = 16;
 
 // Eq. 2-3 with the z term at one vertex; the neighbours are already clamped
 // at the boundary and the coefficients chosen (1/(2h) inside, 1/h on a
@@ -324,8 +334,8 @@ __global__ __launch_bounds__(kBlock) void lcp3d_kernel(Planes6 src, int nz, int 
   if (band >= n_bands) return;
   const int k0 = grp * LZ;
   const int nl = min(LZ, nz - 1 - k0);
-  const int j0 = band * kBandRows3;
-  const int j1 = min(j0 + kBandRows3, ny - 1);
+  const int j0 = band * band_rows3<FUSED, LINES>();
+  const int j1 = min(j0 + band_rows3<FUSED, LINES>(), ny - 1);
   const int x0 = strip * kW;
   const uint32_t store_bytes = uint32_t(min(kW, nx - 1 - x0)) * 4u;
   const uint32_t soff = uint32_t(lane) * 4u;
@@ -508,7 +518,8 @@ hipError_t launch_lcp3d_kc(const Planes6& src, int nz, int ny, int nx, const Ste
   constexpr int kW = LINES ? 64 : 63;
   const int n_groups = (nz - 1 + LZ - 1) / LZ;
   const int n_strips = (nx - 1 + kW - 1) / kW;
-  const int n_bands = (ny - 1 + kBandRows3 - 1) / kBandRows3;
+  constexpr int kRows = band_rows3<FUSED, LINES>();
+  const int n_bands = (ny - 1 + kRows - 1) / kRows;
   const int64_t waves = int64_t(n_groups) * n_strips * n_bands;
   const int64_t blocks = (waves + kWavesPerBlock - 1) / kWavesPerBlock;
   if (!launch_fits(blocks, kBlock)) return hipErrorInvalidConfiguration;
@@ -523,7 +534,7 @@ hipError_t launch_lcp3d_kc(const Planes6& src, int nz, int ny, int nx, const Ste
 int64_t lcp3d_blocks(int64_t nz, int64_t ny, int64_t nx, int kc) {
   const int lz = kc <= 4 ? 4 : 2;  // the fewest layers any launch uses
   const int64_t waves = ((nz - 1 + lz - 1) / lz) * ((nx - 1 + 62) / 63) *
-                        ((ny - 1 + kBandRows3 - 1) / kBandRows3);
+                        ((ny - 1 + kMinBandRows3 - 1) / kMinBandRows3);
   return (waves + kWavesPerBlock - 1) / kWavesPerBlock;
 }
 
