@@ -23,9 +23,12 @@
 // the masks of 32/K cells share a 32-bit word and are counted in bit-sliced
 // counters (bit plane b holds bit b of every count): a 4-plane counter takes
 // each pair of samples with a handful of logic operations and is added into
-// a 16-plane counter every 7 pairs.  At 16 isovalues about a third of the
-// instructions of 16 compares and a carry-add per isovalue and cell, for the
-// same counts.
+// a 16-plane counter before it can overflow (every 7 pairs; every 6 in the
+// vertex mode, which takes samples four at a time).  At 16 isovalues about a
+// third of the instructions of 16 compares and a carry-add per isovalue and
+// cell, for the same counts.  Both sampling modes use it; chunks of 1, 2 or
+// 4 isovalues, chunks holding a NaN isovalue and runs of more than 65535
+// samples take the direct test.
 //
 // Vertex-level sampling (PDIV_MC_VERTEX) draws each vertex divergence on its
 // own from the Gaussian of Eq. 2-3 instead, so the four corners of every cell
