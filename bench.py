@@ -204,7 +204,7 @@ def cpu_legs(stored, iso, rows, mc_rows=34, mc_samples=100, mc_target=1000):
 
 PROFILE_MC = os.path.join(ROOT, "profiles", "mc_8192x8192_k16_s1000_valu.txt")
 MC_SRC = [os.path.join(ROOT, "paper_2510_01190_amd", "csrc", f)
-          for f in ("k_mc.hip", "pdiv_device.hpp")]
+          for f in ("k_mc.hip", "mc_rank.hpp", "pdiv_device.hpp")]
 
 
 def read_mc_valu():

@@ -35,6 +35,7 @@
 // are independent -- the closed form's model, which it converges to on every
 // cell, boundary cells included (where the paper's vector-level sampling
 // shares grid points between the one-sided differences).
+#include "mc_rank.hpp"
 #include "pdiv_device.hpp"
 #include "pdiv_internal.hpp"
 
@@ -64,16 +65,6 @@ __device__ __forceinline__ float fd_div(float ul, float ur, float vl, float vr, 
 #pragma clang fp contract(off)
   return (ur - ul) * cxm + (vr - vl) * cym;
 }
-
-// The isovalues of a chunk of K = 8 or 16 slots in ascending order:
-// tree[1..K-1] holds the K-1 smallest in breadth-first order of a complete
-// binary search tree (node i's children are 2i and 2i+1; an in-order walk
-// visits them sorted), tree[0] the largest; perm[q] is the output plane of
-// the q-th smallest.
-struct RankTable {
-  float tree[16];
-  int perm[16];
-};
 
 // #{q : c_q <= d} over the K sorted isovalues (0..K); NaN ranks 0, below
 // every isovalue, as every >= comparison with it is false.  The walk keeps
@@ -542,46 +533,6 @@ __global__ __launch_bounds__(kBlock) void mc_sample_kernel(const T* __restrict__
   vs[p] = draw(ld(mv, p), __fsqrt_rn(ld(vv, p)), z.y);
 }
 
-// The ranked test's table for a chunk of kc <= slots isovalues (slots = 8 or
-// 16), or false when the chunk holds a NaN (which no ordering places).  Slots
-// past kc hold +inf: a vertex ranks above them only at +inf, and their counts
-// are not stored.
-bool rank_table(const IsoChunk& iso, int kc, int slots, RankTable* rt) {
-  int idx[16];
-  for (int q = 0; q < 16; ++q) {
-    if (q < kc && iso.c[q] != iso.c[q]) return false;
-    idx[q] = q;
-  }
-  // stable insertion sort of the kc real isovalues
-  for (int a = 1; a < kc; ++a) {
-    const int v = idx[a];
-    int b = a;
-    for (; b > 0 && iso.c[idx[b - 1]] > iso.c[v]; --b) idx[b] = idx[b - 1];
-    idx[b] = v;
-  }
-  float sorted[16];
-  for (int q = 0; q < 16; ++q) {
-    sorted[q] = q < kc ? iso.c[idx[q]] : __builtin_inff();
-    rt->perm[q] = q < kc ? idx[q] : 0;
-    rt->tree[q] = __builtin_inff();
-  }
-  // breadth-first placement of sorted[0..slots-2]: an in-order walk of the
-  // nodes 1..slots-1
-  int next = 0;
-  int stack[8], top = 0, node = 1;
-  while (top > 0 || node < slots) {
-    while (node < slots) {
-      stack[top++] = node;
-      node *= 2;
-    }
-    node = stack[--top];
-    rt->tree[node] = sorted[next++];
-    node = 2 * node + 1;
-  }
-  rt->tree[0] = sorted[slots - 1];
-  return true;
-}
-
 template <int KC, typename T>
 hipError_t launch_kc(const void* mu, const void* vu, const void* mv, const void* vv, int ny,
                      int nx, const StencilCoef& k, const IsoChunk& iso, int kc, int n_samples,
@@ -590,7 +541,7 @@ hipError_t launch_kc(const void* mu, const void* vu, const void* mv, const void*
   const int64_t plane = static_cast<int64_t>(ny - 1) * (nx - 1);
   RankTable rt{};
   if constexpr (KC == 8 || KC == 16) {
-    if (n_samples <= 65535 && rank_table(iso, kc, KC, &rt)) {
+    if (n_samples <= 65535 && rank_table(iso.c, kc, KC, &rt)) {
       if (vertex)
         hipLaunchKernelGGL((mc_vertex_kernel<KC, true, T>), grid, dim3(kBlock), 0, s,
                            static_cast<const T*>(mu), static_cast<const T*>(vu),

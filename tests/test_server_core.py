@@ -35,3 +35,25 @@ def test_server_policy_with_fake_executor(tmp_path):
                  "failed_upload_isolated", "failed_launch_isolated", "shutdown_fails_queued",
                  "dtype_staging_bytes", "random_soak"):
         assert f"PASS {name}" in r.stdout
+
+
+def test_monte_carlo_rank_table(tmp_path):
+    """The Monte Carlo kernel's sorted isovalue table (csrc/mc_rank.hpp):
+    the search the kernel takes gives every value's rank over the chunk,
+    with ties, infinities, empty slots, 8 and 16 slots; NaN isovalues are
+    refused.  Host C++ under AddressSanitizer and UndefinedBehaviorSanitizer."""
+    gxx = shutil.which("g++")
+    if gxx is None:
+        pytest.skip("no host C++ compiler")
+    exe = str(tmp_path / "mc_rank_test")
+    src = os.path.join(HERE, "host_checks", "mc_rank_test.cpp")
+    cmd = [gxx, "-std=c++17", "-O1", "-g", "-Wall", "-Wextra", "-Werror",
+           "-fsanitize=address,undefined", "-fno-sanitize-recover=all", src, "-o", exe]
+    r = subprocess.run(cmd, capture_output=True, text=True, timeout=300)
+    assert r.returncode == 0, r.stderr[-3000:]
+    env = dict(os.environ)
+    env.pop("LD_PRELOAD", None)
+    env["ASAN_OPTIONS"] = "detect_leaks=1:abort_on_error=1"
+    r = subprocess.run([exe], capture_output=True, text=True, timeout=300, env=env)
+    assert r.returncode == 0, (r.stdout[-3000:], r.stderr[-3000:])
+    assert "ALL PASS" in r.stdout
