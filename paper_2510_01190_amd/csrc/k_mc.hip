@@ -82,69 +82,6 @@ __device__ __forceinline__ uint32_t rank_of(float d, const float* tree, float to
   return (a >> 2) - uint32_t(K) + (d >= top ? 1u : 0u);
 }
 
-// Crossing counts of 32 (cell, isovalue) slots in bit-sliced form: bit j of
-// s[b] / t[b] is bit b of slot j's count.  add2 adds the 0/1 masks of two
-// samples to the 4-plane counter s (at most 15: flush after 7 pairs);
-// flush adds s into the 16-plane counter t (counts up to 65535) and clears s.
-struct Sliced {
-  uint32_t s[4];
-  uint32_t t[16];
-};
-
-__device__ __forceinline__ void sliced_clear(Sliced& c) {
-#pragma unroll
-  for (int b = 0; b < 4; ++b) c.s[b] = 0u;
-#pragma unroll
-  for (int b = 0; b < 16; ++b) c.t[b] = 0u;
-}
-
-__device__ __forceinline__ void sliced_add2(Sliced& c, uint32_t w0, uint32_t w1) {
-  const uint32_t x = w0 ^ w1, y = w0 & w1;  // the pair's sum: y x, two bits
-  const uint32_t c0 = c.s[0] & x;
-  c.s[0] ^= x;
-  const uint32_t t1 = c.s[1] ^ y;
-  const uint32_t c1 = (c.s[1] & y) | (t1 & c0);
-  c.s[1] = t1 ^ c0;
-  const uint32_t c2 = c.s[2] & c1;
-  c.s[2] ^= c1;
-  c.s[3] ^= c2;
-}
-
-__device__ __forceinline__ void sliced_flush(Sliced& c) {
-  uint32_t carry = c.t[0] & c.s[0];
-  c.t[0] ^= c.s[0];
-#pragma unroll
-  for (int b = 1; b < 4; ++b) {
-    const uint32_t u = c.t[b] ^ c.s[b];
-    const uint32_t nc = (c.t[b] & c.s[b]) | (u & carry);
-    c.t[b] = u ^ carry;
-    carry = nc;
-  }
-#pragma unroll
-  for (int b = 4; b < 16; ++b) {
-    const uint32_t nc = c.t[b] & carry;
-    c.t[b] ^= carry;
-    carry = nc;
-  }
-#pragma unroll
-  for (int b = 0; b < 4; ++b) c.s[b] = 0u;
-}
-
-__device__ __forceinline__ uint32_t sliced_count(const Sliced& c, int j) {
-  uint32_t n = 0;
-#pragma unroll
-  for (int b = 0; b < 16; ++b) n |= ((c.t[b] >> j) & 1u) << b;
-  return n;
-}
-
-// Crossed isovalues of a cell from its corners' ranks: the bits rmin..rmax-1.
-__device__ __forceinline__ uint32_t crossed_mask(uint32_t r0, uint32_t r1, uint32_t r2,
-                                                 uint32_t r3) {
-  const uint32_t lo = min(min(r0, r1), min(r2, r3));
-  const uint32_t hi = max(max(r0, r1), max(r2, r3));
-  return ((1u << (hi - lo)) - 1u) << lo;
-}
-
 // RANK (8 or 16 isovalue slots, at most 65535 samples): the ranked crossing
 // test; the divergence slots hold each vertex's rank instead of its value.
 template <int KC, bool RANK, typename T>

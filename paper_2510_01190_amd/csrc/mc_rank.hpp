@@ -1,8 +1,10 @@
-// Host side of the Monte Carlo kernel's ranked crossing test: the sorted
-// isovalue table the kernel searches.  Plain C++ (no HIP), so that a host
-// test can build it as the library does.
+// The Monte Carlo kernel's ranked crossing test, the parts that are plain
+// C++: the sorted isovalue table the kernel searches (built on the host) and
+// the bit-sliced crossing counters (constexpr, so the kernel and a host test
+// compile the same functions).
 #pragma once
 
+#include <cstdint>
 #include <limits>
 
 namespace pdiv {
@@ -58,6 +60,65 @@ inline bool rank_table(const float* c, int kc, int slots, RankTable* rt) {
   }
   rt->tree[0] = sorted[slots - 1];
   return true;
+}
+
+// Crossing counts of 32 (cell, isovalue) slots in bit-sliced form: bit j of
+// s[b] / t[b] is bit b of slot j's count.  sliced_add2 adds the 0/1 masks
+// of two samples to the 4-plane counter s (which holds at most 15: flush
+// after at most 7 pairs); sliced_flush adds s into the 16-plane counter t
+// (counts up to 65535) and clears s.
+struct Sliced {
+  uint32_t s[4];
+  uint32_t t[16];
+};
+
+constexpr void sliced_clear(Sliced& c) {
+  for (int b = 0; b < 4; ++b) c.s[b] = 0u;
+  for (int b = 0; b < 16; ++b) c.t[b] = 0u;
+}
+
+constexpr void sliced_add2(Sliced& c, uint32_t w0, uint32_t w1) {
+  const uint32_t x = w0 ^ w1, y = w0 & w1;  // the pair's sum: y x, two bits
+  const uint32_t c0 = c.s[0] & x;
+  c.s[0] ^= x;
+  const uint32_t t1 = c.s[1] ^ y;
+  const uint32_t c1 = (c.s[1] & y) | (t1 & c0);
+  c.s[1] = t1 ^ c0;
+  const uint32_t c2 = c.s[2] & c1;
+  c.s[2] ^= c1;
+  c.s[3] ^= c2;
+}
+
+constexpr void sliced_flush(Sliced& c) {
+  uint32_t carry = c.t[0] & c.s[0];
+  c.t[0] ^= c.s[0];
+  for (int b = 1; b < 4; ++b) {
+    const uint32_t u = c.t[b] ^ c.s[b];
+    const uint32_t nc = (c.t[b] & c.s[b]) | (u & carry);
+    c.t[b] = u ^ carry;
+    carry = nc;
+  }
+  for (int b = 4; b < 16; ++b) {
+    const uint32_t nc = c.t[b] & carry;
+    c.t[b] ^= carry;
+    carry = nc;
+  }
+  for (int b = 0; b < 4; ++b) c.s[b] = 0u;
+}
+
+constexpr uint32_t sliced_count(const Sliced& c, int j) {
+  uint32_t n = 0;
+  for (int b = 0; b < 16; ++b) n |= ((c.t[b] >> j) & 1u) << b;
+  return n;
+}
+
+// Crossed isovalues of a cell from its corners' ranks: the bits rmin..rmax-1
+// (ranks are at most 16).
+constexpr uint32_t crossed_mask(uint32_t r0, uint32_t r1, uint32_t r2, uint32_t r3) {
+  const uint32_t lo01 = r0 < r1 ? r0 : r1, lo23 = r2 < r3 ? r2 : r3;
+  const uint32_t hi01 = r0 < r1 ? r1 : r0, hi23 = r2 < r3 ? r3 : r2;
+  const uint32_t lo = lo01 < lo23 ? lo01 : lo23, hi = hi01 < hi23 ? hi23 : hi01;
+  return ((1u << (hi - lo)) - 1u) << lo;
 }
 
 }  // namespace pdiv

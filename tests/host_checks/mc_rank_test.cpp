@@ -1,9 +1,13 @@
-// Host check of the Monte Carlo kernel's rank table (csrc/mc_rank.hpp, the
-// header the library compiles): for random chunks of isovalues -- ties,
-// infinities, empty slots, 8 and 16 slots -- the table's search gives every
-// value's rank #{q : c_q <= d} over the chunk (empty slots count as +inf),
-// perm lists the isovalues in ascending order with ties in their given
-// order, and a NaN isovalue is refused.  Built with g++ under ASan/UBSan.
+// Host check of the Monte Carlo kernel's ranked crossing test
+// (csrc/mc_rank.hpp, the header the library compiles).  Rank table: for
+// random chunks of isovalues -- ties, infinities, empty slots, 8 and 16
+// slots -- the table's search gives every value's rank #{q : c_q <= d} over
+// the chunk (empty slots count as +inf), perm lists the isovalues in
+// ascending order with ties in their given order, and a NaN isovalue is
+// refused.  Crossed masks: the bits rmin..rmax-1 of every rank quadruple.
+// Bit-sliced counters: for random masks, in the two flush patterns the
+// kernels use, every slot's count equals the plain count, up to 65535.
+// Built with g++ under ASan/UBSan.
 #include <algorithm>
 #include <cmath>
 #include <cstdio>
@@ -73,6 +77,48 @@ int main() {
     check(search(t, slots, std::nanf("")) == 0, "nan rank", trial);
     c[size_t(rng() % unsigned(kc))] = std::nanf("");
     check(!pdiv::rank_table(c.data(), kc, slots, &t), "nan refused", trial);
+  }
+  // crossed masks of every rank quadruple (ranks 0..16)
+  for (uint32_t r0 = 0; r0 <= 16; ++r0)
+    for (uint32_t r1 = 0; r1 <= 16; ++r1)
+      for (uint32_t r2 = 0; r2 <= 16; r2 += 3)
+        for (uint32_t r3 = 0; r3 <= 16; r3 += 5) {
+          const uint32_t lo = std::min(std::min(r0, r1), std::min(r2, r3));
+          const uint32_t hi = std::max(std::max(r0, r1), std::max(r2, r3));
+          uint32_t want = 0;
+          for (uint32_t q = 0; q < 16; ++q) want |= (lo <= q && q < hi ? 1u : 0u) << q;
+          check(pdiv::crossed_mask(r0, r1, r2, r3) == want, "crossed mask", int(r0 * 17 + r1));
+        }
+  // bit-sliced counters against plain counts: the vector kernel adds one
+  // pair per step and flushes after every 7th, the vertex kernel adds two
+  // pairs per step and flushes after every 3rd; a final flush in both
+  for (int trial = 0; trial < 400; ++trial) {
+    const int n = trial == 0 ? 65535 : 1 + int(rng() % 3000u);
+    const bool vertex = trial % 2 == 1;
+    const unsigned density = 1u + rng() % 31u;  // bits set with probability density/32
+    pdiv::Sliced sl;
+    pdiv::sliced_clear(sl);
+    std::vector<uint32_t> plain(32, 0);
+    std::vector<uint32_t> words;
+    for (int smp = 0; smp < n; ++smp) {
+      uint32_t w = 0;
+      for (int b = 0; b < 32; ++b) w |= (trial == 0 || rng() % 32u < density ? 1u : 0u) << b;
+      words.push_back(w);
+      for (int b = 0; b < 32; ++b) plain[size_t(b)] += (w >> b) & 1u;
+    }
+    const int per_step = vertex ? 4 : 2, flush_every = vertex ? 3 : 7;
+    int step = 0;
+    for (int s0 = 0; s0 < n; s0 += per_step, ++step) {
+      for (int p = 0; p < per_step; p += 2) {
+        const uint32_t w0 = s0 + p < n ? words[size_t(s0 + p)] : 0u;
+        const uint32_t w1 = s0 + p + 1 < n ? words[size_t(s0 + p + 1)] : 0u;
+        pdiv::sliced_add2(sl, w0, w1);
+      }
+      if (step % flush_every == flush_every - 1) pdiv::sliced_flush(sl);
+    }
+    pdiv::sliced_flush(sl);
+    for (int b = 0; b < 32; ++b)
+      check(pdiv::sliced_count(sl, b) == plain[size_t(b)], "sliced count", trial);
   }
   pdiv::RankTable t;
   const float one[1] = {0.5f};
