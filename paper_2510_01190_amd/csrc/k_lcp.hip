@@ -197,7 +197,10 @@ __global__ __launch_bounds__(kBlock) void lcp_kernel_split(
 template <typename Kernel>
 size_t two_waves_per_simd_lds(Kernel kernel) {
   hipFuncAttributes a{};
-  if (hipFuncGetAttributes(&a, reinterpret_cast<const void*>(kernel)) != hipSuccess) return 0;
+  if (hipFuncGetAttributes(&a, reinterpret_cast<const void*>(kernel)) != hipSuccess) {
+    (void)hipGetLastError();  // not the launch's error
+    return 0;
+  }
   constexpr size_t kPerBlock = 54 * 1024;
   return a.sharedSizeBytes < kPerBlock ? kPerBlock - a.sharedSizeBytes : 0;
 }
